@@ -1,0 +1,164 @@
+/*
+ * bfgsuq — BFGS inverse Hessian, randomized SVD and posterior variance on MI355X.
+ *
+ * C ABI of libbfgsuq.so.  It follows the problem statement of "Preconditioned
+ * BFGS-based Uncertainty Quantification in Elastic Full Waveform Inversion"
+ * (Liu, Beller, Lei, Peter & Tromp, 2020), section "Preconditioned BFGS-based
+ * Uncertainty Quantification": after an optimizer has stored its pairs
+ * s_i = m_{i+1} - m_i, y_i = g_{i+1} - g_i and a diagonal initial inverse
+ * Hessian B_0, the inverse Hessian B_k of eq. (3) is applied to blocks of
+ * vectors, the difference B_k - B_0 is factored by the single-pass randomized
+ * SVD of Alg. 3, and the posterior variance diag(V Lambda V^T + B_0) of
+ * eqs. (10) and (14) is returned.
+ *
+ * Conventions for every call
+ *   - Pointers marked (device) are HIP device pointers; (host) are host memory.
+ *   - Blocks of vectors are column-major n x ncols with leading dimension n:
+ *     element (row r, column j) is at offset j * n + r.
+ *   - Work is enqueued on the handle's HIP stream; calls return once it is
+ *     enqueued unless stated otherwise.  The caller keeps every buffer it
+ *     passes alive and unmodified until the stream has reached the call.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Return value: BFGS_OK (0) or a negative BFGS_ERR_* code.  Argument
+ *     errors are detected before anything is enqueued.  No C++ exception
+ *     crosses this boundary.
+ *   - Storage type: pairs, h0 and probe blocks are stored in the handle's
+ *     storage type (float64, float32 or bfloat16).  Results (apply output,
+ *     U, posterior diagonal) are float64 for float64 storage and float32
+ *     otherwise.  The k x k and c x c steps always run in float64.
+ */
+#ifndef BFGSUQ_H
+#define BFGSUQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bfgsuq_ctx* bfgs_t;
+
+typedef enum { BFGS_F64 = 0, BFGS_F32 = 1, BFGS_BF16 = 2 } bfgs_dtype;
+
+enum {
+    BFGS_OK = 0,
+    BFGS_ERR_ARG = -1,        /* bad argument: NULL pointer, size out of range, bad dtype      */
+    BFGS_ERR_FULL = -2,       /* push after k_max pairs                                        */
+    BFGS_ERR_STATE = -3,      /* call out of order, e.g. posterior_diag before any rsvd        */
+    BFGS_ERR_CURVATURE = -4,  /* stored pair has s^T y <= 0: the update of eq. (3) is undefined */
+    BFGS_ERR_NONFINITE = -5,  /* NaN or Inf met in inputs or intermediate results              */
+    BFGS_ERR_NUMERIC = -6,    /* numerical breakdown: singular Q^T X, eigensolver did not converge */
+    BFGS_ERR_ALLOC = -7,      /* device allocation failed                                       */
+    BFGS_ERR_HIP = -8         /* other HIP runtime failure                                       */
+};
+
+/* Largest probe block (rank + oversampling, and ncols of one apply call). */
+#define BFGS_MAX_COLS 256
+/* Largest number of stored pairs per handle. */
+#define BFGS_MAX_PAIRS 1024
+
+/* bfgs_create — a handle for models of size n holding up to k_max pairs.
+ *   n        model size, n >= 1
+ *   k_max    capacity in pairs, 1 <= k_max <= BFGS_MAX_PAIRS
+ *   H0       (device) n entries of the diagonal initial inverse Hessian B_0
+ *            (eq. (4): the inverse of the damped diagonal Hessian guess),
+ *            double for BFGS_F64 storage, float otherwise; every entry finite
+ *            and > 0 (not checked on the device; a zero or negative entry
+ *            gives a matrix that is not positive definite).  Copied.
+ *            NULL selects B_0 = gamma I with gamma = s_0^T y_0 / y_0^T y_0
+ *            from the first accepted pair (the scaling of Alg. 1), then kept
+ *            fixed for the whole history as full-memory BFGS keeps B_0.
+ *   storage  type in which pairs, h0 and probes are stored
+ *   stream   hipStream_t to enqueue on (NULL = the null stream)
+ *   out      (host) receives the handle
+ * Allocates about 2 * n * k_max * sizeof(storage) bytes (twice that for the
+ * bfloat16 form, which keeps a second, row-blocked copy of S and Y) plus
+ * O(k_max^2) float64 and small workspaces.  Synchronous.                      */
+int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, void* stream,
+                bfgs_t* out);
+
+/* bfgs_destroy — frees the handle and all its device memory.  Synchronizes
+ * the handle's stream first.  NULL is accepted and ignored.                  */
+int bfgs_destroy(bfgs_t h);
+
+/* bfgs_push_pair — appends the pair (s, y) (definitions after eq. (2)).
+ *   s, y      (device) n entries each, float64 or float32 per in_dtype
+ *   in_dtype  BFGS_F64 or BFGS_F32; the values are rounded to nearest-even
+ *             into the storage type
+ * The curvature s^T y, r = 1 / (y^T s) of Alg. 1 and the k x k matrices of
+ * the compact form are computed from the *stored* (rounded) values.
+ * Synchronizes the stream once and then returns BFGS_ERR_CURVATURE if the
+ * stored s^T y <= 0, or BFGS_ERR_NONFINITE if it is not finite; the pair is
+ * then dropped and the handle stays usable.  BFGS_ERR_FULL after k_max pairs.
+ * s and y may be reused once the call has returned.                           */
+int bfgs_push_pair(bfgs_t h, const void* s, const void* y, bfgs_dtype in_dtype);
+
+/* bfgs_num_pairs — number of accepted pairs k (host). */
+int bfgs_num_pairs(bfgs_t h, int32_t* k_out);
+
+/* bfgs_apply_Hinv — out = B_k V, the inverse BFGS matrix of eq. (3) after the k
+ * stored pairs (the product Alg. 2 computes one column at a time), for
+ * 1 <= ncols <= BFGS_MAX_COLS columns at once.
+ *   V    (device) n x ncols, storage type
+ *   out  (device) n x ncols, float64 (F64 storage) or float32; must not alias V
+ * With k = 0 the result is B_0 V.  Never synchronizes; non-finite results set
+ * the deferred status (bfgs_get_status).                                      */
+int bfgs_apply_Hinv(bfgs_t h, const void* V, int32_t ncols, void* out);
+
+/* bfgs_apply_Hdiff — out = (B_k - B_0) V: Alg. 2 including its final
+ * subtraction of B_0 e_j, the operator that Alg. 3 samples.  Same arguments
+ * and behaviour as bfgs_apply_Hinv.                                           */
+int bfgs_apply_Hdiff(bfgs_t h, const void* V, int32_t ncols, void* out);
+
+/* bfgs_generate_probes — X, the block of independent random probe vectors of
+ * Alg. 3: entry (r, j) is N(0,1) from Philox4x64-10 (key (seed, 0), counter
+ * (r / 4, j, 0, 0)) and the Box-Muller transform in float64, rounded to float32
+ * and then (bfloat16 storage) to bfloat16, both to nearest-even.
+ *   X  (device) n x ncols in the storage type, 1 <= ncols <= BFGS_MAX_COLS   */
+int bfgs_generate_probes(bfgs_t h, uint64_t seed, int32_t ncols, void* X);
+
+/* bfgs_rsvd — single-pass randomized SVD of B_k - B_0 (Alg. 3) with
+ * c = rank + oversample probe columns drawn as in bfgs_generate_probes:
+ *   E = (B_k - B_0) X;  Q R = E (Householder, tall-skinny);  Omega (Q^T X) = Q^T E
+ *   (LU with partial pivoting, then symmetrised);  Omega = U_s Lambda U_s^T
+ *   (symmetric eigendecomposition, signed eigenvalues ordered by |lambda|
+ *   descending, ties by signed value descending then index; each eigenvector's
+ *   largest-magnitude entry made positive, lowest index on ties);
+ *   U = Q U_s[:, :rank], Sigma = lambda[:rank].
+ *   rank        1 <= rank, rank + oversample <= min(n, BFGS_MAX_COLS), oversample >= 0
+ *   U           (device) n x rank, float64 (F64 storage) or float32
+ *   Sigma       (device) rank doubles (signed eigenvalues of eq. (10)'s Lambda)
+ * Also caches the posterior diagonal for bfgs_posterior_diag.  With k = 0,
+ * B_k - B_0 = 0: Sigma = 0 and U = 0.  Never synchronizes; a singular Q^T X
+ * or an eigensolver failure sets BFGS_ERR_NUMERIC in the deferred status.     */
+int bfgs_rsvd(bfgs_t h, int32_t rank, int32_t oversample, uint64_t seed, void* U, double* Sigma);
+
+/* bfgs_posterior_diag — out_j = h0_j + sum_i Sigma_i U_ji^2, the diagonal of
+ * V Lambda V^T + B_0 (eq. (10)), i.e. the posterior variance of eq. (14) with
+ * prior C_m = I, from the last bfgs_rsvd on this handle.
+ *   out (device) n entries, float64 (F64 storage) or float32.
+ * BFGS_ERR_STATE if no rsvd has run since the last push.                      */
+int bfgs_posterior_diag(bfgs_t h, void* out);
+
+/* bfgs_get_pair — copies stored pair j (0 <= j < k), upcast exactly to
+ * float64 (F64 storage) or float32, into s_out / y_out (device, n entries
+ * each; either may be NULL).  For checking what the library stored.           */
+int bfgs_get_pair(bfgs_t h, int32_t j, void* s_out, void* y_out);
+
+/* bfgs_get_h0 — copies the diagonal B_0 in effect (gamma filled in after the
+ * first pair when created with H0 = NULL), float64 or float32, into out
+ * (device, n entries).  BFGS_ERR_STATE if gamma is not known yet.            */
+int bfgs_get_h0(bfgs_t h, void* out);
+
+/* bfgs_get_status — synchronizes the stream, returns the first deferred error
+ * recorded on the device since the last call (or BFGS_OK) and clears it.     */
+int bfgs_get_status(bfgs_t h);
+
+/* bfgs_status_string — static description of a return code. */
+const char* bfgs_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFGSUQ_H */

@@ -1,0 +1,240 @@
+"""ctypes binding of libbfgsuq.so (include/bfgsuq.h).
+
+Argument marshalling only: torch tensors provide device memory and the HIP
+stream; every step of the computation runs in the library's HIP kernels.  The
+library must be built (``paper_2009_12663_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbfgsuq.so")
+
+F64, F32, BF16 = 0, 1, 2
+STORAGE_CODES = {"f64": F64, "f32": F32, "bf16": BF16}
+STORAGE_TORCH = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+RESULT_TORCH = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}
+
+BFGS_OK = 0
+BFGS_ERR_ARG = -1
+BFGS_ERR_FULL = -2
+BFGS_ERR_STATE = -3
+BFGS_ERR_CURVATURE = -4
+BFGS_ERR_NONFINITE = -5
+BFGS_ERR_NUMERIC = -6
+BFGS_ERR_ALLOC = -7
+BFGS_ERR_HIP = -8
+MAX_COLS = 256
+MAX_PAIRS = 1024
+
+EXPORTS = [
+    "bfgs_create", "bfgs_destroy", "bfgs_push_pair", "bfgs_num_pairs", "bfgs_apply_Hinv",
+    "bfgs_apply_Hdiff", "bfgs_generate_probes", "bfgs_rsvd", "bfgs_posterior_diag",
+    "bfgs_get_pair", "bfgs_get_h0", "bfgs_get_status", "bfgs_status_string",
+]
+
+_lib = None
+
+
+class BfgsError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {status_string(code)} ({code})")
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libbfgsuq.so not built at {path}; run paper_2009_12663_amd.build.build()")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    sig = {
+        "bfgs_create": [i64, i32, vp, ctypes.c_int, vp, ctypes.POINTER(vp)],
+        "bfgs_destroy": [vp],
+        "bfgs_push_pair": [vp, vp, vp, ctypes.c_int],
+        "bfgs_num_pairs": [vp, ctypes.POINTER(i32)],
+        "bfgs_apply_Hinv": [vp, vp, i32, vp],
+        "bfgs_apply_Hdiff": [vp, vp, i32, vp],
+        "bfgs_generate_probes": [vp, u64, i32, vp],
+        "bfgs_rsvd": [vp, i32, i32, u64, vp, vp],
+        "bfgs_posterior_diag": [vp, vp],
+        "bfgs_get_pair": [vp, i32, vp, vp],
+        "bfgs_get_h0": [vp, vp],
+        "bfgs_get_status": [vp],
+        "bfgs_status_string": [ctypes.c_int],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name == "bfgs_status_string" else ctypes.c_int
+    _lib = L
+    return L
+
+
+def status_string(code: int) -> str:
+    try:
+        return load().bfgs_status_string(code).decode()
+    except Exception:  # pragma: no cover
+        return "status"
+
+
+def _check(code: int, where: str) -> int:
+    if code < 0:
+        raise BfgsError(code, where)
+    return code
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Bfgs:
+    """One BFGS history on the current CUDA/HIP device and stream.
+
+    Vectors and blocks are torch tensors on the device; a block of ncols
+    vectors of length n has shape (ncols, n) (column-major n x ncols)."""
+
+    def __init__(self, n: int, k_max: int, h0: torch.Tensor | None = None, storage: str = "f32",
+                 stream: torch.cuda.Stream | None = None):
+        self.L = load()
+        self.n, self.k_max, self.storage = int(n), int(k_max), storage
+        self.sdt = STORAGE_TORCH[storage]
+        self.rdt = RESULT_TORCH[storage]
+        self.hdt = torch.float64 if storage == "f64" else torch.float32
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._h0 = None
+        if h0 is not None:
+            assert h0.is_cuda and h0.numel() == self.n
+            self._h0 = h0.to(self.hdt).contiguous()
+        handle = ctypes.c_void_p()
+        _check(self.L.bfgs_create(self.n, self.k_max, _ptr(self._h0), STORAGE_CODES[storage],
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)),
+               "bfgs_create")
+        self.h = handle
+
+    # -- life cycle -------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.bfgs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- calls ------------------------------------------------------------------------
+    def push_pair(self, s: torch.Tensor, y: torch.Tensor) -> None:
+        dt = torch.float64 if s.dtype == torch.float64 else torch.float32
+        s = s.to(dt).contiguous()
+        y = y.to(dt).contiguous()
+        assert s.numel() == self.n and y.numel() == self.n and s.is_cuda and y.is_cuda
+        _check(self.L.bfgs_push_pair(self.h, _ptr(s), _ptr(y), F64 if dt == torch.float64 else F32),
+               "bfgs_push_pair")
+
+    @property
+    def k(self) -> int:
+        out = ctypes.c_int32()
+        _check(self.L.bfgs_num_pairs(self.h, ctypes.byref(out)), "bfgs_num_pairs")
+        return out.value
+
+    def _block(self, V):
+        assert V.is_cuda and V.dim() == 2 and V.shape[1] == self.n
+        return V.to(self.sdt).contiguous()
+
+    def apply_Hinv(self, V: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        V = self._block(V)
+        if out is None:
+            out = torch.empty(V.shape, dtype=self.rdt, device=V.device)
+        _check(self.L.bfgs_apply_Hinv(self.h, _ptr(V), V.shape[0], _ptr(out)), "bfgs_apply_Hinv")
+        return out
+
+    def apply_Hdiff(self, V: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        V = self._block(V)
+        if out is None:
+            out = torch.empty(V.shape, dtype=self.rdt, device=V.device)
+        _check(self.L.bfgs_apply_Hdiff(self.h, _ptr(V), V.shape[0], _ptr(out)), "bfgs_apply_Hdiff")
+        return out
+
+    def generate_probes(self, seed: int, ncols: int) -> torch.Tensor:
+        X = torch.empty((ncols, self.n), dtype=self.sdt, device="cuda")
+        _check(self.L.bfgs_generate_probes(self.h, ctypes.c_uint64(seed), ncols, _ptr(X)),
+               "bfgs_generate_probes")
+        return X
+
+    def rsvd(self, rank: int, oversample: int, seed: int, U: torch.Tensor | None = None,
+             Sigma: torch.Tensor | None = None):
+        if U is None:
+            U = torch.empty((rank, self.n), dtype=self.rdt, device="cuda")
+        if Sigma is None:
+            Sigma = torch.empty(rank, dtype=torch.float64, device="cuda")
+        _check(self.L.bfgs_rsvd(self.h, rank, oversample, ctypes.c_uint64(seed), _ptr(U), _ptr(Sigma)),
+               "bfgs_rsvd")
+        return U, Sigma
+
+    def posterior_diag(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.n, dtype=self.rdt, device="cuda")
+        _check(self.L.bfgs_posterior_diag(self.h, _ptr(out)), "bfgs_posterior_diag")
+        return out
+
+    def get_pair(self, j: int):
+        s = torch.empty(self.n, dtype=self.rdt, device="cuda")
+        y = torch.empty(self.n, dtype=self.rdt, device="cuda")
+        _check(self.L.bfgs_get_pair(self.h, j, _ptr(s), _ptr(y)), "bfgs_get_pair")
+        return s, y
+
+    def get_h0(self) -> torch.Tensor:
+        out = torch.empty(self.n, dtype=self.hdt, device="cuda")
+        _check(self.L.bfgs_get_h0(self.h, _ptr(out)), "bfgs_get_h0")
+        return out
+
+    def get_status(self) -> int:
+        return self.L.bfgs_get_status(self.h)
+
+
+# Same names as the C ABI.
+def bfgs_create(n, k, H0=None, storage="f32", stream=None) -> Bfgs:
+    return Bfgs(n, k, H0, storage, stream)
+
+
+def bfgs_push_pair(h: Bfgs, s, y):
+    return h.push_pair(s, y)
+
+
+def bfgs_apply_Hinv(h: Bfgs, V, out=None):
+    return h.apply_Hinv(V, out)
+
+
+def bfgs_apply_Hdiff(h: Bfgs, V, out=None):
+    return h.apply_Hdiff(V, out)
+
+
+def bfgs_rsvd(h: Bfgs, rank, oversample, seed, U=None, Sigma=None):
+    return h.rsvd(rank, oversample, seed, U, Sigma)
+
+
+def bfgs_posterior_diag(h: Bfgs, out=None):
+    return h.posterior_diag(out)
+
+
+def bfgs_generate_probes(h: Bfgs, seed, ncols):
+    return h.generate_probes(seed, ncols)
+
+
+def bfgs_destroy(h: Bfgs):
+    h.close()

@@ -1,0 +1,119 @@
+// Internal definitions shared by the HIP sources of libbfgsuq (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/bfgsuq.h"
+
+// ---------------------------------------------------------------------------
+// Storage types.  bf16_t is the raw bit pattern of a bfloat16.
+// ---------------------------------------------------------------------------
+struct bf16_t {
+    uint16_t bits;
+};
+
+__host__ __device__ inline float bf16_to_float(bf16_t h) {
+    union { uint32_t u; float f; } v;
+    v.u = ((uint32_t)h.bits) << 16;
+    return v.f;
+}
+
+// Round-to-nearest-even float -> bfloat16; NaN stays NaN (quiet).
+__host__ __device__ inline bf16_t float_to_bf16(float f) {
+    union { uint32_t u; float f; } v;
+    v.f = f;
+    uint32_t u = v.u;
+    bf16_t out;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+        out.bits = (uint16_t)((u >> 16) | 0x40u);
+        return out;
+    }
+    u += 0x7fffu + ((u >> 16) & 1u);
+    out.bits = (uint16_t)(u >> 16);
+    return out;
+}
+
+template <typename T> struct DT;
+template <> struct DT<double> { static constexpr bfgs_dtype code = BFGS_F64; };
+template <> struct DT<float> { static constexpr bfgs_dtype code = BFGS_F32; };
+template <> struct DT<bf16_t> { static constexpr bfgs_dtype code = BFGS_BF16; };
+
+__device__ __forceinline__ double to_f64(double x) { return x; }
+__device__ __forceinline__ double to_f64(float x) { return (double)x; }
+__device__ __forceinline__ double to_f64(bf16_t x) { return (double)bf16_to_float(x); }
+__device__ __forceinline__ float to_f32(float x) { return x; }
+__device__ __forceinline__ float to_f32(bf16_t x) { return bf16_to_float(x); }
+__device__ __forceinline__ float to_f32(double x) { return (float)x; }
+
+template <typename T> __device__ __forceinline__ T from_f64(double x);
+template <> __device__ __forceinline__ double from_f64<double>(double x) { return x; }
+template <> __device__ __forceinline__ float from_f64<float>(double x) { return (float)x; }
+// float64 -> float32 -> bfloat16, each to nearest-even.
+template <> __device__ __forceinline__ bf16_t from_f64<bf16_t>(double x) { return float_to_bf16((float)x); }
+
+template <typename T> __device__ __forceinline__ T from_f32(float x);
+template <> __device__ __forceinline__ float from_f32<float>(float x) { return x; }
+template <> __device__ __forceinline__ double from_f32<double>(float x) { return (double)x; }
+template <> __device__ __forceinline__ bf16_t from_f32<bf16_t>(float x) { return float_to_bf16(x); }
+
+inline size_t dtype_size(bfgs_dtype d) { return d == BFGS_F64 ? 8 : d == BFGS_F32 ? 4 : 2; }
+
+// ---------------------------------------------------------------------------
+// Handle.
+// ---------------------------------------------------------------------------
+struct Workspace {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct bfgsuq_ctx {
+    int64_t n = 0;
+    int64_t ld = 0;            // leading dimension of S and Y (n rounded up to 128)
+    int32_t kmax = 0;
+    int32_t k = 0;
+    bfgs_dtype storage = BFGS_F32;
+    bool gamma_mode = false;   // B_0 = gamma I, gamma from the first pair
+    bool gamma_known = false;
+    hipStream_t stream = nullptr;
+
+    void* S = nullptr;         // ld x kmax, column-major, storage type
+    void* Y = nullptr;
+    void* h0 = nullptr;        // n, storage-real type (double for F64, float otherwise)
+    double* Rm = nullptr;      // kmax x kmax column-major: Rm[j*kmax + i] = s_i^T y_j
+    double* YHY = nullptr;     // kmax x kmax symmetric: y_i^T B_0 y_j
+    double* gram_part = nullptr;   // partial sums for push
+    double* scalars = nullptr; // [0] = gamma, [1] = last s^T y, [2] = last y^T y
+    int32_t* status = nullptr; // deferred device status (0 = OK)
+    int gram_blocks = 0;
+
+    // apply workspaces (grow-only)
+    Workspace part, Z, PT;
+    // rsvd workspaces
+    Workspace X, E, Q, refl, tau, Rtree, small, lam, diag;
+    int32_t last_rank = 0;
+    bool have_rsvd = false;
+};
+
+#define BFGS_HIP(expr)                                  \
+    do {                                                \
+        hipError_t _e = (expr);                         \
+        if (_e != hipSuccess) return BFGS_ERR_HIP;      \
+    } while (0)
+
+int ensure_ws(Workspace& w, size_t bytes);
+
+// Deferred status codes written by kernels (plain stores, no atomics).
+__device__ __forceinline__ void set_status(int32_t* status, int32_t code) {
+    if (status[0] == 0) status[0] = code;
+}
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Entry points implemented in the other translation units.
+// ---------------------------------------------------------------------------
+int apply_block(bfgsuq_ctx* h, const void* V, int32_t ncols, void* out, bool diff);
+int rsvd_run(bfgsuq_ctx* h, int32_t rank, int32_t oversample, uint64_t seed, void* U, double* Sigma);
+int probes_run(bfgsuq_ctx* h, uint64_t seed, int32_t ncols, void* X);

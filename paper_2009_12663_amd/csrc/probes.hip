@@ -1,0 +1,96 @@
+// Probe block of Alg. 3: independent N(0,1) vectors from a counter-based
+// generator, so any entry can be regenerated from (seed, row, column) alone.
+//
+// Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11): key (seed, 0), counter
+// (row / 4, column, 0, 0); the four 64-bit words give uniforms
+// u = ((x >> 11) + 1) 2^-53 in (0, 1] and Box-Muller pairs
+// (sqrt(-2 ln u0) cos(2 pi u1), sqrt(-2 ln u0) sin(2 pi u1)) for rows 4q, 4q+1 and
+// the same from (u2, u3) for rows 4q+2, 4q+3, all in float64, then rounded to
+// float32 and (bfloat16 storage) to bfloat16.
+#include <cmath>
+
+#include "common.h"
+
+namespace {
+
+struct u64x4 {
+    uint64_t v[4];
+};
+
+__device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                               uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    u64x4 r;
+    r.v[0] = c0;
+    r.v[1] = c1;
+    r.v[2] = c2;
+    r.v[3] = c3;
+    return r;
+}
+
+__device__ __forceinline__ double unit_open0(uint64_t x) { return (double)((x >> 11) + 1) * 0x1.0p-53; }
+
+// One thread per group of four rows of one column.
+template <typename T>
+__global__ void probes_kernel(int64_t n, int c, uint64_t seed, T* __restrict__ X) {
+    const int64_t quads = (n + 3) / 4;
+    const int64_t total = quads * c;
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = e % quads;
+        const int j = (int)(e / quads);
+        const u64x4 x = philox4x64_10((uint64_t)q, (uint64_t)j, 0, 0, seed, 0);
+        double z[4];
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const double rad = sqrt(-2.0 * log(unit_open0(x.v[2 * half])));
+            const double ang = two_pi * unit_open0(x.v[2 * half + 1]);
+            z[2 * half] = rad * cos(ang);
+            z[2 * half + 1] = rad * sin(ang);
+        }
+        T* col = X + (int64_t)j * n;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t r = 4 * q + t;
+            if (r < n) col[r] = from_f64<T>(z[t]);
+        }
+    }
+}
+
+}  // namespace
+
+int probes_launch(bfgsuq_ctx* h, uint64_t seed, int32_t c, void* X, hipStream_t stream) {
+    const int64_t total = (h->n + 3) / 4 * c;
+    const int grid = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (total + 255) / 256));
+    switch (h->storage) {
+        case BFGS_F64:
+            hipLaunchKernelGGL(probes_kernel<double>, dim3(grid), dim3(256), 0, stream, h->n, c, seed, (double*)X);
+            break;
+        case BFGS_F32:
+            hipLaunchKernelGGL(probes_kernel<float>, dim3(grid), dim3(256), 0, stream, h->n, c, seed, (float*)X);
+            break;
+        case BFGS_BF16:
+            hipLaunchKernelGGL(probes_kernel<bf16_t>, dim3(grid), dim3(256), 0, stream, h->n, c, seed, (bf16_t*)X);
+            break;
+    }
+    return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+}
+
+int probes_run(bfgsuq_ctx* h, uint64_t seed, int32_t ncols, void* X) {
+    return probes_launch(h, seed, ncols, X, h->stream);
+}

@@ -1,0 +1,390 @@
+// Handle life cycle, pair storage and the k x k matrices of the compact form.
+//
+// The inverse BFGS matrix of eq. (3) after k pairs is kept implicitly: the
+// pairs themselves (column-major S, Y in HBM, in the storage type) plus two
+// k x k float64 matrices built from the *stored* values as pairs arrive,
+//   Rm(i, j)  = s_i^T y_j   (upper triangle i <= j is the R of the compact form,
+//                            its diagonal the curvatures 1 / r_i of Alg. 1)
+//   YHY(i, j) = y_i^T B_0 y_j
+// Pushing pair j costs one pass over the j + 1 stored columns (O(n j)).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+int ensure_ws(Workspace& w, size_t bytes) {
+    if (bytes <= w.bytes) return BFGS_OK;
+    if (w.ptr) {
+        if (hipFree(w.ptr) != hipSuccess) return BFGS_ERR_HIP;
+        w.ptr = nullptr;
+        w.bytes = 0;
+    }
+    if (hipMalloc(&w.ptr, bytes) != hipSuccess) {
+        w.ptr = nullptr;
+        return BFGS_ERR_ALLOC;
+    }
+    w.bytes = bytes;
+    return BFGS_OK;
+}
+
+static void free_ws(Workspace& w) {
+    if (w.ptr) (void)hipFree(w.ptr);
+    w.ptr = nullptr;
+    w.bytes = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+template <typename Tin, typename Tst>
+__global__ void store_pair_kernel(int64_t n, const Tin* __restrict__ s, const Tin* __restrict__ y,
+                                  Tst* __restrict__ Scol, Tst* __restrict__ Ycol) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        Scol[r] = from_f64<Tst>(to_f64(s[r]));
+        Ycol[r] = from_f64<Tst>(to_f64(y[r]));
+    }
+}
+
+// float32 input to bfloat16 storage: one rounding (float32 -> bfloat16).
+template <>
+__global__ void store_pair_kernel<float, bf16_t>(int64_t n, const float* __restrict__ s,
+                                                 const float* __restrict__ y, bf16_t* __restrict__ Scol,
+                                                 bf16_t* __restrict__ Ycol) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        Scol[r] = float_to_bf16(s[r]);
+        Ycol[r] = float_to_bf16(y[r]);
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 64; ++w) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
+// Partial sums over row chunk b of s_i^T y_j and y_i^T (h0 o y_j) (or y_i^T y_j
+// when B_0 = gamma I), for i = blockIdx.y.
+template <typename Tst, typename Th>
+__global__ void __launch_bounds__(256) gram_partial_kernel(int64_t n, int64_t ld, int j, const Tst* __restrict__ S,
+                                                           const Tst* __restrict__ Y, const Th* __restrict__ h0,
+                                                           int gamma_mode, double* __restrict__ part) {
+    __shared__ double sh[8];
+    const int i = blockIdx.y, b = blockIdx.x, nb = gridDim.x;
+    const int64_t chunk = (n + nb - 1) / nb;
+    const int64_t r0 = b * chunk, r1 = min(n, r0 + chunk);
+    const Tst* si = S + (int64_t)i * ld;
+    const Tst* yi = Y + (int64_t)i * ld;
+    const Tst* yj = Y + (int64_t)j * ld;
+    double sy = 0.0, yhy = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+        const double y = to_f64(yj[r]);
+        sy += to_f64(si[r]) * y;
+        const double w = gamma_mode ? y : to_f64(h0[r]) * y;
+        yhy += to_f64(yi[r]) * w;
+    }
+    sy = block_sum<256>(sy, sh);
+    yhy = block_sum<256>(yhy, sh);
+    if (threadIdx.x == 0) {
+        part[((int64_t)i * nb + b) * 2 + 0] = sy;
+        part[((int64_t)i * nb + b) * 2 + 1] = yhy;
+    }
+}
+
+// Fixed-order sums of the partials; writes column j of Rm and row/column j of YHY.
+__global__ void gram_finish_kernel(int j, int kmax, int nb, const double* __restrict__ part,
+                                   double* __restrict__ Rm, double* __restrict__ YHY,
+                                   double* __restrict__ scalars, int gamma_mode) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > j) return;
+    double sy = 0.0, yhy = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        sy += part[((int64_t)i * nb + b) * 2 + 0];
+        yhy += part[((int64_t)i * nb + b) * 2 + 1];
+    }
+    Rm[(int64_t)j * kmax + i] = sy;
+    if (gamma_mode) {
+        if (j == 0) scalars[0] = sy / yhy;   // gamma = s_0^T y_0 / y_0^T y_0 (i == j == 0 here)
+        yhy *= scalars[0];
+    }
+    YHY[(int64_t)j * kmax + i] = yhy;
+    YHY[(int64_t)i * kmax + j] = yhy;
+    if (i == j) {
+        scalars[1] = sy;
+        scalars[2] = yhy;
+    }
+}
+
+template <typename Th>
+__global__ void fill_h0_kernel(int64_t n, Th* __restrict__ h0, const double* __restrict__ scalars) {
+    const double g = scalars[0];
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+        h0[r] = (Th)g;
+}
+
+template <typename Tst, typename To>
+__global__ void upcast_kernel(int64_t n, const Tst* __restrict__ src, To* __restrict__ dst) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+        dst[r] = (To)to_f64(src[r]);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+static int grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return (int)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
+}
+
+template <typename Tin, typename Tst>
+static void launch_store(bfgsuq_ctx* h, const void* s, const void* y, int j) {
+    Tst* S = (Tst*)h->S + (int64_t)j * h->ld;
+    Tst* Y = (Tst*)h->Y + (int64_t)j * h->ld;
+    hipLaunchKernelGGL((store_pair_kernel<Tin, Tst>), dim3(grid_for(h->n)), dim3(256), 0, h->stream, h->n,
+                       (const Tin*)s, (const Tin*)y, S, Y);
+}
+
+template <typename Tst, typename Th>
+static void launch_gram(bfgsuq_ctx* h, int j) {
+    hipLaunchKernelGGL((gram_partial_kernel<Tst, Th>), dim3(h->gram_blocks, j + 1), dim3(256), 0, h->stream, h->n,
+                       h->ld, j, (const Tst*)h->S, (const Tst*)h->Y, (const Th*)h->h0, h->gamma_mode ? 1 : 0,
+                       h->gram_part);
+}
+
+extern "C" {
+
+const char* bfgs_status_string(int code) {
+    switch (code) {
+        case BFGS_OK: return "ok";
+        case BFGS_ERR_ARG: return "invalid argument";
+        case BFGS_ERR_FULL: return "pair storage full";
+        case BFGS_ERR_STATE: return "call out of order";
+        case BFGS_ERR_CURVATURE: return "stored pair has s^T y <= 0";
+        case BFGS_ERR_NONFINITE: return "non-finite value";
+        case BFGS_ERR_NUMERIC: return "numerical breakdown";
+        case BFGS_ERR_ALLOC: return "device allocation failed";
+        case BFGS_ERR_HIP: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+int bfgs_destroy(bfgs_t h) {
+    if (!h) return BFGS_OK;
+    (void)hipStreamSynchronize(h->stream);
+    void* ptrs[] = {h->S, h->Y, h->h0, h->Rm, h->YHY, h->gram_part, h->scalars, h->status};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    Workspace* ws[] = {&h->part, &h->Z, &h->PT, &h->X, &h->E, &h->Q, &h->refl, &h->tau,
+                       &h->Rtree, &h->small, &h->lam, &h->diag};
+    for (Workspace* w : ws) free_ws(*w);
+    delete h;
+    return BFGS_OK;
+}
+
+int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, void* stream, bfgs_t* out) {
+    if (!out) return BFGS_ERR_ARG;
+    *out = nullptr;
+    if (n < 1 || k_max < 1 || k_max > BFGS_MAX_PAIRS) return BFGS_ERR_ARG;
+    if (storage != BFGS_F64 && storage != BFGS_F32 && storage != BFGS_BF16) return BFGS_ERR_ARG;
+    bfgsuq_ctx* h = new (std::nothrow) bfgsuq_ctx();
+    if (!h) return BFGS_ERR_ALLOC;
+    h->n = n;
+    h->ld = round_up(n, 128);
+    h->kmax = k_max;
+    h->storage = storage;
+    h->stream = (hipStream_t)stream;
+    h->gamma_mode = (H0 == nullptr);
+    const size_t es = dtype_size(storage);
+    const size_t hs = storage == BFGS_F64 ? 8 : 4;
+    h->gram_blocks = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 4095) / 4096));
+    int rc = BFGS_OK;
+    auto alloc = [&](void** p, size_t bytes) {
+        if (rc != BFGS_OK) return;
+        if (hipMalloc(p, bytes) != hipSuccess) {
+            *p = nullptr;
+            rc = BFGS_ERR_ALLOC;
+        }
+    };
+    alloc(&h->S, (size_t)h->ld * k_max * es);
+    alloc(&h->Y, (size_t)h->ld * k_max * es);
+    alloc(&h->h0, (size_t)h->ld * hs);
+    alloc((void**)&h->Rm, (size_t)k_max * k_max * 8);
+    alloc((void**)&h->YHY, (size_t)k_max * k_max * 8);
+    alloc((void**)&h->gram_part, (size_t)k_max * h->gram_blocks * 2 * 8);
+    alloc((void**)&h->scalars, 8 * 8);
+    alloc((void**)&h->status, 64);
+    if (rc != BFGS_OK) {
+        bfgs_destroy(h);
+        return rc;
+    }
+    if (hipMemsetAsync(h->S, 0, (size_t)h->ld * k_max * es, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->Y, 0, (size_t)h->ld * k_max * es, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->h0, 0, (size_t)h->ld * hs, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->Rm, 0, (size_t)k_max * k_max * 8, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->YHY, 0, (size_t)k_max * k_max * 8, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->scalars, 0, 64, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->status, 0, 64, h->stream) != hipSuccess) {
+        bfgs_destroy(h);
+        return BFGS_ERR_HIP;
+    }
+    if (H0) {
+        if (hipMemcpyAsync(h->h0, H0, (size_t)n * hs, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) {
+            bfgs_destroy(h);
+            return BFGS_ERR_HIP;
+        }
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) {
+        bfgs_destroy(h);
+        return BFGS_ERR_HIP;
+    }
+    *out = h;
+    return BFGS_OK;
+}
+
+int bfgs_num_pairs(bfgs_t h, int32_t* k_out) {
+    if (!h || !k_out) return BFGS_ERR_ARG;
+    *k_out = h->k;
+    return BFGS_OK;
+}
+
+int bfgs_push_pair(bfgs_t h, const void* s, const void* y, bfgs_dtype in_dtype) {
+    if (!h || !s || !y) return BFGS_ERR_ARG;
+    if (in_dtype != BFGS_F64 && in_dtype != BFGS_F32) return BFGS_ERR_ARG;
+    if (h->k >= h->kmax) return BFGS_ERR_FULL;
+    const int j = h->k;
+    switch (h->storage) {
+        case BFGS_F64:
+            if (in_dtype == BFGS_F64) launch_store<double, double>(h, s, y, j);
+            else launch_store<float, double>(h, s, y, j);
+            launch_gram<double, double>(h, j);
+            break;
+        case BFGS_F32:
+            if (in_dtype == BFGS_F64) launch_store<double, float>(h, s, y, j);
+            else launch_store<float, float>(h, s, y, j);
+            launch_gram<float, float>(h, j);
+            break;
+        case BFGS_BF16:
+            if (in_dtype == BFGS_F64) launch_store<double, bf16_t>(h, s, y, j);
+            else launch_store<float, bf16_t>(h, s, y, j);
+            launch_gram<bf16_t, float>(h, j);
+            break;
+    }
+    BFGS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(gram_finish_kernel, dim3((j + 1 + 255) / 256), dim3(256), 0, h->stream, j, h->kmax,
+                       h->gram_blocks, h->gram_part, h->Rm, h->YHY, h->scalars, h->gamma_mode ? 1 : 0);
+    BFGS_HIP(hipGetLastError());
+    double sc[3];
+    BFGS_HIP(hipMemcpyAsync(sc, h->scalars, sizeof(sc), hipMemcpyDeviceToHost, h->stream));
+    BFGS_HIP(hipStreamSynchronize(h->stream));
+    const double sy = sc[1], yhy = sc[2];
+    if (!std::isfinite(sy) || !std::isfinite(yhy) || (h->gamma_mode && j == 0 && !std::isfinite(sc[0])))
+        return BFGS_ERR_NONFINITE;
+    if (!(sy > 0.0)) return BFGS_ERR_CURVATURE;
+    if (h->gamma_mode && j == 0) {
+        if (!(sc[0] > 0.0)) return BFGS_ERR_CURVATURE;
+        if (h->storage == BFGS_F64)
+            hipLaunchKernelGGL(fill_h0_kernel<double>, dim3(grid_for(h->n)), dim3(256), 0, h->stream, h->n,
+                               (double*)h->h0, (const double*)h->scalars);
+        else
+            hipLaunchKernelGGL(fill_h0_kernel<float>, dim3(grid_for(h->n)), dim3(256), 0, h->stream, h->n,
+                               (float*)h->h0, (const double*)h->scalars);
+        BFGS_HIP(hipGetLastError());
+        h->gamma_known = true;
+    }
+    h->k = j + 1;
+    h->have_rsvd = false;
+    return BFGS_OK;
+}
+
+int bfgs_apply_Hinv(bfgs_t h, const void* V, int32_t ncols, void* out) {
+    if (!h || !V || !out || ncols < 1 || ncols > BFGS_MAX_COLS) return BFGS_ERR_ARG;
+    if (V == out) return BFGS_ERR_ARG;
+    if (h->gamma_mode && !h->gamma_known) return BFGS_ERR_STATE;
+    return apply_block(h, V, ncols, out, false);
+}
+
+int bfgs_apply_Hdiff(bfgs_t h, const void* V, int32_t ncols, void* out) {
+    if (!h || !V || !out || ncols < 1 || ncols > BFGS_MAX_COLS) return BFGS_ERR_ARG;
+    if (V == out) return BFGS_ERR_ARG;
+    if (h->gamma_mode && !h->gamma_known) return BFGS_ERR_STATE;
+    return apply_block(h, V, ncols, out, true);
+}
+
+int bfgs_get_pair(bfgs_t h, int32_t j, void* s_out, void* y_out) {
+    if (!h || j < 0 || j >= h->k) return BFGS_ERR_ARG;
+    const int64_t off = (int64_t)j * h->ld;
+    for (int w = 0; w < 2; ++w) {
+        void* dst = w == 0 ? s_out : y_out;
+        if (!dst) continue;
+        const void* base = w == 0 ? h->S : h->Y;
+        switch (h->storage) {
+            case BFGS_F64:
+                hipLaunchKernelGGL((upcast_kernel<double, double>), dim3(grid_for(h->n)), dim3(256), 0, h->stream,
+                                   h->n, (const double*)base + off, (double*)dst);
+                break;
+            case BFGS_F32:
+                hipLaunchKernelGGL((upcast_kernel<float, float>), dim3(grid_for(h->n)), dim3(256), 0, h->stream,
+                                   h->n, (const float*)base + off, (float*)dst);
+                break;
+            case BFGS_BF16:
+                hipLaunchKernelGGL((upcast_kernel<bf16_t, float>), dim3(grid_for(h->n)), dim3(256), 0, h->stream,
+                                   h->n, (const bf16_t*)base + off, (float*)dst);
+                break;
+        }
+        BFGS_HIP(hipGetLastError());
+    }
+    return BFGS_OK;
+}
+
+int bfgs_get_h0(bfgs_t h, void* out) {
+    if (!h || !out) return BFGS_ERR_ARG;
+    if (h->gamma_mode && !h->gamma_known) return BFGS_ERR_STATE;
+    const size_t hs = h->storage == BFGS_F64 ? 8 : 4;
+    BFGS_HIP(hipMemcpyAsync(out, h->h0, (size_t)h->n * hs, hipMemcpyDeviceToDevice, h->stream));
+    return BFGS_OK;
+}
+
+int bfgs_get_status(bfgs_t h) {
+    if (!h) return BFGS_ERR_ARG;
+    int32_t st = 0;
+    BFGS_HIP(hipMemcpyAsync(&st, h->status, 4, hipMemcpyDeviceToHost, h->stream));
+    BFGS_HIP(hipStreamSynchronize(h->stream));
+    if (st != 0) {
+        BFGS_HIP(hipMemsetAsync(h->status, 0, 4, h->stream));
+        BFGS_HIP(hipStreamSynchronize(h->stream));
+    }
+    return st;
+}
+
+int bfgs_generate_probes(bfgs_t h, uint64_t seed, int32_t ncols, void* X) {
+    if (!h || !X || ncols < 1 || ncols > BFGS_MAX_COLS) return BFGS_ERR_ARG;
+    return probes_run(h, seed, ncols, X);
+}
+
+int bfgs_rsvd(bfgs_t h, int32_t rank, int32_t oversample, uint64_t seed, void* U, double* Sigma) {
+    if (!h || !U || !Sigma || rank < 1 || oversample < 0) return BFGS_ERR_ARG;
+    const int64_t c = (int64_t)rank + oversample;
+    if (c > BFGS_MAX_COLS || c > h->n) return BFGS_ERR_ARG;
+    if (h->gamma_mode && !h->gamma_known) return BFGS_ERR_STATE;
+    return rsvd_run(h, rank, oversample, seed, U, Sigma);
+}
+
+int bfgs_posterior_diag(bfgs_t h, void* out) {
+    if (!h || !out) return BFGS_ERR_ARG;
+    if (!h->have_rsvd) return BFGS_ERR_STATE;
+    const size_t hs = h->storage == BFGS_F64 ? 8 : 4;
+    BFGS_HIP(hipMemcpyAsync(out, h->diag.ptr, (size_t)h->n * hs, hipMemcpyDeviceToDevice, h->stream));
+    return BFGS_OK;
+}
+
+}  // extern "C"
