@@ -1,7 +1,888 @@
-// Randomized SVD of B_k - B_0 (Alg. 3) — filled in below.
+// Single-pass randomized SVD of B_k - B_0 (Alg. 3) and the posterior variance
+// of eqs. (10) and (14).
+//
+//   X = probes (c = rank + oversample columns)
+//   E = (B_k - B_0) X                                  apply.hip, "difference" form
+//   E = Q R                                            Householder TSQR (below)
+//   Omega (Q^T X) = Q^T E = R                          LU with partial pivoting, float64
+//   Omega <- (Omega + Omega^T) / 2;  Omega = U_s Lambda U_s^T     tridiagonal QL, float64
+//   U = Q U_s[:, :rank],  Sigma = lambda[:rank],  d = h0 + sum_i lambda_i U_i^2
+//
+// Q^T E equals R exactly for E = Q R, so the R of the factorisation is used
+// instead of a second product with E.
+//
+// TSQR layout.  E (n x c, c <= 256) is split into `nchains` contiguous row
+// ranges, one workgroup each.  A workgroup keeps an upper-triangular c x c
+// "slot" in LDS and folds the rows in, TR rows at a time, with Householder
+// reflectors acting on (slot row j, the TR tile rows); one thread owns one
+// column and keeps its TR tile entries in registers.  The slot starts at zero:
+// a column's first non-zero tile swaps into the slot exactly (tau = 1), so the
+// slot rows carry no part of Q.  The per-chain R factors are then combined
+// pairwise (binary tree) by the same routine, reading the second R as tile
+// rows.  Q is formed explicitly by applying the stored reflectors backwards to
+// the identity at the root; every slot matrix met on the way stays upper
+// triangular, so the packed triangle suffices in both directions.  The slot is
+// float64 when it fits in LDS (c <= 180) and float32 above that.
+#include <cmath>
+#include <utility>
+
 #include "common.h"
 
+int probes_launch(bfgsuq_ctx* h, uint64_t seed, int32_t c, void* X, hipStream_t stream);
+
+namespace {
+
+constexpr int TR = 64;          // tile rows per Householder update
+constexpr int QR_THREADS = 256; // one thread per column (c <= 256)
+constexpr int SLOT_F64_MAX_C = 180;
+
+__device__ __forceinline__ int tri_index(int j, int col, int c) {
+    // packed upper triangle, row-major: row j holds columns j..c-1
+    return j * c - (j * (j - 1)) / 2 + (col - j);
+}
+
+// Forward: fold TR tile rows (a[] of this thread's column) into the slot.
+// Reflector j's tile part replaces a[] in thread j; taus[j] receives tau.
+template <typename SlotT>
+__device__ __forceinline__ void fold_tile(SlotT* slot, double (&a)[TR], int c, int jstart, double* vbuf,
+                                          double* tau_sh, double* taus_out) {
+    const int col = threadIdx.x;
+    for (int j = jstart; j < c; ++j) {
+        if (col == j) {
+            const double rjj = (double)slot[tri_index(j, j, c)];
+            double xn2 = 0.0;
+#pragma unroll
+            for (int t = 0; t < TR; ++t) xn2 = fma(a[t], a[t], xn2);
+            double tau = 0.0;
+            if (xn2 > 0.0) {
+                const double beta = -copysign(sqrt(fma(rjj, rjj, xn2)), rjj);
+                tau = (beta - rjj) / beta;
+                const double sc = 1.0 / (rjj - beta);
+#pragma unroll
+                for (int t = 0; t < TR; ++t) a[t] *= sc;
+                slot[tri_index(j, j, c)] = (SlotT)beta;
+            }
+#pragma unroll
+            for (int t = 0; t < TR; ++t) vbuf[t] = a[t];
+            *tau_sh = tau;
+            taus_out[j] = tau;
+        }
+        __syncthreads();
+        const double tau = *tau_sh;
+        if (col > j && col < c && tau != 0.0) {
+            double w = (double)slot[tri_index(j, col, c)];
+#pragma unroll
+            for (int t = 0; t < TR; ++t) w = fma(vbuf[t], a[t], w);
+            w *= tau;
+            slot[tri_index(j, col, c)] = (SlotT)((double)slot[tri_index(j, col, c)] - w);
+#pragma unroll
+            for (int t = 0; t < TR; ++t) a[t] = fma(-w, vbuf[t], a[t]);
+        }
+        __syncthreads();
+    }
+}
+
+// Backward: apply the tile's reflectors (j = c-1 .. jstart) to (slot, a[] = tile rows).
+// vsrc(t, j) gives reflector j's tile entry t; tau_of(j) its tau.
+template <typename SlotT>
+__device__ __forceinline__ void unfold_tile(SlotT* slot, double (&a)[TR], int c, int jstart, const double* refl_rows,
+                                            int ld_refl, int rows_valid, const double* taus, double* vbuf) {
+    const int col = threadIdx.x;
+    for (int j = c - 1; j >= jstart; --j) {
+        const double tau = taus[j];
+        if (tau == 0.0) continue;   // uniform across the workgroup
+        for (int t = col; t < TR; t += blockDim.x)
+            vbuf[t] = t < rows_valid ? refl_rows[(int64_t)t * ld_refl + j] : 0.0;
+        __syncthreads();
+        if (col >= j && col < c) {
+            double w = (double)slot[tri_index(j, col, c)];
+#pragma unroll
+            for (int t = 0; t < TR; ++t) w = fma(vbuf[t], a[t], w);
+            w *= tau;
+            slot[tri_index(j, col, c)] = (SlotT)((double)slot[tri_index(j, col, c)] - w);
+#pragma unroll
+            for (int t = 0; t < TR; ++t) a[t] = fma(-w, vbuf[t], a[t]);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename SlotT>
+__device__ void slot_zero(SlotT* slot, int c) {
+    const int tri = c * (c + 1) / 2;
+    for (int e = threadIdx.x; e < tri; e += blockDim.x) slot[e] = (SlotT)0;
+    __syncthreads();
+}
+
+// Slot <-> dense row-major c x c float64 (upper triangle only).
+template <typename SlotT>
+__device__ void slot_load(SlotT* slot, const double* M, int c) {
+    for (int j = 0; j < c; ++j)
+        for (int col = j + threadIdx.x; col < c; col += blockDim.x) slot[tri_index(j, col, c)] = (SlotT)M[(int64_t)j * c + col];
+    __syncthreads();
+}
+
+template <typename SlotT>
+__device__ void slot_store(const SlotT* slot, double* M, int c) {
+    for (int j = 0; j < c; ++j)
+        for (int col = threadIdx.x; col < c; col += blockDim.x)
+            M[(int64_t)j * c + col] = col >= j ? (double)slot[tri_index(j, col, c)] : 0.0;
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Leaf chains
+// ---------------------------------------------------------------------------
+// refl: tile-major rows, row g of the chain layout is refl[g * c + col]; taus[tile * c + j].
+template <typename TE, typename SlotT>
+__global__ void __launch_bounds__(QR_THREADS) tsqr_leaf_forward(int64_t n, int c, int64_t rows_per_chain,
+                                                                const TE* __restrict__ E, double* __restrict__ refl,
+                                                                double* __restrict__ taus, double* __restrict__ Rs) {
+    extern __shared__ unsigned char smem_raw[];
+    double* vbuf = (double*)smem_raw;
+    double* tau_sh = vbuf + TR;
+    SlotT* slot = (SlotT*)(vbuf + TR + 2);
+    const int ch = blockIdx.x, col = threadIdx.x;
+    const int64_t r_begin = ch * rows_per_chain;
+    const int64_t r_end = min(n, r_begin + rows_per_chain);
+    const int tiles_per_chain = (int)(rows_per_chain / TR);
+    slot_zero(slot, c);
+    for (int tile = 0; r_begin + (int64_t)tile * TR < r_end; ++tile) {
+        const int64_t r0 = r_begin + (int64_t)tile * TR;
+        double a[TR];
+#pragma unroll
+        for (int t = 0; t < TR; ++t) {
+            const int64_t r = r0 + t;
+            a[t] = (col < c && r < r_end) ? to_f64(E[(int64_t)col * n + r]) : 0.0;
+        }
+        const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
+        fold_tile(slot, a, c, 0, vbuf, tau_sh, taus + gtile * c);
+        if (col < c) {
+#pragma unroll
+            for (int t = 0; t < TR; ++t) refl[(gtile * TR + t) * c + col] = a[t];
+        }
+    }
+    slot_store(slot, Rs + (int64_t)ch * c * c, c);
+}
+
+template <typename TQ, typename SlotT>
+__global__ void __launch_bounds__(QR_THREADS) tsqr_leaf_backward(int64_t n, int c, int64_t rows_per_chain,
+                                                                 const double* __restrict__ refl,
+                                                                 const double* __restrict__ taus,
+                                                                 const double* __restrict__ Qtop, TQ* __restrict__ Q) {
+    extern __shared__ unsigned char smem_raw[];
+    double* vbuf = (double*)smem_raw;
+    SlotT* slot = (SlotT*)(vbuf + TR + 2);
+    const int ch = blockIdx.x, col = threadIdx.x;
+    const int64_t r_begin = ch * rows_per_chain;
+    if (r_begin >= n) return;   // uniform: whole workgroup leaves
+    const int64_t r_end = min(n, r_begin + rows_per_chain);
+    const int tiles_per_chain = (int)(rows_per_chain / TR);
+    const int ntiles = (int)((r_end - r_begin + TR - 1) / TR);
+    slot_load(slot, Qtop + (int64_t)ch * c * c, c);
+    for (int tile = ntiles - 1; tile >= 0; --tile) {
+        const int64_t r0 = r_begin + (int64_t)tile * TR;
+        const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
+        double a[TR];
+#pragma unroll
+        for (int t = 0; t < TR; ++t) a[t] = 0.0;
+        unfold_tile(slot, a, c, 0, refl + gtile * TR * c, c, TR, taus + gtile * c, vbuf);
+        if (col < c) {
+#pragma unroll
+            for (int t = 0; t < TR; ++t) {
+                const int64_t r = r0 + t;
+                if (r < r_end) Q[(int64_t)col * n + r] = (TQ)a[t];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tree over the per-chain R factors.  At level l, combine i merges chain
+// a = i * 2^(l+1) with b = a + 2^l.  The reflectors of combine (l, i) live at
+// tree_refl[(off_l + i) * c * c] (rows of R_b, row-major) and
+// tree_tau[((off_l + i) * ntile_c + t) * c + j].
+// ---------------------------------------------------------------------------
+template <typename SlotT>
+__global__ void __launch_bounds__(QR_THREADS) tsqr_tree_forward(int c, int stride, int64_t comb_off, double* __restrict__ Rs,
+                                                                double* __restrict__ tree_refl,
+                                                                double* __restrict__ tree_tau) {
+    extern __shared__ unsigned char smem_raw[];
+    double* vbuf = (double*)smem_raw;
+    double* tau_sh = vbuf + TR;
+    SlotT* slot = (SlotT*)(vbuf + TR + 2);
+    const int i = blockIdx.x, col = threadIdx.x;
+    const int a_idx = i * 2 * stride, b_idx = a_idx + stride;
+    const double* Rb = Rs + (int64_t)b_idx * c * c;
+    const int ntc = (c + TR - 1) / TR;
+    double* rf = tree_refl + (comb_off + i) * (int64_t)c * c;
+    double* tt = tree_tau + (comb_off + i) * (int64_t)ntc * c;
+    slot_load(slot, Rs + (int64_t)a_idx * c * c, c);
+    for (int tile = 0; tile < ntc; ++tile) {
+        double a[TR];
+#pragma unroll
+        for (int t = 0; t < TR; ++t) {
+            const int row = tile * TR + t;
+            a[t] = (col < c && row < c && col >= row) ? Rb[(int64_t)row * c + col] : 0.0;
+        }
+        fold_tile(slot, a, c, tile * TR, vbuf, tau_sh, tt + (int64_t)tile * c);
+        if (col < c) {
+#pragma unroll
+            for (int t = 0; t < TR; ++t) {
+                const int row = tile * TR + t;
+                if (row < c) rf[(int64_t)row * c + col] = a[t];
+            }
+        }
+    }
+    slot_store(slot, Rs + (int64_t)a_idx * c * c, c);
+}
+
+template <typename SlotT>
+__global__ void __launch_bounds__(QR_THREADS) tsqr_tree_backward(int c, int stride, int64_t comb_off, double* __restrict__ Qtop,
+                                                                 const double* __restrict__ tree_refl,
+                                                                 const double* __restrict__ tree_tau) {
+    extern __shared__ unsigned char smem_raw[];
+    double* vbuf = (double*)smem_raw;
+    SlotT* slot = (SlotT*)(vbuf + TR + 2);
+    const int i = blockIdx.x, col = threadIdx.x;
+    const int a_idx = i * 2 * stride, b_idx = a_idx + stride;
+    const int ntc = (c + TR - 1) / TR;
+    const double* rf = tree_refl + (comb_off + i) * (int64_t)c * c;
+    const double* tt = tree_tau + (comb_off + i) * (int64_t)ntc * c;
+    double* Qb = Qtop + (int64_t)b_idx * c * c;
+    slot_load(slot, Qtop + (int64_t)a_idx * c * c, c);
+    for (int tile = ntc - 1; tile >= 0; --tile) {
+        double a[TR];
+#pragma unroll
+        for (int t = 0; t < TR; ++t) a[t] = 0.0;
+        const int rows_here = min(TR, c - tile * TR);
+        // reflector rows beyond c are zero; pass a row pointer and guard via rows_here
+        unfold_tile(slot, a, c, tile * TR, rf + (int64_t)tile * TR * c, c, rows_here, tt + (int64_t)tile * c, vbuf);
+        if (col < c) {
+#pragma unroll
+            for (int t = 0; t < TR; ++t) {
+                const int row = tile * TR + t;
+                if (t < rows_here) Qb[(int64_t)row * c + col] = a[t];
+            }
+        }
+    }
+    slot_store(slot, Qtop + (int64_t)a_idx * c * c, c);
+}
+
+// F = R2 R1 for upper-triangular row-major c x c factors.
+__global__ void tri_mul(int c, const double* __restrict__ R2, const double* __restrict__ R1, double* __restrict__ F) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < c * c; e += gridDim.x * blockDim.x) {
+        const int i = e / c, j = e % c;
+        double s = 0.0;
+        for (int l = i; l <= j; ++l) s = fma(R2[(int64_t)i * c + l], R1[(int64_t)l * c + j], s);
+        F[e] = s;
+    }
+}
+
+__global__ void set_identity(double* __restrict__ M, int c) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < c * c; e += gridDim.x * blockDim.x)
+        M[e] = (e / c == e % c) ? 1.0 : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// T = Q^T X (tall-skinny, float64 partials per row chunk, then fixed-order sum)
+// ---------------------------------------------------------------------------
+constexpr int TN_T = 64, TN_R = 32;
+
+template <typename TA, typename TB>
+__global__ void __launch_bounds__(256) gemm_tn_partial(int64_t n, int m1, int m2, const TA* __restrict__ A,
+                                                       const TB* __restrict__ B, double* __restrict__ part,
+                                                       int64_t rows_per_chunk) {
+    __shared__ double As[TN_R][TN_T + 1];
+    __shared__ double Bs[TN_R][TN_T + 1];
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    const int i0 = blockIdx.x * TN_T, j0 = blockIdx.y * TN_T, chunk = blockIdx.z;
+    const int64_t rb = chunk * rows_per_chunk, re = min(n, rb + rows_per_chunk);
+    double acc[4][4] = {};
+    for (int64_t r0 = rb; r0 < re; r0 += TN_R) {
+        for (int e = tid; e < TN_R * TN_T; e += 256) {
+            const int rr = e % TN_R, cc = e / TN_R;
+            const int64_t r = r0 + rr;
+            As[rr][cc] = (r < re && i0 + cc < m1) ? to_f64(A[(int64_t)(i0 + cc) * n + r]) : 0.0;
+            Bs[rr][cc] = (r < re && j0 + cc < m2) ? to_f64(B[(int64_t)(j0 + cc) * n + r]) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int rr = 0; rr < TN_R; ++rr) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = As[rr][ty * 4 + u];
+                b[u] = Bs[rr][tx * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+    double* dst = part + (int64_t)chunk * m1 * m2;
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
+            if (i < m1 && j < m2) dst[(int64_t)j * m1 + i] = acc[u][v];   // column-major m1 x m2
+        }
+}
+
+__global__ void sum_chunks(int64_t count, int nchunks, const double* __restrict__ part, double* __restrict__ out) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double s = 0.0;
+    for (int ch = 0; ch < nchunks; ++ch) s += part[(int64_t)ch * count + e];
+    out[e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Small float64 steps, one workgroup of 256 threads.  Matrices live in global
+// memory (at most 256 x 256 doubles, cache resident).
+// ---------------------------------------------------------------------------
+constexpr int SMALL_THREADS = 256;
+
+__device__ double wg_sum(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < SMALL_THREADS / 64; ++i) s += red[i];
+    __syncthreads();
+    return s;
+}
+
+// Omega = F T^-1, symmetrised.  T column-major c x c (T[j*c + i] = T(i, j)).
+// F = R, row-major c x c upper triangular.  Work: M = T^T (row-major M[i*c + j] =
+// T(j, i) = T[i*c + j], i.e. the same array), B = F^T; solve M X = B, Omega = X^T.
+__global__ void __launch_bounds__(SMALL_THREADS) omega_solve(int c, double* __restrict__ M, const double* __restrict__ F,
+                                                             double* __restrict__ B, double* __restrict__ Omega,
+                                                             int* __restrict__ piv, int32_t* __restrict__ status) {
+    __shared__ double red_v[SMALL_THREADS];
+    __shared__ int red_i[SMALL_THREADS];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    // B(i, j) = F(j, i), row-major B[i*c + j]
+    for (int e = tid; e < c * c; e += SMALL_THREADS) {
+        const int i = e / c, j = e % c;
+        B[e] = F[(int64_t)j * c + i];
+    }
+    __syncthreads();
+    for (int kk = 0; kk < c; ++kk) {
+        double best = -1.0;
+        int bi = kk;
+        for (int i = kk + tid; i < c; i += SMALL_THREADS) {
+            const double v = fabs(M[(int64_t)i * c + kk]);
+            if (v > best) { best = v; bi = i; }
+        }
+        red_v[tid] = best;
+        red_i[tid] = bi;
+        __syncthreads();
+        for (int s = SMALL_THREADS / 2; s > 0; s >>= 1) {
+            if (tid < s) {
+                const double v2 = red_v[tid + s];
+                const int i2 = red_i[tid + s];
+                if (v2 > red_v[tid] || (v2 == red_v[tid] && i2 < red_i[tid])) {
+                    red_v[tid] = v2;
+                    red_i[tid] = i2;
+                }
+            }
+            __syncthreads();
+        }
+        const int p = red_i[0];
+        const double pv = red_v[0];
+        if (tid == 0) {
+            piv[kk] = p;
+            if (!(pv > 0.0) || !isfinite(pv)) bad = 1;
+        }
+        if (p != kk) {
+            for (int j = tid; j < c; j += SMALL_THREADS) {
+                double t = M[(int64_t)kk * c + j];
+                M[(int64_t)kk * c + j] = M[(int64_t)p * c + j];
+                M[(int64_t)p * c + j] = t;
+                t = B[(int64_t)kk * c + j];
+                B[(int64_t)kk * c + j] = B[(int64_t)p * c + j];
+                B[(int64_t)p * c + j] = t;
+            }
+        }
+        __syncthreads();
+        const double d = M[(int64_t)kk * c + kk];
+        if (d != 0.0) {
+            for (int i = kk + 1 + tid; i < c; i += SMALL_THREADS) M[(int64_t)i * c + kk] /= d;
+        }
+        __syncthreads();
+        const int m = c - kk - 1;
+        for (int e = tid; e < m * m; e += SMALL_THREADS) {
+            const int i = kk + 1 + e / m, j = kk + 1 + e % m;
+            M[(int64_t)i * c + j] -= M[(int64_t)i * c + kk] * M[(int64_t)kk * c + j];
+        }
+        __syncthreads();
+    }
+    // forward (unit lower) then backward (upper) substitution, one right-hand side per thread
+    for (int j = tid; j < c; j += SMALL_THREADS) {
+        for (int i = 0; i < c; ++i) {
+            double s = B[(int64_t)i * c + j];
+            for (int l = 0; l < i; ++l) s -= M[(int64_t)i * c + l] * B[(int64_t)l * c + j];
+            B[(int64_t)i * c + j] = s;
+        }
+        for (int i = c - 1; i >= 0; --i) {
+            double s = B[(int64_t)i * c + j];
+            for (int l = i + 1; l < c; ++l) s -= M[(int64_t)i * c + l] * B[(int64_t)l * c + j];
+            B[(int64_t)i * c + j] = s / M[(int64_t)i * c + i];
+        }
+    }
+    __syncthreads();
+    // X = B (row-major); Omega = X^T; symmetrise.  Omega(i, j) = (X(j, i) + X(i, j)) / 2
+    for (int e = tid; e < c * c; e += SMALL_THREADS) {
+        const int i = e / c, j = e % c;
+        const double v = 0.5 * (B[(int64_t)j * c + i] + B[(int64_t)i * c + j]);
+        Omega[e] = v;
+        if (!isfinite(v)) bad = 1;
+    }
+    __syncthreads();
+    if (tid == 0 && bad) set_status(status, BFGS_ERR_NUMERIC);
+}
+
+// Symmetric eigendecomposition of A (row-major c x c, overwritten): Householder
+// tridiagonalisation with explicit accumulation, then implicit QL iterations
+// with Wilkinson-type shifts; rotation angles are computed by one thread and
+// applied to the rows of the eigenvector matrix in parallel.
+// Z: column-major c x c eigenvectors (Z[i*c + r] = component r of vector i).
+__global__ void __launch_bounds__(SMALL_THREADS) sym_eig(int c, double* __restrict__ A, double* __restrict__ Z,
+                                                         double* __restrict__ d, double* __restrict__ e,
+                                                         double* __restrict__ taus, double* __restrict__ rot,
+                                                         int32_t* __restrict__ status) {
+    __shared__ double red[SMALL_THREADS / 64];
+    __shared__ double vsh[256];
+    __shared__ double wsh[256];
+    __shared__ int sh_m, sh_fail;
+    __shared__ double sh_k;
+    const int tid = threadIdx.x;
+    if (tid == 0) sh_fail = 0;
+    // --- tridiagonalisation: for column kk, reflect rows kk+1..c-1 ---
+    for (int kk = 0; kk + 2 < c; ++kk) {
+        const int m = c - kk - 1;   // length of x = A(kk+1:, kk)
+        double part = 0.0;
+        for (int i = 1 + tid; i < m; i += SMALL_THREADS) {
+            const double x = A[(int64_t)(kk + 1 + i) * c + kk];
+            part = fma(x, x, part);
+        }
+        const double xn2 = wg_sum(part, red);
+        const double alpha = A[(int64_t)(kk + 1) * c + kk];
+        double tau = 0.0, beta = alpha, scale = 0.0;
+        if (xn2 > 0.0) {
+            beta = -copysign(sqrt(fma(alpha, alpha, xn2)), alpha);
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        for (int i = tid; i < m; i += SMALL_THREADS)
+            vsh[i] = (i == 0) ? 1.0 : A[(int64_t)(kk + 1 + i) * c + kk] * scale;
+        __syncthreads();
+        if (tid == 0) {
+            taus[kk] = tau;
+            d[kk] = A[(int64_t)kk * c + kk];
+            e[kk] = beta;
+        }
+        // keep v below the subdiagonal for the accumulation step
+        for (int i = 1 + tid; i < m; i += SMALL_THREADS) A[(int64_t)(kk + 1 + i) * c + kk] = vsh[i];
+        if (tau != 0.0) {
+            // p = tau * A22 v
+            for (int i = tid; i < m; i += SMALL_THREADS) {
+                double s = 0.0;
+                const double* row = A + (int64_t)(kk + 1 + i) * c + (kk + 1);
+                for (int l = 0; l < m; ++l) s = fma(row[l], vsh[l], s);
+                wsh[i] = tau * s;
+            }
+            __syncthreads();
+            double pp = 0.0;
+            for (int i = tid; i < m; i += SMALL_THREADS) pp = fma(wsh[i], vsh[i], pp);
+            const double K = 0.5 * tau * wg_sum(pp, red);
+            for (int i = tid; i < m; i += SMALL_THREADS) wsh[i] -= K * vsh[i];
+            __syncthreads();
+            for (int q = tid; q < m * m; q += SMALL_THREADS) {
+                const int i = q / m, l = q % m;
+                A[(int64_t)(kk + 1 + i) * c + (kk + 1 + l)] -= vsh[i] * wsh[l] + wsh[i] * vsh[l];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (c >= 2) {
+            d[c - 2] = A[(int64_t)(c - 2) * c + (c - 2)];
+            e[c - 2] = A[(int64_t)(c - 1) * c + (c - 2)];
+        }
+        d[c - 1] = A[(int64_t)(c - 1) * c + (c - 1)];
+        e[c - 1] = 0.0;
+        if (c >= 2) taus[c - 2] = 0.0;
+    }
+    // --- accumulate the orthogonal factor: Z = H_0 H_1 ... (column-major) ---
+    for (int q = tid; q < c * c; q += SMALL_THREADS) Z[q] = (q / c == q % c) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int kk = c - 3; kk >= 0; --kk) {
+        const double tau = taus[kk];
+        const int m = c - kk - 1;
+        if (tau == 0.0) continue;
+        for (int i = tid; i < m; i += SMALL_THREADS) vsh[i] = (i == 0) ? 1.0 : A[(int64_t)(kk + 1 + i) * c + kk];
+        __syncthreads();
+        // columns kk+1.. of Z, rows kk+1..: Z_sub -= tau v (v^T Z_sub)
+        for (int col = kk + 1 + tid; col < c; col += SMALL_THREADS) {
+            double* zc = Z + (int64_t)col * c + (kk + 1);
+            double s = 0.0;
+            for (int i = 0; i < m; ++i) s = fma(vsh[i], zc[i], s);
+            s *= tau;
+            for (int i = 0; i < m; ++i) zc[i] -= s * vsh[i];
+        }
+        __syncthreads();
+    }
+    // --- implicit QL on (d, e): e[i] couples d[i] and d[i+1] ---
+    for (int l = 0; l < c; ++l) {
+        int iter = 0;
+        while (true) {
+            if (tid == 0) {
+                int m = l;
+                for (; m < c - 1; ++m) {
+                    const double dd = fabs(d[m]) + fabs(d[m + 1]);
+                    if (fabs(e[m]) + dd == dd) break;
+                }
+                sh_m = m;
+            }
+            __syncthreads();
+            const int m = sh_m;
+            __syncthreads();
+            if (m == l) break;
+            if (++iter > 60) {
+                if (tid == 0) sh_fail = 1;
+                break;
+            }
+            const int nrot = m - l;
+            if (tid == 0) {
+                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+                double r = hypot(g, 1.0);
+                g = d[m] - d[l] + e[l] / (g + copysign(r, g));
+                double s = 1.0, cc = 1.0, p = 0.0;
+                int i;
+                bool early = false;
+                for (i = m - 1; i >= l; --i) {
+                    double f = s * e[i];
+                    const double b = cc * e[i];
+                    r = hypot(f, g);
+                    e[i + 1] = r;
+                    if (r == 0.0) {
+                        d[i + 1] -= p;
+                        e[m] = 0.0;
+                        early = true;
+                        // mark the remaining rotations as identity
+                        for (int q = i; q >= l; --q) {
+                            rot[2 * (q - l)] = 1.0;
+                            rot[2 * (q - l) + 1] = 0.0;
+                        }
+                        break;
+                    }
+                    s = f / r;
+                    cc = g / r;
+                    g = d[i + 1] - p;
+                    r = (d[i] - g) * s + 2.0 * cc * b;
+                    p = s * r;
+                    d[i + 1] = g + p;
+                    g = cc * r - b;
+                    rot[2 * (i - l)] = cc;
+                    rot[2 * (i - l) + 1] = s;
+                }
+                if (!early) {
+                    d[l] -= p;
+                    e[l] = g;
+                    e[m] = 0.0;
+                }
+            }
+            __syncthreads();
+            // apply rotations i = m-1 .. l to columns (i, i+1) of Z, one row per thread
+            for (int r = tid; r < c; r += SMALL_THREADS) {
+                for (int i = m - 1; i >= l; --i) {
+                    const double cc = rot[2 * (i - l)], s = rot[2 * (i - l) + 1];
+                    double* zi = Z + (int64_t)i * c + r;
+                    double* zi1 = Z + (int64_t)(i + 1) * c + r;
+                    const double f = *zi1;
+                    *zi1 = s * (*zi) + cc * f;
+                    *zi = cc * (*zi) - s * f;
+                }
+            }
+            __syncthreads();
+            (void)nrot;
+        }
+        __syncthreads();
+        const int failed = sh_fail;
+        __syncthreads();
+        if (failed) break;
+    }
+    __syncthreads();
+    if (tid == 0 && sh_fail) set_status(status, BFGS_ERR_NUMERIC);
+}
+
+// Order eigenpairs by |lambda| descending (ties: lambda descending, then index),
+// make each eigenvector's largest-magnitude entry positive (lowest index on ties),
+// write lam_out (c) and Us (column-major c x c, sorted).
+__global__ void __launch_bounds__(SMALL_THREADS) order_sign(int c, const double* __restrict__ d, const double* __restrict__ Z,
+                                                            double* __restrict__ lam_out, double* __restrict__ Us) {
+    __shared__ int dest[256];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < c; i += SMALL_THREADS) {
+        const double ai = fabs(d[i]), li = d[i];
+        int rank = 0;
+        for (int j = 0; j < c; ++j) {
+            if (j == i) continue;
+            const double aj = fabs(d[j]), lj = d[j];
+            const bool before = (aj > ai) || (aj == ai && lj > li) || (aj == ai && lj == li && j < i);
+            rank += before ? 1 : 0;
+        }
+        dest[i] = rank;
+    }
+    __syncthreads();
+    for (int i = tid; i < c; i += SMALL_THREADS) {
+        const int o = dest[i];
+        lam_out[o] = d[i];
+        const double* zc = Z + (int64_t)i * c;
+        int arg = 0;
+        double best = -1.0;
+        for (int r = 0; r < c; ++r) {
+            const double v = fabs(zc[r]);
+            if (v > best) { best = v; arg = r; }
+        }
+        const double sg = zc[arg] < 0.0 ? -1.0 : 1.0;
+        for (int r = 0; r < c; ++r) Us[(int64_t)o * c + r] = sg * zc[r];
+    }
+}
+
+// U = Q Us[:, :rank] (n x rank, column-major) from column-major Q (n x c) and Us (c x c).
+constexpr int BS_R = 64, BS_C = 64, BS_I = 16;
+
+template <typename TQ, typename TO>
+__global__ void __launch_bounds__(256) basis_gemm(int64_t n, int c, int rank, const TQ* __restrict__ Q,
+                                                  const double* __restrict__ Us, TO* __restrict__ U) {
+    __shared__ double Qs[BS_I][BS_R + 2];
+    __shared__ double Ms[BS_I][BS_C + 2];
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    const int64_t r0 = (int64_t)blockIdx.y * BS_R;
+    const int j0 = blockIdx.x * BS_C;
+    double acc[4][4] = {};
+    for (int i0 = 0; i0 < c; i0 += BS_I) {
+        for (int q = tid; q < BS_I * BS_R; q += 256) {
+            const int rr = q % BS_R, ii = q / BS_R;
+            const int64_t r = r0 + rr;
+            Qs[ii][rr] = (r < n && i0 + ii < c) ? to_f64(Q[(int64_t)(i0 + ii) * n + r]) : 0.0;
+        }
+        for (int q = tid; q < BS_I * BS_C; q += 256) {
+            const int ii = q % BS_I, jj = q / BS_I;
+            Ms[ii][jj] = (i0 + ii < c && j0 + jj < rank) ? Us[(int64_t)(j0 + jj) * c + i0 + ii] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int ii = 0; ii < BS_I; ++ii) {
+            double qv[4], mv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                qv[u] = Qs[ii][tx * 4 + u];
+                mv[u] = Ms[ii][ty * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(qv[u], mv[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+    for (int v = 0; v < 4; ++v) {
+        const int j = j0 + ty * 4 + v;
+        if (j >= rank) continue;
+        for (int u = 0; u < 4; ++u) {
+            const int64_t r = r0 + tx * 4 + u;
+            if (r < n) U[(int64_t)j * n + r] = (TO)acc[u][v];
+        }
+    }
+}
+
+template <typename TO, typename Th>
+__global__ void posterior_diag_kernel(int64_t n, int rank, const TO* __restrict__ U, const double* __restrict__ lam,
+                                      const Th* __restrict__ h0, TO* __restrict__ dout) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        double s = to_f64(h0[r]);
+        for (int i = 0; i < rank; ++i) {
+            const double u = to_f64(U[(int64_t)i * n + r]);
+            s = fma(lam[i], u * u, s);
+        }
+        dout[r] = (TO)s;
+    }
+}
+
+template <typename TO, typename Th>
+__global__ void zero_rsvd(int64_t n, int rank, TO* __restrict__ U, double* __restrict__ Sigma, const Th* __restrict__ h0,
+                          TO* __restrict__ dout) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * rank; e += (int64_t)gridDim.x * blockDim.x)
+        U[e] = (TO)0;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+        dout[r] = (TO)to_f64(h0[r]);
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < rank; i += blockDim.x) Sigma[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Host driver
+// ---------------------------------------------------------------------------
+inline int floor_pow2(int64_t x) {
+    int p = 1;
+    while ((int64_t)p * 2 <= x) p *= 2;
+    return p;
+}
+
+template <typename SlotT>
+size_t slot_smem(int c) {
+    return (TR + 2) * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
+}
+
+template <typename TO, typename SlotT>
+int tsqr(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
+    const int64_t n = h->n;
+    const int64_t tiles_total = (n + TR - 1) / TR;
+    const int nchains = (int)std::min<int64_t>(256, floor_pow2(std::max<int64_t>(1, tiles_total / 2)));
+    const int64_t rows_per_chain = round_up((n + nchains - 1) / nchains, TR);
+    const int tiles_per_chain = (int)(rows_per_chain / TR);
+    const int ntc = (c + TR - 1) / TR;
+    int rc;
+    const size_t refl_bytes = (size_t)nchains * rows_per_chain * c * 8;
+    const size_t tau_bytes = (size_t)nchains * tiles_per_chain * c * 8;
+    if ((rc = ensure_ws(h->refl, refl_bytes)) != BFGS_OK) return rc;
+    if ((rc = ensure_ws(h->tau, tau_bytes + (size_t)nchains * ntc * c * 8)) != BFGS_OK) return rc;
+    // Rtree: Rs (nchains c*c) + Qtop (nchains c*c) + tree reflectors (nchains c*c)
+    if ((rc = ensure_ws(h->Rtree, (size_t)3 * nchains * c * c * 8)) != BFGS_OK) return rc;
+    double* refl = (double*)h->refl.ptr;
+    double* taus = (double*)h->tau.ptr;
+    double* tree_tau = taus + (size_t)nchains * tiles_per_chain * c;
+    double* Rs = (double*)h->Rtree.ptr;
+    double* Qtop = Rs + (size_t)nchains * c * c;
+    double* tree_refl = Qtop + (size_t)nchains * c * c;
+    const size_t smem = slot_smem<SlotT>(c);
+    if (hipFuncSetAttribute((const void*)tsqr_leaf_forward<TO, SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess ||
+        hipFuncSetAttribute((const void*)tsqr_leaf_backward<TO, SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess ||
+        hipFuncSetAttribute((const void*)tsqr_tree_forward<SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess ||
+        hipFuncSetAttribute((const void*)tsqr_tree_backward<SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
+        return BFGS_ERR_HIP;
+    hipLaunchKernelGGL((tsqr_leaf_forward<TO, SlotT>), dim3(nchains), dim3(QR_THREADS), smem, h->stream, n, c,
+                       rows_per_chain, E, refl, taus, Rs);
+    int64_t off = 0;
+    int levels = 0;
+    for (int stride = 1; stride < nchains; stride *= 2, ++levels) {
+        const int ncomb = nchains / (2 * stride);
+        hipLaunchKernelGGL((tsqr_tree_forward<SlotT>), dim3(ncomb), dim3(QR_THREADS), smem, h->stream, c, stride, off, Rs,
+                           tree_refl, tree_tau);
+        off += ncomb;
+    }
+    hipLaunchKernelGGL(set_identity, dim3(64), dim3(256), 0, h->stream, Qtop, c);
+    for (int stride = nchains / 2; stride >= 1; stride /= 2) {
+        const int ncomb = nchains / (2 * stride);
+        off -= ncomb;
+        hipLaunchKernelGGL((tsqr_tree_backward<SlotT>), dim3(ncomb), dim3(QR_THREADS), smem, h->stream, c, stride, off,
+                           Qtop, tree_refl, tree_tau);
+    }
+    hipLaunchKernelGGL((tsqr_leaf_backward<TO, SlotT>), dim3(nchains), dim3(QR_THREADS), smem, h->stream, n, c,
+                       rows_per_chain, refl, taus, Qtop, Q);
+    *R_out = Rs;   // chain 0 holds the final R (row-major, upper triangular)
+    return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+}
+
+template <typename TS, typename TO, typename Th>
+int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, double* Sigma) {
+    const int64_t n = h->n;
+    const int c = rank + oversample;
+    int rc;
+    if ((rc = ensure_ws(h->diag, (size_t)n * sizeof(TO))) != BFGS_OK) return rc;
+    TO* dout = (TO*)h->diag.ptr;
+    if (h->k == 0) {
+        hipLaunchKernelGGL((zero_rsvd<TO, Th>), dim3(1024), dim3(256), 0, h->stream, n, rank, U, Sigma,
+                           (const Th*)h->h0, dout);
+        if (hipGetLastError() != hipSuccess) return BFGS_ERR_HIP;
+        h->have_rsvd = true;
+        h->last_rank = rank;
+        return BFGS_OK;
+    }
+    if ((rc = ensure_ws(h->X, (size_t)n * c * sizeof(TS))) != BFGS_OK) return rc;
+    if ((rc = ensure_ws(h->E, (size_t)n * c * sizeof(TO))) != BFGS_OK) return rc;
+    if ((rc = ensure_ws(h->Q, (size_t)n * c * sizeof(TO))) != BFGS_OK) return rc;
+    // small: part(nchunks*c*c) + T, M, B, Omega, Z (5 c*c) + d, e, taus, rot, lam (5 c) + piv
+    const int ctiles = ceil_div(c, TN_T);
+    const int64_t max_chunks = std::max<int64_t>(1, (n + TN_R - 1) / TN_R);
+    int nchunks = (int)std::min<int64_t>(max_chunks, std::max(1, 2048 / (ctiles * ctiles)));
+    const int64_t rows_per_chunk = round_up((n + nchunks - 1) / nchunks, TN_R);
+    nchunks = (int)((n + rows_per_chunk - 1) / rows_per_chunk);
+    const size_t cc = (size_t)c * c;
+    if ((rc = ensure_ws(h->small, ((size_t)nchunks * cc + 8 * cc + 6 * (size_t)c) * 8 + (size_t)c * 4)) != BFGS_OK)
+        return rc;
+    double* part = (double*)h->small.ptr;
+    double* Tm = part + (size_t)nchunks * cc;
+    double* Bm = Tm + cc;
+    double* Om = Bm + cc;
+    double* Zm = Om + cc;
+    double* Usm = Zm + cc;
+    double* dv = Usm + cc;
+    double* ev = dv + c;
+    double* tv = ev + c;
+    double* rot = tv + c;
+    double* lam = rot + 2 * (size_t)c;
+    double* R1c = lam + c;
+    double* Fm = R1c + cc;
+    int* piv = (int*)(Fm + cc);
+    TS* X = (TS*)h->X.ptr;
+    TO* E = (TO*)h->E.ptr;
+    TO* Q = (TO*)h->Q.ptr;
+
+    if ((rc = probes_launch(h, seed, c, X, h->stream)) != BFGS_OK) return rc;
+    if ((rc = apply_block(h, X, c, E, true)) != BFGS_OK) return rc;
+    double* R = nullptr;
+    auto run_tsqr = [&](const TO* src, TO* dst) {
+        if (c <= SLOT_F64_MAX_C) return tsqr<TO, double>(h, c, src, dst, &R);
+        return tsqr<TO, float>(h, c, src, dst, &R);
+    };
+    if ((rc = run_tsqr(E, Q)) != BFGS_OK) return rc;
+    if (h->storage == BFGS_F64) {
+        // E at float64 noise level is exactly rank deficient; the zero-started
+        // slot then keeps part of Q.  A second pass over the (well conditioned)
+        // Q restores orthonormality: E = Q2 (R2 R1).
+        if (hipMemcpyAsync(R1c, R, cc * 8, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) return BFGS_ERR_HIP;
+        if ((rc = run_tsqr(Q, E)) != BFGS_OK) return rc;
+        hipLaunchKernelGGL(tri_mul, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, h->stream, c, R, R1c, Fm);
+        std::swap(E, Q);   // Q now points at the second-pass factor
+        R = Fm;
+    }
+    hipLaunchKernelGGL((gemm_tn_partial<TO, TS>), dim3(ctiles, ctiles, nchunks), dim3(256), 0, h->stream, n, c, c, Q, X,
+                       part, rows_per_chunk);
+    hipLaunchKernelGGL(sum_chunks, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, h->stream, (int64_t)cc, nchunks, part,
+                       Tm);
+    hipLaunchKernelGGL(omega_solve, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, Tm, R, Bm, Om, piv, h->status);
+    hipLaunchKernelGGL(sym_eig, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, Om, Zm, dv, ev, tv, rot, h->status);
+    hipLaunchKernelGGL(order_sign, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, dv, Zm, lam, Usm);
+    if (hipMemcpyAsync(Sigma, lam, (size_t)rank * 8, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
+        return BFGS_ERR_HIP;
+    hipLaunchKernelGGL((basis_gemm<TO, TO>), dim3(ceil_div(rank, BS_C), ceil_div(n, BS_R)), dim3(256), 0, h->stream, n, c,
+                       rank, Q, Usm, U);
+    const int g = (int)std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL((posterior_diag_kernel<TO, Th>), dim3(g), dim3(256), 0, h->stream, n, rank, U, lam,
+                       (const Th*)h->h0, dout);
+    if (hipGetLastError() != hipSuccess) return BFGS_ERR_HIP;
+    h->have_rsvd = true;
+    h->last_rank = rank;
+    return BFGS_OK;
+}
+
+}  // namespace
+
 int rsvd_run(bfgsuq_ctx* h, int32_t rank, int32_t oversample, uint64_t seed, void* U, double* Sigma) {
-    (void)h; (void)rank; (void)oversample; (void)seed; (void)U; (void)Sigma;
-    return BFGS_ERR_STATE;
+    switch (h->storage) {
+        case BFGS_F64: return rsvd_impl<double, double, double>(h, rank, oversample, seed, (double*)U, Sigma);
+        case BFGS_F32: return rsvd_impl<float, float, float>(h, rank, oversample, seed, (float*)U, Sigma);
+        case BFGS_BF16: return rsvd_impl<bf16_t, float, float>(h, rank, oversample, seed, (float*)U, Sigma);
+    }
+    return BFGS_ERR_ARG;
 }

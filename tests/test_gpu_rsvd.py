@@ -1,0 +1,160 @@
+"""GPU parity of the probe generator, bfgs_rsvd (Alg. 3) and bfgs_posterior_diag
+(eqs. 10/14) against the float64 oracle on the same seeded inputs.
+
+Q and the eigenvector signs are not unique when E is rank deficient, so the
+comparisons use what is unique: Sigma, the low-rank operator U diag(Sigma) U^T
+applied to test vectors, the posterior diagonal; U is checked for
+orthonormality."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import rsvd as orsvd, probes as oprobes, dense
+from workloads import quadratic as wq
+from tests.helpers import rel_f, gpu_input, oracle_input, h0_storage, make_pairs, gamma_of
+
+pytestmark = pytest.mark.gpu
+
+SIG_TOL = {"f64": 1e-11, "f32": 1e-6, "bf16": 1e-3}
+
+
+def lib():
+    import paper_2009_12663_amd as P
+    return P
+
+
+def build_handle(storage, S, Y, h0=None):
+    P = lib()
+    H = P.Bfgs(S.shape[1], max(1, S.shape[0]), None if h0 is None else gpu_input(h0, storage), storage)
+    for s, y in zip(S, Y):
+        H.push_pair(gpu_input(s, storage), gpu_input(y, storage))
+    return H
+
+
+def oracle_h0(storage, S, Y, h0):
+    if h0 is None:
+        Sq, Yq = oracle_input(S, storage), oracle_input(Y, storage)
+        g = gamma_of(Sq, Yq)
+        return np.full(S.shape[1], g if storage == "f64" else float(np.float32(g)))
+    return h0_storage(h0, storage)
+
+
+def run_case(storage, S, Y, h0, rank, p, seed):
+    n = S.shape[1]
+    H = build_handle(storage, S, Y, h0)
+    U, Sig = H.rsvd(rank, p, seed)
+    d = H.posterior_diag()
+    assert H.get_status() == 0
+    U = U.double().cpu().numpy()
+    Sig = Sig.cpu().numpy()
+    d = d.double().cpu().numpy()
+    h = oracle_h0(storage, S, Y, h0)
+    X = oprobes.round_to(oprobes.normal_block(n, rank + p, seed), storage)
+    ref = orsvd.rsvd(h, oracle_input(S, storage), oracle_input(Y, storage), X, rank)
+    dref = orsvd.posterior_diag(h, ref["U"], ref["Sigma"])
+    s1 = abs(ref["Sigma"][0])
+    sig_err = np.abs(Sig - ref["Sigma"]).max() / s1
+    W = wq.normal_block(n, 8, seed=99).numpy()
+    rec_err = rel_f(orsvd.low_rank_apply(U, Sig, W), orsvd.low_rank_apply(ref["U"], ref["Sigma"], W))
+    diag_err = rel_f(d, dref)
+    diag_max = np.abs(d - dref).max() / np.abs(dref).max()
+    orth = np.abs(U @ U.T - np.eye(rank)).max()
+    H.close()
+    return dict(sig=sig_err, rec=rec_err, diag=diag_err, diag_max=diag_max, orth=orth, ref=ref, U=U, Sig=Sig, d=d)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_probes_match_oracle(storage):
+    P = lib()
+    n, c, seed = 10007, 13, 1234
+    H = P.Bfgs(n, 1, torch.ones(n, device="cuda", dtype=torch.float64 if storage == "f64" else torch.float32), storage)
+    X = H.generate_probes(seed, c).double().cpu().numpy()
+    ref = oprobes.round_to(oprobes.normal_block(n, c, seed), storage)
+    diff = X != ref
+    frac = diff.mean()
+    if storage == "f64":
+        assert np.abs(X - ref).max() <= 4e-15 * np.abs(ref).max()
+    else:
+        ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+        if storage == "bf16":
+            ulp = ulp * 2.0 ** 16
+        assert (np.abs(X - ref) <= ulp + 1e-30).all()
+        assert frac < 1e-4
+    H.close()
+
+
+def test_rsvd_tiny_f64_is_exact():
+    """Tiny dense problem, 40 exact-line-search pairs, gamma I, rank 40, p 10, seed 0:
+    rank + p > rank(B_k - B_0), so U Sigma U^T is B_k - B_0 of eq. (3)."""
+    prob = wq.make_problem("tiny")
+    S, Y, _ = wq.cg_pairs(prob, 40)
+    r = run_case("f64", S, Y, None, 40, 10, 0)
+    print(f"\n[rsvd tiny f64] sigma {r['sig']:.2e} rec {r['rec']:.2e} diag {r['diag']:.2e} orth {r['orth']:.2e}")
+    assert r["sig"] <= SIG_TOL["f64"] and r["rec"] <= 1e-10 and r["diag_max"] <= 1e-11
+    assert r["orth"] <= 1e-12
+    g = float(S[0] @ Y[0] / (Y[0] @ Y[0]))
+    Bd = dense.inverse_hessian(np.full(300, g), S.numpy(), Y.numpy()) - g * np.eye(300)
+    rec = (r["U"].T * r["Sig"]) @ r["U"]
+    assert np.abs(rec - Bd).max() <= 1e-10 * np.abs(Bd).max()
+    np.testing.assert_allclose(r["d"], np.diag(Bd) + g, rtol=1e-11)
+
+
+CASES = [
+    # storage, kind, nx, nz, k, rank, p, precond
+    ("f64", "secant", 12, 9, 12, 20, 6, True),
+    ("f32", "cg", 40, 30, 30, 30, 10, False),
+    ("f32", "secant", 33, 17, 20, 24, 8, True),
+    ("bf16", "cg", 40, 30, 30, 30, 10, True),
+    ("bf16", "secant", 45, 23, 25, 40, 12, False),
+    ("f32", "cg", 61, 29, 60, 60, 20, False),
+]
+
+
+@pytest.mark.parametrize("storage,kind,nx,nz,k,rank,p,precond", CASES)
+def test_rsvd_parity(storage, kind, nx, nz, k, rank, p, precond):
+    print(f"\n[rsvd parity] {storage} {kind} n={3*nx*nz} k={k} rank={rank} p={p}", flush=True)
+    prob, S, Y, h0 = make_pairs(kind, nx, nz, k, seed=k + 1, precond=precond)
+    r = run_case(storage, S, Y, h0, rank, p, seed=7)
+    print(f"  sigma {r['sig']:.2e} rec {r['rec']:.2e} diag {r['diag']:.2e} diag_max {r['diag_max']:.2e} "
+          f"orth {r['orth']:.2e}", flush=True)
+    tol = SIG_TOL[storage]
+    assert r["sig"] <= tol
+    assert r["rec"] <= (10 * tol if storage != "f64" else 1e-10)
+    assert r["diag_max"] <= tol
+    assert r["orth"] <= (1e-12 if storage == "f64" else 1e-5)
+
+
+def test_rsvd_max_columns_and_ragged():
+    prob, S, Y, h0 = make_pairs("cg", 37, 13, 120, seed=3, precond=False)     # n = 1443
+    r = run_case("f32", S, Y, h0, 200, 56, seed=11)                          # c = 256
+    print(f"\n[rsvd c=256] sigma {r['sig']:.2e} rec {r['rec']:.2e} diag {r['diag_max']:.2e} orth {r['orth']:.2e}")
+    assert r["sig"] <= 1e-5 and r["diag_max"] <= 1e-6 and r["orth"] <= 1e-5
+
+
+def test_rsvd_zero_pairs_and_errors():
+    P = lib()
+    n = 500
+    h0 = torch.rand(n, device="cuda") + 0.5
+    H = P.Bfgs(n, 4, h0, "f32")
+    with pytest.raises(P.BfgsError) as e:
+        H.posterior_diag()
+    assert e.value.code == -3
+    U, Sig = H.rsvd(5, 3, 1)
+    assert torch.all(Sig == 0) and torch.all(U == 0)
+    assert torch.equal(H.posterior_diag(), h0)
+    Ub = torch.empty(512, n, device="cuda")
+    Sb = torch.empty(512, dtype=torch.float64, device="cuda")
+    for rank, p in [(200, 57), (0, 3), (5, -1), (499, 2)]:   # c > 256, rank < 1, p < 0, c > n
+        assert H.L.bfgs_rsvd(H.h, rank, p, 0, Ub.data_ptr(), Sb.data_ptr()) == -1
+    assert H.L.bfgs_rsvd(H.h, 5, 3, 0, None, Sb.data_ptr()) == -1
+    H.close()
+
+
+def test_rsvd_deterministic():
+    prob, S, Y, h0 = make_pairs("cg", 30, 20, 25, seed=5, precond=True)
+    H = build_handle("bf16", S, Y, h0)
+    U1, S1 = H.rsvd(25, 10, 3)
+    U1, S1 = U1.clone(), S1.clone()
+    U2, S2 = H.rsvd(25, 10, 3)
+    assert torch.equal(U1, U2) and torch.equal(S1, S2)
+    H.close()
