@@ -154,6 +154,17 @@ int bfgs_get_h0(bfgs_t h, void* out);
  * recorded on the device since the last call (or BFGS_OK) and clears it.     */
 int bfgs_get_status(bfgs_t h);
 
+/* Measurement support (not an operation of the method).
+ * bfgs_profile — enable (1) or disable (0) per-kernel timing: while enabled,
+ *   every kernel group the library enqueues on the handle's stream is
+ *   bracketed by HIP events.
+ * bfgs_profile_report — synchronizes the stream and writes a JSON object
+ *   {"kernel group": [launches, total_ms], ...} of everything recorded since
+ *   the last report into buf (host, len bytes, NUL-terminated); clears the
+ *   record.  BFGS_ERR_ARG if buf is too small.                               */
+int bfgs_profile(bfgs_t h, int32_t enable);
+int bfgs_profile_report(bfgs_t h, char* buf, int32_t len);
+
 /* bfgs_status_string — static description of a return code. */
 const char* bfgs_status_string(int code);
 

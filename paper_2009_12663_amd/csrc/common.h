@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/bfgsuq.h"
 
 // ---------------------------------------------------------------------------
@@ -67,6 +69,19 @@ struct Workspace {
     size_t bytes = 0;
 };
 
+// Optional per-kernel timing with HIP events on the handle's stream.
+struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+
+struct Profiler {
+    bool on = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+};
+
 struct bfgsuq_ctx {
     int64_t n = 0;
     int64_t ld = 0;            // leading dimension of S and Y (n rounded up to 128)
@@ -93,6 +108,17 @@ struct bfgsuq_ctx {
     Workspace X, E, Q, refl, tau, Rtree, small, lam, diag;
     int32_t last_rank = 0;
     bool have_rsvd = false;
+    Profiler prof;
+};
+
+void prof_begin(bfgsuq_ctx* h, const char* name);
+void prof_end(bfgsuq_ctx* h);
+
+// Scoped helper: times the launches issued while it lives.
+struct ProfScope {
+    bfgsuq_ctx* h;
+    ProfScope(bfgsuq_ctx* hh, const char* name) : h(hh) { prof_begin(h, name); }
+    ~ProfScope() { prof_end(h); }
 };
 
 #define BFGS_HIP(expr)                                  \

@@ -770,8 +770,11 @@ int tsqr(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
         hipFuncSetAttribute((const void*)tsqr_tree_forward<SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess ||
         hipFuncSetAttribute((const void*)tsqr_tree_backward<SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
         return BFGS_ERR_HIP;
+    ProfScope ps(h, "tsqr_leaf_fwd");
     hipLaunchKernelGGL((tsqr_leaf_forward<TO, SlotT>), dim3(nchains), dim3(QR_THREADS), smem, h->stream, n, c,
                        rows_per_chain, E, refl, taus, Rs);
+    prof_end(h);
+    prof_begin(h, "tsqr_tree");
     int64_t off = 0;
     int levels = 0;
     for (int stride = 1; stride < nchains; stride *= 2, ++levels) {
@@ -787,6 +790,8 @@ int tsqr(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
         hipLaunchKernelGGL((tsqr_tree_backward<SlotT>), dim3(ncomb), dim3(QR_THREADS), smem, h->stream, c, stride, off,
                            Qtop, tree_refl, tree_tau);
     }
+    prof_end(h);
+    prof_begin(h, "tsqr_leaf_bwd");
     hipLaunchKernelGGL((tsqr_leaf_backward<TO, SlotT>), dim3(nchains), dim3(QR_THREADS), smem, h->stream, n, c,
                        rows_per_chain, refl, taus, Qtop, Q);
     *R_out = Rs;   // chain 0 holds the final R (row-major, upper triangular)
@@ -838,7 +843,10 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     TO* E = (TO*)h->E.ptr;
     TO* Q = (TO*)h->Q.ptr;
 
-    if ((rc = probes_launch(h, seed, c, X, h->stream)) != BFGS_OK) return rc;
+    {
+        ProfScope ps(h, "probes");
+        if ((rc = probes_launch(h, seed, c, X, h->stream)) != BFGS_OK) return rc;
+    }
     if ((rc = apply_block(h, X, c, E, true)) != BFGS_OK) return rc;
     double* R = nullptr;
     auto run_tsqr = [&](const TO* src, TO* dst) {
@@ -856,15 +864,22 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
         std::swap(E, Q);   // Q now points at the second-pass factor
         R = Fm;
     }
+    ProfScope ps(h, "proj_QtX");
     hipLaunchKernelGGL((gemm_tn_partial<TO, TS>), dim3(ctiles, ctiles, nchunks), dim3(256), 0, h->stream, n, c, c, Q, X,
                        part, rows_per_chunk);
     hipLaunchKernelGGL(sum_chunks, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, h->stream, (int64_t)cc, nchunks, part,
                        Tm);
+    prof_end(h);
+    prof_begin(h, "omega_lu");
     hipLaunchKernelGGL(omega_solve, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, Tm, R, Bm, Om, piv, h->status);
+    prof_end(h);
+    prof_begin(h, "sym_eig");
     hipLaunchKernelGGL(sym_eig, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, Om, Zm, dv, ev, tv, rot, h->status);
     hipLaunchKernelGGL(order_sign, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, dv, Zm, lam, Usm);
     if (hipMemcpyAsync(Sigma, lam, (size_t)rank * 8, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
         return BFGS_ERR_HIP;
+    prof_end(h);
+    prof_begin(h, "basis_diag");
     hipLaunchKernelGGL((basis_gemm<TO, TO>), dim3(ceil_div(rank, BS_C), ceil_div(n, BS_R)), dim3(256), 0, h->stream, n, c,
                        rank, Q, Usm, U);
     const int g = (int)std::min<int64_t>(4096, (n + 255) / 256);

@@ -29,6 +29,32 @@ int ensure_ws(Workspace& w, size_t bytes) {
     return BFGS_OK;
 }
 
+static hipEvent_t prof_event(bfgsuq_ctx* h) {
+    Profiler& P = h->prof;
+    if (P.used == P.pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        P.pool.push_back(e);
+    }
+    return P.pool[P.used++];
+}
+
+void prof_begin(bfgsuq_ctx* h, const char* name) {
+    if (!h->prof.on) return;
+    ProfRec r;
+    r.name = name;
+    r.a = prof_event(h);
+    r.b = prof_event(h);
+    if (!r.a || !r.b) return;
+    (void)hipEventRecord(r.a, h->stream);
+    h->prof.recs.push_back(r);
+}
+
+void prof_end(bfgsuq_ctx* h) {
+    if (!h->prof.on || h->prof.recs.empty()) return;
+    (void)hipEventRecord(h->prof.recs.back().b, h->stream);
+}
+
 static void free_ws(Workspace& w) {
     if (w.ptr) (void)hipFree(w.ptr);
     w.ptr = nullptr;
@@ -187,6 +213,7 @@ int bfgs_destroy(bfgs_t h) {
     Workspace* ws[] = {&h->part, &h->Z, &h->PT, &h->X, &h->E, &h->Q, &h->refl, &h->tau,
                        &h->Rtree, &h->small, &h->lam, &h->diag};
     for (Workspace* w : ws) free_ws(*w);
+    for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
     delete h;
     return BFGS_OK;
 }
@@ -377,6 +404,41 @@ int bfgs_rsvd(bfgs_t h, int32_t rank, int32_t oversample, uint64_t seed, void* U
     if (c > BFGS_MAX_COLS || c > h->n) return BFGS_ERR_ARG;
     if (h->gamma_mode && !h->gamma_known) return BFGS_ERR_STATE;
     return rsvd_run(h, rank, oversample, seed, U, Sigma);
+}
+
+int bfgs_profile(bfgs_t h, int32_t enable) {
+    if (!h) return BFGS_ERR_ARG;
+    h->prof.on = enable != 0;
+    return BFGS_OK;
+}
+
+int bfgs_profile_report(bfgs_t h, char* buf, int32_t len) {
+    if (!h || !buf || len < 3) return BFGS_ERR_ARG;
+    BFGS_HIP(hipStreamSynchronize(h->stream));
+    std::vector<const char*> names;
+    std::vector<double> tot;
+    std::vector<int> cnt;
+    for (const ProfRec& r : h->prof.recs) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+        size_t i = 0;
+        for (; i < names.size(); ++i)
+            if (std::strcmp(names[i], r.name) == 0) break;
+        if (i == names.size()) {
+            names.push_back(r.name);
+            tot.push_back(0.0);
+            cnt.push_back(0);
+        }
+        tot[i] += ms;
+        cnt[i] += 1;
+    }
+    h->prof.recs.clear();
+    h->prof.used = 0;
+    int off = std::snprintf(buf, len, "{");
+    for (size_t i = 0; i < names.size() && off < len; ++i)
+        off += std::snprintf(buf + off, len - off, "%s\"%s\": [%d, %.6f]", i ? ", " : "", names[i], cnt[i], tot[i]);
+    if (off < len) std::snprintf(buf + off, len - off, "}");
+    return off < len - 1 ? BFGS_OK : BFGS_ERR_ARG;
 }
 
 int bfgs_posterior_diag(bfgs_t h, void* out) {

@@ -69,6 +69,19 @@ class GridQuadratic:
         p = torch.full((self.nparam, self.nparam), self.coupling, dtype=torch.float64, device=self.D.device)
         p.fill_diagonal_(1.0)
         self.P = p
+        self._Gx = self._banded(self.nx)
+        self._Gz = self._banded(self.nz)
+
+    def _banded(self, m: int) -> torch.Tensor:
+        """Dense m x m matrix of the truncated smoother with zero boundary (symmetric Toeplitz)."""
+        taps = self._taps.view(-1)
+        half = taps.numel() // 2
+        idx = torch.arange(m, device=taps.device)
+        off = idx.view(-1, 1) - idx.view(1, -1)
+        G = torch.zeros(m, m, dtype=torch.float64, device=taps.device)
+        band = off.abs() <= half
+        G[band] = taps[(off[band] + half)]
+        return G
 
     @property
     def n(self) -> int:
@@ -79,13 +92,10 @@ class GridQuadratic:
         return self.D.device
 
     def _smooth(self, x: torch.Tensor) -> torch.Tensor:
-        """x: (B, nparam, nz, nx) -> separable Gaussian smoothing of each field."""
-        B = x.shape[0]
-        pad = self._taps.shape[-1] // 2
-        y = torch.nn.functional.conv1d(x.reshape(-1, 1, self.nx), self._taps, padding=pad)
-        y = y.view(B, self.nparam, self.nz, self.nx).transpose(2, 3).reshape(-1, 1, self.nz)
-        y = torch.nn.functional.conv1d(y, self._taps, padding=pad)
-        return y.view(B, self.nparam, self.nx, self.nz).transpose(2, 3)
+        """x: (B, nparam, nz, nx) -> separable Gaussian smoothing of each field
+        (G_z X G_x with the symmetric banded smoothers)."""
+        y = torch.matmul(x, self._Gx)
+        return torch.matmul(self._Gz, y)
 
     def matvec(self, x: torch.Tensor) -> torch.Tensor:
         """A x for x of shape (n,) or (ncols, n)."""
