@@ -269,7 +269,7 @@ int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
     double* Z = (double*)h->Z.ptr;
     double* P = (double*)h->PT.ptr;
     double* T = P + (size_t)k * c;
-    ProfScope ps1(h, "apply_gemm1");
+    prof_begin(h, "apply_gemm1");
     hipLaunchKernelGGL((gemm1_generic<Ts, Th, Ts>), dim3(ptiles, ctiles, nchunks), dim3(256), 0, h->stream, n, h->ld,
                        k, c, (const Ts*)h->S, (const Ts*)h->Y, h0, V, part, rows_per_chunk);
     const int64_t count = (int64_t)twok * c;
@@ -277,20 +277,27 @@ int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
     prof_begin(h, "apply_reduce");
     hipLaunchKernelGGL(reduce_partials, dim3(ceil_div(count, 256)), dim3(256), 0, h->stream, count, nchunks, part, Z);
     prof_end(h);
-    prof_begin(h, "apply_solve");
-    hipLaunchKernelGGL(small_solve, dim3(c), dim3(64), 3 * k * sizeof(double), h->stream, k, h->kmax, c, h->Rm,
-                       h->YHY, Z, P, T, h->status);
-    prof_end(h);
+    if (int rc2 = apply_small_solve(h, c, Z, P, T)) return rc2;
     prof_begin(h, "apply_gemm2");
     hipLaunchKernelGGL((gemm2_generic<Ts, Th, Ts, To>), dim3(ceil_div(c, G2_TC), ceil_div(n, G2_TR)), dim3(256), 0,
                        h->stream, n, h->ld, k, c, (const Ts*)h->S, (const Ts*)h->Y, h0, V, P, T, out,
                        diff ? 1 : 0);
+    prof_end(h);
     return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
 }
 
 }  // namespace
 
+int apply_small_solve(bfgsuq_ctx* h, int c, const double* Z, double* P, double* T) {
+    ProfScope ps(h, "apply_solve");
+    const int k = h->k;
+    hipLaunchKernelGGL(small_solve, dim3(c), dim3(64), 3 * k * sizeof(double), h->stream, k, h->kmax, c, h->Rm,
+                       h->YHY, Z, P, T, h->status);
+    return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+}
+
 int apply_block(bfgsuq_ctx* h, const void* V, int32_t ncols, void* out, bool diff) {
+    if (mfma_apply_supported(h, ncols)) return mfma_apply(h, V, ncols, out, diff);
     switch (h->storage) {
         case BFGS_F64: return apply_generic<double, double, double>(h, V, ncols, out, diff);
         case BFGS_F32: return apply_generic<float, float, float>(h, V, ncols, out, diff);

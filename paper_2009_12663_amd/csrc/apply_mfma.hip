@@ -1,0 +1,493 @@
+// B_k V for bfloat16 storage on the CDNA4 matrix cores.
+//
+// Same compact form as apply.hip (two streaming passes over S and Y around a
+// float64 k x k solve), with both passes as bfloat16 MFMA (32x32x16, float32
+// accumulation) over layouts written at push time so that every wave's operand
+// load is one contiguous 1 KB block:
+//
+//   F1 (pass 1, contraction over rows): 16-row blocks, pair-major inside:
+//        element (r, p) at (r / 16) * kmax * 16 + p * 16 + r % 16
+//   F2 (pass 2, contraction over pairs): 32-row blocks of 16-pair groups:
+//        element (r, p) at (r / 32) * G * 512 + (p / 16) * 512 + (r % 32) * 16 + p % 16
+//        with G = ceil(kmax / 16) groups (missing pairs are zero)
+//
+// Pass 1:  Z_s = S^T V and Z_y = Y^T (B_0 V).  One workgroup per (row range,
+//          S or Y); the S and Y workgroups of a row range sit on the same XCD so
+//          the V block they both stage through LDS is read from HBM once.  With
+//          a diagonal B_0 the Y workgroup multiplies V by h0 in float32 and
+//          splits the product into bfloat16 hi + lo (two MFMAs); with B_0 = gamma I
+//          the scale is applied in float64 after the reduction.
+// Pass 2:  computed transposed, out^T = small^T W^T, so that a lane owns one
+//          output row and all writes are coalesced.  The small operand is
+//          [-P ; T] split into bfloat16 hi + lo (the float64 solve result would
+//          otherwise lose 8 bits); the Y half is accumulated first, the
+//          accumulator is scaled by h0[row] (one per lane), then the S half
+//          is added: out = h0 o (V - Y P) + S T.
+#include <cmath>
+
+#include "common.h"
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
+
+struct alignas(16) u16x8 {
+    uint16_t v[8];
+};
+
+__device__ __forceinline__ bf16x8 as_bf16x8(const uint4 u) { return __builtin_bit_cast(bf16x8, u); }
+
+__device__ __forceinline__ floatx16 mfma32(bf16x8 a, bf16x8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ uint16_t bf16_bits_rne(float f) { return float_to_bf16(f).bits; }
+__device__ __forceinline__ float bits_to_f32(uint16_t b) {
+    bf16_t h;
+    h.bits = b;
+    return bf16_to_float(h);
+}
+
+// ---------------------------------------------------------------------------
+// Push: scatter stored column j into F1 and F2.
+// ---------------------------------------------------------------------------
+__global__ void scatter_pair_layouts(int64_t n, int64_t rows_f1, int64_t rows_f2, int kmax, int G, int j,
+                                     const bf16_t* __restrict__ Scol, const bf16_t* __restrict__ Ycol,
+                                     bf16_t* __restrict__ S1, bf16_t* __restrict__ Y1, bf16_t* __restrict__ S2,
+                                     bf16_t* __restrict__ Y2) {
+    const int64_t rows = rows_f1 > rows_f2 ? rows_f1 : rows_f2;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x) {
+        bf16_t s, y;
+        s.bits = 0;
+        y.bits = 0;
+        if (r < n) {
+            s = Scol[r];
+            y = Ycol[r];
+        }
+        if (r < rows_f1) {
+            const int64_t o = (r / 16) * (int64_t)kmax * 16 + (int64_t)j * 16 + r % 16;
+            S1[o] = s;
+            Y1[o] = y;
+        }
+        if (r < rows_f2) {
+            const int64_t o = (r / 32) * (int64_t)G * 512 + (int64_t)(j / 16) * 512 + (r % 32) * 16 + j % 16;
+            S2[o] = s;
+            Y2[o] = y;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1
+// ---------------------------------------------------------------------------
+constexpr int G1_STAGE = 64;      // rows per stage (4 MFMA k-steps of 16)
+constexpr int VS_LD = 72;         // LDS row pitch (elements) of a staged V column: 64 rows + 8 pad
+
+// blockDim = 64 * MT (one 32-pair tile per wave); grid = 16 * ceil(nk / 8)
+template <int NT, bool DIAG>
+__global__ void __launch_bounds__(512) gemm1_mfma(int64_t n, int k, int kmax, int c, const bf16_t* __restrict__ S1,
+                                                  const bf16_t* __restrict__ Y1, const float* __restrict__ h0,
+                                                  const bf16_t* __restrict__ V, float* __restrict__ part,
+                                                  int64_t rows_per_wg, int64_t rows_f1, int nk, int v_aligned) {
+    extern __shared__ unsigned char smem_raw[];
+    uint16_t* Vs = (uint16_t*)smem_raw;                 // [NT*32][VS_LD]
+    uint16_t* Vl = Vs + NT * 32 * VS_LD;                // low halves (Y part, diagonal B_0)
+    const int g = blockIdx.x;
+    const int kr = 8 * (g / 16) + (g % 8);
+    const int part_id = (g / 8) % 2;
+    if (kr >= nk) return;                                // whole workgroup
+    const bool scaled = DIAG && part_id == 1;
+    const bf16_t* W = part_id ? Y1 : S1;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int p = wave * 32 + (lane & 31);               // pair owned by this lane in the A fragment
+    const bool active = wave * 32 < k;                   // waves past the last pair tile only stage V
+    const int half = lane >> 5;
+    const int64_t r_begin = (int64_t)kr * rows_per_wg;
+    int64_t r_end = r_begin + rows_per_wg;
+    if (r_end > rows_f1) r_end = rows_f1;
+
+    floatx16 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
+
+    constexpr int VCH = NT * 32 * 8;                     // 16-byte chunks per staged V block
+    constexpr int VQ = (VCH + 511) / 512;                // per thread (512 threads)
+    uint4 vreg[VQ];
+    uint4 areg[4];
+
+    auto load_v = [&](int64_t r0) {
+#pragma unroll
+        for (int q = 0; q < VQ; ++q) {
+            const int idx = tid + q * 512;
+            if (idx >= VCH) continue;
+            const int col = idx >> 3, ch = idx & 7;
+            const int64_t r = r0 + ch * 8;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (col < c && r < n) {
+                const bf16_t* src = V + (int64_t)col * n + r;
+                if (v_aligned && r + 8 <= n) {
+                    val = *(const uint4*)src;
+                } else {
+                    u16x8 t;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) t.v[e] = (r + e < n) ? src[e].bits : (uint16_t)0;
+                    val = __builtin_bit_cast(uint4, t);
+                }
+            }
+            vreg[q] = val;
+        }
+    };
+    auto store_v = [&](int64_t r0) {
+#pragma unroll
+        for (int q = 0; q < VQ; ++q) {
+            const int idx = tid + q * 512;
+            if (idx >= VCH) continue;
+            const int col = idx >> 3, ch = idx & 7;
+            uint16_t* dst = Vs + col * VS_LD + ch * 8;
+            if (!scaled) {
+                *(uint4*)dst = vreg[q];
+            } else {
+                u16x8 raw = __builtin_bit_cast(u16x8, vreg[q]);
+                u16x8 hi, lo;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int64_t r = r0 + ch * 8 + e;
+                    const float hv = r < n ? h0[r] : 0.f;
+                    const float prod = hv * bits_to_f32(raw.v[e]);
+                    hi.v[e] = bf16_bits_rne(prod);
+                    lo.v[e] = bf16_bits_rne(prod - bits_to_f32(hi.v[e]));
+                }
+                *(uint4*)dst = __builtin_bit_cast(uint4, hi);
+                *(uint4*)(Vl + col * VS_LD + ch * 8) = __builtin_bit_cast(uint4, lo);
+            }
+        }
+    };
+    auto load_a = [&](int64_t r0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int64_t rr = r0 + 16 * s;
+            if (active && p < k && rr < r_end)
+                areg[s] = *(const uint4*)(W + (rr / 16) * (int64_t)kmax * 16 + (int64_t)p * 16 + half * 8);
+            else
+                areg[s] = make_uint4(0, 0, 0, 0);
+        }
+    };
+
+    if (r_begin < r_end) {
+        load_v(r_begin);
+        load_a(r_begin);
+    }
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += G1_STAGE) {
+        __syncthreads();
+        store_v(r0);
+        __syncthreads();
+        uint4 acur[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acur[s] = areg[s];
+        if (r0 + G1_STAGE < r_end) {
+            load_v(r0 + G1_STAGE);
+            load_a(r0 + G1_STAGE);
+        }
+        if (active) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const bf16x8 a = as_bf16x8(acur[s]);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const uint16_t* bp = Vs + (t * 32 + (lane & 31)) * VS_LD + s * 16 + half * 8;
+                acc[t] = mfma32(a, as_bf16x8(*(const uint4*)bp), acc[t]);
+                if (scaled) {
+                    const uint16_t* bl = Vl + (t * 32 + (lane & 31)) * VS_LD + s * 16 + half * 8;
+                    acc[t] = mfma32(a, as_bf16x8(*(const uint4*)bl), acc[t]);
+                }
+            }
+        }
+        }
+    }
+    if (!active) return;
+    // partial Z for this row range: part[kr][col][2k], float32
+    const int twok = 2 * k;
+    float* dst = part + (int64_t)kr * twok * c;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int m = 8 * (i / 4) + 4 * half + (i % 4);
+            const int pp = wave * 32 + m;
+            const int col = t * 32 + (lane & 31);
+            if (pp < k && col < c) dst[(int64_t)col * twok + part_id * k + pp] = acc[t][i];
+        }
+    }
+}
+
+// Z (float64, column-major 2k x c) = fixed-order sum of the float32 partials;
+// the Y rows are multiplied by gamma when B_0 = gamma I.
+__global__ void reduce_z(int64_t count, int twok, int k, int nk, const float* __restrict__ part,
+                         const double* __restrict__ scalars, int gamma_mode, double* __restrict__ Z) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double s = 0.0;
+    for (int q = 0; q < nk; ++q) s += (double)part[(int64_t)q * count + e];
+    const int prow = (int)(e % twok);
+    if (gamma_mode && prow >= k) s *= scalars[0];
+    Z[e] = s;
+}
+
+// small^T (hi, lo): column j, position q of [Y phase (Gp*16) | S phase (Gp*16)]:
+//   Y phase: -P(p, j), S phase: T(p, j), zero beyond k or c.
+__global__ void pack_small(int k, int c, int cpad, int Gp, const double* __restrict__ P, const double* __restrict__ T,
+                           uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
+    const int K2 = 2 * Gp * 16;
+    const int64_t total = (int64_t)cpad * K2;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e / K2), q = (int)(e % K2);
+        const int phase = q / (Gp * 16), pp = q % (Gp * 16);
+        double v = 0.0;
+        if (j < c && pp < k) v = phase == 0 ? -P[(int64_t)j * k + pp] : T[(int64_t)j * k + pp];
+        const float vf = (float)v;
+        const uint16_t h = bf16_bits_rne(vf);
+        hi[e] = h;
+        lo[e] = bf16_bits_rne((float)(v - (double)bits_to_f32(h)));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2: 8 waves, one 32-row tile each (256 rows per workgroup), MT2 column tiles.
+// ---------------------------------------------------------------------------
+constexpr int G2_ROWS = 256;
+constexpr int SM_LD = 40;        // LDS pitch of a staged small column: 32 pairs + 8 pad
+
+template <int MT2, bool DIFF>
+__global__ void __launch_bounds__(512) gemm2_mfma(int64_t n, int c, int G, int Gp, const bf16_t* __restrict__ Y2,
+                                                  const bf16_t* __restrict__ S2, const uint16_t* __restrict__ shi,
+                                                  const uint16_t* __restrict__ slo, const float* __restrict__ h0,
+                                                  const bf16_t* __restrict__ V, float* __restrict__ out) {
+    __shared__ uint16_t Sh[MT2 * 32 * SM_LD];
+    __shared__ uint16_t Sl[MT2 * 32 * SM_LD];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, half = lane >> 5;
+    const int64_t row_base = (int64_t)blockIdx.x * G2_ROWS + wave * 32;
+    const int64_t rb32 = row_base / 32;
+    const int K2 = 2 * Gp * 16;
+    const int nchunks = K2 / 32;
+    const int row_lane = (int)(row_base + (lane & 31) < n) ? 1 : 0;
+    const float h0r = row_lane ? h0[row_base + (lane & 31)] : 0.f;
+
+    floatx16 acc[MT2];
+#pragma unroll
+    for (int t = 0; t < MT2; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
+
+    constexpr int SCH = MT2 * 32 * 4;        // 16-byte chunks of one array per staged chunk (<= 1024)
+    uint4 sh0 = make_uint4(0, 0, 0, 0), sl0 = sh0, sh1 = sh0, sl1 = sh0;
+#define LOAD_SMALL(t)                                                                    \
+    {                                                                                    \
+        if (tid < SCH) {                                                                 \
+            const int64_t off = (int64_t)(tid >> 2) * K2 + (t) * 32 + (tid & 3) * 8;     \
+            sh0 = *(const uint4*)(shi + off);                                            \
+            sl0 = *(const uint4*)(slo + off);                                            \
+        }                                                                                \
+        if (tid + 512 < SCH) {                                                           \
+            const int64_t off = (int64_t)((tid + 512) >> 2) * K2 + (t) * 32 + (tid & 3) * 8; \
+            sh1 = *(const uint4*)(shi + off);                                            \
+            sl1 = *(const uint4*)(slo + off);                                            \
+        }                                                                                \
+    }
+#define STORE_SMALL()                                                                    \
+    {                                                                                    \
+        if (tid < SCH) {                                                                 \
+            *(uint4*)(Sh + (tid >> 2) * SM_LD + (tid & 3) * 8) = sh0;                    \
+            *(uint4*)(Sl + (tid >> 2) * SM_LD + (tid & 3) * 8) = sl0;                    \
+        }                                                                                \
+        if (tid + 512 < SCH) {                                                           \
+            *(uint4*)(Sh + ((tid + 512) >> 2) * SM_LD + (tid & 3) * 8) = sh1;            \
+            *(uint4*)(Sl + ((tid + 512) >> 2) * SM_LD + (tid & 3) * 8) = sl1;            \
+        }                                                                                \
+    }
+    auto load_b = [&](int t, int sg) -> uint4 {
+        const int gq = 2 * t + sg;
+        const int phase = gq >= Gp ? 1 : 0;
+        const int grp = gq - phase * Gp;
+        if (grp >= G) return make_uint4(0, 0, 0, 0);
+        const bf16_t* W = phase ? S2 : Y2;
+        return *(const uint4*)(W + rb32 * (int64_t)G * 512 + (int64_t)grp * 512 + (lane & 31) * 16 + half * 8);
+    };
+
+    LOAD_SMALL(0);
+    uint4 bnext0 = load_b(0, 0), bnext1 = load_b(0, 1);
+    for (int t = 0; t < nchunks; ++t) {
+        __syncthreads();
+        STORE_SMALL();
+        __syncthreads();
+        const uint4 b0 = bnext0, b1 = bnext1;
+        if (t + 1 < nchunks) {
+            LOAD_SMALL(t + 1);
+            bnext0 = load_b(t + 1, 0);
+            bnext1 = load_b(t + 1, 1);
+        }
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+            const bf16x8 b = as_bf16x8(sg ? b1 : b0);
+#pragma unroll
+            for (int m = 0; m < MT2; ++m) {
+                const int off = (m * 32 + (lane & 31)) * SM_LD + sg * 16 + half * 8;
+                acc[m] = mfma32(as_bf16x8(*(const uint4*)(Sh + off)), b, acc[m]);
+                acc[m] = mfma32(as_bf16x8(*(const uint4*)(Sl + off)), b, acc[m]);
+            }
+        }
+        if (2 * t + 2 == Gp) {
+            // end of the Y phase: acc holds -(Y P)^T for this lane's row; scale by h0[row]
+#pragma unroll
+            for (int m = 0; m < MT2; ++m)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[m][i] *= h0r;
+        }
+    }
+#undef LOAD_SMALL
+#undef STORE_SMALL
+    if (!row_lane) return;
+    const int64_t row = row_base + (lane & 31);
+#pragma unroll
+    for (int m = 0; m < MT2; ++m) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int col = m * 32 + 8 * (i / 4) + 4 * half + (i % 4);
+            if (col < c) {
+                float o = acc[m][i];
+                if (!DIFF) o += h0r * bf16_to_float(V[(int64_t)col * n + row]);
+                out[(int64_t)col * n + row] = o;
+            }
+        }
+    }
+}
+
+template <int NT, bool DIAG>
+void launch_g1(int grid, int threads, size_t smem, hipStream_t st, int64_t n, int k, int kmax, int c, const bf16_t* S1,
+               const bf16_t* Y1, const float* h0, const bf16_t* V, float* part, int64_t rows_per_wg, int64_t rows_f1,
+               int nk, int aligned) {
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)gemm1_mfma<NT, DIAG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  2 * 8 * 32 * VS_LD * (int)sizeof(uint16_t));
+        attr = true;
+    }
+    hipLaunchKernelGGL((gemm1_mfma<NT, DIAG>), dim3(grid), dim3(threads), smem, st, n, k, kmax, c, S1, Y1, h0, V, part,
+                       rows_per_wg, rows_f1, nk, aligned);
+}
+
+typedef void (*g1_fn)(int, int, size_t, hipStream_t, int64_t, int, int, int, const bf16_t*, const bf16_t*, const float*,
+                      const bf16_t*, float*, int64_t, int64_t, int, int);
+
+g1_fn pick_g1(int NT, bool diag) {
+#define G1CASE(N)                                        \
+    case N:                                              \
+        return diag ? launch_g1<N, true> : launch_g1<N, false>;
+    switch (NT) {
+        G1CASE(1) G1CASE(2) G1CASE(3) G1CASE(4) G1CASE(5) G1CASE(6) G1CASE(7) G1CASE(8)
+    }
+#undef G1CASE
+    return nullptr;
+}
+
+template <int MT2, bool DIFF>
+void launch_g2(int grid, hipStream_t st, int64_t n, int c, int G, int Gp, const bf16_t* Y2, const bf16_t* S2,
+               const uint16_t* shi, const uint16_t* slo, const float* h0, const bf16_t* V, float* out) {
+    hipLaunchKernelGGL((gemm2_mfma<MT2, DIFF>), dim3(grid), dim3(512), 0, st, n, c, G, Gp, Y2, S2, shi, slo, h0, V, out);
+}
+
+typedef void (*g2_fn)(int, hipStream_t, int64_t, int, int, int, const bf16_t*, const bf16_t*, const uint16_t*,
+                      const uint16_t*, const float*, const bf16_t*, float*);
+
+g2_fn pick_g2(int MT2, bool diff) {
+#define G2CASE(N)                                        \
+    case N:                                              \
+        return diff ? launch_g2<N, true> : launch_g2<N, false>;
+    switch (MT2) {
+        G2CASE(1) G2CASE(2) G2CASE(3) G2CASE(4) G2CASE(5) G2CASE(6) G2CASE(7) G2CASE(8)
+    }
+#undef G2CASE
+    return nullptr;
+}
+
+}  // namespace
+
+// Layout sizes shared with the runtime.
+int64_t mfma_rows_f1(int64_t n) { return round_up(n, 64); }
+int64_t mfma_rows_f2(int64_t n) { return round_up(n, 256); }
+int mfma_groups(int kmax) { return (kmax + 15) / 16; }
+
+int mfma_scatter_pair(bfgsuq_ctx* h, int j) {
+    const int G = mfma_groups(h->kmax);
+    const int64_t r1 = mfma_rows_f1(h->n), r2 = mfma_rows_f2(h->n);
+    const int64_t rows = r1 > r2 ? r1 : r2;
+    const int grid = (int)std::min<int64_t>(4096, (rows + 255) / 256);
+    hipLaunchKernelGGL(scatter_pair_layouts, dim3(grid), dim3(256), 0, h->stream, h->n, r1, r2, h->kmax, G, j,
+                       (const bf16_t*)h->S + (int64_t)j * h->ld, (const bf16_t*)h->Y + (int64_t)j * h->ld,
+                       (bf16_t*)h->S1, (bf16_t*)h->Y1, (bf16_t*)h->S2, (bf16_t*)h->Y2);
+    return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+}
+
+bool mfma_apply_supported(const bfgsuq_ctx* h, int c) {
+    return h->storage == BFGS_BF16 && h->S1 != nullptr && h->k >= 1 && h->k <= 256 && c >= 1 && c <= 256;
+}
+
+int apply_small_solve(bfgsuq_ctx* h, int c, const double* Z, double* P, double* T);
+
+int mfma_apply(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
+    const int64_t n = h->n;
+    const int k = h->k;
+    const bf16_t* V = (const bf16_t*)Vv;
+    float* out = (float*)outv;
+    const int NT = (c + 31) / 32;
+    const int nk = 128;                                   // row ranges (multiple of 8)
+    const int64_t rows_f1 = mfma_rows_f1(n);
+    const int64_t rows_per_wg = round_up((rows_f1 + nk - 1) / nk, G1_STAGE);
+    const int twok = 2 * k;
+    const int G = mfma_groups(h->kmax);
+    const int Gk = (k + 15) / 16;                          // groups that hold pairs
+    const int Gp = (Gk + 1) / 2 * 2;
+    const int cpad = NT * 32;
+    int rc;
+    if ((rc = ensure_ws(h->part, (size_t)nk * twok * c * sizeof(float))) != BFGS_OK) return rc;
+    if ((rc = ensure_ws(h->Z, (size_t)2 * h->kmax * BFGS_MAX_COLS * 8)) != BFGS_OK) return rc;
+    if ((rc = ensure_ws(h->PT, (size_t)2 * h->kmax * BFGS_MAX_COLS * 8)) != BFGS_OK) return rc;
+    if ((rc = ensure_ws(h->small16, (size_t)2 * 256 * 2 * (G + 1) * 16 * 2)) != BFGS_OK) return rc;
+    float* part = (float*)h->part.ptr;
+    double* Z = (double*)h->Z.ptr;
+    double* P = (double*)h->PT.ptr;
+    double* T = P + (size_t)k * c;
+    uint16_t* shi = (uint16_t*)h->small16.ptr;
+    uint16_t* slo = shi + (size_t)cpad * 2 * Gp * 16;
+    const bool diag = !h->gamma_mode;
+    {
+        ProfScope ps(h, "apply_gemm1");
+        const size_t smem = (size_t)(diag ? 2 : 1) * NT * 32 * VS_LD * sizeof(uint16_t);
+        const int grid = 16 * ((nk + 7) / 8);
+        const int aligned = (n % 8 == 0) && (((uintptr_t)V) % 16 == 0);
+        pick_g1(NT, diag)(grid, 512, smem, h->stream, n, k, h->kmax, c, (const bf16_t*)h->S1,
+                          (const bf16_t*)h->Y1, (const float*)h->h0, V, part, rows_per_wg, rows_f1, nk, aligned);
+    }
+    {
+        ProfScope ps(h, "apply_reduce");
+        const int64_t count = (int64_t)twok * c;
+        hipLaunchKernelGGL(reduce_z, dim3(ceil_div(count, 256)), dim3(256), 0, h->stream, count, twok, k, nk, part,
+                           h->scalars, h->gamma_mode ? 1 : 0, Z);
+    }
+    if ((rc = apply_small_solve(h, c, Z, P, T)) != BFGS_OK) return rc;
+    {
+        ProfScope ps(h, "apply_pack");
+        const int64_t total = (int64_t)cpad * 2 * Gp * 16;
+        hipLaunchKernelGGL(pack_small, dim3((int)std::min<int64_t>(2048, (total + 255) / 256)), dim3(256), 0, h->stream,
+                           k, c, cpad, Gp, P, T, shi, slo);
+    }
+    {
+        ProfScope ps(h, "apply_gemm2");
+        const int grid = ceil_div(n, G2_ROWS);
+        pick_g2(NT, diff)(grid, h->stream, n, c, G, Gp, (const bf16_t*)h->Y2, (const bf16_t*)h->S2, shi, slo,
+                          (const float*)h->h0, V, out);
+    }
+    return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+}

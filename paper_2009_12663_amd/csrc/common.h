@@ -102,8 +102,14 @@ struct bfgsuq_ctx {
     int32_t* status = nullptr; // deferred device status (0 = OK)
     int gram_blocks = 0;
 
+    // bfloat16 MFMA layouts of S and Y (see apply_mfma.hip); null for other storage types
+    void* S1 = nullptr;
+    void* Y1 = nullptr;
+    void* S2 = nullptr;
+    void* Y2 = nullptr;
+
     // apply workspaces (grow-only)
-    Workspace part, Z, PT;
+    Workspace part, Z, PT, small16;
     // rsvd workspaces
     Workspace X, E, Q, refl, tau, Rtree, small, lam, diag;
     int32_t last_rank = 0;
@@ -143,3 +149,10 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 int apply_block(bfgsuq_ctx* h, const void* V, int32_t ncols, void* out, bool diff);
 int rsvd_run(bfgsuq_ctx* h, int32_t rank, int32_t oversample, uint64_t seed, void* U, double* Sigma);
 int probes_run(bfgsuq_ctx* h, uint64_t seed, int32_t ncols, void* X);
+int64_t mfma_rows_f1(int64_t n);
+int64_t mfma_rows_f2(int64_t n);
+int mfma_groups(int kmax);
+int mfma_scatter_pair(bfgsuq_ctx* h, int j);
+bool mfma_apply_supported(const bfgsuq_ctx* h, int c);
+int mfma_apply(bfgsuq_ctx* h, const void* V, int c, void* out, bool diff);
+int apply_small_solve(bfgsuq_ctx* h, int c, const double* Z, double* P, double* T);

@@ -207,10 +207,11 @@ const char* bfgs_status_string(int code) {
 int bfgs_destroy(bfgs_t h) {
     if (!h) return BFGS_OK;
     (void)hipStreamSynchronize(h->stream);
-    void* ptrs[] = {h->S, h->Y, h->h0, h->Rm, h->YHY, h->gram_part, h->scalars, h->status};
+    void* ptrs[] = {h->S, h->Y, h->h0, h->Rm, h->YHY, h->gram_part, h->scalars, h->status,
+                    h->S1, h->Y1, h->S2, h->Y2};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    Workspace* ws[] = {&h->part, &h->Z, &h->PT, &h->X, &h->E, &h->Q, &h->refl, &h->tau,
+    Workspace* ws[] = {&h->part, &h->Z, &h->PT, &h->small16, &h->X, &h->E, &h->Q, &h->refl, &h->tau,
                        &h->Rtree, &h->small, &h->lam, &h->diag};
     for (Workspace* w : ws) free_ws(*w);
     for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
@@ -250,6 +251,15 @@ int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, vo
     alloc((void**)&h->gram_part, (size_t)k_max * h->gram_blocks * 2 * 8);
     alloc((void**)&h->scalars, 8 * 8);
     alloc((void**)&h->status, 64);
+    size_t f1_bytes = 0, f2_bytes = 0;
+    if (storage == BFGS_BF16) {
+        f1_bytes = (size_t)mfma_rows_f1(n) * k_max * 2;
+        f2_bytes = (size_t)mfma_rows_f2(n) * mfma_groups(k_max) * 16 * 2;
+        alloc(&h->S1, f1_bytes);
+        alloc(&h->Y1, f1_bytes);
+        alloc(&h->S2, f2_bytes);
+        alloc(&h->Y2, f2_bytes);
+    }
     if (rc != BFGS_OK) {
         bfgs_destroy(h);
         return rc;
@@ -260,7 +270,11 @@ int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, vo
         hipMemsetAsync(h->Rm, 0, (size_t)k_max * k_max * 8, h->stream) != hipSuccess ||
         hipMemsetAsync(h->YHY, 0, (size_t)k_max * k_max * 8, h->stream) != hipSuccess ||
         hipMemsetAsync(h->scalars, 0, 64, h->stream) != hipSuccess ||
-        hipMemsetAsync(h->status, 0, 64, h->stream) != hipSuccess) {
+        hipMemsetAsync(h->status, 0, 64, h->stream) != hipSuccess ||
+        (f1_bytes && (hipMemsetAsync(h->S1, 0, f1_bytes, h->stream) != hipSuccess ||
+                      hipMemsetAsync(h->Y1, 0, f1_bytes, h->stream) != hipSuccess ||
+                      hipMemsetAsync(h->S2, 0, f2_bytes, h->stream) != hipSuccess ||
+                      hipMemsetAsync(h->Y2, 0, f2_bytes, h->stream) != hipSuccess))) {
         bfgs_destroy(h);
         return BFGS_ERR_HIP;
     }
@@ -303,6 +317,7 @@ int bfgs_push_pair(bfgs_t h, const void* s, const void* y, bfgs_dtype in_dtype) 
         case BFGS_BF16:
             if (in_dtype == BFGS_F64) launch_store<double, bf16_t>(h, s, y, j);
             else launch_store<float, bf16_t>(h, s, y, j);
+            if (mfma_scatter_pair(h, j) != BFGS_OK) return BFGS_ERR_HIP;
             launch_gram<bf16_t, float>(h, j);
             break;
     }

@@ -37,7 +37,8 @@ def make_pairs(kind: str, nx: int, nz: int, k: int, seed: int = 0, precond: bool
     prob = wq.make_grid(nx, nz, seed)
     h0 = (1.0 / prob.diag()) if precond else None
     if kind == "cg":
-        S, Y, _ = wq.cg_pairs(prob, k, precond=h0)
+        # stop once the gradient is at rounding level: later steps underflow float32
+        S, Y, _ = wq.cg_pairs(prob, k, precond=h0, rel_tol=1e-12)
     else:
         S, Y = wq.random_secant_pairs(prob, k, seed=seed + 7)
     return prob, S, Y, h0

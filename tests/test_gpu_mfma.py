@@ -1,0 +1,99 @@
+"""Parity of the bfloat16 MFMA path of bfgs_apply_Hinv / bfgs_apply_Hdiff against the
+float64 oracle on the same stored (bfloat16-rounded) inputs: ragged and unaligned n,
+k and ncols at tile edges, diagonal and scalar B_0, and the full-size workload
+(n = 1,785,000, k = 200, 220 columns) on sampled columns."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import twoloop
+from workloads import quadratic as wq
+from tests.helpers import rel_f, gpu_input, oracle_input, h0_storage, make_pairs, gamma_of
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-3
+
+
+def build(S, Y, h0):
+    import paper_2009_12663_amd as P
+    H = P.Bfgs(S.shape[1], S.shape[0], None if h0 is None else gpu_input(h0, "bf16"), "bf16")
+    for s, y in zip(S, Y):
+        H.push_pair(gpu_input(s, "bf16"), gpu_input(y, "bf16"))
+    return H
+
+
+def oracle(S, Y, V, h0, diff=False):
+    Sq, Yq, Vq = oracle_input(S, "bf16"), oracle_input(Y, "bf16"), oracle_input(V, "bf16")
+    h = np.full(S.shape[1], float(np.float32(gamma_of(Sq, Yq)))) if h0 is None else h0_storage(h0, "bf16")
+    return twoloop.two_loop(h, Sq, Yq, Vq, subtract_b0=diff), h, Vq
+
+
+SHAPES = [
+    # kind, nx, nz, k, c, precond
+    ("secant", 7, 5, 1, 1, True),
+    ("cg", 20, 11, 31, 33, False),
+    ("secant", 13, 17, 33, 64, True),
+    ("cg", 60, 40, 200, 220, False),
+    ("secant", 30, 30, 256, 256, True),
+    ("cg", 64, 32, 96, 120, True),
+    ("secant", 61, 23, 47, 97, False),
+]
+
+
+@pytest.mark.parametrize("kind,nx,nz,k,c,precond", SHAPES)
+def test_mfma_apply_parity(kind, nx, nz, k, c, precond):
+    print(f"\n[mfma apply] {kind} n={3*nx*nz} k={k} c={c} diagB0={precond}", flush=True)
+    prob, S, Y, h0 = make_pairs(kind, nx, nz, k, seed=k + c, precond=precond)
+    H = build(S, Y, h0)
+    V = wq.normal_block(prob.n, c, seed=c + 1)
+    out = H.apply_Hinv(gpu_input(V, "bf16")).double().cpu().numpy()
+    want, h, Vq = oracle(S, Y, V, h0)
+    err = rel_f(out, want)
+    corr = rel_f(out - h * Vq, want - h * Vq)
+    outd = H.apply_Hdiff(gpu_input(V, "bf16")).double().cpu().numpy()
+    wantd, _, _ = oracle(S, Y, V, h0, diff=True)
+    errd = rel_f(outd, wantd)
+    print(f"  rel_F={err:.3e} correction={corr:.3e} diff={errd:.3e}", flush=True)
+    assert err <= TOL and errd <= TOL
+    assert H.get_status() == 0
+    H.close()
+
+
+def test_mfma_matches_generic_beyond_256_pairs():
+    """k = 257 runs the portable kernels; both paths must agree with the oracle."""
+    prob, S, Y, h0 = make_pairs("secant", 20, 10, 257, seed=3, precond=True)
+    H = build(S, Y, h0)
+    V = wq.normal_block(prob.n, 17, seed=5)
+    out = H.apply_Hinv(gpu_input(V, "bf16")).double().cpu().numpy()
+    want, _, _ = oracle(S, Y, V, h0)
+    assert rel_f(out, want) <= TOL
+    H.close()
+
+
+def test_mfma_full_size_sampled_columns():
+    """The benchmark workload: 1700 x 350 x 3 grid, k = 200, 220 probe columns, launched
+    exactly as bench.py does; three columns checked against the oracle."""
+    import paper_2009_12663_amd as P
+    print("\n[mfma full size] generating pairs", flush=True)
+    prob = wq.make_problem("grid3", device="cuda")
+    S, Y, _ = wq.cg_pairs(prob, 200)
+    H = P.Bfgs(prob.n, 200, None, "bf16")
+    for s, y in zip(S, Y):
+        H.push_pair(s.float(), y.float())
+    V = H.generate_probes(2, 220)
+    out = H.apply_Hinv(V)
+    cols = [0, 111, 219]
+    Sq = S.float().to(torch.bfloat16).double().cpu().numpy()
+    Yq = Y.float().to(torch.bfloat16).double().cpu().numpy()
+    del S, Y
+    g = float(np.float32(gamma_of(Sq, Yq)))
+    h = np.full(prob.n, g)
+    Vq = V[cols].double().cpu().numpy()
+    want = twoloop.two_loop(h, Sq, Yq, Vq)
+    got = out[cols].double().cpu().numpy()
+    err = rel_f(got, want)
+    corr = rel_f(got - h * Vq, want - h * Vq)
+    print(f"  sampled columns rel_F={err:.3e} correction={corr:.3e}", flush=True)
+    assert err <= TOL
+    assert H.get_status() == 0
+    H.close()
