@@ -161,6 +161,79 @@ __global__ void __launch_bounds__(64) small_solve(int k, int kmax, int c, const 
     if (bad) set_status(status, BFGS_ERR_NONFINITE);
 }
 
+// Same solve through the stored R^-1, for k <= 256: one workgroup per block of 8
+// probe columns, one thread per pair index.
+//   P = R^-1 Z_s;  W = (D + YHY) P - Z_y;  T = R^-T W
+constexpr int SB_COLS = 4;
+
+__global__ void __launch_bounds__(256) small_solve_blocks(int k, int kmax, int c, const double* __restrict__ Rm,
+                                                          const double* __restrict__ Rinv,
+                                                          const double* __restrict__ RinvT,
+                                                          const double* __restrict__ YHY, const double* __restrict__ Z,
+                                                          double* __restrict__ P, double* __restrict__ T,
+                                                          int32_t* __restrict__ status) {
+    __shared__ double a_sh[256][SB_COLS + 1];
+    __shared__ double b_sh[256][SB_COLS + 1];
+    const int i = threadIdx.x;
+    const int j0 = blockIdx.x * SB_COLS;
+    const int nj = min(SB_COLS, c - j0);
+    for (int e = threadIdx.x; e < k * SB_COLS; e += blockDim.x) {
+        const int l = e % k, jj = e / k;
+        a_sh[l][jj] = jj < nj ? Z[(int64_t)(j0 + jj) * 2 * k + l] : 0.0;
+        b_sh[l][jj] = jj < nj ? Z[(int64_t)(j0 + jj) * 2 * k + k + l] : 0.0;
+    }
+    __syncthreads();
+    double acc[SB_COLS];
+#pragma unroll
+    for (int jj = 0; jj < SB_COLS; ++jj) acc[jj] = 0.0;
+    if (i < k)
+#pragma unroll 8
+        for (int l = i; l < k; ++l) {
+            const double r = Rinv[(int64_t)l * kmax + i];
+#pragma unroll
+            for (int jj = 0; jj < SB_COLS; ++jj) acc[jj] = fma(r, a_sh[l][jj], acc[jj]);
+        }
+    __syncthreads();
+    if (i < k)
+#pragma unroll
+        for (int jj = 0; jj < SB_COLS; ++jj) a_sh[i][jj] = acc[jj];   // P
+    __syncthreads();
+    if (i < k) {
+        const double dii = Rm[(int64_t)i * kmax + i];
+#pragma unroll
+        for (int jj = 0; jj < SB_COLS; ++jj) acc[jj] = dii * a_sh[i][jj] - b_sh[i][jj];
+#pragma unroll 8
+        for (int l = 0; l < k; ++l) {
+            const double y = YHY[(int64_t)l * kmax + i];
+#pragma unroll
+            for (int jj = 0; jj < SB_COLS; ++jj) acc[jj] = fma(y, a_sh[l][jj], acc[jj]);
+        }
+    }
+    __syncthreads();
+    if (i < k)
+#pragma unroll
+        for (int jj = 0; jj < SB_COLS; ++jj) b_sh[i][jj] = acc[jj];   // W
+    __syncthreads();
+    bool bad = false;
+    if (i < k) {
+#pragma unroll
+        for (int jj = 0; jj < SB_COLS; ++jj) acc[jj] = 0.0;
+#pragma unroll 8
+        for (int l = 0; l <= i; ++l) {
+            const double r = RinvT[(int64_t)l * kmax + i];
+#pragma unroll
+            for (int jj = 0; jj < SB_COLS; ++jj) acc[jj] = fma(r, b_sh[l][jj], acc[jj]);
+        }
+        for (int jj = 0; jj < nj; ++jj) {
+            const double pv = a_sh[i][jj], tv = acc[jj];
+            P[(int64_t)(j0 + jj) * k + i] = pv;
+            T[(int64_t)(j0 + jj) * k + i] = tv;
+            bad |= !isfinite(pv) || !isfinite(tv);
+        }
+    }
+    if (bad) set_status(status, BFGS_ERR_NONFINITE);
+}
+
 constexpr int G2_TR = 64;   // output rows per tile
 constexpr int G2_TC = 64;   // output columns per tile
 constexpr int G2_TI = 16;   // pair index per LDS stage
@@ -291,8 +364,12 @@ int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
 int apply_small_solve(bfgsuq_ctx* h, int c, const double* Z, double* P, double* T) {
     ProfScope ps(h, "apply_solve");
     const int k = h->k;
-    hipLaunchKernelGGL(small_solve, dim3(c), dim3(64), 3 * k * sizeof(double), h->stream, k, h->kmax, c, h->Rm,
-                       h->YHY, Z, P, T, h->status);
+    if (k <= 256)
+        hipLaunchKernelGGL(small_solve_blocks, dim3(ceil_div(c, SB_COLS)), dim3(256), 0, h->stream, k, h->kmax, c,
+                           h->Rm, h->Rinv, h->RinvT, h->YHY, Z, P, T, h->status);
+    else
+        hipLaunchKernelGGL(small_solve, dim3(c), dim3(64), 3 * k * sizeof(double), h->stream, k, h->kmax, c, h->Rm,
+                           h->YHY, Z, P, T, h->status);
     return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
 }
 

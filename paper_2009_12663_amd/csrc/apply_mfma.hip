@@ -23,6 +23,7 @@
 //          otherwise lose 8 bits); the Y half is accumulated first, the
 //          accumulator is scaled by h0[row] (one per lane), then the S half
 //          is added: out = h0 o (V - Y P) + S T.
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
@@ -229,8 +230,14 @@ __global__ void reduce_z(int64_t count, int twok, int k, int nk, const float* __
                          const double* __restrict__ scalars, int gamma_mode, double* __restrict__ Z) {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= count) return;
-    double s = 0.0;
-    for (int q = 0; q < nk; ++q) s += (double)part[(int64_t)q * count + e];
+    // eight interleaved partial sums in a fixed order keep eight loads in flight
+    double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int q = 0;
+    for (; q + 8 <= nk; q += 8)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s8[u] += (double)part[(int64_t)(q + u) * count + e];
+    for (; q < nk; ++q) s8[0] += (double)part[(int64_t)q * count + e];
+    double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
     const int prow = (int)(e % twok);
     if (gamma_mode && prow >= k) s *= scalars[0];
     Z[e] = s;
@@ -265,15 +272,17 @@ __global__ void __launch_bounds__(512) gemm2_mfma(int64_t n, int c, int G, int G
                                                   const bf16_t* __restrict__ S2, const uint16_t* __restrict__ shi,
                                                   const uint16_t* __restrict__ slo, const float* __restrict__ h0,
                                                   const bf16_t* __restrict__ V, float* __restrict__ out) {
-    __shared__ uint16_t Sh[MT2 * 32 * SM_LD];
-    __shared__ uint16_t Sl[MT2 * 32 * SM_LD];
+    // LDS: two buffers of the staged small operand (hi, lo), [col][SM_LD]
+    extern __shared__ unsigned char smem_raw[];
+    constexpr int BUF = MT2 * 32 * SM_LD;
+    uint16_t* sm = (uint16_t*)smem_raw;   // buffer b: hi at sm + 2*b*BUF, lo at sm + (2*b+1)*BUF
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, half = lane >> 5;
     const int64_t row_base = (int64_t)blockIdx.x * G2_ROWS + wave * 32;
     const int64_t rb32 = row_base / 32;
     const int K2 = 2 * Gp * 16;
     const int nchunks = K2 / 32;
-    const int row_lane = (int)(row_base + (lane & 31) < n) ? 1 : 0;
-    const float h0r = row_lane ? h0[row_base + (lane & 31)] : 0.f;
+    const bool row_ok = row_base + (lane & 31) < n;
+    const float h0r = row_ok ? h0[row_base + (lane & 31)] : 0.f;
 
     floatx16 acc[MT2];
 #pragma unroll
@@ -283,32 +292,33 @@ __global__ void __launch_bounds__(512) gemm2_mfma(int64_t n, int c, int G, int G
 
     constexpr int SCH = MT2 * 32 * 4;        // 16-byte chunks of one array per staged chunk (<= 1024)
     uint4 sh0 = make_uint4(0, 0, 0, 0), sl0 = sh0, sh1 = sh0, sl1 = sh0;
-#define LOAD_SMALL(t)                                                                    \
-    {                                                                                    \
-        if (tid < SCH) {                                                                 \
-            const int64_t off = (int64_t)(tid >> 2) * K2 + (t) * 32 + (tid & 3) * 8;     \
-            sh0 = *(const uint4*)(shi + off);                                            \
-            sl0 = *(const uint4*)(slo + off);                                            \
-        }                                                                                \
-        if (tid + 512 < SCH) {                                                           \
-            const int64_t off = (int64_t)((tid + 512) >> 2) * K2 + (t) * 32 + (tid & 3) * 8; \
-            sh1 = *(const uint4*)(shi + off);                                            \
-            sl1 = *(const uint4*)(slo + off);                                            \
-        }                                                                                \
-    }
-#define STORE_SMALL()                                                                    \
-    {                                                                                    \
-        if (tid < SCH) {                                                                 \
-            *(uint4*)(Sh + (tid >> 2) * SM_LD + (tid & 3) * 8) = sh0;                    \
-            *(uint4*)(Sl + (tid >> 2) * SM_LD + (tid & 3) * 8) = sl0;                    \
-        }                                                                                \
-        if (tid + 512 < SCH) {                                                           \
-            *(uint4*)(Sh + ((tid + 512) >> 2) * SM_LD + (tid & 3) * 8) = sh1;            \
-            *(uint4*)(Sl + ((tid + 512) >> 2) * SM_LD + (tid & 3) * 8) = sl1;            \
-        }                                                                                \
-    }
+    auto load_small = [&](int t) {
+        if (tid < SCH) {
+            const int64_t off = (int64_t)(tid >> 2) * K2 + t * 32 + (tid & 3) * 8;
+            sh0 = *(const uint4*)(shi + off);
+            sl0 = *(const uint4*)(slo + off);
+        }
+        if (tid + 512 < SCH) {
+            const int64_t off = (int64_t)((tid + 512) >> 2) * K2 + t * 32 + (tid & 3) * 8;
+            sh1 = *(const uint4*)(shi + off);
+            sl1 = *(const uint4*)(slo + off);
+        }
+    };
+    auto store_small = [&](int b) {
+        uint16_t* H = sm + 2 * b * BUF;
+        uint16_t* L = H + BUF;
+        if (tid < SCH) {
+            *(uint4*)(H + (tid >> 2) * SM_LD + (tid & 3) * 8) = sh0;
+            *(uint4*)(L + (tid >> 2) * SM_LD + (tid & 3) * 8) = sl0;
+        }
+        if (tid + 512 < SCH) {
+            *(uint4*)(H + ((tid + 512) >> 2) * SM_LD + (tid & 3) * 8) = sh1;
+            *(uint4*)(L + ((tid + 512) >> 2) * SM_LD + (tid & 3) * 8) = sl1;
+        }
+    };
     auto load_b = [&](int t, int sg) -> uint4 {
         const int gq = 2 * t + sg;
+        if (t >= nchunks) return make_uint4(0, 0, 0, 0);
         const int phase = gq >= Gp ? 1 : 0;
         const int grp = gq - phase * Gp;
         if (grp >= G) return make_uint4(0, 0, 0, 0);
@@ -316,49 +326,100 @@ __global__ void __launch_bounds__(512) gemm2_mfma(int64_t n, int c, int G, int G
         return *(const uint4*)(W + rb32 * (int64_t)G * 512 + (int64_t)grp * 512 + (lane & 31) * 16 + half * 8);
     };
 
-    LOAD_SMALL(0);
-    uint4 bnext0 = load_b(0, 0), bnext1 = load_b(0, 1);
-    for (int t = 0; t < nchunks; ++t) {
-        __syncthreads();
-        STORE_SMALL();
-        __syncthreads();
-        const uint4 b0 = bnext0, b1 = bnext1;
-        if (t + 1 < nchunks) {
-            LOAD_SMALL(t + 1);
-            bnext0 = load_b(t + 1, 0);
-            bnext1 = load_b(t + 1, 1);
-        }
+    // W fragments run DEPTH chunks ahead of the MFMAs.
+    constexpr int DEPTH = MT2 >= 8 ? 3 : 4;
+    uint4 bq0[DEPTH], bq1[DEPTH];
 #pragma unroll
-        for (int sg = 0; sg < 2; ++sg) {
-            const bf16x8 b = as_bf16x8(sg ? b1 : b0);
+    for (int d = 0; d < DEPTH; ++d) {
+        bq0[d] = load_b(d, 0);
+        bq1[d] = load_b(d, 1);
+    }
+    load_small(0);
+    store_small(0);
+    if (nchunks > 1) load_small(1);
+    __syncthreads();
+    for (int t0 = 0; t0 < nchunks; t0 += DEPTH) {
 #pragma unroll
-            for (int m = 0; m < MT2; ++m) {
-                const int off = (m * 32 + (lane & 31)) * SM_LD + sg * 16 + half * 8;
-                acc[m] = mfma32(as_bf16x8(*(const uint4*)(Sh + off)), b, acc[m]);
-                acc[m] = mfma32(as_bf16x8(*(const uint4*)(Sl + off)), b, acc[m]);
+        for (int d = 0; d < DEPTH; ++d) {
+            const int t = t0 + d;
+            if (t < nchunks) {
+                const int buf = t & 1;
+                if (t + 1 < nchunks) store_small(buf ^ 1);
+                if (t + 2 < nchunks) load_small(t + 2);
+                const uint4 b0 = bq0[d], b1 = bq1[d];
+                bq0[d] = load_b(t + DEPTH, 0);
+                bq1[d] = load_b(t + DEPTH, 1);
+                const uint16_t* H = sm + 2 * buf * BUF;
+                const uint16_t* L = H + BUF;
+#pragma unroll
+                for (int sg = 0; sg < 2; ++sg) {
+                    const bf16x8 b = as_bf16x8(sg ? b1 : b0);
+#pragma unroll
+                    for (int m = 0; m < MT2; ++m) {
+                        const int off = (m * 32 + (lane & 31)) * SM_LD + sg * 16 + half * 8;
+                        acc[m] = mfma32(as_bf16x8(*(const uint4*)(H + off)), b, acc[m]);
+                        acc[m] = mfma32(as_bf16x8(*(const uint4*)(L + off)), b, acc[m]);
+                    }
+                }
+                if (2 * t + 2 == Gp) {
+                    // end of the Y phase: acc holds -(Y P)^T for this lane's row; scale by h0[row]
+#pragma unroll
+                    for (int m = 0; m < MT2; ++m)
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) acc[m][i] *= h0r;
+                }
+                __syncthreads();
             }
         }
-        if (2 * t + 2 == Gp) {
-            // end of the Y phase: acc holds -(Y P)^T for this lane's row; scale by h0[row]
-#pragma unroll
-            for (int m = 0; m < MT2; ++m)
-#pragma unroll
-                for (int i = 0; i < 16; ++i) acc[m][i] *= h0r;
-        }
     }
-#undef LOAD_SMALL
-#undef STORE_SMALL
-    if (!row_lane) return;
     const int64_t row = row_base + (lane & 31);
+    if (!DIFF) {
+        // V tile of this wave (32 columns x 32 rows per column tile) through LDS: each
+        // column's 32 rows are one 64-byte load (4 lanes x 16 bytes), then every lane
+        // reads its own row.  The small-operand buffers are free by now (last barrier).
+        uint16_t* vt = sm + wave * (32 * 40);             // [col][40] per wave, 2.5 KB
+        const bool vec_ok = (n % 8) == 0 && (((uintptr_t)V) & 15) == 0;
 #pragma unroll
-    for (int m = 0; m < MT2; ++m) {
+        for (int m = 0; m < MT2; ++m) {
+            // lane -> (column q = lane / 4 + 16 * u, 8-row chunk lane % 4); two passes cover 32 columns
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int col = m * 32 + 8 * (i / 4) + 4 * half + (i % 4);
-            if (col < c) {
-                float o = acc[m][i];
-                if (!DIFF) o += h0r * bf16_to_float(V[(int64_t)col * n + row]);
-                out[(int64_t)col * n + row] = o;
+            for (int u = 0; u < 2; ++u) {
+                const int q = (lane >> 2) + 16 * u, ch = lane & 3;
+                const int col = m * 32 + q;
+                const int64_t r = row_base + ch * 8;
+                uint4 val = make_uint4(0, 0, 0, 0);
+                if (col < c && r < n) {
+                    const bf16_t* src = V + (int64_t)col * n + r;
+                    if (vec_ok && r + 8 <= n) {
+                        val = *(const uint4*)src;
+                    } else {
+                        u16x8 t;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) t.v[e] = (r + e < n) ? src[e].bits : (uint16_t)0;
+                        val = __builtin_bit_cast(uint4, t);
+                    }
+                }
+                *(uint4*)(vt + q * 40 + ch * 8) = val;
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_s_waitcnt(0);
+            if (row_ok) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int cl = 8 * (i / 4) + 4 * half + (i % 4);
+                    const int col = m * 32 + cl;
+                    if (col < c) out[(int64_t)col * n + row] = acc[m][i] + h0r * bits_to_f32(vt[cl * 40 + (lane & 31)]);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    } else if (row_ok) {
+#pragma unroll
+        for (int m = 0; m < MT2; ++m) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int col = m * 32 + 8 * (i / 4) + 4 * half + (i % 4);
+                if (col < c) out[(int64_t)col * n + row] = acc[m][i];
             }
         }
     }
@@ -395,7 +456,16 @@ g1_fn pick_g1(int NT, bool diag) {
 template <int MT2, bool DIFF>
 void launch_g2(int grid, hipStream_t st, int64_t n, int c, int G, int Gp, const bf16_t* Y2, const bf16_t* S2,
                const uint16_t* shi, const uint16_t* slo, const float* h0, const bf16_t* V, float* out) {
-    hipLaunchKernelGGL((gemm2_mfma<MT2, DIFF>), dim3(grid), dim3(512), 0, st, n, c, G, Gp, Y2, S2, shi, slo, h0, V, out);
+    // small-operand double buffer, reused by the epilogue for 8 per-wave V tiles of 32 x 40
+    const size_t smem = std::max((size_t)4 * MT2 * 32 * SM_LD, (size_t)8 * 32 * 40) * sizeof(uint16_t);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)gemm2_mfma<MT2, DIFF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)smem);
+        attr = true;
+    }
+    hipLaunchKernelGGL((gemm2_mfma<MT2, DIFF>), dim3(grid), dim3(512), smem, st, n, c, G, Gp, Y2, S2, shi, slo, h0, V,
+                       out);
 }
 
 typedef void (*g2_fn)(int, hipStream_t, int64_t, int, int, int, const bf16_t*, const bf16_t*, const uint16_t*,

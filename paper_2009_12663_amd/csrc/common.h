@@ -97,6 +97,8 @@ struct bfgsuq_ctx {
     void* h0 = nullptr;        // n, storage-real type (double for F64, float otherwise)
     double* Rm = nullptr;      // kmax x kmax column-major: Rm[j*kmax + i] = s_i^T y_j
     double* YHY = nullptr;     // kmax x kmax symmetric: y_i^T B_0 y_j
+    double* Rinv = nullptr;    // kmax x kmax column-major: inverse of the upper triangle of Rm
+    double* RinvT = nullptr;   // its transpose, column-major (RinvT[l * kmax + i] = Rinv(l, i))
     double* gram_part = nullptr;   // partial sums for push
     double* scalars = nullptr; // [0] = gamma, [1] = last s^T y, [2] = last y^T y
     int32_t* status = nullptr; // deferred device status (0 = OK)

@@ -151,6 +151,25 @@ __global__ void gram_finish_kernel(int j, int kmax, int nb, const double* __rest
     }
 }
 
+// Column j of R^-1 for the upper-triangular R = triu(S^T Y), by the column
+// recurrence R^-1(0:j, j) = -R^-1(0:j, 0:j) R(0:j, j) / R(j, j).
+__global__ void rinv_update_kernel(int j, int kmax, const double* __restrict__ Rm, double* __restrict__ Rinv,
+                                   double* __restrict__ RinvT) {
+    const double rjj = Rm[(int64_t)j * kmax + j];
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        double v;
+        if (i == j) {
+            v = 1.0 / rjj;
+        } else {
+            double s = 0.0;
+            for (int l = i; l < j; ++l) s = fma(Rinv[(int64_t)l * kmax + i], Rm[(int64_t)j * kmax + l], s);
+            v = -s / rjj;
+        }
+        Rinv[(int64_t)j * kmax + i] = v;
+        RinvT[(int64_t)i * kmax + j] = v;
+    }
+}
+
 template <typename Th>
 __global__ void fill_h0_kernel(int64_t n, Th* __restrict__ h0, const double* __restrict__ scalars) {
     const double g = scalars[0];
@@ -207,7 +226,7 @@ const char* bfgs_status_string(int code) {
 int bfgs_destroy(bfgs_t h) {
     if (!h) return BFGS_OK;
     (void)hipStreamSynchronize(h->stream);
-    void* ptrs[] = {h->S, h->Y, h->h0, h->Rm, h->YHY, h->gram_part, h->scalars, h->status,
+    void* ptrs[] = {h->S, h->Y, h->h0, h->Rm, h->YHY, h->Rinv, h->RinvT, h->gram_part, h->scalars, h->status,
                     h->S1, h->Y1, h->S2, h->Y2};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -248,6 +267,8 @@ int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, vo
     alloc(&h->h0, (size_t)h->ld * hs);
     alloc((void**)&h->Rm, (size_t)k_max * k_max * 8);
     alloc((void**)&h->YHY, (size_t)k_max * k_max * 8);
+    alloc((void**)&h->Rinv, (size_t)k_max * k_max * 8);
+    alloc((void**)&h->RinvT, (size_t)k_max * k_max * 8);
     alloc((void**)&h->gram_part, (size_t)k_max * h->gram_blocks * 2 * 8);
     alloc((void**)&h->scalars, 8 * 8);
     alloc((void**)&h->status, 64);
@@ -269,6 +290,8 @@ int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, vo
         hipMemsetAsync(h->h0, 0, (size_t)h->ld * hs, h->stream) != hipSuccess ||
         hipMemsetAsync(h->Rm, 0, (size_t)k_max * k_max * 8, h->stream) != hipSuccess ||
         hipMemsetAsync(h->YHY, 0, (size_t)k_max * k_max * 8, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->Rinv, 0, (size_t)k_max * k_max * 8, h->stream) != hipSuccess ||
+        hipMemsetAsync(h->RinvT, 0, (size_t)k_max * k_max * 8, h->stream) != hipSuccess ||
         hipMemsetAsync(h->scalars, 0, 64, h->stream) != hipSuccess ||
         hipMemsetAsync(h->status, 0, 64, h->stream) != hipSuccess ||
         (f1_bytes && (hipMemsetAsync(h->S1, 0, f1_bytes, h->stream) != hipSuccess ||
@@ -324,6 +347,8 @@ int bfgs_push_pair(bfgs_t h, const void* s, const void* y, bfgs_dtype in_dtype) 
     BFGS_HIP(hipGetLastError());
     hipLaunchKernelGGL(gram_finish_kernel, dim3((j + 1 + 255) / 256), dim3(256), 0, h->stream, j, h->kmax,
                        h->gram_blocks, h->gram_part, h->Rm, h->YHY, h->scalars, h->gamma_mode ? 1 : 0);
+    BFGS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(rinv_update_kernel, dim3(1), dim3(256), 0, h->stream, j, h->kmax, h->Rm, h->Rinv, h->RinvT);
     BFGS_HIP(hipGetLastError());
     double sc[3];
     BFGS_HIP(hipMemcpyAsync(sc, h->scalars, sizeof(sc), hipMemcpyDeviceToHost, h->stream));
