@@ -41,6 +41,21 @@ __device__ __forceinline__ int tri_index(int j, int col, int c) {
     return j * c - (j * (j - 1)) / 2 + (col - j);
 }
 
+// Dot products over a tile with eight independent partial sums (short dependency chains).
+__device__ __forceinline__ double dot_tile(const double (&x)[TR], const double (&y)[TR]) {
+    double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < TR; ++t) p[t & 7] = fma(x[t], y[t], p[t & 7]);
+    return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+}
+
+__device__ __forceinline__ double dot_tile_sh(const double* v, const double (&y)[TR]) {
+    double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < TR; ++t) p[t & 7] = fma(v[t], y[t], p[t & 7]);
+    return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+}
+
 // Forward: fold TR tile rows (a[] of this thread's column) into the slot.
 // Reflector j's tile part replaces a[] in thread j; taus[j] receives tau.
 template <typename SlotT>
@@ -50,9 +65,7 @@ __device__ __forceinline__ void fold_tile(SlotT* slot, double (&a)[TR], int c, i
     for (int j = jstart; j < c; ++j) {
         if (col == j) {
             const double rjj = (double)slot[tri_index(j, j, c)];
-            double xn2 = 0.0;
-#pragma unroll
-            for (int t = 0; t < TR; ++t) xn2 = fma(a[t], a[t], xn2);
+            const double xn2 = dot_tile(a, a);
             double tau = 0.0;
             if (xn2 > 0.0) {
                 const double beta = -copysign(sqrt(fma(rjj, rjj, xn2)), rjj);
@@ -70,9 +83,7 @@ __device__ __forceinline__ void fold_tile(SlotT* slot, double (&a)[TR], int c, i
         __syncthreads();
         const double tau = *tau_sh;
         if (col > j && col < c && tau != 0.0) {
-            double w = (double)slot[tri_index(j, col, c)];
-#pragma unroll
-            for (int t = 0; t < TR; ++t) w = fma(vbuf[t], a[t], w);
+            double w = (double)slot[tri_index(j, col, c)] + dot_tile_sh(vbuf, a);
             w *= tau;
             slot[tri_index(j, col, c)] = (SlotT)((double)slot[tri_index(j, col, c)] - w);
 #pragma unroll
@@ -95,9 +106,7 @@ __device__ __forceinline__ void unfold_tile(SlotT* slot, double (&a)[TR], int c,
             vbuf[t] = t < rows_valid ? refl_rows[(int64_t)t * ld_refl + j] : 0.0;
         __syncthreads();
         if (col >= j && col < c) {
-            double w = (double)slot[tri_index(j, col, c)];
-#pragma unroll
-            for (int t = 0; t < TR; ++t) w = fma(vbuf[t], a[t], w);
+            double w = (double)slot[tri_index(j, col, c)] + dot_tile_sh(vbuf, a);
             w *= tau;
             slot[tri_index(j, col, c)] = (SlotT)((double)slot[tri_index(j, col, c)] - w);
 #pragma unroll
@@ -289,44 +298,59 @@ __global__ void set_identity(double* __restrict__ M, int c) {
 // ---------------------------------------------------------------------------
 constexpr int TN_T = 64, TN_R = 32;
 
+// c x 128 column block of A^T B for one row chunk: 512 threads as a 32 x 16 grid,
+// each owning an 8 x 8 block of outputs (i = ty + 32 u, j = j0 + tx + 16 v),
+// rows staged through LDS 16 at a time.  grid = (chunks, ceil(c / 128)).
+constexpr int FT_ROWS = 16;
+
 template <typename TA, typename TB>
-__global__ void __launch_bounds__(256) gemm_tn_partial(int64_t n, int m1, int m2, const TA* __restrict__ A,
-                                                       const TB* __restrict__ B, double* __restrict__ part,
-                                                       int64_t rows_per_chunk) {
-    __shared__ double As[TN_R][TN_T + 1];
-    __shared__ double Bs[TN_R][TN_T + 1];
+__global__ void __launch_bounds__(512) gemm_tn_full(int64_t n, int c, const TA* __restrict__ A,
+                                                    const TB* __restrict__ B, double* __restrict__ part,
+                                                    int64_t rows_per_chunk) {
+    __shared__ double As[FT_ROWS][256 + 1];
+    __shared__ double Bs[FT_ROWS][128 + 1];
     const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-    const int i0 = blockIdx.x * TN_T, j0 = blockIdx.y * TN_T, chunk = blockIdx.z;
+    const int chunk = blockIdx.x, j0 = blockIdx.y * 128;
     const int64_t rb = chunk * rows_per_chunk, re = min(n, rb + rows_per_chunk);
-    double acc[4][4] = {};
-    for (int64_t r0 = rb; r0 < re; r0 += TN_R) {
-        for (int e = tid; e < TN_R * TN_T; e += 256) {
-            const int rr = e % TN_R, cc = e / TN_R;
+    double acc[8][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[u][v] = 0.0;
+    for (int64_t r0 = rb; r0 < re; r0 += FT_ROWS) {
+        for (int e = tid; e < FT_ROWS * 256; e += 512) {
+            const int rr = e % FT_ROWS, cc = e / FT_ROWS;
             const int64_t r = r0 + rr;
-            As[rr][cc] = (r < re && i0 + cc < m1) ? to_f64(A[(int64_t)(i0 + cc) * n + r]) : 0.0;
-            Bs[rr][cc] = (r < re && j0 + cc < m2) ? to_f64(B[(int64_t)(j0 + cc) * n + r]) : 0.0;
+            As[rr][cc] = (r < re && cc < c) ? to_f64(A[(int64_t)cc * n + r]) : 0.0;
+        }
+        for (int e = tid; e < FT_ROWS * 128; e += 512) {
+            const int rr = e % FT_ROWS, cc = e / FT_ROWS;
+            const int64_t r = r0 + rr;
+            Bs[rr][cc] = (r < re && j0 + cc < c) ? to_f64(B[(int64_t)(j0 + cc) * n + r]) : 0.0;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int rr = 0; rr < TN_R; ++rr) {
-            double a[4], b[4];
+#pragma unroll 2
+        for (int rr = 0; rr < FT_ROWS; ++rr) {
+            double a[8], b[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = As[rr][ty * 4 + u];
-                b[u] = Bs[rr][tx * 4 + u];
+            for (int u = 0; u < 8; ++u) {
+                a[u] = As[rr][ty + 32 * u];
+                b[u] = Bs[rr][tx + 16 * u];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 8; ++u)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+                for (int v = 0; v < 8; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
         }
         __syncthreads();
     }
-    double* dst = part + (int64_t)chunk * m1 * m2;
-    for (int u = 0; u < 4; ++u)
-        for (int v = 0; v < 4; ++v) {
-            const int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
-            if (i < m1 && j < m2) dst[(int64_t)j * m1 + i] = acc[u][v];   // column-major m1 x m2
+    double* dst = part + (int64_t)chunk * c * c;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int i = ty + 32 * u, j = j0 + tx + 16 * v;
+            if (i < c && j < c) dst[(int64_t)j * c + i] = acc[u][v];
         }
 }
 
@@ -343,6 +367,17 @@ __global__ void sum_chunks(int64_t count, int nchunks, const double* __restrict_
 // memory (at most 256 x 256 doubles, cache resident).
 // ---------------------------------------------------------------------------
 constexpr int SMALL_THREADS = 256;
+
+// sum_l x[l] * y[l] with eight independent partial sums
+__device__ __forceinline__ double dot8(const double* x, const double* y, int m) {
+    double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int l = 0;
+    for (; l + 8 <= m; l += 8)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p[u] = fma(x[l + u], y[l + u], p[u]);
+    for (; l < m; ++l) p[0] = fma(x[l], y[l], p[0]);
+    return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+}
 
 __device__ double wg_sum(double v, double* red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -364,6 +399,7 @@ __global__ void __launch_bounds__(SMALL_THREADS) omega_solve(int c, double* __re
                                                              int* __restrict__ piv, int32_t* __restrict__ status) {
     __shared__ double red_v[SMALL_THREADS];
     __shared__ int red_i[SMALL_THREADS];
+    __shared__ double lcol[256], urow[256];
     __shared__ int bad;
     const int tid = threadIdx.x;
     if (tid == 0) bad = 0;
@@ -412,28 +448,34 @@ __global__ void __launch_bounds__(SMALL_THREADS) omega_solve(int c, double* __re
         }
         __syncthreads();
         const double d = M[(int64_t)kk * c + kk];
-        if (d != 0.0) {
-            for (int i = kk + 1 + tid; i < c; i += SMALL_THREADS) M[(int64_t)i * c + kk] /= d;
+        for (int i = kk + 1 + tid; i < c; i += SMALL_THREADS) {
+            const double l = d != 0.0 ? M[(int64_t)i * c + kk] / d : 0.0;
+            M[(int64_t)i * c + kk] = l;
+            lcol[i] = l;
         }
+        for (int j = kk + 1 + tid; j < c; j += SMALL_THREADS) urow[j] = M[(int64_t)kk * c + j];
         __syncthreads();
         const int m = c - kk - 1;
         for (int e = tid; e < m * m; e += SMALL_THREADS) {
             const int i = kk + 1 + e / m, j = kk + 1 + e % m;
-            M[(int64_t)i * c + j] -= M[(int64_t)i * c + kk] * M[(int64_t)kk * c + j];
+            M[(int64_t)i * c + j] -= lcol[i] * urow[j];
         }
         __syncthreads();
     }
     // forward (unit lower) then backward (upper) substitution, one right-hand side per thread
     for (int j = tid; j < c; j += SMALL_THREADS) {
         for (int i = 0; i < c; ++i) {
-            double s = B[(int64_t)i * c + j];
-            for (int l = 0; l < i; ++l) s -= M[(int64_t)i * c + l] * B[(int64_t)l * c + j];
-            B[(int64_t)i * c + j] = s;
+            double p8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            const double* mr = M + (int64_t)i * c;
+            for (int l = 0; l < i; ++l) p8[l & 7] = fma(mr[l], B[(int64_t)l * c + j], p8[l & 7]);
+            B[(int64_t)i * c + j] -= ((p8[0] + p8[1]) + (p8[2] + p8[3])) + ((p8[4] + p8[5]) + (p8[6] + p8[7]));
         }
         for (int i = c - 1; i >= 0; --i) {
-            double s = B[(int64_t)i * c + j];
-            for (int l = i + 1; l < c; ++l) s -= M[(int64_t)i * c + l] * B[(int64_t)l * c + j];
-            B[(int64_t)i * c + j] = s / M[(int64_t)i * c + i];
+            double p8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            const double* mr = M + (int64_t)i * c;
+            for (int l = i + 1; l < c; ++l) p8[l & 7] = fma(mr[l], B[(int64_t)l * c + j], p8[l & 7]);
+            const double sum = ((p8[0] + p8[1]) + (p8[2] + p8[3])) + ((p8[4] + p8[5]) + (p8[6] + p8[7]));
+            B[(int64_t)i * c + j] = (B[(int64_t)i * c + j] - sum) / mr[i];
         }
     }
     __syncthreads();
@@ -454,16 +496,15 @@ __global__ void __launch_bounds__(SMALL_THREADS) omega_solve(int c, double* __re
 // applied to the rows of the eigenvector matrix in parallel.
 // Z: column-major c x c eigenvectors (Z[i*c + r] = component r of vector i).
 __global__ void __launch_bounds__(SMALL_THREADS) sym_eig(int c, double* __restrict__ A, double* __restrict__ Z,
-                                                         double* __restrict__ d, double* __restrict__ e,
+                                                         double* __restrict__ dg, double* __restrict__ eg,
                                                          double* __restrict__ taus, double* __restrict__ rot,
+                                                         int* __restrict__ sweeps, int* __restrict__ nsweeps_out,
+                                                         int64_t max_rot, int max_sweeps,
                                                          int32_t* __restrict__ status) {
     __shared__ double red[SMALL_THREADS / 64];
     __shared__ double vsh[256];
     __shared__ double wsh[256];
-    __shared__ int sh_m, sh_fail;
-    __shared__ double sh_k;
     const int tid = threadIdx.x;
-    if (tid == 0) sh_fail = 0;
     // --- tridiagonalisation: for column kk, reflect rows kk+1..c-1 ---
     for (int kk = 0; kk + 2 < c; ++kk) {
         const int m = c - kk - 1;   // length of x = A(kk+1:, kk)
@@ -485,18 +526,16 @@ __global__ void __launch_bounds__(SMALL_THREADS) sym_eig(int c, double* __restri
         __syncthreads();
         if (tid == 0) {
             taus[kk] = tau;
-            d[kk] = A[(int64_t)kk * c + kk];
-            e[kk] = beta;
+            dg[kk] = A[(int64_t)kk * c + kk];
+            eg[kk] = beta;
         }
         // keep v below the subdiagonal for the accumulation step
         for (int i = 1 + tid; i < m; i += SMALL_THREADS) A[(int64_t)(kk + 1 + i) * c + kk] = vsh[i];
         if (tau != 0.0) {
             // p = tau * A22 v
             for (int i = tid; i < m; i += SMALL_THREADS) {
-                double s = 0.0;
                 const double* row = A + (int64_t)(kk + 1 + i) * c + (kk + 1);
-                for (int l = 0; l < m; ++l) s = fma(row[l], vsh[l], s);
-                wsh[i] = tau * s;
+                wsh[i] = tau * dot8(row, vsh, m);
             }
             __syncthreads();
             double pp = 0.0;
@@ -513,11 +552,11 @@ __global__ void __launch_bounds__(SMALL_THREADS) sym_eig(int c, double* __restri
     }
     if (tid == 0) {
         if (c >= 2) {
-            d[c - 2] = A[(int64_t)(c - 2) * c + (c - 2)];
-            e[c - 2] = A[(int64_t)(c - 1) * c + (c - 2)];
+            dg[c - 2] = A[(int64_t)(c - 2) * c + (c - 2)];
+            eg[c - 2] = A[(int64_t)(c - 1) * c + (c - 2)];
         }
-        d[c - 1] = A[(int64_t)(c - 1) * c + (c - 1)];
-        e[c - 1] = 0.0;
+        dg[c - 1] = A[(int64_t)(c - 1) * c + (c - 1)];
+        eg[c - 1] = 0.0;
         if (c >= 2) taus[c - 2] = 0.0;
     }
     // --- accumulate the orthogonal factor: Z = H_0 H_1 ... (column-major) ---
@@ -532,95 +571,116 @@ __global__ void __launch_bounds__(SMALL_THREADS) sym_eig(int c, double* __restri
         // columns kk+1.. of Z, rows kk+1..: Z_sub -= tau v (v^T Z_sub)
         for (int col = kk + 1 + tid; col < c; col += SMALL_THREADS) {
             double* zc = Z + (int64_t)col * c + (kk + 1);
-            double s = 0.0;
-            for (int i = 0; i < m; ++i) s = fma(vsh[i], zc[i], s);
-            s *= tau;
+            const double s = tau * dot8(zc, vsh, m);
             for (int i = 0; i < m; ++i) zc[i] -= s * vsh[i];
         }
         __syncthreads();
     }
-    // --- implicit QL on (d, e): e[i] couples d[i] and d[i+1] ---
-    for (int l = 0; l < c; ++l) {
-        int iter = 0;
-        while (true) {
-            if (tid == 0) {
+    // --- implicit QL on (d, e): e[i] couples d[i] and d[i+1].  Thread 0 runs the
+    // iteration and records every sweep's rotations (sweep q: rows l..m, angles at
+    // rot[2 * (off + i - l)] for i = m-1 .. l); apply_rotations applies them to Z. ---
+    __syncthreads();
+    // QL iterations on LDS copies of d and e (every access below is on the dependent chain)
+    __shared__ double dl[256], el[256];
+    for (int i = tid; i < c; i += SMALL_THREADS) {
+        dl[i] = dg[i];
+        el[i] = eg[i];
+    }
+    __syncthreads();
+    double* d = dl;
+    double* e = el;
+    if (tid == 0) {
+        int nsw = 0;
+        int64_t off = 0;
+        int fail = 0;
+        for (int l = 0; l < c && !fail; ++l) {
+            int iter = 0;
+            while (true) {
                 int m = l;
                 for (; m < c - 1; ++m) {
                     const double dd = fabs(d[m]) + fabs(d[m + 1]);
                     if (fabs(e[m]) + dd == dd) break;
                 }
-                sh_m = m;
-            }
-            __syncthreads();
-            const int m = sh_m;
-            __syncthreads();
-            if (m == l) break;
-            if (++iter > 60) {
-                if (tid == 0) sh_fail = 1;
-                break;
-            }
-            const int nrot = m - l;
-            if (tid == 0) {
+                if (m == l) break;
+                if (++iter > 60 || nsw >= max_sweeps || off + (m - l) > max_rot) {
+                    fail = 1;
+                    break;
+                }
                 double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-                double r = hypot(g, 1.0);
+                double r = sqrt(fma(g, g, 1.0));
                 g = d[m] - d[l] + e[l] / (g + copysign(r, g));
-                double s = 1.0, cc = 1.0, p = 0.0;
-                int i;
+                double sn = 1.0, cs = 1.0, p = 0.0;
                 bool early = false;
-                for (i = m - 1; i >= l; --i) {
-                    double f = s * e[i];
-                    const double b = cc * e[i];
-                    r = hypot(f, g);
+                for (int i = m - 1; i >= l; --i) {
+                    const double f = sn * e[i];
+                    const double b = cs * e[i];
+                    r = sqrt(fma(f, f, g * g));
                     e[i + 1] = r;
+                    double* rr = rot + 2 * (off + (i - l));
                     if (r == 0.0) {
                         d[i + 1] -= p;
                         e[m] = 0.0;
                         early = true;
-                        // mark the remaining rotations as identity
                         for (int q = i; q >= l; --q) {
-                            rot[2 * (q - l)] = 1.0;
-                            rot[2 * (q - l) + 1] = 0.0;
+                            rot[2 * (off + (q - l))] = 1.0;
+                            rot[2 * (off + (q - l)) + 1] = 0.0;
                         }
                         break;
                     }
-                    s = f / r;
-                    cc = g / r;
+                    const double ri = 1.0 / r;
+                    sn = f * ri;
+                    cs = g * ri;
                     g = d[i + 1] - p;
-                    r = (d[i] - g) * s + 2.0 * cc * b;
-                    p = s * r;
+                    r = (d[i] - g) * sn + 2.0 * cs * b;
+                    p = sn * r;
                     d[i + 1] = g + p;
-                    g = cc * r - b;
-                    rot[2 * (i - l)] = cc;
-                    rot[2 * (i - l) + 1] = s;
+                    g = cs * r - b;
+                    rr[0] = cs;
+                    rr[1] = sn;
                 }
                 if (!early) {
                     d[l] -= p;
                     e[l] = g;
                     e[m] = 0.0;
                 }
+                sweeps[3 * nsw + 0] = l;
+                sweeps[3 * nsw + 1] = m;
+                sweeps[3 * nsw + 2] = (int)off;
+                ++nsw;
+                off += m - l;
             }
-            __syncthreads();
-            // apply rotations i = m-1 .. l to columns (i, i+1) of Z, one row per thread
-            for (int r = tid; r < c; r += SMALL_THREADS) {
-                for (int i = m - 1; i >= l; --i) {
-                    const double cc = rot[2 * (i - l)], s = rot[2 * (i - l) + 1];
-                    double* zi = Z + (int64_t)i * c + r;
-                    double* zi1 = Z + (int64_t)(i + 1) * c + r;
-                    const double f = *zi1;
-                    *zi1 = s * (*zi) + cc * f;
-                    *zi = cc * (*zi) - s * f;
-                }
-            }
-            __syncthreads();
-            (void)nrot;
         }
-        __syncthreads();
-        const int failed = sh_fail;
-        __syncthreads();
-        if (failed) break;
+        nsweeps_out[0] = nsw;
+        if (fail) set_status(status, BFGS_ERR_NUMERIC);
     }
     __syncthreads();
-    if (tid == 0 && sh_fail) set_status(status, BFGS_ERR_NUMERIC);
+    for (int i = tid; i < c; i += SMALL_THREADS) dg[i] = dl[i];
+}
+
+// Applies the recorded QL rotations to the rows of Z (column-major c x c); one
+// 64-lane workgroup per 64 rows, rows resident in LDS ([i][lane] layout).  A
+// sweep's rotations form a chain through the shared column, carried in a register.
+__global__ void __launch_bounds__(64) apply_rotations(int c, const int* __restrict__ nsweeps_p,
+                                                      const int* __restrict__ sweeps, const double* __restrict__ rot,
+                                                      double* __restrict__ Z) {
+    extern __shared__ double zr[];   // [c][64]
+    const int lane = threadIdx.x;
+    const int r = blockIdx.x * 64 + lane;
+    for (int i = 0; i < c; ++i) zr[i * 64 + lane] = r < c ? Z[(int64_t)i * c + r] : 0.0;
+    const int nsw = nsweeps_p[0];
+    for (int q = 0; q < nsw; ++q) {
+        const int l = sweeps[3 * q], m = sweeps[3 * q + 1], off = sweeps[3 * q + 2];
+        double carry = zr[m * 64 + lane];
+        for (int i = m - 1; i >= l; --i) {
+            const double cs = rot[2 * (off + (i - l))], sn = rot[2 * (off + (i - l)) + 1];
+            const double zi = zr[i * 64 + lane];
+            zr[(i + 1) * 64 + lane] = sn * zi + cs * carry;
+            carry = cs * zi - sn * carry;
+        }
+        zr[l * 64 + lane] = carry;
+    }
+    if (r < c)
+        for (int i = 0; i < c; ++i) Z[(int64_t)i * c + r] = zr[i * 64 + lane];
 }
 
 // Order eigenpairs by |lambda| descending (ties: lambda descending, then index),
@@ -825,6 +885,12 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     const size_t cc = (size_t)c * c;
     if ((rc = ensure_ws(h->small, ((size_t)nchunks * cc + 8 * cc + 6 * (size_t)c) * 8 + (size_t)c * 4)) != BFGS_OK)
         return rc;
+    const int max_sweeps = 64 * c;
+    const int64_t max_rot = (int64_t)32 * c * c;
+    if ((rc = ensure_ws(h->lam, (size_t)max_rot * 2 * 8 + (size_t)(3 * max_sweeps + 4) * 4)) != BFGS_OK) return rc;
+    double* rotbuf = (double*)h->lam.ptr;
+    int* sweeps = (int*)(rotbuf + 2 * max_rot);
+    int* nsweeps = sweeps + 3 * max_sweeps;
     double* part = (double*)h->small.ptr;
     double* Tm = part + (size_t)nchunks * cc;
     double* Bm = Tm + cc;
@@ -865,8 +931,15 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
         R = Fm;
     }
     ProfScope ps(h, "proj_QtX");
-    hipLaunchKernelGGL((gemm_tn_partial<TO, TS>), dim3(ctiles, ctiles, nchunks), dim3(256), 0, h->stream, n, c, c, Q, X,
-                       part, rows_per_chunk);
+    {
+        // one workgroup per row chunk (about 512 chunks), each reading its rows of Q and X once
+        const int nfull = (int)std::min<int64_t>(nchunks, 512);
+        const int64_t rpc = round_up((n + nfull - 1) / nfull, FT_ROWS);
+        const int nf = (int)((n + rpc - 1) / rpc);
+        hipLaunchKernelGGL((gemm_tn_full<TO, TS>), dim3(nf, ceil_div(c, 128)), dim3(512), 0, h->stream, n, c, Q, X,
+                           part, rpc);
+        nchunks = nf;
+    }
     hipLaunchKernelGGL(sum_chunks, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, h->stream, (int64_t)cc, nchunks, part,
                        Tm);
     prof_end(h);
@@ -874,7 +947,19 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     hipLaunchKernelGGL(omega_solve, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, Tm, R, Bm, Om, piv, h->status);
     prof_end(h);
     prof_begin(h, "sym_eig");
-    hipLaunchKernelGGL(sym_eig, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, Om, Zm, dv, ev, tv, rot, h->status);
+    hipLaunchKernelGGL(sym_eig, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, Om, Zm, dv, ev, tv, rotbuf, sweeps,
+                       nsweeps, max_rot, max_sweeps, h->status);
+    {
+        const size_t smem_rot = (size_t)c * 64 * sizeof(double);
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute((const void*)apply_rotations, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      256 * 64 * (int)sizeof(double));
+            attr = true;
+        }
+        hipLaunchKernelGGL(apply_rotations, dim3(ceil_div(c, 64)), dim3(64), smem_rot, h->stream, c, nsweeps, sweeps,
+                           rotbuf, Zm);
+    }
     hipLaunchKernelGGL(order_sign, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, dv, Zm, lam, Usm);
     if (hipMemcpyAsync(Sigma, lam, (size_t)rank * 8, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
         return BFGS_ERR_HIP;
