@@ -112,6 +112,95 @@ def cpu_baseline(H, V, wq_prob_n, storage, ncols):
                       f"float64 two-loop recursion, {dt:.2f} s"}
 
 
+def bench_batch(args):
+    """64-problem batch: plain float32 per-problem launches on one stream vs the
+    bfloat16 batch (forked streams, autotuned, replayed from one captured hipGraph)."""
+    import torch
+    import paper_2009_12663_amd as P
+    from workloads import quadratic as wq
+
+    shapes = wq.batch_shapes()
+    p = 10
+    t0 = time.perf_counter()
+    pairs = []
+    for sh in shapes:
+        prob = wq.make_grid(sh["nx"], sh["nz"], sh["seed"], device="cuda")
+        S, Y, _ = wq.cg_pairs(prob, sh["k"], rel_tol=1e-13)
+        pairs.append((S.float(), Y.float()))
+    ns = [sh["n"] for sh in shapes]
+    ks = [S.shape[0] for S, _ in pairs]
+    cs = [k + p for k in ks]
+    log(f"[bench-batch] 64 problems, sum n = {sum(ns)}, k {min(ks)}..{max(ks)}, pairs in {time.perf_counter() - t0:.1f}s")
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    # plain float32, one problem after another on one stream
+    plain = []
+    for (S, Y), n, k in zip(pairs, ns, ks):
+        H = P.Bfgs(n, k, None, "f32")
+        for s, y in zip(S, Y):
+            H.push_pair(s, y)
+        plain.append(H)
+    Vp = [H.generate_probes(2 + i, c) for i, (H, c) in enumerate(zip(plain, cs))]
+    outp = [torch.empty(v.shape, dtype=torch.float32, device="cuda") for v in Vp]
+    Up = [torch.empty((k, n), dtype=torch.float32, device="cuda") for k, n in zip(ks, ns)]
+    Sp = [torch.empty(k, dtype=torch.float64, device="cuda") for k in ks]
+
+    def plain_apply():
+        for H, v, o in zip(plain, Vp, outp):
+            H.apply_Hinv(v, o)
+
+    def plain_rsvd():
+        for i, (H, k, u, sg) in enumerate(zip(plain, ks, Up, Sp)):
+            H.rsvd(k, p, 7 + i, u, sg)
+
+    t_plain_apply = timed(plain_apply, args.steps)
+    t_plain_rsvd = timed(plain_rsvd, 1)
+    log(f"[bench-batch] plain f32: apply {t_plain_apply:.2f} ms, rsvd {t_plain_rsvd:.2f} ms")
+    for H in plain:
+        H.close()
+    del plain, Vp, outp, Up, Sp
+
+    B = P.BfgsBatch(ns, ks, None, "bf16")
+    for (S, Y), H in zip(pairs, B.problems):
+        for s, y in zip(S, Y):
+            H.push_pair(s, y)
+    del pairs
+    V = [B.problems[i].generate_probes(2 + i, c) for i, c in enumerate(cs)]
+    out = [torch.empty(v.shape, dtype=torch.float32, device="cuda") for v in V]
+    U = [torch.empty((k, n), dtype=torch.float32, device="cuda") for k, n in zip(ks, ns)]
+    Sg = [torch.empty(k, dtype=torch.float64, device="cuda") for k in ks]
+    B.autotune(V, ks, p)
+    t_batch_apply = timed(lambda: B.apply_Hinv(V, out), args.steps)
+    t_batch_rsvd = timed(lambda: B.rsvd(ks, p, 7, U, Sg), 1)
+    B.graph_build(V, out, ks, p, 7, U, Sg)
+    t_graph = timed(B.graph_launch, max(1, args.steps // 2))
+    B.close()
+    cols = sum(cs)
+    res = {
+        "metric": "batched B_k V columns/s + rSVD wall time, 64 problems (n 5e4..1e6, k 20..150)",
+        "value": round(cols / (t_batch_apply / 1e3), 2), "unit": "columns/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": round(t_graph, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "64-problem batch, rank k + 10", "sum_n": sum(ns), "sum_cols": cols},
+        "batch_apply_ms": round(t_batch_apply, 4), "batch_rsvd_ms": round(t_batch_rsvd, 4),
+        "graph_apply_plus_rsvd_ms": round(t_graph, 4),
+        "plain_f32_apply_ms": round(t_plain_apply, 4), "plain_f32_rsvd_ms": round(t_plain_rsvd, 4),
+        "speedup_apply": round(t_plain_apply / t_batch_apply, 3),
+        "speedup_apply_plus_rsvd": round((t_plain_apply + t_plain_rsvd) / t_graph, 3),
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +230,9 @@ def main():
         print("bench.py runs on one GPU only: this build measures the single-GPU path "
               "(multi-GPU sharding is a design note, not implemented). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.config == "batch":
+        bench_batch(args)
+        return
 
     import torch
     import paper_2009_12663_amd as P

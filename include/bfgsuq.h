@@ -154,6 +154,53 @@ int bfgs_get_h0(bfgs_t h, void* out);
  * recorded on the device since the last call (or BFGS_OK) and clears it.     */
 int bfgs_get_status(bfgs_t h);
 
+/* ---------------------------------------------------------------------------
+ * Launch-shape tuning.
+ * bfgs_autotune — times the tunable launch shapes for this handle and ncols
+ *   probe columns (rows per pass-1 workgroup of the bfloat16 MFMA apply; number
+ *   of TSQR chains when rank/U/Sigma are given) with HIP events on the handle's
+ *   stream and keeps the fastest in the handle.  V (device, n x ncols, storage
+ *   type) and out (device, n x ncols) are scratch inputs/outputs it may
+ *   overwrite; U (n x rank) and Sigma (rank) likewise, or NULL to tune the
+ *   apply only.  Synchronous; results are unchanged by tuning except for the
+ *   summation order of the split-K reduction and of the TSQR tree.
+ * bfgs_tuning — reads the current choices (host pointers, either may be NULL).
+ * ------------------------------------------------------------------------- */
+int bfgs_autotune(bfgs_t h, int32_t ncols, int32_t rank, int32_t oversample, void* V, void* out, void* U,
+                  double* Sigma);
+int bfgs_tuning(bfgs_t h, int32_t* g1_rows, int32_t* qr_chains);
+
+/* ---------------------------------------------------------------------------
+ * Batched form: nprob independent inversions of uneven n and k driven as one
+ * unit.  Every array argument below is a HOST array of nprob entries (device
+ * pointers where the single-problem call takes device pointers).  Problem i
+ * has its own handle (bfgs_batch_handle) whose kernels run on one of up to 8
+ * side streams forked from `stream` and joined back into it, so the problems
+ * overlap on the device.  Semantics per problem are those of the
+ * single-problem calls; the rSVD of problem i uses seed + i.
+ * ------------------------------------------------------------------------- */
+typedef struct bfgsuq_batch* bfgs_batch_t;
+
+/* H0 may be NULL (every problem gamma I) or an array whose NULL entries select gamma I. */
+int bfgs_batch_create(int32_t nprob, const int64_t* n, const int32_t* k_max, const void* const* H0, bfgs_dtype storage,
+                      void* stream, bfgs_batch_t* out);
+/* The handle of problem i (for bfgs_push_pair and inspection; owned by the batch). */
+int bfgs_batch_handle(bfgs_batch_t b, int32_t i, bfgs_t* h_out);
+int bfgs_batch_apply_Hinv(bfgs_batch_t b, const void* const* V, const int32_t* ncols, void* const* out);
+int bfgs_batch_rsvd(bfgs_batch_t b, const int32_t* rank, int32_t oversample, uint64_t seed, void* const* U,
+                    double* const* Sigma);
+/* bfgs_autotune for every problem (rank/U/Sigma may be NULL). */
+int bfgs_batch_autotune(bfgs_batch_t b, const void* const* V, const int32_t* ncols, void* const* out,
+                        const int32_t* rank, int32_t oversample, void* const* U, double* const* Sigma);
+/* Runs apply + rSVD of every problem once, then captures the same sequence into a
+ * hipGraph on `stream` (synchronous).  The buffers passed are baked into the graph. */
+int bfgs_batch_graph_build(bfgs_batch_t b, const void* const* V, const int32_t* ncols, void* const* out,
+                           const int32_t* rank, int32_t oversample, uint64_t seed, void* const* U,
+                           double* const* Sigma);
+/* Replays the captured graph on `stream` (BFGS_ERR_STATE if none was built). */
+int bfgs_batch_graph_launch(bfgs_batch_t b);
+int bfgs_batch_destroy(bfgs_batch_t b);
+
 /* Measurement support (not an operation of the method).
  * bfgs_profile — enable (1) or disable (0) per-kernel timing: while enabled,
  *   every kernel group the library enqueues on the handle's stream is
@@ -164,6 +211,9 @@ int bfgs_get_status(bfgs_t h);
  *   record.  BFGS_ERR_ARG if buf is too small.                               */
 int bfgs_profile(bfgs_t h, int32_t enable);
 int bfgs_profile_report(bfgs_t h, char* buf, int32_t len);
+
+/* bfgs_sync — waits until all work enqueued on the handle's stream is done. */
+int bfgs_sync(bfgs_t h);
 
 /* bfgs_status_string — static description of a return code. */
 const char* bfgs_status_string(int code);

@@ -5,6 +5,7 @@ Python binding.  See include/bfgsuq.h for the C ABI.
 """
 from ._lib import (  # noqa: F401
     Bfgs,
+    BfgsBatch,
     BfgsError,
     bfgs_create,
     bfgs_push_pair,

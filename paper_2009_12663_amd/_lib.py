@@ -35,6 +35,9 @@ EXPORTS = [
     "bfgs_create", "bfgs_destroy", "bfgs_push_pair", "bfgs_num_pairs", "bfgs_apply_Hinv",
     "bfgs_apply_Hdiff", "bfgs_generate_probes", "bfgs_rsvd", "bfgs_posterior_diag",
     "bfgs_get_pair", "bfgs_get_h0", "bfgs_get_status", "bfgs_status_string",
+    "bfgs_profile", "bfgs_profile_report", "bfgs_autotune", "bfgs_tuning", "bfgs_sync",
+    "bfgs_batch_create", "bfgs_batch_handle", "bfgs_batch_apply_Hinv", "bfgs_batch_rsvd",
+    "bfgs_batch_autotune", "bfgs_batch_graph_build", "bfgs_batch_graph_launch", "bfgs_batch_destroy",
 ]
 
 _lib = None
@@ -69,6 +72,19 @@ def load(path: str = LIB_PATH):
         "bfgs_get_h0": [vp, vp],
         "bfgs_get_status": [vp],
         "bfgs_status_string": [ctypes.c_int],
+        "bfgs_profile": [vp, i32],
+        "bfgs_profile_report": [vp, ctypes.c_char_p, i32],
+        "bfgs_autotune": [vp, i32, i32, i32, vp, vp, vp, vp],
+        "bfgs_tuning": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "bfgs_sync": [vp],
+        "bfgs_batch_create": [i32, vp, vp, vp, ctypes.c_int, vp, ctypes.POINTER(vp)],
+        "bfgs_batch_handle": [vp, i32, ctypes.POINTER(vp)],
+        "bfgs_batch_apply_Hinv": [vp, vp, vp, vp],
+        "bfgs_batch_rsvd": [vp, vp, i32, u64, vp, vp],
+        "bfgs_batch_autotune": [vp, vp, vp, vp, vp, i32, vp, vp],
+        "bfgs_batch_graph_build": [vp, vp, vp, vp, vp, i32, u64, vp, vp],
+        "bfgs_batch_graph_launch": [vp],
+        "bfgs_batch_destroy": [vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -102,12 +118,17 @@ class Bfgs:
     vectors of length n has shape (ncols, n) (column-major n x ncols)."""
 
     def __init__(self, n: int, k_max: int, h0: torch.Tensor | None = None, storage: str = "f32",
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, _handle=None):
         self.L = load()
         self.n, self.k_max, self.storage = int(n), int(k_max), storage
         self.sdt = STORAGE_TORCH[storage]
         self.rdt = RESULT_TORCH[storage]
         self.hdt = torch.float64 if storage == "f64" else torch.float32
+        self._owns = _handle is None
+        if _handle is not None:          # a problem handle owned by a BfgsBatch
+            self.h = _handle
+            self.stream = None
+            return
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._h0 = None
         if h0 is not None:
@@ -122,7 +143,8 @@ class Bfgs:
     # -- life cycle -------------------------------------------------------------------
     def close(self):
         if getattr(self, "h", None):
-            self.L.bfgs_destroy(self.h)
+            if getattr(self, "_owns", True):
+                self.L.bfgs_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -138,13 +160,24 @@ class Bfgs:
         self.close()
 
     # -- calls ------------------------------------------------------------------------
+    def _enter(self):
+        # A batch-owned handle runs on its own side stream: order it after torch's stream.
+        if not self._owns:
+            torch.cuda.current_stream().synchronize()
+
+    def _leave(self):
+        if not self._owns:
+            _check(self.L.bfgs_sync(self.h), "bfgs_sync")
+
     def push_pair(self, s: torch.Tensor, y: torch.Tensor) -> None:
         dt = torch.float64 if s.dtype == torch.float64 else torch.float32
         s = s.to(dt).contiguous()
         y = y.to(dt).contiguous()
         assert s.numel() == self.n and y.numel() == self.n and s.is_cuda and y.is_cuda
+        self._enter()
         _check(self.L.bfgs_push_pair(self.h, _ptr(s), _ptr(y), F64 if dt == torch.float64 else F32),
                "bfgs_push_pair")
+        self._leave()
 
     @property
     def k(self) -> int:
@@ -160,20 +193,26 @@ class Bfgs:
         V = self._block(V)
         if out is None:
             out = torch.empty(V.shape, dtype=self.rdt, device=V.device)
+        self._enter()
         _check(self.L.bfgs_apply_Hinv(self.h, _ptr(V), V.shape[0], _ptr(out)), "bfgs_apply_Hinv")
+        self._leave()
         return out
 
     def apply_Hdiff(self, V: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         V = self._block(V)
         if out is None:
             out = torch.empty(V.shape, dtype=self.rdt, device=V.device)
+        self._enter()
         _check(self.L.bfgs_apply_Hdiff(self.h, _ptr(V), V.shape[0], _ptr(out)), "bfgs_apply_Hdiff")
+        self._leave()
         return out
 
     def generate_probes(self, seed: int, ncols: int) -> torch.Tensor:
         X = torch.empty((ncols, self.n), dtype=self.sdt, device="cuda")
+        self._enter()
         _check(self.L.bfgs_generate_probes(self.h, ctypes.c_uint64(seed), ncols, _ptr(X)),
                "bfgs_generate_probes")
+        self._leave()
         return X
 
     def rsvd(self, rank: int, oversample: int, seed: int, U: torch.Tensor | None = None,
@@ -182,29 +221,162 @@ class Bfgs:
             U = torch.empty((rank, self.n), dtype=self.rdt, device="cuda")
         if Sigma is None:
             Sigma = torch.empty(rank, dtype=torch.float64, device="cuda")
+        self._enter()
         _check(self.L.bfgs_rsvd(self.h, rank, oversample, ctypes.c_uint64(seed), _ptr(U), _ptr(Sigma)),
                "bfgs_rsvd")
+        self._leave()
         return U, Sigma
 
     def posterior_diag(self, out: torch.Tensor | None = None) -> torch.Tensor:
         if out is None:
             out = torch.empty(self.n, dtype=self.rdt, device="cuda")
+        self._enter()
         _check(self.L.bfgs_posterior_diag(self.h, _ptr(out)), "bfgs_posterior_diag")
+        self._leave()
         return out
 
     def get_pair(self, j: int):
         s = torch.empty(self.n, dtype=self.rdt, device="cuda")
         y = torch.empty(self.n, dtype=self.rdt, device="cuda")
+        self._enter()
         _check(self.L.bfgs_get_pair(self.h, j, _ptr(s), _ptr(y)), "bfgs_get_pair")
+        self._leave()
         return s, y
 
     def get_h0(self) -> torch.Tensor:
         out = torch.empty(self.n, dtype=self.hdt, device="cuda")
+        self._enter()
         _check(self.L.bfgs_get_h0(self.h, _ptr(out)), "bfgs_get_h0")
+        self._leave()
         return out
 
     def get_status(self) -> int:
         return self.L.bfgs_get_status(self.h)
+
+    def autotune(self, V: torch.Tensor, out: torch.Tensor | None = None, rank: int = 0, oversample: int = 0):
+        """Times the tunable launch shapes on these buffers and keeps the fastest."""
+        V = self._block(V)
+        if out is None:
+            out = torch.empty(V.shape, dtype=self.rdt, device=V.device)
+        U = Sig = None
+        if rank:
+            U = torch.empty((rank, self.n), dtype=self.rdt, device="cuda")
+            Sig = torch.empty(rank, dtype=torch.float64, device="cuda")
+        _check(self.L.bfgs_autotune(self.h, V.shape[0], rank, oversample, _ptr(V), _ptr(out), _ptr(U), _ptr(Sig)),
+               "bfgs_autotune")
+        return self.tuning()
+
+    def tuning(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.L.bfgs_tuning(self.h, ctypes.byref(a), ctypes.byref(b)), "bfgs_tuning")
+        return {"g1_rows": a.value, "qr_chains": b.value}
+
+    def profile(self, enable: bool):
+        _check(self.L.bfgs_profile(self.h, 1 if enable else 0), "bfgs_profile")
+
+    def profile_report(self) -> dict:
+        import json
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(self.L.bfgs_profile_report(self.h, buf, len(buf)), "bfgs_profile_report")
+        return json.loads(buf.value.decode())
+
+
+def _ptr_array(tensors):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+def _i32_array(vals):
+    return (ctypes.c_int32 * len(vals))(*[int(v) for v in vals])
+
+
+class BfgsBatch:
+    """nprob independent histories driven together (bfgs_batch_* of the C ABI).
+
+    `problems[i]` is a non-owning Bfgs view of problem i (push pairs through it).
+    Blocks are lists of per-problem tensors."""
+
+    def __init__(self, n: list, k_max: list, h0: list | None = None, storage: str = "f32",
+                 stream: torch.cuda.Stream | None = None):
+        self.L = load()
+        self.nprob = len(n)
+        self.storage = storage
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        hdt = torch.float64 if storage == "f64" else torch.float32
+        self._h0 = None if h0 is None else [None if x is None else x.to(hdt).contiguous() for x in h0]
+        n_arr = (ctypes.c_int64 * self.nprob)(*[int(x) for x in n])
+        k_arr = _i32_array(k_max)
+        h0_arr = None if self._h0 is None else _ptr_array(self._h0)
+        handle = ctypes.c_void_p()
+        _check(self.L.bfgs_batch_create(self.nprob, n_arr, k_arr, h0_arr, STORAGE_CODES[storage],
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)),
+               "bfgs_batch_create")
+        self.b = handle
+        self.problems = []
+        for i in range(self.nprob):
+            hp = ctypes.c_void_p()
+            _check(self.L.bfgs_batch_handle(self.b, i, ctypes.byref(hp)), "bfgs_batch_handle")
+            self.problems.append(Bfgs(n[i], k_max[i], storage=storage, _handle=hp))
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "b", None):
+            for p in self.problems:
+                p.h = None
+            self.L.bfgs_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply_Hinv(self, V: list, out: list | None = None) -> list:
+        V = [p._block(v) for p, v in zip(self.problems, V)]
+        if out is None:
+            out = [torch.empty(v.shape, dtype=p.rdt, device=v.device) for p, v in zip(self.problems, V)]
+        self._keep = [V, out]
+        _check(self.L.bfgs_batch_apply_Hinv(self.b, _ptr_array(V), _i32_array([v.shape[0] for v in V]),
+                                            _ptr_array(out)), "bfgs_batch_apply_Hinv")
+        return out
+
+    def _rsvd_bufs(self, rank):
+        U = [torch.empty((r, p.n), dtype=p.rdt, device="cuda") for p, r in zip(self.problems, rank)]
+        Sig = [torch.empty(r, dtype=torch.float64, device="cuda") for r in rank]
+        return U, Sig
+
+    def rsvd(self, rank: list, oversample: int, seed: int, U=None, Sigma=None):
+        if U is None:
+            U, Sigma = self._rsvd_bufs(rank)
+        self._keep = [U, Sigma]
+        _check(self.L.bfgs_batch_rsvd(self.b, _i32_array(rank), oversample, ctypes.c_uint64(seed), _ptr_array(U),
+                                      _ptr_array(Sigma)), "bfgs_batch_rsvd")
+        return U, Sigma
+
+    def autotune(self, V: list, rank: list | None = None, oversample: int = 0):
+        V = [p._block(v) for p, v in zip(self.problems, V)]
+        out = [torch.empty(v.shape, dtype=p.rdt, device=v.device) for p, v in zip(self.problems, V)]
+        U = Sig = None
+        if rank is not None:
+            U, Sig = self._rsvd_bufs(rank)
+        _check(self.L.bfgs_batch_autotune(self.b, _ptr_array(V), _i32_array([v.shape[0] for v in V]), _ptr_array(out),
+                                          None if rank is None else _i32_array(rank), oversample,
+                                          None if U is None else _ptr_array(U),
+                                          None if Sig is None else _ptr_array(Sig)), "bfgs_batch_autotune")
+        return [p.tuning() for p in self.problems]
+
+    def graph_build(self, V: list, out: list, rank: list, oversample: int, seed: int, U: list, Sigma: list):
+        V = [p._block(v) for p, v in zip(self.problems, V)]
+        self._graph_keep = [V, out, U, Sigma]
+        _check(self.L.bfgs_batch_graph_build(self.b, _ptr_array(V), _i32_array([v.shape[0] for v in V]),
+                                             _ptr_array(out), _i32_array(rank), oversample, ctypes.c_uint64(seed),
+                                             _ptr_array(U), _ptr_array(Sigma)), "bfgs_batch_graph_build")
+
+    def graph_launch(self):
+        _check(self.L.bfgs_batch_graph_launch(self.b), "bfgs_batch_graph_launch")
 
 
 # Same names as the C ABI.

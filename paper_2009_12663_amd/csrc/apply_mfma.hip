@@ -512,7 +512,7 @@ int mfma_apply(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
     const bf16_t* V = (const bf16_t*)Vv;
     float* out = (float*)outv;
     const int NT = (c + 31) / 32;
-    const int nk = 128;                                   // row ranges (multiple of 8)
+    const int nk = h->g1_nk;                              // row ranges (multiple of 8, tunable)
     const int64_t rows_f1 = mfma_rows_f1(n);
     const int64_t rows_per_wg = round_up((rows_f1 + nk - 1) / nk, G1_STAGE);
     const int twok = 2 * k;

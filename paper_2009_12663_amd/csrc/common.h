@@ -116,6 +116,9 @@ struct bfgsuq_ctx {
     Workspace X, E, Q, refl, tau, Rtree, small, lam, diag;
     int32_t last_rank = 0;
     bool have_rsvd = false;
+    // tunables (bfgs_autotune): row ranges of the pass-1 MFMA kernel, TSQR chains (power of two)
+    int g1_nk = 128;
+    int qr_chains = 256;
     Profiler prof;
 };
 

@@ -807,7 +807,7 @@ template <typename TO, typename SlotT>
 int tsqr(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     const int64_t n = h->n;
     const int64_t tiles_total = (n + TR - 1) / TR;
-    const int nchains = (int)std::min<int64_t>(256, floor_pow2(std::max<int64_t>(1, tiles_total / 2)));
+    const int nchains = (int)std::min<int64_t>(h->qr_chains, floor_pow2(std::max<int64_t>(1, tiles_total / 2)));
     const int64_t rows_per_chain = round_up((n + nchains - 1) / nchains, TR);
     const int tiles_per_chain = (int)(rows_per_chain / TR);
     const int ntc = (c + TR - 1) / TR;
@@ -825,11 +825,17 @@ int tsqr(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     double* Qtop = Rs + (size_t)nchains * c * c;
     double* tree_refl = Qtop + (size_t)nchains * c * c;
     const size_t smem = slot_smem<SlotT>(c);
-    if (hipFuncSetAttribute((const void*)tsqr_leaf_forward<TO, SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess ||
-        hipFuncSetAttribute((const void*)tsqr_leaf_backward<TO, SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess ||
-        hipFuncSetAttribute((const void*)tsqr_tree_forward<SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess ||
-        hipFuncSetAttribute((const void*)tsqr_tree_backward<SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess)
-        return BFGS_ERR_HIP;
+    // Raise the dynamic-LDS limit once per instantiation (never while a graph is being captured).
+    static bool attr_done = false;
+    if (!attr_done) {
+        const int lim = 160 * 1024;
+        if (hipFuncSetAttribute((const void*)tsqr_leaf_forward<TO, SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
+            hipFuncSetAttribute((const void*)tsqr_leaf_backward<TO, SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
+            hipFuncSetAttribute((const void*)tsqr_tree_forward<SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
+            hipFuncSetAttribute((const void*)tsqr_tree_backward<SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
+            return BFGS_ERR_HIP;
+        attr_done = true;
+    }
     ProfScope ps(h, "tsqr_leaf_fwd");
     hipLaunchKernelGGL((tsqr_leaf_forward<TO, SlotT>), dim3(nchains), dim3(QR_THREADS), smem, h->stream, n, c,
                        rows_per_chain, E, refl, taus, Rs);
