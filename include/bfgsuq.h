@@ -201,6 +201,38 @@ int bfgs_batch_graph_build(bfgs_batch_t b, const void* const* V, const int32_t* 
 int bfgs_batch_graph_launch(bfgs_batch_t b);
 int bfgs_batch_destroy(bfgs_batch_t b);
 
+/* ---------------------------------------------------------------------------
+ * Learned diagonal B_0: a per-(grid point, parameter) network predicting log h0,
+ * the learned counterpart of the diagonal preconditioners of eqs. (4)-(8)
+ * (gamma I remains the fallback).  Architecture 8 -> 64 -> 64 -> 1 with GELU
+ * (x Phi(x), exact erf); float32 master weights, bfloat16 compute copies,
+ * float32 accumulation.  BFGS_MLP_NPARAM parameters flattened as
+ * W1 (64 x 8, row-major), b1 (64), W2 (64 x 64, row-major), b2 (64), w3 (64), b3.
+ * Features (8 per point, row-major n x 8) of point (param p, iz, ix) of a
+ * field-major 3-field model: [logD_p, logD_p+1, logD_p+2, |g0|_p, |g0|_p+1,
+ * |g0|_p+2, iz / (nz - 1), sigma_scale] (parameter indices mod 3).
+ * All pointers are device pointers; work is enqueued on the stream given at
+ * creation.  Gradients and losses are deterministic (fixed-order reductions).
+ * ------------------------------------------------------------------------- */
+#define BFGS_MLP_NPARAM 4801
+typedef struct bfgsuq_mlp* bfgs_mlp_t;
+
+int bfgs_mlp_create(void* stream, bfgs_mlp_t* out);
+int bfgs_mlp_destroy(bfgs_mlp_t m);
+/* Sets the float32 master weights (and their bfloat16 copy); resets Adam's state. */
+int bfgs_mlp_set_params(bfgs_mlp_t m, const float* params);
+int bfgs_mlp_get_params(bfgs_mlp_t m, float* params);
+/* logD, gabs: n = 3 nx nz floats each; X: n x 8 floats. */
+int bfgs_mlp_features(int64_t nx, int64_t nz, const float* logD, const float* gabs, float sigma_scale, float* X,
+                      void* stream);
+/* out[i] = network(X[i]) (exp_out = 0) or h0_i = exp(network(X[i])) (exp_out = 1). */
+int bfgs_mlp_forward(bfgs_mlp_t m, const float* X, int64_t N, float* out, int32_t exp_out);
+/* Gradient of mean((network(X) - target)^2) w.r.t. the parameters (grad: NPARAM floats,
+ * may be NULL) and the loss (1 float, may be NULL); no update. */
+int bfgs_mlp_grad(bfgs_mlp_t m, const float* X, const float* target, int64_t N, float* grad, float* loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that loss; loss may be NULL. */
+int bfgs_mlp_train_step(bfgs_mlp_t m, const float* X, const float* target, int64_t N, float lr, float* loss);
+
 /* Measurement support (not an operation of the method).
  * bfgs_profile — enable (1) or disable (0) per-kernel timing: while enabled,
  *   every kernel group the library enqueues on the handle's stream is

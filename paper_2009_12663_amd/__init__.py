@@ -6,6 +6,7 @@ Python binding.  See include/bfgsuq.h for the C ABI.
 from ._lib import (  # noqa: F401
     Bfgs,
     BfgsBatch,
+    Mlp,
     BfgsError,
     bfgs_create,
     bfgs_push_pair,

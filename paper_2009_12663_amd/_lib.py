@@ -38,7 +38,10 @@ EXPORTS = [
     "bfgs_profile", "bfgs_profile_report", "bfgs_autotune", "bfgs_tuning", "bfgs_sync",
     "bfgs_batch_create", "bfgs_batch_handle", "bfgs_batch_apply_Hinv", "bfgs_batch_rsvd",
     "bfgs_batch_autotune", "bfgs_batch_graph_build", "bfgs_batch_graph_launch", "bfgs_batch_destroy",
+    "bfgs_mlp_create", "bfgs_mlp_destroy", "bfgs_mlp_set_params", "bfgs_mlp_get_params", "bfgs_mlp_features",
+    "bfgs_mlp_forward", "bfgs_mlp_grad", "bfgs_mlp_train_step",
 ]
+MLP_NPARAM = 4801
 
 _lib = None
 
@@ -85,6 +88,14 @@ def load(path: str = LIB_PATH):
         "bfgs_batch_graph_build": [vp, vp, vp, vp, vp, i32, u64, vp, vp],
         "bfgs_batch_graph_launch": [vp],
         "bfgs_batch_destroy": [vp],
+        "bfgs_mlp_create": [vp, ctypes.POINTER(vp)],
+        "bfgs_mlp_destroy": [vp],
+        "bfgs_mlp_set_params": [vp, vp],
+        "bfgs_mlp_get_params": [vp, vp],
+        "bfgs_mlp_features": [i64, i64, vp, vp, ctypes.c_float, vp, vp],
+        "bfgs_mlp_forward": [vp, vp, i64, vp, i32],
+        "bfgs_mlp_grad": [vp, vp, vp, i64, vp, vp],
+        "bfgs_mlp_train_step": [vp, vp, vp, i64, ctypes.c_float, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -410,3 +421,71 @@ def bfgs_generate_probes(h: Bfgs, seed, ncols):
 
 def bfgs_destroy(h: Bfgs):
     h.close()
+
+
+class Mlp:
+    """The learned-B_0 network (bfgs_mlp_* of the C ABI)."""
+
+    def __init__(self, params: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None):
+        self.L = load()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(self.L.bfgs_mlp_create(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "bfgs_mlp_create")
+        self.m = h
+        if params is not None:
+            self.set_params(params)
+
+    def close(self):
+        if getattr(self, "m", None):
+            self.L.bfgs_mlp_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: torch.Tensor):
+        p = params.to("cuda", torch.float32).contiguous()
+        assert p.numel() == MLP_NPARAM
+        _check(self.L.bfgs_mlp_set_params(self.m, _ptr(p)), "bfgs_mlp_set_params")
+        torch.cuda.current_stream().synchronize()
+
+    def get_params(self) -> torch.Tensor:
+        p = torch.empty(MLP_NPARAM, dtype=torch.float32, device="cuda")
+        _check(self.L.bfgs_mlp_get_params(self.m, _ptr(p)), "bfgs_mlp_get_params")
+        return p
+
+    @staticmethod
+    def features(logD: torch.Tensor, gabs: torch.Tensor, nx: int, nz: int, sigma_scale: float = 1.0) -> torch.Tensor:
+        L = load()
+        logD = logD.to("cuda", torch.float32).contiguous()
+        gabs = gabs.to("cuda", torch.float32).contiguous()
+        X = torch.empty((logD.numel(), 8), dtype=torch.float32, device="cuda")
+        _check(L.bfgs_mlp_features(nx, nz, _ptr(logD), _ptr(gabs), ctypes.c_float(sigma_scale), _ptr(X),
+                                   ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)), "bfgs_mlp_features")
+        return X
+
+    def forward(self, X: torch.Tensor, exp_out: bool = False) -> torch.Tensor:
+        X = X.to("cuda", torch.float32).contiguous()
+        out = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
+        _check(self.L.bfgs_mlp_forward(self.m, _ptr(X), X.shape[0], _ptr(out), 1 if exp_out else 0),
+               "bfgs_mlp_forward")
+        return out
+
+    def grad(self, X: torch.Tensor, target: torch.Tensor):
+        X = X.to("cuda", torch.float32).contiguous()
+        t = target.to("cuda", torch.float32).contiguous()
+        g = torch.empty(MLP_NPARAM, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(self.L.bfgs_mlp_grad(self.m, _ptr(X), _ptr(t), X.shape[0], _ptr(g), _ptr(loss)), "bfgs_mlp_grad")
+        return g, loss
+
+    def train_step(self, X: torch.Tensor, target: torch.Tensor, lr: float, loss: torch.Tensor | None = None):
+        """One Adam step; X, target (and loss, if given) should already be float32 device tensors."""
+        X = X.to("cuda", torch.float32).contiguous()
+        target = target.to("cuda", torch.float32).contiguous()
+        _check(self.L.bfgs_mlp_train_step(self.m, _ptr(X), _ptr(target), X.shape[0], ctypes.c_float(lr), _ptr(loss)),
+               "bfgs_mlp_train_step")
+        return loss
