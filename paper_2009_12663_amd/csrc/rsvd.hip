@@ -33,7 +33,10 @@ int probes_launch(bfgsuq_ctx* h, uint64_t seed, int32_t c, void* X, hipStream_t 
 namespace {
 
 constexpr int TR = 64;          // tile rows per Householder update
-constexpr int QR_THREADS = 256; // one thread per column (c <= 256)
+constexpr int LPC = 4;          // lanes per column (a quad); lane g owns tile rows t = i * LPC + g
+constexpr int RPL = TR / LPC;   // tile rows per lane
+constexpr int QR_MAX_THREADS = 1024;  // c <= 256 columns x LPC
+constexpr int NB = 16;          // reflectors staged per barrier when applying known reflectors
 constexpr int SLOT_F64_MAX_C = 180;
 
 __device__ __forceinline__ int tri_index(int j, int col, int c) {
@@ -41,79 +44,118 @@ __device__ __forceinline__ int tri_index(int j, int col, int c) {
     return j * c - (j * (j - 1)) / 2 + (col - j);
 }
 
-// Dot products over a tile with eight independent partial sums (short dependency chains).
-__device__ __forceinline__ double dot_tile(const double (&x)[TR], const double (&y)[TR]) {
-    double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int t = 0; t < TR; ++t) p[t & 7] = fma(x[t], y[t], p[t & 7]);
-    return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+// Exchange within a quad of lanes (DPP quad_perm); every lane of the quad must be active.
+template <int CTRL>
+__device__ __forceinline__ double quad_perm(double x) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
-__device__ __forceinline__ double dot_tile_sh(const double* v, const double (&y)[TR]) {
-    double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int t = 0; t < TR; ++t) p[t & 7] = fma(v[t], y[t], p[t & 7]);
-    return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+__device__ __forceinline__ double quad_sum(double x) {
+    x += quad_perm<0xB1>(x);   // lanes (1,0,3,2)
+    x += quad_perm<0x4E>(x);   // lanes (2,3,0,1)
+    return x;
 }
 
-// Forward: fold TR tile rows (a[] of this thread's column) into the slot.
-// Reflector j's tile part replaces a[] in thread j; taus[j] receives tau.
+// This lane's share of v^T a over the tile (v in LDS, row t at v[t]); four partial chains.
+__device__ __forceinline__ double dot_lane(const double* v, const double (&a)[RPL], int g) {
+    double p[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) p[i & 3] = fma(v[i * LPC + g], a[i], p[i & 3]);
+    return (p[0] + p[1]) + (p[2] + p[3]);
+}
+
+__device__ __forceinline__ double norm2_lane(const double (&a)[RPL]) {
+    double p[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) p[i & 3] = fma(a[i], a[i], p[i & 3]);
+    return (p[0] + p[1]) + (p[2] + p[3]);
+}
+
+// Reflector j from (slot[j][j], tile column j held by this quad): the tile part of v
+// overwrites a[], goes to vbuf, tau to tau_sh and taus_out[j].
 template <typename SlotT>
-__device__ __forceinline__ void fold_tile(SlotT* slot, double (&a)[TR], int c, int jstart, double* vbuf,
-                                          double* tau_sh, double* taus_out) {
-    const int col = threadIdx.x;
+__device__ __forceinline__ void make_reflector(SlotT* slot, double (&a)[RPL], int c, int j, int g, double* vbuf,
+                                               double* tau_sh, double* taus_out) {
+    const double xn2 = quad_sum(norm2_lane(a));
+    const int dj = tri_index(j, j, c);
+    const double rjj = (double)slot[dj];
+    double tau = 0.0;
+    if (xn2 > 0.0) {
+        const double beta = -copysign(sqrt(fma(rjj, rjj, xn2)), rjj);
+        tau = (beta - rjj) / beta;
+        const double sc = 1.0 / (rjj - beta);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) a[i] *= sc;
+        if (g == 0) slot[dj] = (SlotT)beta;
+    }
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) vbuf[i * LPC + g] = a[i];
+    if (g == 0) {
+        *tau_sh = tau;
+        taus_out[j] = tau;
+    }
+}
+
+// Apply reflector (v, tau) with slot row j to this quad's column col: slot[j][col] and a[].
+template <typename SlotT>
+__device__ __forceinline__ void reflect_column(SlotT* slot, double (&a)[RPL], int c, int j, int col, int g,
+                                               const double* v, double tau) {
+    const double s = quad_sum(dot_lane(v, a, g));
+    const int idx = tri_index(j, col, c);
+    const double r = (double)slot[idx];
+    const double w = (r + s) * tau;
+    if (g == 0) slot[idx] = (SlotT)(r - w);
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) a[i] = fma(-w, v[i * LPC + g], a[i]);
+}
+
+// Forward: fold the tile (a[] = this quad's column, TR rows) into the slot with
+// reflectors jstart..c-1.  Reflector j's tile part replaces column j's a[].
+// vbuf holds two reflectors (double buffer) so one barrier per reflector suffices:
+// the quad of column j+1 builds reflector j+1 as soon as it has applied reflector j.
+template <typename SlotT>
+__device__ void fold_tile(SlotT* slot, double (&a)[RPL], int c, int jstart, double* vbuf, double* tau_sh,
+                          double* taus_out) {
+    const int col = threadIdx.x / LPC, g = threadIdx.x % LPC;
+    if (col == jstart) make_reflector(slot, a, c, jstart, g, vbuf, tau_sh, taus_out);
+    __syncthreads();
     for (int j = jstart; j < c; ++j) {
-        if (col == j) {
-            const double rjj = (double)slot[tri_index(j, j, c)];
-            const double xn2 = dot_tile(a, a);
-            double tau = 0.0;
-            if (xn2 > 0.0) {
-                const double beta = -copysign(sqrt(fma(rjj, rjj, xn2)), rjj);
-                tau = (beta - rjj) / beta;
-                const double sc = 1.0 / (rjj - beta);
-#pragma unroll
-                for (int t = 0; t < TR; ++t) a[t] *= sc;
-                slot[tri_index(j, j, c)] = (SlotT)beta;
-            }
-#pragma unroll
-            for (int t = 0; t < TR; ++t) vbuf[t] = a[t];
-            *tau_sh = tau;
-            taus_out[j] = tau;
-        }
-        __syncthreads();
-        const double tau = *tau_sh;
-        if (col > j && col < c && tau != 0.0) {
-            double w = (double)slot[tri_index(j, col, c)] + dot_tile_sh(vbuf, a);
-            w *= tau;
-            slot[tri_index(j, col, c)] = (SlotT)((double)slot[tri_index(j, col, c)] - w);
-#pragma unroll
-            for (int t = 0; t < TR; ++t) a[t] = fma(-w, vbuf[t], a[t]);
-        }
+        const int buf = (j - jstart) & 1;
+        const double tau = tau_sh[buf];
+        if (col > j && col < c && tau != 0.0) reflect_column(slot, a, c, j, col, g, vbuf + buf * TR, tau);
+        if (col == j + 1 && j + 1 < c)
+            make_reflector(slot, a, c, j + 1, g, vbuf + (buf ^ 1) * TR, tau_sh + (buf ^ 1), taus_out);
         __syncthreads();
     }
 }
 
-// Backward: apply the tile's reflectors (j = c-1 .. jstart) to (slot, a[] = tile rows).
-// vsrc(t, j) gives reflector j's tile entry t; tau_of(j) its tau.
+// Backward: apply the tile's known reflectors j = c-1 .. jstart to (slot, a[] = tile
+// rows of this quad's column).  Reflector j's tile part is refl[j * TR + t]; its tau taus[j].
+// Reflectors are staged NB at a time; no barrier is needed between them because a
+// column is touched only by its own quad.
 template <typename SlotT>
-__device__ __forceinline__ void unfold_tile(SlotT* slot, double (&a)[TR], int c, int jstart, const double* refl_rows,
-                                            int ld_refl, int rows_valid, const double* taus, double* vbuf) {
-    const int col = threadIdx.x;
-    for (int j = c - 1; j >= jstart; --j) {
-        const double tau = taus[j];
-        if (tau == 0.0) continue;   // uniform across the workgroup
-        for (int t = col; t < TR; t += blockDim.x)
-            vbuf[t] = t < rows_valid ? refl_rows[(int64_t)t * ld_refl + j] : 0.0;
+__device__ void unfold_tile(SlotT* slot, double (&a)[RPL], int c, int jstart, const double* refl,
+                            const double* taus, double* vst, double* tst) {
+    const int col = threadIdx.x / LPC, g = threadIdx.x % LPC;
+    for (int jhi = c - 1; jhi >= jstart; jhi -= NB) {
+        const int jlo = max(jstart, jhi - NB + 1);
+        const int cnt = jhi - jlo + 1;
         __syncthreads();
-        if (col >= j && col < c) {
-            double w = (double)slot[tri_index(j, col, c)] + dot_tile_sh(vbuf, a);
-            w *= tau;
-            slot[tri_index(j, col, c)] = (SlotT)((double)slot[tri_index(j, col, c)] - w);
-#pragma unroll
-            for (int t = 0; t < TR; ++t) a[t] = fma(-w, vbuf[t], a[t]);
+        for (int e = threadIdx.x; e < cnt * TR; e += blockDim.x) vst[e] = refl[(int64_t)jlo * TR + e];
+        if (threadIdx.x < cnt) tst[threadIdx.x] = taus[jlo + threadIdx.x];
+        __syncthreads();
+        if (col < c) {
+            for (int j = jhi; j >= jlo; --j) {
+                const double tau = tst[j - jlo];
+                if (tau == 0.0 || col < j) continue;   // uniform within the quad
+                reflect_column(slot, a, c, j, col, g, vst + (j - jlo) * TR, tau);
+            }
         }
-        __syncthreads();
     }
+    __syncthreads();
 }
 
 template <typename SlotT>
@@ -139,50 +181,56 @@ __device__ void slot_store(const SlotT* slot, double* M, int c) {
     __syncthreads();
 }
 
+// LDS layout shared by the four TSQR kernels: reflector staging (NB x TR doubles;
+// the forward pass uses the first 2 x TR as its double buffer), NB taus, then the slot.
+constexpr int STAGE_DOUBLES = NB * TR + NB;
+
 // ---------------------------------------------------------------------------
-// Leaf chains
+// Leaf chains.  Reflectors are stored per tile, column-major: reflector j of
+// global tile gt has its tile part at refl[(gt * c + j) * TR + t]; taus[gt * c + j].
 // ---------------------------------------------------------------------------
-// refl: tile-major rows, row g of the chain layout is refl[g * c + col]; taus[tile * c + j].
 template <typename TE, typename SlotT>
-__global__ void __launch_bounds__(QR_THREADS) tsqr_leaf_forward(int64_t n, int c, int64_t rows_per_chain,
-                                                                const TE* __restrict__ E, double* __restrict__ refl,
-                                                                double* __restrict__ taus, double* __restrict__ Rs) {
+__global__ void __launch_bounds__(QR_MAX_THREADS) tsqr_leaf_forward(int64_t n, int c, int64_t rows_per_chain,
+                                                                    const TE* __restrict__ E, double* __restrict__ refl,
+                                                                    double* __restrict__ taus, double* __restrict__ Rs) {
     extern __shared__ unsigned char smem_raw[];
     double* vbuf = (double*)smem_raw;
-    double* tau_sh = vbuf + TR;
-    SlotT* slot = (SlotT*)(vbuf + TR + 2);
-    const int ch = blockIdx.x, col = threadIdx.x;
+    double* tau_sh = vbuf + NB * TR;
+    SlotT* slot = (SlotT*)(vbuf + STAGE_DOUBLES);
+    const int ch = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
     const int64_t r_begin = ch * rows_per_chain;
     const int64_t r_end = min(n, r_begin + rows_per_chain);
     const int tiles_per_chain = (int)(rows_per_chain / TR);
     slot_zero(slot, c);
     for (int tile = 0; r_begin + (int64_t)tile * TR < r_end; ++tile) {
         const int64_t r0 = r_begin + (int64_t)tile * TR;
-        double a[TR];
+        double a[RPL];
 #pragma unroll
-        for (int t = 0; t < TR; ++t) {
-            const int64_t r = r0 + t;
-            a[t] = (col < c && r < r_end) ? to_f64(E[(int64_t)col * n + r]) : 0.0;
+        for (int i = 0; i < RPL; ++i) {
+            const int64_t r = r0 + i * LPC + g;
+            a[i] = (col < c && r < r_end) ? to_f64(E[(int64_t)col * n + r]) : 0.0;
         }
         const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
         fold_tile(slot, a, c, 0, vbuf, tau_sh, taus + gtile * c);
         if (col < c) {
+            double* dst = refl + (gtile * c + col) * TR;
 #pragma unroll
-            for (int t = 0; t < TR; ++t) refl[(gtile * TR + t) * c + col] = a[t];
+            for (int i = 0; i < RPL; ++i) dst[i * LPC + g] = a[i];
         }
     }
     slot_store(slot, Rs + (int64_t)ch * c * c, c);
 }
 
 template <typename TQ, typename SlotT>
-__global__ void __launch_bounds__(QR_THREADS) tsqr_leaf_backward(int64_t n, int c, int64_t rows_per_chain,
-                                                                 const double* __restrict__ refl,
-                                                                 const double* __restrict__ taus,
-                                                                 const double* __restrict__ Qtop, TQ* __restrict__ Q) {
+__global__ void __launch_bounds__(QR_MAX_THREADS) tsqr_leaf_backward(int64_t n, int c, int64_t rows_per_chain,
+                                                                     const double* __restrict__ refl,
+                                                                     const double* __restrict__ taus,
+                                                                     const double* __restrict__ Qtop, TQ* __restrict__ Q) {
     extern __shared__ unsigned char smem_raw[];
-    double* vbuf = (double*)smem_raw;
-    SlotT* slot = (SlotT*)(vbuf + TR + 2);
-    const int ch = blockIdx.x, col = threadIdx.x;
+    double* vst = (double*)smem_raw;
+    double* tst = vst + NB * TR;
+    SlotT* slot = (SlotT*)(vst + STAGE_DOUBLES);
+    const int ch = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
     const int64_t r_begin = ch * rows_per_chain;
     if (r_begin >= n) return;   // uniform: whole workgroup leaves
     const int64_t r_end = min(n, r_begin + rows_per_chain);
@@ -192,15 +240,15 @@ __global__ void __launch_bounds__(QR_THREADS) tsqr_leaf_backward(int64_t n, int 
     for (int tile = ntiles - 1; tile >= 0; --tile) {
         const int64_t r0 = r_begin + (int64_t)tile * TR;
         const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
-        double a[TR];
+        double a[RPL];
 #pragma unroll
-        for (int t = 0; t < TR; ++t) a[t] = 0.0;
-        unfold_tile(slot, a, c, 0, refl + gtile * TR * c, c, TR, taus + gtile * c, vbuf);
+        for (int i = 0; i < RPL; ++i) a[i] = 0.0;
+        unfold_tile(slot, a, c, 0, refl + gtile * c * TR, taus + gtile * c, vst, tst);
         if (col < c) {
 #pragma unroll
-            for (int t = 0; t < TR; ++t) {
-                const int64_t r = r0 + t;
-                if (r < r_end) Q[(int64_t)col * n + r] = (TQ)a[t];
+            for (int i = 0; i < RPL; ++i) {
+                const int64_t r = r0 + i * LPC + g;
+                if (r < r_end) Q[(int64_t)col * n + r] = (TQ)a[i];
             }
         }
     }
@@ -209,69 +257,68 @@ __global__ void __launch_bounds__(QR_THREADS) tsqr_leaf_backward(int64_t n, int 
 // ---------------------------------------------------------------------------
 // Tree over the per-chain R factors.  At level l, combine i merges chain
 // a = i * 2^(l+1) with b = a + 2^l.  The reflectors of combine (l, i) live at
-// tree_refl[(off_l + i) * c * c] (rows of R_b, row-major) and
-// tree_tau[((off_l + i) * ntile_c + t) * c + j].
+// tree_refl[(off_l + i) * ntc * c * TR] (per row tile of R_b, as in the leaves)
+// and tree_tau[((off_l + i) * ntc + t) * c + j].
 // ---------------------------------------------------------------------------
 template <typename SlotT>
-__global__ void __launch_bounds__(QR_THREADS) tsqr_tree_forward(int c, int stride, int64_t comb_off, double* __restrict__ Rs,
-                                                                double* __restrict__ tree_refl,
-                                                                double* __restrict__ tree_tau) {
+__global__ void __launch_bounds__(QR_MAX_THREADS) tsqr_tree_forward(int c, int stride, int64_t comb_off,
+                                                                    double* __restrict__ Rs,
+                                                                    double* __restrict__ tree_refl,
+                                                                    double* __restrict__ tree_tau) {
     extern __shared__ unsigned char smem_raw[];
     double* vbuf = (double*)smem_raw;
-    double* tau_sh = vbuf + TR;
-    SlotT* slot = (SlotT*)(vbuf + TR + 2);
-    const int i = blockIdx.x, col = threadIdx.x;
+    double* tau_sh = vbuf + NB * TR;
+    SlotT* slot = (SlotT*)(vbuf + STAGE_DOUBLES);
+    const int i = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
     const int a_idx = i * 2 * stride, b_idx = a_idx + stride;
     const double* Rb = Rs + (int64_t)b_idx * c * c;
     const int ntc = (c + TR - 1) / TR;
-    double* rf = tree_refl + (comb_off + i) * (int64_t)c * c;
+    double* rf = tree_refl + (comb_off + i) * (int64_t)ntc * c * TR;
     double* tt = tree_tau + (comb_off + i) * (int64_t)ntc * c;
     slot_load(slot, Rs + (int64_t)a_idx * c * c, c);
     for (int tile = 0; tile < ntc; ++tile) {
-        double a[TR];
+        double a[RPL];
 #pragma unroll
-        for (int t = 0; t < TR; ++t) {
-            const int row = tile * TR + t;
-            a[t] = (col < c && row < c && col >= row) ? Rb[(int64_t)row * c + col] : 0.0;
+        for (int q = 0; q < RPL; ++q) {
+            const int row = tile * TR + q * LPC + g;
+            a[q] = (col < c && row < c && col >= row) ? Rb[(int64_t)row * c + col] : 0.0;
         }
         fold_tile(slot, a, c, tile * TR, vbuf, tau_sh, tt + (int64_t)tile * c);
         if (col < c) {
+            double* dst = rf + ((int64_t)tile * c + col) * TR;
 #pragma unroll
-            for (int t = 0; t < TR; ++t) {
-                const int row = tile * TR + t;
-                if (row < c) rf[(int64_t)row * c + col] = a[t];
-            }
+            for (int q = 0; q < RPL; ++q) dst[q * LPC + g] = a[q];
         }
     }
     slot_store(slot, Rs + (int64_t)a_idx * c * c, c);
 }
 
 template <typename SlotT>
-__global__ void __launch_bounds__(QR_THREADS) tsqr_tree_backward(int c, int stride, int64_t comb_off, double* __restrict__ Qtop,
-                                                                 const double* __restrict__ tree_refl,
-                                                                 const double* __restrict__ tree_tau) {
+__global__ void __launch_bounds__(QR_MAX_THREADS) tsqr_tree_backward(int c, int stride, int64_t comb_off,
+                                                                     double* __restrict__ Qtop,
+                                                                     const double* __restrict__ tree_refl,
+                                                                     const double* __restrict__ tree_tau) {
     extern __shared__ unsigned char smem_raw[];
-    double* vbuf = (double*)smem_raw;
-    SlotT* slot = (SlotT*)(vbuf + TR + 2);
-    const int i = blockIdx.x, col = threadIdx.x;
+    double* vst = (double*)smem_raw;
+    double* tst = vst + NB * TR;
+    SlotT* slot = (SlotT*)(vst + STAGE_DOUBLES);
+    const int i = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
     const int a_idx = i * 2 * stride, b_idx = a_idx + stride;
     const int ntc = (c + TR - 1) / TR;
-    const double* rf = tree_refl + (comb_off + i) * (int64_t)c * c;
+    const double* rf = tree_refl + (comb_off + i) * (int64_t)ntc * c * TR;
     const double* tt = tree_tau + (comb_off + i) * (int64_t)ntc * c;
     double* Qb = Qtop + (int64_t)b_idx * c * c;
     slot_load(slot, Qtop + (int64_t)a_idx * c * c, c);
     for (int tile = ntc - 1; tile >= 0; --tile) {
-        double a[TR];
+        double a[RPL];
 #pragma unroll
-        for (int t = 0; t < TR; ++t) a[t] = 0.0;
-        const int rows_here = min(TR, c - tile * TR);
-        // reflector rows beyond c are zero; pass a row pointer and guard via rows_here
-        unfold_tile(slot, a, c, tile * TR, rf + (int64_t)tile * TR * c, c, rows_here, tt + (int64_t)tile * c, vbuf);
+        for (int q = 0; q < RPL; ++q) a[q] = 0.0;
+        unfold_tile(slot, a, c, tile * TR, rf + (int64_t)tile * c * TR, tt + (int64_t)tile * c, vst, tst);
         if (col < c) {
 #pragma unroll
-            for (int t = 0; t < TR; ++t) {
-                const int row = tile * TR + t;
-                if (t < rows_here) Qb[(int64_t)row * c + col] = a[t];
+            for (int q = 0; q < RPL; ++q) {
+                const int row = tile * TR + q * LPC + g;
+                if (row < c) Qb[(int64_t)row * c + col] = a[q];
             }
         }
     }
@@ -800,7 +847,7 @@ inline int floor_pow2(int64_t x) {
 
 template <typename SlotT>
 size_t slot_smem(int c) {
-    return (TR + 2) * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
+    return STAGE_DOUBLES * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
 }
 
 template <typename TO, typename SlotT>
@@ -816,8 +863,9 @@ int tsqr(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     const size_t tau_bytes = (size_t)nchains * tiles_per_chain * c * 8;
     if ((rc = ensure_ws(h->refl, refl_bytes)) != BFGS_OK) return rc;
     if ((rc = ensure_ws(h->tau, tau_bytes + (size_t)nchains * ntc * c * 8)) != BFGS_OK) return rc;
-    // Rtree: Rs (nchains c*c) + Qtop (nchains c*c) + tree reflectors (nchains c*c)
-    if ((rc = ensure_ws(h->Rtree, (size_t)3 * nchains * c * c * 8)) != BFGS_OK) return rc;
+    // Rtree: Rs (nchains c*c) + Qtop (nchains c*c) + tree reflectors (nchains ntc*c*TR)
+    if ((rc = ensure_ws(h->Rtree, ((size_t)2 * nchains * c * c + (size_t)nchains * ntc * c * TR) * 8)) != BFGS_OK)
+        return rc;
     double* refl = (double*)h->refl.ptr;
     double* taus = (double*)h->tau.ptr;
     double* tree_tau = taus + (size_t)nchains * tiles_per_chain * c;
@@ -825,6 +873,7 @@ int tsqr(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     double* Qtop = Rs + (size_t)nchains * c * c;
     double* tree_refl = Qtop + (size_t)nchains * c * c;
     const size_t smem = slot_smem<SlotT>(c);
+    const int qr_threads = LPC * round_up(c, 16);
     // Raise the dynamic-LDS limit once per instantiation (never while a graph is being captured).
     static bool attr_done = false;
     if (!attr_done) {
@@ -837,7 +886,7 @@ int tsqr(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
         attr_done = true;
     }
     ProfScope ps(h, "tsqr_leaf_fwd");
-    hipLaunchKernelGGL((tsqr_leaf_forward<TO, SlotT>), dim3(nchains), dim3(QR_THREADS), smem, h->stream, n, c,
+    hipLaunchKernelGGL((tsqr_leaf_forward<TO, SlotT>), dim3(nchains), dim3(qr_threads), smem, h->stream, n, c,
                        rows_per_chain, E, refl, taus, Rs);
     prof_end(h);
     prof_begin(h, "tsqr_tree");
@@ -845,7 +894,7 @@ int tsqr(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     int levels = 0;
     for (int stride = 1; stride < nchains; stride *= 2, ++levels) {
         const int ncomb = nchains / (2 * stride);
-        hipLaunchKernelGGL((tsqr_tree_forward<SlotT>), dim3(ncomb), dim3(QR_THREADS), smem, h->stream, c, stride, off, Rs,
+        hipLaunchKernelGGL((tsqr_tree_forward<SlotT>), dim3(ncomb), dim3(qr_threads), smem, h->stream, c, stride, off, Rs,
                            tree_refl, tree_tau);
         off += ncomb;
     }
@@ -853,12 +902,12 @@ int tsqr(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     for (int stride = nchains / 2; stride >= 1; stride /= 2) {
         const int ncomb = nchains / (2 * stride);
         off -= ncomb;
-        hipLaunchKernelGGL((tsqr_tree_backward<SlotT>), dim3(ncomb), dim3(QR_THREADS), smem, h->stream, c, stride, off,
+        hipLaunchKernelGGL((tsqr_tree_backward<SlotT>), dim3(ncomb), dim3(qr_threads), smem, h->stream, c, stride, off,
                            Qtop, tree_refl, tree_tau);
     }
     prof_end(h);
     prof_begin(h, "tsqr_leaf_bwd");
-    hipLaunchKernelGGL((tsqr_leaf_backward<TO, SlotT>), dim3(nchains), dim3(QR_THREADS), smem, h->stream, n, c,
+    hipLaunchKernelGGL((tsqr_leaf_backward<TO, SlotT>), dim3(nchains), dim3(qr_threads), smem, h->stream, n, c,
                        rows_per_chain, refl, taus, Qtop, Q);
     *R_out = Rs;   // chain 0 holds the final R (row-major, upper triangular)
     return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
