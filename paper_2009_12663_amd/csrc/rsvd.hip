@@ -537,22 +537,24 @@ __global__ void __launch_bounds__(SMALL_THREADS) omega_solve(int c, double* __re
     if (tid == 0 && bad) set_status(status, BFGS_ERR_NUMERIC);
 }
 
-// Symmetric eigendecomposition of A (row-major c x c, overwritten): Householder
-// tridiagonalisation with explicit accumulation, then implicit QL iterations
-// with Wilkinson-type shifts; rotation angles are computed by one thread and
-// applied to the rows of the eigenvector matrix in parallel.
+// Symmetric eigendecomposition of A (row-major c x c, overwritten), in four kernels:
+//   sym_tridiag        Householder tridiagonalisation (one workgroup); reflector kk
+//                      (unit first entry, acting on rows kk+1..c-1) is stored
+//                      contiguously at V[kk * c + r] with tau in taus[kk]
+//   householder_accum  Z = H_0 H_1 ... H_{c-3} explicitly, one wave per column
+//   ql_tridiag         implicit QL with Wilkinson-type shifts on (d, e), one wave:
+//                      deflation tests in parallel (ballot), the sweep itself is
+//                      evaluated uniformly by the wave; every sweep's rotations are
+//                      recorded (sweep q: rows l..m, angles at rot[2 * (off + i - l)])
+//   apply_rotations    Z <- Z G (the recorded rotations), rows in parallel
 // Z: column-major c x c eigenvectors (Z[i*c + r] = component r of vector i).
-__global__ void __launch_bounds__(SMALL_THREADS) sym_eig(int c, double* __restrict__ A, double* __restrict__ Z,
-                                                         double* __restrict__ dg, double* __restrict__ eg,
-                                                         double* __restrict__ taus, double* __restrict__ rot,
-                                                         int* __restrict__ sweeps, int* __restrict__ nsweeps_out,
-                                                         int64_t max_rot, int max_sweeps,
-                                                         int32_t* __restrict__ status) {
+__global__ void __launch_bounds__(SMALL_THREADS) sym_tridiag(int c, double* __restrict__ A, double* __restrict__ V,
+                                                             double* __restrict__ dg, double* __restrict__ eg,
+                                                             double* __restrict__ taus) {
     __shared__ double red[SMALL_THREADS / 64];
     __shared__ double vsh[256];
     __shared__ double wsh[256];
     const int tid = threadIdx.x;
-    // --- tridiagonalisation: for column kk, reflect rows kk+1..c-1 ---
     for (int kk = 0; kk + 2 < c; ++kk) {
         const int m = c - kk - 1;   // length of x = A(kk+1:, kk)
         double part = 0.0;
@@ -568,18 +570,19 @@ __global__ void __launch_bounds__(SMALL_THREADS) sym_eig(int c, double* __restri
             tau = (beta - alpha) / beta;
             scale = 1.0 / (alpha - beta);
         }
-        for (int i = tid; i < m; i += SMALL_THREADS)
-            vsh[i] = (i == 0) ? 1.0 : A[(int64_t)(kk + 1 + i) * c + kk] * scale;
+        for (int i = tid; i < m; i += SMALL_THREADS) {
+            const double v = (i == 0) ? 1.0 : A[(int64_t)(kk + 1 + i) * c + kk] * scale;
+            vsh[i] = v;
+            V[(int64_t)kk * c + kk + 1 + i] = v;
+        }
         __syncthreads();
         if (tid == 0) {
             taus[kk] = tau;
             dg[kk] = A[(int64_t)kk * c + kk];
             eg[kk] = beta;
         }
-        // keep v below the subdiagonal for the accumulation step
-        for (int i = 1 + tid; i < m; i += SMALL_THREADS) A[(int64_t)(kk + 1 + i) * c + kk] = vsh[i];
         if (tau != 0.0) {
-            // p = tau * A22 v
+            // p = tau * A22 v;  w = p - (tau/2)(p^T v) v;  A22 -= v w^T + w v^T
             for (int i = tid; i < m; i += SMALL_THREADS) {
                 const double* row = A + (int64_t)(kk + 1 + i) * c + (kk + 1);
                 wsh[i] = tau * dot8(row, vsh, m);
@@ -601,89 +604,146 @@ __global__ void __launch_bounds__(SMALL_THREADS) sym_eig(int c, double* __restri
         if (c >= 2) {
             dg[c - 2] = A[(int64_t)(c - 2) * c + (c - 2)];
             eg[c - 2] = A[(int64_t)(c - 1) * c + (c - 2)];
+            taus[c - 2] = 0.0;
         }
         dg[c - 1] = A[(int64_t)(c - 1) * c + (c - 1)];
         eg[c - 1] = 0.0;
-        if (c >= 2) taus[c - 2] = 0.0;
     }
-    // --- accumulate the orthogonal factor: Z = H_0 H_1 ... (column-major) ---
-    for (int q = tid; q < c * c; q += SMALL_THREADS) Z[q] = (q / c == q % c) ? 1.0 : 0.0;
-    __syncthreads();
+}
+
+__device__ __forceinline__ double wave_sum_d(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Column col of Z = H_0 H_1 ... H_{c-3} e_col: the reflectors are applied to e_col
+// from the last to the first.  One wave per column; lane holds rows lane + 64 q.
+__global__ void __launch_bounds__(256) householder_accum(int c, const double* __restrict__ V,
+                                                         const double* __restrict__ taus, double* __restrict__ Z) {
+    const int lane = threadIdx.x & 63;
+    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= c) return;   // uniform per wave
+    double z[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) z[q] = (lane + 64 * q == col) ? 1.0 : 0.0;
     for (int kk = c - 3; kk >= 0; --kk) {
         const double tau = taus[kk];
-        const int m = c - kk - 1;
         if (tau == 0.0) continue;
-        for (int i = tid; i < m; i += SMALL_THREADS) vsh[i] = (i == 0) ? 1.0 : A[(int64_t)(kk + 1 + i) * c + kk];
-        __syncthreads();
-        // columns kk+1.. of Z, rows kk+1..: Z_sub -= tau v (v^T Z_sub)
-        for (int col = kk + 1 + tid; col < c; col += SMALL_THREADS) {
-            double* zc = Z + (int64_t)col * c + (kk + 1);
-            const double s = tau * dot8(zc, vsh, m);
-            for (int i = 0; i < m; ++i) zc[i] -= s * vsh[i];
+        double v[4];
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = lane + 64 * q;
+            v[q] = (r > kk && r < c) ? V[(int64_t)kk * c + r] : 0.0;
+            s = fma(v[q], z[q], s);
         }
-        __syncthreads();
+        s = tau * wave_sum_d(s);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) z[q] = fma(-s, v[q], z[q]);
     }
-    // --- implicit QL on (d, e): e[i] couples d[i] and d[i+1].  Thread 0 runs the
-    // iteration and records every sweep's rotations (sweep q: rows l..m, angles at
-    // rot[2 * (off + i - l)] for i = m-1 .. l); apply_rotations applies them to Z. ---
-    __syncthreads();
-    // QL iterations on LDS copies of d and e (every access below is on the dependent chain)
-    __shared__ double dl[256], el[256];
-    for (int i = tid; i < c; i += SMALL_THREADS) {
-        dl[i] = dg[i];
-        el[i] = eg[i];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = lane + 64 * q;
+        if (r < c) Z[(int64_t)col * c + r] = z[q];
+    }
+}
+
+// 1 / sqrt(t) for t > 0 (hardware estimate refined by two Newton steps).
+__device__ __forceinline__ double rsqrt_refined(double t) {
+    double y = __builtin_amdgcn_rsq(t);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double ty = t * y;
+        const double e = fma(-ty, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+__global__ void __launch_bounds__(64) ql_tridiag(int c, double* __restrict__ dg, const double* __restrict__ eg,
+                                                 double* __restrict__ rot, int* __restrict__ sweeps,
+                                                 int* __restrict__ nsweeps_out, int64_t max_rot, int max_sweeps,
+                                                 int32_t* __restrict__ status) {
+    // d[-1] and e[-1] exist so that the sweep can read one entry ahead unconditionally
+    __shared__ double d_pad[257], e_pad[257];
+    double* d = d_pad + 1;
+    double* e = e_pad + 1;
+    const int lane = threadIdx.x;
+    for (int i = lane; i < c; i += 64) {
+        d[i] = dg[i];
+        e[i] = eg[i];
+    }
+    if (lane == 0) {
+        d_pad[0] = 0.0;
+        e_pad[0] = 0.0;
     }
     __syncthreads();
-    double* d = dl;
-    double* e = el;
-    if (tid == 0) {
-        int nsw = 0;
-        int64_t off = 0;
-        int fail = 0;
-        for (int l = 0; l < c && !fail; ++l) {
-            int iter = 0;
-            while (true) {
-                int m = l;
-                for (; m < c - 1; ++m) {
-                    const double dd = fabs(d[m]) + fabs(d[m + 1]);
-                    if (fabs(e[m]) + dd == dd) break;
+    int nsw = 0;
+    int64_t off = 0;
+    int fail = 0;
+    for (int l = 0; l < c && !fail; ++l) {
+        int iter = 0;
+        while (true) {
+            // smallest m >= l with m == c-1 or e[m] negligible against d[m], d[m+1]
+            int m = c - 1;
+            for (int base = l; base < c - 1; base += 64) {
+                const int mm = base + lane;
+                bool hit = true;
+                if (mm < c - 1) {
+                    const double dd = fabs(d[mm]) + fabs(d[mm + 1]);
+                    hit = (fabs(e[mm]) + dd == dd);
                 }
-                if (m == l) break;
-                if (++iter > 60 || nsw >= max_sweeps || off + (m - l) > max_rot) {
-                    fail = 1;
+                const unsigned long long bal = __ballot(hit);
+                if (bal) {
+                    m = min(c - 1, base + __ffsll((long long)bal) - 1);
                     break;
                 }
+            }
+            if (m == l) break;
+            if (++iter > 60 || nsw >= max_sweeps || off + (m - l) > max_rot) {
+                fail = 1;
+                break;
+            }
+            // one lane runs the sweep (single-lane LDS traffic, no exec changes inside)
+            if (lane == 0) {
                 double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-                double r = sqrt(fma(g, g, 1.0));
-                g = d[m] - d[l] + e[l] / (g + copysign(r, g));
+                const double r0 = sqrt(fma(g, g, 1.0));
+                g = d[m] - d[l] + e[l] / (g + copysign(r0, g));
                 double sn = 1.0, cs = 1.0, p = 0.0;
                 bool early = false;
+                double ei = e[m - 1], di = d[m - 1], dip1 = d[m];
+                double* rr = rot + 2 * off;
                 for (int i = m - 1; i >= l; --i) {
-                    const double f = sn * e[i];
-                    const double b = cs * e[i];
-                    r = sqrt(fma(f, f, g * g));
-                    e[i + 1] = r;
-                    double* rr = rot + 2 * (off + (i - l));
-                    if (r == 0.0) {
-                        d[i + 1] -= p;
+                    const double ei_next = e[i - 1];   // i - 1 >= -1: padded
+                    const double di_next = d[i - 1];
+                    const double f = sn * ei;
+                    const double b = cs * ei;
+                    const double t = fma(f, f, g * g);
+                    if (t == 0.0) {
+                        d[i + 1] = dip1 - p;
                         e[m] = 0.0;
                         early = true;
-                        for (int q = i; q >= l; --q) {
-                            rot[2 * (off + (q - l))] = 1.0;
-                            rot[2 * (off + (q - l)) + 1] = 0.0;
+                        for (int q = 0; q <= i - l; ++q) {
+                            rr[2 * q] = 1.0;
+                            rr[2 * q + 1] = 0.0;
                         }
                         break;
                     }
-                    const double ri = 1.0 / r;
+                    const double ri = rsqrt_refined(t);
+                    e[i + 1] = t * ri;
                     sn = f * ri;
                     cs = g * ri;
-                    g = d[i + 1] - p;
-                    r = (d[i] - g) * sn + 2.0 * cs * b;
+                    g = dip1 - p;
+                    const double r = fma(di - g, sn, 2.0 * cs * b);
                     p = sn * r;
                     d[i + 1] = g + p;
-                    g = cs * r - b;
-                    rr[0] = cs;
-                    rr[1] = sn;
+                    g = fma(cs, r, -b);
+                    rr[2 * (i - l)] = cs;
+                    rr[2 * (i - l) + 1] = sn;
+                    dip1 = di;
+                    di = di_next;
+                    ei = ei_next;
                 }
                 if (!early) {
                     d[l] -= p;
@@ -693,36 +753,61 @@ __global__ void __launch_bounds__(SMALL_THREADS) sym_eig(int c, double* __restri
                 sweeps[3 * nsw + 0] = l;
                 sweeps[3 * nsw + 1] = m;
                 sweeps[3 * nsw + 2] = (int)off;
-                ++nsw;
-                off += m - l;
             }
+            __syncthreads();
+            ++nsw;
+            off += m - l;
         }
+    }
+    __syncthreads();
+    if (lane == 0) {
         nsweeps_out[0] = nsw;
         if (fail) set_status(status, BFGS_ERR_NUMERIC);
     }
-    __syncthreads();
-    for (int i = tid; i < c; i += SMALL_THREADS) dg[i] = dl[i];
+    for (int i = lane; i < c; i += 64) dg[i] = d[i];
 }
 
 // Applies the recorded QL rotations to the rows of Z (column-major c x c); one
-// 64-lane workgroup per 64 rows, rows resident in LDS ([i][lane] layout).  A
-// sweep's rotations form a chain through the shared column, carried in a register.
+// 64-lane workgroup per 64 rows, rows resident in LDS ([i][lane] layout), each
+// sweep's angles staged in LDS.  A sweep's rotations form a chain through the
+// shared column, carried in a register.
 __global__ void __launch_bounds__(64) apply_rotations(int c, const int* __restrict__ nsweeps_p,
                                                       const int* __restrict__ sweeps, const double* __restrict__ rot,
                                                       double* __restrict__ Z) {
-    extern __shared__ double zr[];   // [c][64]
+    extern __shared__ double zr[];   // [c][64], then 2 * c staged angles
+    double* rs = zr + (size_t)c * 64;
     const int lane = threadIdx.x;
     const int r = blockIdx.x * 64 + lane;
     for (int i = 0; i < c; ++i) zr[i * 64 + lane] = r < c ? Z[(int64_t)i * c + r] : 0.0;
     const int nsw = nsweeps_p[0];
     for (int q = 0; q < nsw; ++q) {
         const int l = sweeps[3 * q], m = sweeps[3 * q + 1], off = sweeps[3 * q + 2];
+        __syncthreads();
+        for (int e = lane; e < 2 * (m - l); e += 64) rs[e] = rot[2 * (int64_t)off + e];
+        __syncthreads();
         double carry = zr[m * 64 + lane];
-        for (int i = m - 1; i >= l; --i) {
-            const double cs = rot[2 * (off + (i - l))], sn = rot[2 * (off + (i - l)) + 1];
+        int i = m - 1;
+        // blocks of 8: the operands of 8 steps are loaded before any of them stores
+        // (step j overwrites entry j + 1, which step j + 1 has already read)
+        for (; i - 7 >= l; i -= 8) {
+            double zb[8], cb[8], sb[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                zb[u] = zr[(i - u) * 64 + lane];
+                cb[u] = rs[2 * (i - u - l)];
+                sb[u] = rs[2 * (i - u - l) + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                zr[(i - u + 1) * 64 + lane] = fma(sb[u], zb[u], cb[u] * carry);
+                carry = fma(cb[u], zb[u], -sb[u] * carry);
+            }
+        }
+        for (; i >= l; --i) {
+            const double cs = rs[2 * (i - l)], sn = rs[2 * (i - l) + 1];
             const double zi = zr[i * 64 + lane];
-            zr[(i + 1) * 64 + lane] = sn * zi + cs * carry;
-            carry = cs * zi - sn * carry;
+            zr[(i + 1) * 64 + lane] = fma(sn, zi, cs * carry);
+            carry = fma(cs, zi, -sn * carry);
         }
         zr[l * 64 + lane] = carry;
     }
@@ -1002,14 +1087,17 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     hipLaunchKernelGGL(omega_solve, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, Tm, R, Bm, Om, piv, h->status);
     prof_end(h);
     prof_begin(h, "sym_eig");
-    hipLaunchKernelGGL(sym_eig, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, Om, Zm, dv, ev, tv, rotbuf, sweeps,
-                       nsweeps, max_rot, max_sweeps, h->status);
+    // Bm (the LU right-hand sides) is free after omega_solve: it holds the reflectors
+    hipLaunchKernelGGL(sym_tridiag, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, Om, Bm, dv, ev, tv);
+    hipLaunchKernelGGL(householder_accum, dim3(ceil_div(c, 4)), dim3(256), 0, h->stream, c, Bm, tv, Zm);
+    hipLaunchKernelGGL(ql_tridiag, dim3(1), dim3(64), 0, h->stream, c, dv, ev, rotbuf, sweeps, nsweeps, max_rot,
+                       max_sweeps, h->status);
     {
-        const size_t smem_rot = (size_t)c * 64 * sizeof(double);
+        const size_t smem_rot = (size_t)c * 66 * sizeof(double);
         static bool attr = false;
         if (!attr) {
             (void)hipFuncSetAttribute((const void*)apply_rotations, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      256 * 64 * (int)sizeof(double));
+                                      256 * 66 * (int)sizeof(double));
             attr = true;
         }
         hipLaunchKernelGGL(apply_rotations, dim3(ceil_div(c, 64)), dim3(64), smem_rot, h->stream, c, nsweeps, sweeps,
