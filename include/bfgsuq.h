@@ -71,9 +71,12 @@ enum {
  *   storage  type in which pairs, h0 and probes are stored
  *   stream   hipStream_t to enqueue on (NULL = the null stream)
  *   out      (host) receives the handle
- * Allocates about 2 * n * k_max * sizeof(storage) bytes (twice that for the
- * bfloat16 form, which keeps a second, row-blocked copy of S and Y) plus
- * O(k_max^2) float64 and small workspaces.  Synchronous.                      */
+ * Allocates about 2 * n * k_max * sizeof(storage) bytes for S and Y (three
+ * times that for the bfloat16 form, which also keeps two copies laid out as
+ * the matrix-core fragments of the two apply passes read them) plus
+ * O(k_max^2) float64 and small workspaces.  Probe, TSQR and basis workspaces
+ * (about n * (rank + oversample) * 20 bytes) are allocated on the first
+ * rSVD and kept.  Synchronous.                                                */
 int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, void* stream,
                 bfgs_t* out);
 
