@@ -441,93 +441,189 @@ __device__ double wg_sum(double v, double* red) {
 // Omega = F T^-1, symmetrised.  T column-major c x c (T[j*c + i] = T(i, j)).
 // F = R, row-major c x c upper triangular.  Work: M = T^T (row-major M[i*c + j] =
 // T(j, i) = T[i*c + j], i.e. the same array), B = F^T; solve M X = B, Omega = X^T.
-__global__ void __launch_bounds__(SMALL_THREADS) omega_solve(int c, double* __restrict__ M, const double* __restrict__ F,
-                                                             double* __restrict__ B, double* __restrict__ Omega,
-                                                             int* __restrict__ piv, int32_t* __restrict__ status) {
-    __shared__ double red_v[SMALL_THREADS];
-    __shared__ int red_i[SMALL_THREADS];
-    __shared__ double lcol[256], urow[256];
+//
+// Blocked right-looking LU with partial pivoting in one workgroup: a panel of
+// LU_NB columns is factored in LDS; each column of the rest of [M | B] then
+// takes the panel's row swaps and the forward substitution with the panel's
+// unit-lower block (one thread per column); the trailing rows are updated from
+// the panel (L21) and the new U row block, both in LDS.  The backward
+// substitution with U is blocked the same way.
+constexpr int LU_NB = 16;
+constexpr int LU_THREADS = 1024;
+constexpr int LU_PLD = LU_NB + 1;        // panel row stride (doubles)
+constexpr int LU_ULD = 2 * 256 + 1;      // row-block stride: M's right columns then B's columns
+
+size_t omega_smem_bytes() { return ((size_t)256 * LU_PLD + (size_t)LU_NB * LU_ULD + LU_NB + 8) * sizeof(double); }
+
+__global__ void __launch_bounds__(LU_THREADS) omega_solve(int c, double* __restrict__ M, const double* __restrict__ F,
+                                                          double* __restrict__ B, double* __restrict__ Omega,
+                                                          int* __restrict__ piv, int32_t* __restrict__ status) {
+    extern __shared__ double lu_sh[];
+    double* P = lu_sh;                              // panel rows kb..c-1: P[(r - kb) * LU_PLD + j]
+    double* Ub = P + 256 * LU_PLD;                  // row block: Ub[i * LU_ULD + ec]
+    double* red = Ub + LU_NB * LU_ULD;              // pivot value / index exchange
+    __shared__ int pivl[LU_NB];
     __shared__ int bad;
     const int tid = threadIdx.x;
     if (tid == 0) bad = 0;
     // B(i, j) = F(j, i), row-major B[i*c + j]
-    for (int e = tid; e < c * c; e += SMALL_THREADS) {
+    for (int e = tid; e < c * c; e += LU_THREADS) {
         const int i = e / c, j = e % c;
         B[e] = F[(int64_t)j * c + i];
     }
     __syncthreads();
-    for (int kk = 0; kk < c; ++kk) {
-        double best = -1.0;
-        int bi = kk;
-        for (int i = kk + tid; i < c; i += SMALL_THREADS) {
-            const double v = fabs(M[(int64_t)i * c + kk]);
-            if (v > best) { best = v; bi = i; }
+    for (int kb = 0; kb < c; kb += LU_NB) {
+        const int nb = min(LU_NB, c - kb);
+        const int rows = c - kb;
+        for (int e = tid; e < rows * nb; e += LU_THREADS) {
+            const int r = e / nb, j = e % nb;
+            P[r * LU_PLD + j] = M[(int64_t)(kb + r) * c + kb + j];
         }
-        red_v[tid] = best;
-        red_i[tid] = bi;
         __syncthreads();
-        for (int s = SMALL_THREADS / 2; s > 0; s >>= 1) {
-            if (tid < s) {
-                const double v2 = red_v[tid + s];
-                const int i2 = red_i[tid + s];
-                if (v2 > red_v[tid] || (v2 == red_v[tid] && i2 < red_i[tid])) {
-                    red_v[tid] = v2;
-                    red_i[tid] = i2;
+        // --- panel factorisation in LDS ---
+        for (int j = 0; j < nb; ++j) {
+            if (tid < 64) {
+                double best = -1.0;
+                int bi = j;
+                for (int r = j + tid; r < rows; r += 64) {
+                    const double v = fabs(P[r * LU_PLD + j]);
+                    if (v > best) { best = v; bi = r; }
+                }
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double v2 = __shfl_xor(best, off, 64);
+                    const int i2 = __shfl_xor(bi, off, 64);
+                    if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
+                }
+                if (tid == 0) {
+                    pivl[j] = bi;
+                    piv[kb + j] = kb + bi;
+                    if (!(best > 0.0) || !isfinite(best)) bad = 1;
                 }
             }
             __syncthreads();
+            const int p = pivl[j];
+            if (p != j && tid < nb) {
+                const double t = P[j * LU_PLD + tid];
+                P[j * LU_PLD + tid] = P[p * LU_PLD + tid];
+                P[p * LU_PLD + tid] = t;
+            }
+            __syncthreads();
+            const double d = P[j * LU_PLD + j];
+            for (int r = j + 1 + tid; r < rows; r += LU_THREADS) {
+                const double l = d != 0.0 ? P[r * LU_PLD + j] / d : 0.0;
+                P[r * LU_PLD + j] = l;
+                for (int jj = j + 1; jj < nb; ++jj) P[r * LU_PLD + jj] = fma(-l, P[j * LU_PLD + jj], P[r * LU_PLD + jj]);
+            }
+            __syncthreads();
         }
-        const int p = red_i[0];
-        const double pv = red_v[0];
-        if (tid == 0) {
-            piv[kk] = p;
-            if (!(pv > 0.0) || !isfinite(pv)) bad = 1;
+        for (int e = tid; e < rows * nb; e += LU_THREADS) {
+            const int r = e / nb, j = e % nb;
+            M[(int64_t)(kb + r) * c + kb + j] = P[r * LU_PLD + j];
         }
-        if (p != kk) {
-            for (int j = tid; j < c; j += SMALL_THREADS) {
-                double t = M[(int64_t)kk * c + j];
-                M[(int64_t)kk * c + j] = M[(int64_t)p * c + j];
-                M[(int64_t)p * c + j] = t;
-                t = B[(int64_t)kk * c + j];
-                B[(int64_t)kk * c + j] = B[(int64_t)p * c + j];
-                B[(int64_t)p * c + j] = t;
+        // --- swaps and forward substitution, one thread per column outside the panel ---
+        // extended column ec: [0, kb) M left columns (swaps only); [kb + nb, c) M right
+        // columns; then c columns of B
+        const int right = c - kb - nb;
+        for (int ec = tid; ec < kb + right + c; ec += LU_THREADS) {
+            double* col;
+            int stride = c;
+            int ub = -1;
+            if (ec < kb) {
+                col = M + ec;
+            } else if (ec < kb + right) {
+                col = M + (kb + nb + (ec - kb));
+                ub = ec - kb;
+            } else {
+                col = B + (ec - kb - right);
+                ub = right + (ec - kb - right);
+            }
+            for (int j = 0; j < nb; ++j) {
+                const int p = pivl[j];
+                if (p != j) {
+                    const double t = col[(int64_t)(kb + j) * stride];
+                    col[(int64_t)(kb + j) * stride] = col[(int64_t)(kb + p) * stride];
+                    col[(int64_t)(kb + p) * stride] = t;
+                }
+            }
+            if (ub >= 0) {
+                double x[LU_NB];
+#pragma unroll
+                for (int i = 0; i < LU_NB; ++i) {
+                    if (i < nb) {
+                        double v = col[(int64_t)(kb + i) * stride];
+#pragma unroll
+                        for (int l = 0; l < LU_NB; ++l)
+                            if (l < i) v = fma(-P[i * LU_PLD + l], x[l], v);
+                        x[i] = v;
+                        col[(int64_t)(kb + i) * stride] = v;
+                        Ub[i * LU_ULD + ub] = v;
+                    }
+                }
             }
         }
         __syncthreads();
-        const double d = M[(int64_t)kk * c + kk];
-        for (int i = kk + 1 + tid; i < c; i += SMALL_THREADS) {
-            const double l = d != 0.0 ? M[(int64_t)i * c + kk] / d : 0.0;
-            M[(int64_t)i * c + kk] = l;
-            lcol[i] = l;
-        }
-        for (int j = kk + 1 + tid; j < c; j += SMALL_THREADS) urow[j] = M[(int64_t)kk * c + j];
-        __syncthreads();
-        const int m = c - kk - 1;
-        for (int e = tid; e < m * m; e += SMALL_THREADS) {
-            const int i = kk + 1 + e / m, j = kk + 1 + e % m;
-            M[(int64_t)i * c + j] -= lcol[i] * urow[j];
+        // --- trailing update of rows kb + nb .. c-1 over M's right columns and B ---
+        const int trows = rows - nb;
+        const int wcols = right + c;
+        for (int e = tid; e < trows * wcols; e += LU_THREADS) {
+            const int rr = e / wcols, ec = e % wcols;
+            double* dst = ec < right ? M + (int64_t)(kb + nb + rr) * c + kb + nb + ec
+                                     : B + (int64_t)(kb + nb + rr) * c + (ec - right);
+            const double* lrow = P + (nb + rr) * LU_PLD;
+            double acc = *dst;
+            for (int i = 0; i < nb; ++i) acc = fma(-lrow[i], Ub[i * LU_ULD + ec], acc);
+            *dst = acc;
         }
         __syncthreads();
     }
-    // forward (unit lower) then backward (upper) substitution, one right-hand side per thread
-    for (int j = tid; j < c; j += SMALL_THREADS) {
-        for (int i = 0; i < c; ++i) {
-            double p8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            const double* mr = M + (int64_t)i * c;
-            for (int l = 0; l < i; ++l) p8[l & 7] = fma(mr[l], B[(int64_t)l * c + j], p8[l & 7]);
-            B[(int64_t)i * c + j] -= ((p8[0] + p8[1]) + (p8[2] + p8[3])) + ((p8[4] + p8[5]) + (p8[6] + p8[7]));
+    // --- backward substitution U X = B, blocks from the bottom ---
+    const int nblk = (c + LU_NB - 1) / LU_NB;
+    for (int bidx = nblk - 1; bidx >= 0; --bidx) {
+        const int kb = bidx * LU_NB;
+        const int nb = min(LU_NB, c - kb);
+        // U11 (nb x nb) into Ub's first rows; U[0:kb, kb:kb+nb] into P
+        for (int e = tid; e < nb * nb; e += LU_THREADS) {
+            const int i = e / nb, j = e % nb;
+            Ub[i * LU_ULD + j] = M[(int64_t)(kb + i) * c + kb + j];
         }
-        for (int i = c - 1; i >= 0; --i) {
-            double p8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            const double* mr = M + (int64_t)i * c;
-            for (int l = i + 1; l < c; ++l) p8[l & 7] = fma(mr[l], B[(int64_t)l * c + j], p8[l & 7]);
-            const double sum = ((p8[0] + p8[1]) + (p8[2] + p8[3])) + ((p8[4] + p8[5]) + (p8[6] + p8[7]));
-            B[(int64_t)i * c + j] = (B[(int64_t)i * c + j] - sum) / mr[i];
+        for (int e = tid; e < kb * nb; e += LU_THREADS) {
+            const int r = e / nb, j = e % nb;
+            P[r * LU_PLD + j] = M[(int64_t)r * c + kb + j];
         }
+        __syncthreads();
+        double* X = Ub + LU_NB;   // X[i * LU_ULD + col] for col < c (offset past U11's columns)
+        for (int col = tid; col < c; col += LU_THREADS) {
+            double x[LU_NB];
+#pragma unroll
+            for (int ii = LU_NB - 1; ii >= 0; --ii) {
+                if (ii < nb) {
+                    double v = B[(int64_t)(kb + ii) * c + col];
+#pragma unroll
+                    for (int l = 0; l < LU_NB; ++l)
+                        if (l > ii && l < nb) v = fma(-Ub[ii * LU_ULD + l], x[l], v);
+                    const double dii = Ub[ii * LU_ULD + ii];
+                    v = dii != 0.0 ? v / dii : 0.0;
+                    x[ii] = v;
+                    B[(int64_t)(kb + ii) * c + col] = v;
+                }
+            }
+#pragma unroll
+            for (int ii = 0; ii < LU_NB; ++ii)
+                if (ii < nb) X[ii * LU_ULD + col] = x[ii];
+        }
+        __syncthreads();
+        for (int e = tid; e < kb * c; e += LU_THREADS) {
+            const int r = e / c, col = e % c;
+            const double* urow = P + r * LU_PLD;
+            double acc = B[(int64_t)r * c + col];
+            for (int i = 0; i < nb; ++i) acc = fma(-urow[i], X[i * LU_ULD + col], acc);
+            B[(int64_t)r * c + col] = acc;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     // X = B (row-major); Omega = X^T; symmetrise.  Omega(i, j) = (X(j, i) + X(i, j)) / 2
-    for (int e = tid; e < c * c; e += SMALL_THREADS) {
+    for (int e = tid; e < c * c; e += LU_THREADS) {
         const int i = e / c, j = e % c;
         const double v = 0.5 * (B[(int64_t)j * c + i] + B[(int64_t)i * c + j]);
         Omega[e] = v;
@@ -1084,7 +1180,17 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
                        Tm);
     prof_end(h);
     prof_begin(h, "omega_lu");
-    hipLaunchKernelGGL(omega_solve, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, Tm, R, Bm, Om, piv, h->status);
+    {
+        static bool attr = false;
+        if (!attr) {
+            if (hipFuncSetAttribute((const void*)omega_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)omega_smem_bytes()) != hipSuccess)
+                return BFGS_ERR_HIP;
+            attr = true;
+        }
+        hipLaunchKernelGGL(omega_solve, dim3(1), dim3(LU_THREADS), omega_smem_bytes(), h->stream, c, Tm, R, Bm, Om,
+                           piv, h->status);
+    }
     prof_end(h);
     prof_begin(h, "sym_eig");
     // Bm (the LU right-hand sides) is free after omega_solve: it holds the reflectors
