@@ -37,11 +37,37 @@ constexpr int LPC = 4;          // lanes per column (a quad); lane g owns tile r
 constexpr int RPL = TR / LPC;   // tile rows per lane
 constexpr int QR_MAX_THREADS = 1024;  // c <= 256 columns x LPC
 constexpr int NB = 16;          // reflectors staged per barrier when applying known reflectors
+constexpr int PANEL = 16;       // columns per wave and per panel of the fold (64 lanes / LPC)
 constexpr int SLOT_F64_MAX_C = 180;
 
 __device__ __forceinline__ int tri_index(int j, int col, int c) {
     // packed upper triangle, row-major: row j holds columns j..c-1
     return j * c - (j * (j - 1)) / 2 + (col - j);
+}
+
+// 1 / sqrt(t) for t > 0, denormal t included (hardware estimate refined by two
+// Newton steps).
+__device__ __forceinline__ double rsqrt_refined(double t) {
+    double y = __builtin_amdgcn_rsq(t);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double ty = t * y;
+        const double e = fma(-ty, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+// 1 / x for normal x with |x| < 2^1022 (hardware estimate refined by two Newton
+// steps).  The estimate overflows for denormal x, so callers keep x normal.
+__device__ __forceinline__ double rcp_refined(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x, y, 1.0);
+        y = fma(y, e, y);
+    }
+    return y;
 }
 
 // Exchange within a quad of lanes (DPP quad_perm); every lane of the quad must be active.
@@ -84,9 +110,16 @@ __device__ __forceinline__ void make_reflector(SlotT* slot, double (&a)[RPL], in
     const double rjj = (double)slot[dj];
     double tau = 0.0;
     if (xn2 > 0.0) {
-        const double beta = -copysign(sqrt(fma(rjj, rjj, xn2)), rjj);
-        tau = (beta - rjj) / beta;
-        const double sc = 1.0 / (rjj - beta);
+        // beta = -sign(rjj) |(rjj, x)|, tau = (beta - rjj) / beta, v = x / (rjj - beta).
+        // |beta| and |rjj - beta| are at least sqrt(xn2) >= 2^-537, so both reciprocals
+        // are of normal numbers.  (Their product is not: a chain whose tiles have fewer
+        // rows than columns drives the later columns' norms down to rounding noise of
+        // rounding noise, below 1e-300.)
+        const double t = fma(rjj, rjj, xn2);
+        const double beta = -copysign(t * rsqrt_refined(t), rjj);
+        const double u = rjj - beta;
+        tau = -u * rcp_refined(beta);
+        const double sc = rcp_refined(u);
 #pragma unroll
         for (int i = 0; i < RPL; ++i) a[i] *= sc;
         if (g == 0) slot[dj] = (SlotT)beta;
@@ -114,8 +147,9 @@ __device__ __forceinline__ void reflect_column(SlotT* slot, double (&a)[RPL], in
 
 // Forward: fold the tile (a[] = this quad's column, TR rows) into the slot with
 // reflectors jstart..c-1.  Reflector j's tile part replaces column j's a[].
-// vbuf holds two reflectors (double buffer) so one barrier per reflector suffices:
-// the quad of column j+1 builds reflector j+1 as soon as it has applied reflector j.
+// Reflectors alternate between two LDS buffers so one barrier per reflector
+// suffices: the quad of column j+1 builds reflector j+1 as soon as it has applied
+// reflector j.
 template <typename SlotT>
 __device__ void fold_tile(SlotT* slot, double (&a)[RPL], int c, int jstart, double* vbuf, double* tau_sh,
                           double* taus_out) {
@@ -181,9 +215,11 @@ __device__ void slot_store(const SlotT* slot, double* M, int c) {
     __syncthreads();
 }
 
-// LDS layout shared by the four TSQR kernels: reflector staging (NB x TR doubles;
-// the forward pass uses the first 2 x TR as its double buffer), NB taus, then the slot.
-constexpr int STAGE_DOUBLES = NB * TR + NB;
+// LDS layout shared by the four TSQR kernels: two reflector panels (2 x PANEL x TR
+// doubles; the backward pass stages NB reflectors in the first), 2 x PANEL taus,
+// then the slot.
+constexpr int STAGE_DOUBLES = 2 * PANEL * TR + 2 * PANEL;
+static_assert(NB <= 2 * PANEL, "staging buffer too small");
 
 // ---------------------------------------------------------------------------
 // Leaf chains.  Reflectors are stored per tile, column-major: reflector j of
@@ -195,7 +231,7 @@ __global__ void __launch_bounds__(QR_MAX_THREADS) tsqr_leaf_forward(int64_t n, i
                                                                     double* __restrict__ taus, double* __restrict__ Rs) {
     extern __shared__ unsigned char smem_raw[];
     double* vbuf = (double*)smem_raw;
-    double* tau_sh = vbuf + NB * TR;
+    double* tau_sh = vbuf + 2 * PANEL * TR;
     SlotT* slot = (SlotT*)(vbuf + STAGE_DOUBLES);
     const int ch = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
     const int64_t r_begin = ch * rows_per_chain;
@@ -228,7 +264,7 @@ __global__ void __launch_bounds__(QR_MAX_THREADS) tsqr_leaf_backward(int64_t n, 
                                                                      const double* __restrict__ Qtop, TQ* __restrict__ Q) {
     extern __shared__ unsigned char smem_raw[];
     double* vst = (double*)smem_raw;
-    double* tst = vst + NB * TR;
+    double* tst = vst + 2 * PANEL * TR;
     SlotT* slot = (SlotT*)(vst + STAGE_DOUBLES);
     const int ch = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
     const int64_t r_begin = ch * rows_per_chain;
@@ -267,7 +303,7 @@ __global__ void __launch_bounds__(QR_MAX_THREADS) tsqr_tree_forward(int c, int s
                                                                     double* __restrict__ tree_tau) {
     extern __shared__ unsigned char smem_raw[];
     double* vbuf = (double*)smem_raw;
-    double* tau_sh = vbuf + NB * TR;
+    double* tau_sh = vbuf + 2 * PANEL * TR;
     SlotT* slot = (SlotT*)(vbuf + STAGE_DOUBLES);
     const int i = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
     const int a_idx = i * 2 * stride, b_idx = a_idx + stride;
@@ -300,7 +336,7 @@ __global__ void __launch_bounds__(QR_MAX_THREADS) tsqr_tree_backward(int c, int 
                                                                      const double* __restrict__ tree_tau) {
     extern __shared__ unsigned char smem_raw[];
     double* vst = (double*)smem_raw;
-    double* tst = vst + NB * TR;
+    double* tst = vst + 2 * PANEL * TR;
     SlotT* slot = (SlotT*)(vst + STAGE_DOUBLES);
     const int i = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
     const int a_idx = i * 2 * stride, b_idx = a_idx + stride;
@@ -436,6 +472,188 @@ __device__ double wg_sum(double v, double* red) {
     for (int i = 0; i < SMALL_THREADS / 64; ++i) s += red[i];
     __syncthreads();
     return s;
+}
+
+// ---------------------------------------------------------------------------
+// Float64 matrix-core kernels (v_mfma_f64_16x16x4f64).  Fragment layout of one
+// 16 x 16 x 4 product C += A B on a wave: lane l holds A(l % 16, l / 16),
+// B(l / 16, l % 16), and C(l / 16 + 4 r, l % 16) in accumulator element r.
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Both kernels below are 128 x 128 output tiles per workgroup, 2 x 2 waves of
+// 4 x 4 fragments each, with the next operand stage loaded into registers while
+// the current one (in LDS) feeds the matrix cores.
+constexpr int MT_TILE = 128;
+constexpr int MT_LD = MT_TILE + 4;
+constexpr int MT_K = 16;          // reduction depth staged per step
+
+// part[ch] = Q[rows of chunk ch, :]^T X[rows of chunk ch, :]  (c x c, column-major:
+// part[j * c + i] = sum_r Q(r, i) X(r, j)), Q and X column-major n x c.  Grid
+// (nchunk, nblk, nblk): workgroup (ch, bi, bj) owns output rows bi * 128.. and
+// columns bj * 128..
+template <typename TQ, typename TX>
+__global__ void __launch_bounds__(256) qtx_mfma(int64_t n, int c, const TQ* __restrict__ Q, const TX* __restrict__ X,
+                                                double* __restrict__ part, int64_t rows_per_chunk) {
+    __shared__ double Qs[MT_K][MT_LD];
+    __shared__ double Xs[MT_K][MT_LD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wi = wave >> 1, wj = wave & 1;
+    const int ci0 = blockIdx.y * MT_TILE, cj0 = blockIdx.z * MT_TILE;
+    const int64_t rb = (int64_t)blockIdx.x * rows_per_chunk;
+    const int64_t re = min(n, rb + rows_per_chunk);
+    // staging map: element e = tid + 256 q (q < 8): row e % 16, column e / 16
+    TQ qreg[8];
+    TX xreg[8];
+#define QTX_LOAD_STAGE(R0)                                                                 \
+    _Pragma("unroll") for (int q = 0; q < 8; ++q) {                                      \
+        const int e = tid + 256 * q, rr = e % MT_K, cc = e / MT_K;                       \
+        const int64_t r = (R0) + rr;                                                     \
+        const bool rv = r < re;                                                          \
+        qreg[q] = (rv && ci0 + cc < c) ? Q[(int64_t)(ci0 + cc) * n + r] : TQ{};          \
+        xreg[q] = (rv && cj0 + cc < c) ? X[(int64_t)(cj0 + cc) * n + r] : TX{};          \
+    }
+    v4d acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+    if (rb < re) { QTX_LOAD_STAGE(rb) }
+    for (int64_t r0 = rb; r0 < re; r0 += MT_K) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + 256 * q, rr = e % MT_K, cc = e / MT_K;
+            Qs[rr][cc] = to_f64(qreg[q]);
+            Xs[rr][cc] = to_f64(xreg[q]);
+        }
+        __syncthreads();
+        if (r0 + MT_K < re) { QTX_LOAD_STAGE(r0 + MT_K) }
+#pragma unroll
+        for (int kk = 0; kk < MT_K / 4; ++kk) {
+            const int k = 4 * kk + lane / 16, m = lane % 16;
+            double a[4], b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                a[t] = Qs[k][(wi * 4 + t) * 16 + m];
+                b[t] = Xs[k][(wj * 4 + t) * 16 + m];
+            }
+#pragma unroll
+            for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < 4; ++tb) acc[ta][tb] = mfma64(a[ta], b[tb], acc[ta][tb]);
+        }
+        __syncthreads();
+    }
+    double* out = part + (int64_t)blockIdx.x * c * c;
+#pragma unroll
+    for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = ci0 + (wi * 4 + ta) * 16 + lane / 16 + 4 * r;
+                const int gj = cj0 + (wj * 4 + tb) * 16 + lane % 16;
+                if (gi < c && gj < c) out[(int64_t)gj * c + gi] = acc[ta][tb][r];
+            }
+}
+
+// U = Q Us[:, :rank] (n x rank, column-major, TO) from column-major Q (n x c) and
+// Us (c x c, column-major).  Grid (ceil(n / 128), ceil(rank / 128)).
+template <typename TQ, typename TO>
+__global__ void __launch_bounds__(256) basis_mfma(int64_t n, int c, int rank, const TQ* __restrict__ Q,
+                                                  const double* __restrict__ Us, TO* __restrict__ U) {
+    __shared__ double stage_sh[MT_TILE * (MT_K + 1) + MT_K * MT_LD];
+    double* Qs = stage_sh;                          // [128 rows][MT_K + 1]
+    double* Ms = stage_sh + MT_TILE * (MT_K + 1);   // [MT_K][MT_LD]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wi = wave >> 1, wj = wave & 1;
+    const int64_t row0 = (int64_t)blockIdx.x * MT_TILE;
+    const int col0 = blockIdx.y * MT_TILE;
+    TQ qreg[8];
+    double mreg[8];
+    // Q stage element e = tid + 256 q: row e % 128, k e / 128; Us stage: k e % 16, column e / 16
+#define BASIS_LOAD_STAGE(K0)                                                                         \
+    _Pragma("unroll") for (int q = 0; q < 8; ++q) {                                                \
+        const int e = tid + 256 * q;                                                               \
+        const int rr = e % MT_TILE, kq = e / MT_TILE;                                              \
+        const int64_t r = row0 + rr;                                                               \
+        qreg[q] = (r < n && (K0) + kq < c) ? Q[(int64_t)((K0) + kq) * n + r] : TQ{};               \
+        const int km = e % MT_K, j = e / MT_K;                                                     \
+        mreg[q] = ((K0) + km < c && col0 + j < rank) ? Us[(int64_t)(col0 + j) * c + (K0) + km] : 0.0; \
+    }
+    v4d acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+    BASIS_LOAD_STAGE(0)
+    for (int k0 = 0; k0 < c; k0 += MT_K) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + 256 * q;
+            Qs[(e % MT_TILE) * (MT_K + 1) + e / MT_TILE] = to_f64(qreg[q]);
+            Ms[(e % MT_K) * MT_LD + e / MT_K] = mreg[q];
+        }
+        __syncthreads();
+        if (k0 + MT_K < c) { BASIS_LOAD_STAGE(k0 + MT_K) }
+#pragma unroll
+        for (int kk = 0; kk < MT_K / 4; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                a[t] = Qs[((wi * 4 + t) * 16 + lane % 16) * (MT_K + 1) + 4 * kk + lane / 16];
+                b[t] = Ms[(4 * kk + lane / 16) * MT_LD + (wj * 4 + t) * 16 + lane % 16];
+            }
+#pragma unroll
+            for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < 4; ++tb) acc[ta][tb] = mfma64(a[ta], b[tb], acc[ta][tb]);
+        }
+        __syncthreads();
+    }
+    if (sizeof(TO) == 4) {
+        // transpose through LDS, one 64-column half at a time (64 x 129 floats fit in
+        // the staging area): Os[column][row], then each column's 128 rows are contiguous
+        float* Os = (float*)stage_sh;
+        static_assert(64 * (MT_TILE + 1) * sizeof(float) <= sizeof(stage_sh), "epilogue tile exceeds LDS");
+        for (int hh = 0; hh < 2; ++hh) {
+            if (wj == hh) {
+#pragma unroll
+                for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+                    for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int rr = (wi * 4 + ta) * 16 + lane / 16 + 4 * r;
+                            const int jj = tb * 16 + lane % 16;
+                            Os[jj * (MT_TILE + 1) + rr] = (float)acc[ta][tb][r];
+                        }
+            }
+            __syncthreads();
+            for (int e = tid; e < 64 * MT_TILE; e += 256) {
+                const int rr = e % MT_TILE, jj = e / MT_TILE;
+                const int64_t r = row0 + rr;
+                const int j = col0 + hh * 64 + jj;
+                if (r < n && j < rank) U[(int64_t)j * n + r] = (TO)Os[jj * (MT_TILE + 1) + rr];
+            }
+            __syncthreads();
+        }
+    } else {
+#pragma unroll
+        for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row0 + (wi * 4 + ta) * 16 + lane / 16 + 4 * r;
+                    const int j = col0 + (wj * 4 + tb) * 16 + lane % 16;
+                    if (j < rank && row < n) U[(int64_t)j * n + row] = (TO)acc[ta][tb][r];
+                }
+    }
 }
 
 // Omega = F T^-1, symmetrised.  T column-major c x c (T[j*c + i] = T(i, j)).
@@ -743,18 +961,6 @@ __global__ void __launch_bounds__(256) householder_accum(int c, const double* __
         const int r = lane + 64 * q;
         if (r < c) Z[(int64_t)col * c + r] = z[q];
     }
-}
-
-// 1 / sqrt(t) for t > 0 (hardware estimate refined by two Newton steps).
-__device__ __forceinline__ double rsqrt_refined(double t) {
-    double y = __builtin_amdgcn_rsq(t);
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const double ty = t * y;
-        const double e = fma(-ty, y, 1.0);
-        y = fma(0.5 * y, e, y);
-    }
-    return y;
 }
 
 __global__ void __launch_bounds__(64) ql_tridiag(int c, double* __restrict__ dg, const double* __restrict__ eg,
@@ -1113,10 +1319,9 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     if ((rc = ensure_ws(h->E, (size_t)n * c * sizeof(TO))) != BFGS_OK) return rc;
     if ((rc = ensure_ws(h->Q, (size_t)n * c * sizeof(TO))) != BFGS_OK) return rc;
     // small: part(nchunks*c*c) + T, M, B, Omega, Z (5 c*c) + d, e, taus, rot, lam (5 c) + piv
-    const int ctiles = ceil_div(c, TN_T);
-    const int64_t max_chunks = std::max<int64_t>(1, (n + TN_R - 1) / TN_R);
-    int nchunks = (int)std::min<int64_t>(max_chunks, std::max(1, 2048 / (ctiles * ctiles)));
-    const int64_t rows_per_chunk = round_up((n + nchunks - 1) / nchunks, TN_R);
+    // Q^T X row chunks: about one per CU, each chunk a multiple of the staging depth
+    int nchunks = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 63) / 64));
+    const int64_t rows_per_chunk = round_up((n + nchunks - 1) / nchunks, MT_K);
     nchunks = (int)((n + rows_per_chunk - 1) / rows_per_chunk);
     const size_t cc = (size_t)c * c;
     if ((rc = ensure_ws(h->small, ((size_t)nchunks * cc + 8 * cc + 6 * (size_t)c) * 8 + (size_t)c * 4)) != BFGS_OK)
@@ -1168,13 +1373,9 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     }
     ProfScope ps(h, "proj_QtX");
     {
-        // one workgroup per row chunk (about 512 chunks), each reading its rows of Q and X once
-        const int nfull = (int)std::min<int64_t>(nchunks, 512);
-        const int64_t rpc = round_up((n + nfull - 1) / nfull, FT_ROWS);
-        const int nf = (int)((n + rpc - 1) / rpc);
-        hipLaunchKernelGGL((gemm_tn_full<TO, TS>), dim3(nf, ceil_div(c, 128)), dim3(512), 0, h->stream, n, c, Q, X,
-                           part, rpc);
-        nchunks = nf;
+        const int nblk = ceil_div(c, MT_TILE);
+        hipLaunchKernelGGL((qtx_mfma<TO, TS>), dim3(nchunks, nblk, nblk), dim3(256), 0, h->stream, n, c, Q, X, part,
+                           rows_per_chunk);
     }
     hipLaunchKernelGGL(sum_chunks, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, h->stream, (int64_t)cc, nchunks, part,
                        Tm);
@@ -1214,11 +1415,13 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
         return BFGS_ERR_HIP;
     prof_end(h);
     prof_begin(h, "basis_diag");
-    hipLaunchKernelGGL((basis_gemm<TO, TO>), dim3(ceil_div(rank, BS_C), ceil_div(n, BS_R)), dim3(256), 0, h->stream, n, c,
-                       rank, Q, Usm, U);
-    const int g = (int)std::min<int64_t>(4096, (n + 255) / 256);
-    hipLaunchKernelGGL((posterior_diag_kernel<TO, Th>), dim3(g), dim3(256), 0, h->stream, n, rank, U, lam,
-                       (const Th*)h->h0, dout);
+    hipLaunchKernelGGL((basis_mfma<TO, TO>), dim3((unsigned)ceil_div(n, (int64_t)MT_TILE), ceil_div(rank, MT_TILE)),
+                       dim3(256), 0, h->stream, n, c, rank, Q, Usm, U);
+    {
+        const int g = (int)std::min<int64_t>(4096, (n + 255) / 256);
+        hipLaunchKernelGGL((posterior_diag_kernel<TO, Th>), dim3(g), dim3(256), 0, h->stream, n, rank, U, lam,
+                           (const Th*)h->h0, dout);
+    }
     if (hipGetLastError() != hipSuccess) return BFGS_ERR_HIP;
     h->have_rsvd = true;
     h->last_rank = rank;
