@@ -86,13 +86,14 @@ def load_traffic(kernel, digest):
     return entry.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(H, V, wq_prob_n, storage, ncols):
-    """Oracle (Alg. 2 two-loop, float64 C/OpenMP) on a bounded sample of the same workload."""
+def cpu_baseline(H, V, out, wq_prob_n, storage, ncols, budget_s=15.0):
+    """Oracle (Alg. 2 two-loop, float64 C/OpenMP) on a bounded sample of the same
+    workload: whole chunks of `threads` probe columns until about `budget_s` seconds
+    of oracle time (or all columns).  Also returns the relative error of the GPU's
+    H_k V on those columns against the oracle (both from the stored values)."""
     import numpy as np
-    import torch
     from oracle import twoloop
     threads = len(os.sched_getaffinity(0))
-    sample = max(1, min(threads, ncols))
     k = H.k
     n = wq_prob_n
     S = np.empty((k, n))
@@ -102,14 +103,25 @@ def cpu_baseline(H, V, wq_prob_n, storage, ncols):
         S[j] = s.double().cpu().numpy()
         Y[j] = y.double().cpu().numpy()
     h0 = H.get_h0().double().cpu().numpy()
-    Vs = V[:sample].double().cpu().numpy()
-    t0 = time.perf_counter()
-    twoloop.two_loop(h0, S, Y, Vs, nthreads=threads)
-    dt = time.perf_counter() - t0
-    used = min(threads, twoloop.max_threads(), sample)
-    return {"value": round(sample / dt, 4), "unit": "columns/s", "cores": used, "kind": "oracle",
-            "sample": f"{sample} of the {ncols} probe columns of the same workload (n={n}, k={k}), "
-                      f"float64 two-loop recursion, {dt:.2f} s"}
+    chunk = max(1, min(threads, ncols))
+    done, spent = 0, 0.0
+    num = den = 0.0
+    while done < ncols and (done == 0 or spent < budget_s):
+        cols = list(range(done, min(ncols, done + chunk)))
+        Vs = V[cols].double().cpu().numpy()
+        t0 = time.perf_counter()
+        ref = twoloop.two_loop(h0, S, Y, Vs, nthreads=threads)
+        spent += time.perf_counter() - t0
+        got = out[cols].double().cpu().numpy()
+        num += float(((got - ref) ** 2).sum())
+        den += float((ref ** 2).sum())
+        done += len(cols)
+        log(f"[bench] oracle: {done} columns in {spent:.1f} s")
+    used = min(threads, twoloop.max_threads(), chunk)
+    rel = (num / den) ** 0.5 if den > 0 else None
+    return {"value": round(done / spent, 4), "unit": "columns/s", "cores": used, "kind": "oracle",
+            "sample": f"{done} of the {ncols} probe columns of the same workload (n={n}, k={k}), "
+                      f"float64 two-loop recursion over the stored pairs, {spent:.1f} s"}, rel
 
 
 def bench_batch(args):
@@ -201,6 +213,115 @@ def bench_batch(args):
     print(json.dumps(res), flush=True)
 
 
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries (CSV output of --kernel-trace --stats and of --pmc runs)
+# ---------------------------------------------------------------------------
+KERNEL_GROUPS = [
+    ("gemm1_mfma", "apply_gemm1"), ("gemm1_generic", "apply_gemm1"), ("reduce_z", "apply_reduce"),
+    ("reduce_partials", "apply_reduce"), ("small_solve", "apply_solve"), ("pack_small", "apply_pack"),
+    ("gemm2_mfma", "apply_gemm2"), ("gemm2_generic", "apply_gemm2"), ("scale_by_h0", "apply_gemm2"),
+    ("probes_kernel", "probes"), ("tsqr_leaf_forward", "tsqr_leaf_fwd"), ("tsqr_tree", "tsqr_tree"),
+    ("set_identity", "tsqr_tree"), ("tsqr_leaf_backward", "tsqr_leaf_bwd"), ("tri_mul", "tsqr_tree"),
+    ("qtx_mfma", "proj_QtX"), ("sum_chunks", "proj_QtX"), ("omega_solve", "omega_lu"),
+    ("sym_tridiag", "sym_eig"), ("householder_accum", "sym_eig"), ("ql_tridiag", "sym_eig"),
+    ("apply_rotations", "sym_eig"), ("order_sign", "sym_eig"), ("basis_mfma", "basis_diag"),
+    ("posterior_diag_kernel", "basis_diag"), ("store_pair_kernel", "push_pair"), ("gram_partial_kernel", "push_pair"),
+    ("gram_finish_kernel", "push_pair"), ("rinv_update_kernel", "push_pair"), ("scatter_pair_layouts", "push_pair"),
+    ("fill_h0_kernel", "push_pair"), ("upcast_kernel", "push_pair"),
+]
+
+
+def group_of(kernel_name):
+    for key, grp in KERNEL_GROUPS:
+        if key in kernel_name:
+            return grp
+    return None
+
+
+def short_name(kernel_name):
+    k = kernel_name.replace("(anonymous namespace)::", "")
+    return k.split("(")[0].replace("void ", "")
+
+
+def summarize_profiles(d, out_dir, digest, cmd_prefix):
+    """Turns the CSVs of one profiling session (kt = kernel trace, fetch/write =
+    FETCH_SIZE/WRITE_SIZE of the bench, cfetch/cwrite = the same counters over a plain
+    1 GiB device copy) into profiles/*.md and profiles/traffic.json."""
+    import csv
+    import glob
+
+    def rows(pattern):
+        files = glob.glob(os.path.join(d, pattern))
+        return list(csv.DictReader(open(files[0]))) if files else []
+
+    os.makedirs(out_dir, exist_ok=True)
+    stats = rows("kt_*kernel_stats.csv")
+    lines = ["# Kernel times: 1700 x 350 x 3 grid, n = 1,785,000, k = 200, bfloat16, 220 columns, rSVD 200 + 20", "",
+             "Command (from the repository root, on one MI355X):", "",
+             f"    {cmd_prefix} --kernel-trace --stats -d <dir> -o kt --output-format csv -- "
+             "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline", "",
+             "| kernel | group | calls | total ms | avg ms |", "|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:40]:
+        g = group_of(r["Name"])
+        if g is None and float(r["TotalDurationNs"]) < 2e6:
+            continue
+        lines.append(f"| {short_name(r['Name'])[:70]} | {g or '(input generation, torch)'} | {r['Calls']} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['AverageNs']) / 1e6:.4f} |")
+    open(os.path.join(out_dir, "kernels_grid3_bf16.md"), "w").write("\n".join(lines) + "\n")
+
+    def counter_means(pattern, counter):
+        acc = {}
+        for r in rows(pattern):
+            if r.get("Counter_Name") != counter:
+                continue
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fetch = counter_means("fetch_*counter_collection.csv", "FETCH_SIZE")
+    write = counter_means("write_*counter_collection.csv", "WRITE_SIZE")
+    cf = counter_means("cfetch_*counter_collection.csv", "FETCH_SIZE")
+    cw = counter_means("cwrite_*counter_collection.csv", "WRITE_SIZE")
+    copy_f = max([v for k, v in cf.items() if "copyBuffer" in k] or [0.0])
+    copy_w = max([v for k, v in cw.items() if "copyBuffer" in k] or [0.0])
+    gib_kib = float(1 << 20)
+    f_scale = gib_kib / copy_f if copy_f else None
+    w_scale = gib_kib / copy_w if copy_w else None
+    lines = ["# HBM traffic per dispatch: 1700 x 350 x 3 grid, n = 1,785,000, k = 200, bfloat16", "",
+             "Commands (from the repository root, one counter per run):", "",
+             f"    {cmd_prefix} --pmc FETCH_SIZE -d <dir> -o fetch --output-format csv -- "
+             "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline",
+             f"    {cmd_prefix} --pmc WRITE_SIZE -d <dir> -o write --output-format csv -- "
+             "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline",
+             f"    {cmd_prefix} --pmc FETCH_SIZE -d <dir> -o cfetch --output-format csv -- "
+             "python3 bench.py --calibrate-copy 1024",
+             f"    {cmd_prefix} --pmc WRITE_SIZE -d <dir> -o cwrite --output-format csv -- "
+             "python3 bench.py --calibrate-copy 1024", "",
+             f"Calibration: a 1 GiB device copy reads FETCH_SIZE = {copy_f:.0f} KiB and WRITE_SIZE = "
+             f"{copy_w:.0f} KiB per dispatch, so the counters are scaled by {f_scale:.3f} (fetch) and "
+             f"{w_scale:.3f} (write) to bytes moved.", "",
+             "| kernel | group | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) |", "|---|---|---|---|---|"]
+    per_group = {}
+    for k in sorted(set(fetch) | set(write), key=lambda k: -(fetch.get(k, 0) + write.get(k, 0))):
+        g = group_of(k)
+        if g is None:
+            continue
+        fb = fetch.get(k, 0.0) * 1024 * (f_scale or 0)
+        wb = write.get(k, 0.0) * 1024 * (w_scale or 0)
+        lines.append(f"| {short_name(k)[:70]} | {g} | {fetch.get(k, 0):.0f} | {write.get(k, 0):.0f} | {fb + wb:.4g} |")
+        per_group.setdefault(g, []).append(fb + wb)
+    open(os.path.join(out_dir, "hbm_traffic_grid3_bf16.md"), "w").write("\n".join(lines) + "\n")
+    traffic = {g: {"hbm_bytes_per_launch": sum(v) / len(v), "source_digest": digest,
+                   "fetch_scale": f_scale, "write_scale": w_scale} for g, v in per_group.items()}
+    json.dump(traffic, open(os.path.join(out_dir, "traffic.json"), "w"), indent=1)
+    log(f"[bench] wrote profile summaries for {len(per_group)} kernel groups to {out_dir}")
+
+
+def csrc_digest():
+    csrc = sorted(os.path.join("paper_2009_12663_amd", "csrc", f)
+                  for f in os.listdir(os.path.join(ROOT, "paper_2009_12663_amd", "csrc")))
+    return source_digest(csrc)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,7 +333,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (counter calibration)")
+    ap.add_argument("--summarize", default="", metavar="DIR",
+                    help="only summarise the rocprofv3 CSVs in DIR into profiles/ (no GPU needed)")
     args = ap.parse_args()
+
+    if args.summarize:
+        summarize_profiles(args.summarize, os.path.join(ROOT, "profiles"), csrc_digest(), "rocprofv3")
+        return
 
     if args.calibrate_copy:
         import torch
@@ -302,9 +429,7 @@ def main():
     ob = 8 if args.storage == "f64" else 4
     models = kernel_models(n, k, args.ncols, rank, wb, wb, ob)
     models_rsvd = kernel_models(n, k, c_rsvd, rank, wb, wb, ob)
-    csrc = sorted(os.path.join("paper_2009_12663_amd", "csrc", f)
-                  for f in os.listdir(os.path.join(ROOT, "paper_2009_12663_amd", "csrc")))
-    digest = source_digest(csrc)
+    digest = csrc_digest()
     entries = []
     for name, (cnt, tot_ms) in prof.items():
         model = models.get(name)
@@ -354,7 +479,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
-        result["cpu_baseline"] = cpu_baseline(H, V, n, args.storage, args.ncols)
+        result["cpu_baseline"], rel = cpu_baseline(H, V, out, n, args.storage, args.ncols)
+        result["rel_err_vs_oracle"] = {"apply_rel_F": rel, "sample": result["cpu_baseline"]["sample"]}
         log(f"[bench] cpu baseline: {result['cpu_baseline']['value']} columns/s "
             f"({result['cpu_baseline']['cores']} threads)")
     else:
