@@ -267,55 +267,75 @@ __global__ void pack_small(int k, int c, int cpad, int Gp, const double* __restr
 constexpr int G2_ROWS = 256;
 constexpr int SM_LD = 40;        // LDS pitch of a staged small column: 32 pairs + 8 pad
 
+// Two waves share each 32-row group (SPLIT = 2 when MT2 > 1), each owning MH of the
+// MT2 output column tiles: the W fragments are read by both (the second read hits
+// in cache), and the halved accumulator set lets four waves share a SIMD.
+template <int MT2>
+struct G2Shape {
+    static constexpr int SPLIT = MT2 > 1 ? 2 : 1;
+    static constexpr int MH = (MT2 + SPLIT - 1) / SPLIT;
+    static constexpr int THREADS = 512 * SPLIT;
+};
+
 template <int MT2, bool DIFF>
-__global__ void __launch_bounds__(512) gemm2_mfma(int64_t n, int c, int G, int Gp, const bf16_t* __restrict__ Y2,
-                                                  const bf16_t* __restrict__ S2, const uint16_t* __restrict__ shi,
-                                                  const uint16_t* __restrict__ slo, const float* __restrict__ h0,
-                                                  const bf16_t* __restrict__ V, float* __restrict__ out) {
+__global__ void __launch_bounds__(G2Shape<MT2>::THREADS) gemm2_mfma(int64_t n, int c, int G, int Gp,
+                                                                   const bf16_t* __restrict__ Y2,
+                                                                   const bf16_t* __restrict__ S2,
+                                                                   const uint16_t* __restrict__ shi,
+                                                                   const uint16_t* __restrict__ slo,
+                                                                   const float* __restrict__ h0,
+                                                                   const bf16_t* __restrict__ V, float* __restrict__ out) {
+    constexpr int SPLIT = G2Shape<MT2>::SPLIT, MH = G2Shape<MT2>::MH, NTH = G2Shape<MT2>::THREADS;
     // LDS: two buffers of the staged small operand (hi, lo), [col][SM_LD]
     extern __shared__ unsigned char smem_raw[];
     constexpr int BUF = MT2 * 32 * SM_LD;
     uint16_t* sm = (uint16_t*)smem_raw;   // buffer b: hi at sm + 2*b*BUF, lo at sm + (2*b+1)*BUF
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, half = lane >> 5;
-    const int64_t row_base = (int64_t)blockIdx.x * G2_ROWS + wave * 32;
+    const int rg = wave / SPLIT, cs = wave % SPLIT;        // row group, column share
+    const int mt0 = cs * MH;                               // first column tile of this wave
+    const int ntw = min(MH, MT2 - mt0);                    // tiles of this wave (uniform)
+    const int64_t row_base = (int64_t)blockIdx.x * G2_ROWS + rg * 32;
     const int64_t rb32 = row_base / 32;
     const int K2 = 2 * Gp * 16;
     const int nchunks = K2 / 32;
     const bool row_ok = row_base + (lane & 31) < n;
     const float h0r = row_ok ? h0[row_base + (lane & 31)] : 0.f;
 
-    floatx16 acc[MT2];
+    floatx16 acc[MH];
 #pragma unroll
-    for (int t = 0; t < MT2; ++t)
+    for (int t = 0; t < MH; ++t)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
 
     constexpr int SCH = MT2 * 32 * 4;        // 16-byte chunks of one array per staged chunk (<= 1024)
+    static_assert(SCH <= 1024, "one staging chunk per thread and array");
     uint4 sh0 = make_uint4(0, 0, 0, 0), sl0 = sh0, sh1 = sh0, sl1 = sh0;
-    auto load_small = [&](int t) {
-        if (tid < SCH) {
-            const int64_t off = (int64_t)(tid >> 2) * K2 + t * 32 + (tid & 3) * 8;
-            sh0 = *(const uint4*)(shi + off);
-            sl0 = *(const uint4*)(slo + off);
-        }
-        if (tid + 512 < SCH) {
-            const int64_t off = (int64_t)((tid + 512) >> 2) * K2 + t * 32 + (tid & 3) * 8;
-            sh1 = *(const uint4*)(shi + off);
-            sl1 = *(const uint4*)(slo + off);
-        }
-    };
-    auto store_small = [&](int b) {
-        uint16_t* H = sm + 2 * b * BUF;
-        uint16_t* L = H + BUF;
-        if (tid < SCH) {
-            *(uint4*)(H + (tid >> 2) * SM_LD + (tid & 3) * 8) = sh0;
-            *(uint4*)(L + (tid >> 2) * SM_LD + (tid & 3) * 8) = sl0;
-        }
-        if (tid + 512 < SCH) {
-            *(uint4*)(H + ((tid + 512) >> 2) * SM_LD + (tid & 3) * 8) = sh1;
-            *(uint4*)(L + ((tid + 512) >> 2) * SM_LD + (tid & 3) * 8) = sl1;
-        }
-    };
+#define G2_LOAD_SMALL(T)                                                        \
+    {                                                                           \
+        if (tid < SCH) {                                                        \
+            const int64_t off = (int64_t)(tid >> 2) * K2 + (T) * 32 + (tid & 3) * 8; \
+            sh0 = *(const uint4*)(shi + off);                                   \
+            sl0 = *(const uint4*)(slo + off);                                   \
+        }                                                                       \
+        if (NTH < SCH && tid + NTH < SCH) {                                     \
+            const int64_t off = (int64_t)((tid + NTH) >> 2) * K2 + (T) * 32 + (tid & 3) * 8; \
+            sh1 = *(const uint4*)(shi + off);                                   \
+            sl1 = *(const uint4*)(slo + off);                                   \
+        }                                                                       \
+    }
+#define G2_STORE_SMALL(B)                                                                   \
+    {                                                                                       \
+        uint16_t* H_ = sm + 2 * (B) * BUF;                                                  \
+        uint16_t* L_ = H_ + BUF;                                                            \
+        if (tid < SCH) {                                                                    \
+            *(uint4*)(H_ + (tid >> 2) * SM_LD + (tid & 3) * 8) = sh0;                       \
+            *(uint4*)(L_ + (tid >> 2) * SM_LD + (tid & 3) * 8) = sl0;                       \
+        }                                                                                   \
+        if (NTH < SCH && tid + NTH < SCH) {                                                 \
+            *(uint4*)(H_ + ((tid + NTH) >> 2) * SM_LD + (tid & 3) * 8) = sh1;               \
+            *(uint4*)(L_ + ((tid + NTH) >> 2) * SM_LD + (tid & 3) * 8) = sl1;               \
+        }                                                                                   \
+    }
     auto load_b = [&](int t, int sg) -> uint4 {
         const int gq = 2 * t + sg;
         if (t >= nchunks) return make_uint4(0, 0, 0, 0);
@@ -327,16 +347,16 @@ __global__ void __launch_bounds__(512) gemm2_mfma(int64_t n, int c, int G, int G
     };
 
     // W fragments run DEPTH chunks ahead of the MFMAs.
-    constexpr int DEPTH = MT2 >= 8 ? 3 : 4;
+    constexpr int DEPTH = MH >= 4 ? 2 : 4;
     uint4 bq0[DEPTH], bq1[DEPTH];
 #pragma unroll
     for (int d = 0; d < DEPTH; ++d) {
         bq0[d] = load_b(d, 0);
         bq1[d] = load_b(d, 1);
     }
-    load_small(0);
-    store_small(0);
-    if (nchunks > 1) load_small(1);
+    G2_LOAD_SMALL(0)
+    G2_STORE_SMALL(0)
+    if (nchunks > 1) G2_LOAD_SMALL(1)
     __syncthreads();
     for (int t0 = 0; t0 < nchunks; t0 += DEPTH) {
 #pragma unroll
@@ -344,8 +364,8 @@ __global__ void __launch_bounds__(512) gemm2_mfma(int64_t n, int c, int G, int G
             const int t = t0 + d;
             if (t < nchunks) {
                 const int buf = t & 1;
-                if (t + 1 < nchunks) store_small(buf ^ 1);
-                if (t + 2 < nchunks) load_small(t + 2);
+                if (t + 1 < nchunks) G2_STORE_SMALL(buf ^ 1)
+                if (t + 2 < nchunks) G2_LOAD_SMALL(t + 2)
                 const uint4 b0 = bq0[d], b1 = bq1[d];
                 bq0[d] = load_b(t + DEPTH, 0);
                 bq1[d] = load_b(t + DEPTH, 1);
@@ -355,16 +375,18 @@ __global__ void __launch_bounds__(512) gemm2_mfma(int64_t n, int c, int G, int G
                 for (int sg = 0; sg < 2; ++sg) {
                     const bf16x8 b = as_bf16x8(sg ? b1 : b0);
 #pragma unroll
-                    for (int m = 0; m < MT2; ++m) {
-                        const int off = (m * 32 + (lane & 31)) * SM_LD + sg * 16 + half * 8;
-                        acc[m] = mfma32(as_bf16x8(*(const uint4*)(H + off)), b, acc[m]);
-                        acc[m] = mfma32(as_bf16x8(*(const uint4*)(L + off)), b, acc[m]);
+                    for (int m = 0; m < MH; ++m) {
+                        if (m < ntw) {
+                            const int off = ((mt0 + m) * 32 + (lane & 31)) * SM_LD + sg * 16 + half * 8;
+                            acc[m] = mfma32(as_bf16x8(*(const uint4*)(H + off)), b, acc[m]);
+                            acc[m] = mfma32(as_bf16x8(*(const uint4*)(L + off)), b, acc[m]);
+                        }
                     }
                 }
                 if (2 * t + 2 == Gp) {
                     // end of the Y phase: acc holds -(Y P)^T for this lane's row; scale by h0[row]
 #pragma unroll
-                    for (int m = 0; m < MT2; ++m)
+                    for (int m = 0; m < MH; ++m)
 #pragma unroll
                         for (int i = 0; i < 16; ++i) acc[m][i] *= h0r;
                 }
@@ -372,6 +394,8 @@ __global__ void __launch_bounds__(512) gemm2_mfma(int64_t n, int c, int G, int G
             }
         }
     }
+#undef G2_LOAD_SMALL
+#undef G2_STORE_SMALL
     const int64_t row = row_base + (lane & 31);
     if (!DIFF) {
         // V tile of this wave (32 columns x 32 rows per column tile) through LDS: each
@@ -380,12 +404,14 @@ __global__ void __launch_bounds__(512) gemm2_mfma(int64_t n, int c, int G, int G
         uint16_t* vt = sm + wave * (32 * 40);             // [col][40] per wave, 2.5 KB
         const bool vec_ok = (n % 8) == 0 && (((uintptr_t)V) & 15) == 0;
 #pragma unroll
-        for (int m = 0; m < MT2; ++m) {
+        for (int m = 0; m < MH; ++m) {
+            if (m >= ntw) continue;
+            const int mt = mt0 + m;
             // lane -> (column q = lane / 4 + 16 * u, 8-row chunk lane % 4); two passes cover 32 columns
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int q = (lane >> 2) + 16 * u, ch = lane & 3;
-                const int col = m * 32 + q;
+                const int col = mt * 32 + q;
                 const int64_t r = row_base + ch * 8;
                 uint4 val = make_uint4(0, 0, 0, 0);
                 if (col < c && r < n) {
@@ -393,10 +419,10 @@ __global__ void __launch_bounds__(512) gemm2_mfma(int64_t n, int c, int G, int G
                     if (vec_ok && r + 8 <= n) {
                         val = *(const uint4*)src;
                     } else {
-                        u16x8 t;
+                        u16x8 tv;
 #pragma unroll
-                        for (int e = 0; e < 8; ++e) t.v[e] = (r + e < n) ? src[e].bits : (uint16_t)0;
-                        val = __builtin_bit_cast(uint4, t);
+                        for (int e = 0; e < 8; ++e) tv.v[e] = (r + e < n) ? src[e].bits : (uint16_t)0;
+                        val = __builtin_bit_cast(uint4, tv);
                     }
                 }
                 *(uint4*)(vt + q * 40 + ch * 8) = val;
@@ -407,7 +433,7 @@ __global__ void __launch_bounds__(512) gemm2_mfma(int64_t n, int c, int G, int G
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     const int cl = 8 * (i / 4) + 4 * half + (i % 4);
-                    const int col = m * 32 + cl;
+                    const int col = mt * 32 + cl;
                     if (col < c) out[(int64_t)col * n + row] = acc[m][i] + h0r * bits_to_f32(vt[cl * 40 + (lane & 31)]);
                 }
             }
@@ -415,10 +441,11 @@ __global__ void __launch_bounds__(512) gemm2_mfma(int64_t n, int c, int G, int G
         }
     } else if (row_ok) {
 #pragma unroll
-        for (int m = 0; m < MT2; ++m) {
+        for (int m = 0; m < MH; ++m) {
+            if (m >= ntw) continue;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int col = m * 32 + 8 * (i / 4) + 4 * half + (i % 4);
+                const int col = (mt0 + m) * 32 + 8 * (i / 4) + 4 * half + (i % 4);
                 if (col < c) out[(int64_t)col * n + row] = acc[m][i];
             }
         }
@@ -456,15 +483,16 @@ g1_fn pick_g1(int NT, bool diag) {
 template <int MT2, bool DIFF>
 void launch_g2(int grid, hipStream_t st, int64_t n, int c, int G, int Gp, const bf16_t* Y2, const bf16_t* S2,
                const uint16_t* shi, const uint16_t* slo, const float* h0, const bf16_t* V, float* out) {
-    // small-operand double buffer, reused by the epilogue for 8 per-wave V tiles of 32 x 40
-    const size_t smem = std::max((size_t)4 * MT2 * 32 * SM_LD, (size_t)8 * 32 * 40) * sizeof(uint16_t);
+    // small-operand double buffer, reused by the epilogue for one V tile of 32 x 40 per wave
+    constexpr int NTH = G2Shape<MT2>::THREADS;
+    const size_t smem = std::max((size_t)4 * MT2 * 32 * SM_LD, (size_t)(NTH / 64) * 32 * 40) * sizeof(uint16_t);
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void*)gemm2_mfma<MT2, DIFF>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)smem);
         attr = true;
     }
-    hipLaunchKernelGGL((gemm2_mfma<MT2, DIFF>), dim3(grid), dim3(512), smem, st, n, c, G, Gp, Y2, S2, shi, slo, h0, V,
+    hipLaunchKernelGGL((gemm2_mfma<MT2, DIFF>), dim3(grid), dim3(NTH), smem, st, n, c, G, Gp, Y2, S2, shi, slo, h0, V,
                        out);
 }
 
