@@ -167,29 +167,61 @@ __device__ void fold_tile(SlotT* slot, double (&a)[RPL], int c, int jstart, doub
 }
 
 // Backward: apply the tile's known reflectors j = c-1 .. jstart to (slot, a[] = tile
-// rows of this quad's column).  Reflector j's tile part is refl[j * TR + t]; its tau taus[j].
-// Reflectors are staged NB at a time; no barrier is needed between them because a
-// column is touched only by its own quad.
+// rows of this quad's column).  Reflector j's tile part is refl[j * TR + t]; its tau
+// taus[j].  Reflectors go through LDS in blocks of up to NB, double-buffered: the
+// next block is loaded into registers while the current one is applied.  No barrier
+// is needed between the reflectors of a block because a column is touched only by
+// its own quad.
+constexpr int UF_PF = 4;   // prefetched doubles per thread
+
 template <typename SlotT>
 __device__ void unfold_tile(SlotT* slot, double (&a)[RPL], int c, int jstart, const double* refl,
                             const double* taus, double* vst, double* tst) {
     const int col = threadIdx.x / LPC, g = threadIdx.x % LPC;
-    for (int jhi = c - 1; jhi >= jstart; jhi -= NB) {
-        const int jlo = max(jstart, jhi - NB + 1);
-        const int cnt = jhi - jlo + 1;
-        __syncthreads();
-        for (int e = threadIdx.x; e < cnt * TR; e += blockDim.x) vst[e] = refl[(int64_t)jlo * TR + e];
-        if (threadIdx.x < cnt) tst[threadIdx.x] = taus[jlo + threadIdx.x];
-        __syncthreads();
-        if (col < c) {
-            for (int j = jhi; j >= jlo; --j) {
-                const double tau = tst[j - jlo];
-                if (tau == 0.0 || col < j) continue;   // uniform within the quad
-                reflect_column(slot, a, c, j, col, g, vst + (j - jlo) * TR, tau);
-            }
-        }
+    const int nbk = min(NB, (int)(UF_PF * blockDim.x) / TR);     // reflectors per block
+    const int nblocks = (c - jstart + nbk - 1) / nbk;
+    double pre[UF_PF];
+    double ptau = 0.0;
+#define UF_LOAD(B)                                                                 \
+    {                                                                              \
+        const int jhi_ = c - 1 - (B) * nbk, jlo_ = max(jstart, jhi_ - nbk + 1);    \
+        const int cnt_ = jhi_ - jlo_ + 1;                                          \
+        _Pragma("unroll") for (int q = 0; q < UF_PF; ++q) {                        \
+            const int e = threadIdx.x + q * blockDim.x;                            \
+            pre[q] = e < cnt_ * TR ? refl[(int64_t)jlo_ * TR + e] : 0.0;           \
+        }                                                                          \
+        ptau = threadIdx.x < cnt_ ? taus[jlo_ + threadIdx.x] : 0.0;                \
+    }
+#define UF_STORE(BUF)                                                              \
+    {                                                                              \
+        double* v_ = vst + (BUF) * NB * TR;                                        \
+        _Pragma("unroll") for (int q = 0; q < UF_PF; ++q) {                        \
+            const int e = threadIdx.x + q * blockDim.x;                            \
+            if (e < NB * TR) v_[e] = pre[q];                                       \
+        }                                                                          \
+        if (threadIdx.x < NB) tst[(BUF) * NB + threadIdx.x] = ptau;                \
     }
     __syncthreads();
+    UF_LOAD(0)
+    UF_STORE(0)
+    __syncthreads();
+    for (int b = 0; b < nblocks; ++b) {
+        if (b + 1 < nblocks) UF_LOAD(b + 1)
+        const int jhi = c - 1 - b * nbk, jlo = max(jstart, jhi - nbk + 1);
+        const double* vb = vst + (b & 1) * NB * TR;
+        const double* tb = tst + (b & 1) * NB;
+        if (col < c) {
+            for (int j = jhi; j >= jlo; --j) {
+                const double tau = tb[j - jlo];
+                if (tau == 0.0 || col < j) continue;   // uniform within the quad
+                reflect_column(slot, a, c, j, col, g, vb + (j - jlo) * TR, tau);
+            }
+        }
+        if (b + 1 < nblocks) UF_STORE((b + 1) & 1)
+        __syncthreads();
+    }
+#undef UF_LOAD
+#undef UF_STORE
 }
 
 template <typename SlotT>
