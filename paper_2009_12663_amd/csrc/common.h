@@ -153,6 +153,10 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // ---------------------------------------------------------------------------
 int apply_block(bfgsuq_ctx* h, const void* V, int32_t ncols, void* out, bool diff);
 int rsvd_run(bfgsuq_ctx* h, int32_t rank, int32_t oversample, uint64_t seed, void* U, double* Sigma);
+// Blocked Householder TSQR E = Q R (E, Q column-major n x c; *R_out: row-major c x c in
+// the handle's workspace).  tsqr.hip.
+int tsqr_run(bfgsuq_ctx* h, int c, const float* E, float* Q, double** R_out);
+int tsqr_run(bfgsuq_ctx* h, int c, const double* E, double* Q, double** R_out);
 int probes_run(bfgsuq_ctx* h, uint64_t seed, int32_t ncols, void* X);
 int64_t mfma_rows_f1(int64_t n);
 int64_t mfma_rows_f2(int64_t n);

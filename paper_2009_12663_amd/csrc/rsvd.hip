@@ -1388,10 +1388,7 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     }
     if ((rc = apply_block(h, X, c, E, true)) != BFGS_OK) return rc;
     double* R = nullptr;
-    auto run_tsqr = [&](const TO* src, TO* dst) {
-        if (c <= SLOT_F64_MAX_C) return tsqr<TO, double>(h, c, src, dst, &R);
-        return tsqr<TO, float>(h, c, src, dst, &R);
-    };
+    auto run_tsqr = [&](const TO* src, TO* dst) { return tsqr_run(h, c, src, dst, &R); };
     if ((rc = run_tsqr(E, Q)) != BFGS_OK) return rc;
     if (h->storage == BFGS_F64) {
         // E at float64 noise level is exactly rank deficient; the zero-started
