@@ -213,6 +213,97 @@ def bench_batch(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_learned(args):
+    """Learned diagonal B_0: train the network on the posterior variances of 32 runs
+    of the 600 x 200 x 3 grid (k = 100, rank 100 + 20), then compare it with gamma I
+    on 4 held-out 1700 x 350 x 3 problems (k = 200): iterations of the exact-line-search
+    BFGS (= preconditioned CG) to a relative gradient of 1e-6, the secant residual of the
+    library's H_k, and on the first problem the rSVD against the float64 oracle."""
+    import numpy as np
+    import torch
+    import paper_2009_12663_amd as P
+    from paper_2009_12663_amd import learned
+    from workloads import quadratic as wq
+
+    def iters(gn, tol=1e-6):
+        g = np.asarray(gn) / gn[0]
+        hit = np.nonzero(g <= tol)[0]
+        return int(hit[0]) if hit.size else None
+
+    t0 = time.perf_counter()
+    Xs, Ts = [], []
+    for seed in range(32):
+        prob = wq.make_grid(600, 200, seed, device="cuda")
+        S, Y, _ = wq.cg_pairs(prob, 100)
+        Ts.append(learned.posterior_log_diag(S, Y, 100, 20, seed))
+        Xs.append(learned.features(torch.log(prob.D), prob.b.abs(), 600, 200, prob.sigma / 5.0))
+        del S, Y, prob
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    del Xs, Ts
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    log(f"[bench-learned] {X.shape[0]} training samples in {t_data:.1f} s")
+    t0 = time.perf_counter()
+    steps = 3000
+    net, losses = learned.train(X, T, steps=steps, batch=65536, lr=3e-3, seed=0, log_every=500)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"[bench-learned] trained {steps} Adam steps in {t_train:.1f} s, loss {losses[0][1]:.4g} -> {losses[-1][1]:.4g}")
+    del X, T
+
+    evals = []
+    rsvd_err = None
+    for seed in (100, 101, 102, 103):
+        prob = wq.make_grid(1700, 350, seed, device="cuda")
+        h0 = learned.predict_h0(net, torch.log(prob.D), prob.b.abs(), 1700, 350, prob.sigma / 5.0)
+        _, _, gn_g = wq.cg_pairs(prob, 1000, rel_tol=1e-7)
+        S, Y, gn_l = wq.cg_pairs(prob, 1000, precond=h0.double(), rel_tol=1e-7)
+        _, _, gn_j = wq.cg_pairs(prob, 1000, precond=1.0 / prob.diag(), rel_tol=1e-7)
+        k = min(200, S.shape[0])
+        S, Y = S[:k], Y[:k]
+        H = P.Bfgs(prob.n, k, h0, "f32")
+        for s_, y_ in zip(S, Y):
+            H.push_pair(s_.float(), y_.float())
+        idx = list(range(max(0, k - 8), k))
+        HY = H.apply_Hinv(Y[idx].float()).double()
+        Sq = S[idx].float().double()
+        secant = float((torch.linalg.vector_norm(HY - Sq, dim=1) / torch.linalg.vector_norm(Sq, dim=1)).max())
+        row = {"seed": seed, "iters_gamma_I": iters(gn_g), "iters_learned": iters(gn_l), "iters_jacobi": iters(gn_j),
+               "secant_residual_max": secant}
+        if seed == 100 and not args.no_cpu_baseline:
+            # rSVD of the learned-H0 history against the float64 oracle (same stored values)
+            from oracle import rsvd as orsvd, probes as oprobes
+            rank = min(k, 200)
+            U, Sig = H.rsvd(rank, 20, 5)
+            Sq_all = S.float().double().cpu().numpy()
+            Yq_all = Y.float().double().cpu().numpy()
+            hq = h0.double().cpu().numpy()
+            Xp = oprobes.round_to(oprobes.normal_block(prob.n, rank + 20, 5), "f32")
+            ref = orsvd.rsvd(hq, Sq_all, Yq_all, Xp, rank)
+            rsvd_err = float(np.abs(Sig.cpu().numpy() - ref["Sigma"]).max() / abs(ref["Sigma"][0]))
+            row["rsvd_sigma_rel_err_vs_oracle"] = rsvd_err
+        H.close()
+        evals.append(row)
+        log(f"[bench-learned] {row}")
+        del S, Y, prob
+    it_g = [e["iters_gamma_I"] for e in evals]
+    it_l = [e["iters_learned"] for e in evals]
+    res = {
+        "metric": "learned diagonal B_0 vs gamma I: BFGS iterations to |g|/|g0| <= 1e-6 on held-out problems",
+        "value": round(float(np.mean(it_l)), 2), "unit": "iterations", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(t_train * 1e3 / steps, 4), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 weights, f32 accumulation", "data": "synthetic",
+        "config": {"workload": "train: 32 x (600 x 200 x 3 grid, k 100, rank 100 + 20); evaluate: 4 x (1700 x 350 x 3, "
+                               "k 200), seeds 100-103"},
+        "mean_iters_gamma_I": round(float(np.mean(it_g)), 2),
+        "iteration_ratio_gamma_over_learned": round(float(np.mean(it_g)) / float(np.mean(it_l)), 3),
+        "training_seconds": round(t_train, 2), "data_seconds": round(t_data, 2),
+        "loss_first_last": [losses[0][1], losses[-1][1]], "evaluations": evals,
+    }
+    net.close()
+    print(json.dumps(res), flush=True)
+
+
 # ---------------------------------------------------------------------------
 # rocprofv3 summaries (CSV output of --kernel-trace --stats and of --pmc runs)
 # ---------------------------------------------------------------------------
@@ -359,6 +450,9 @@ def main():
         sys.exit(2)
     if args.config == "batch":
         bench_batch(args)
+        return
+    if args.config == "learned":
+        bench_learned(args)
         return
 
     import torch
