@@ -3,26 +3,13 @@
 //
 //   X = probes (c = rank + oversample columns)
 //   E = (B_k - B_0) X                                  apply.hip, "difference" form
-//   E = Q R                                            Householder TSQR (below)
+//   E = Q R                                            Householder TSQR (tsqr.hip)
 //   Omega (Q^T X) = Q^T E = R                          LU with partial pivoting, float64
 //   Omega <- (Omega + Omega^T) / 2;  Omega = U_s Lambda U_s^T     tridiagonal QL, float64
 //   U = Q U_s[:, :rank],  Sigma = lambda[:rank],  d = h0 + sum_i lambda_i U_i^2
 //
 // Q^T E equals R exactly for E = Q R, so the R of the factorisation is used
 // instead of a second product with E.
-//
-// TSQR layout.  E (n x c, c <= 256) is split into `nchains` contiguous row
-// ranges, one workgroup each.  A workgroup keeps an upper-triangular c x c
-// "slot" in LDS and folds the rows in, TR rows at a time, with Householder
-// reflectors acting on (slot row j, the TR tile rows); one thread owns one
-// column and keeps its TR tile entries in registers.  The slot starts at zero:
-// a column's first non-zero tile swaps into the slot exactly (tau = 1), so the
-// slot rows carry no part of Q.  The per-chain R factors are then combined
-// pairwise (binary tree) by the same routine, reading the second R as tile
-// rows.  Q is formed explicitly by applying the stored reflectors backwards to
-// the identity at the root; every slot matrix met on the way stays upper
-// triangular, so the packed triangle suffices in both directions.  The slot is
-// float64 when it fits in LDS (c <= 180) and float32 above that.
 #include <cmath>
 #include <utility>
 
@@ -31,19 +18,6 @@
 int probes_launch(bfgsuq_ctx* h, uint64_t seed, int32_t c, void* X, hipStream_t stream);
 
 namespace {
-
-constexpr int TR = 64;          // tile rows per Householder update
-constexpr int LPC = 4;          // lanes per column (a quad); lane g owns tile rows t = i * LPC + g
-constexpr int RPL = TR / LPC;   // tile rows per lane
-constexpr int QR_MAX_THREADS = 1024;  // c <= 256 columns x LPC
-constexpr int NB = 16;          // reflectors staged per barrier when applying known reflectors
-constexpr int PANEL = 16;       // columns per wave and per panel of the fold (64 lanes / LPC)
-constexpr int SLOT_F64_MAX_C = 180;
-
-__device__ __forceinline__ int tri_index(int j, int col, int c) {
-    // packed upper triangle, row-major: row j holds columns j..c-1
-    return j * c - (j * (j - 1)) / 2 + (col - j);
-}
 
 // 1 / sqrt(t) for t > 0, denormal t included (hardware estimate refined by two
 // Newton steps).
@@ -56,341 +30,6 @@ __device__ __forceinline__ double rsqrt_refined(double t) {
         y = fma(0.5 * y, e, y);
     }
     return y;
-}
-
-// 1 / x for normal x with |x| < 2^1022 (hardware estimate refined by two Newton
-// steps).  The estimate overflows for denormal x, so callers keep x normal.
-__device__ __forceinline__ double rcp_refined(double x) {
-    double y = __builtin_amdgcn_rcp(x);
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const double e = fma(-x, y, 1.0);
-        y = fma(y, e, y);
-    }
-    return y;
-}
-
-// Exchange within a quad of lanes (DPP quad_perm); every lane of the quad must be active.
-template <int CTRL>
-__device__ __forceinline__ double quad_perm(double x) {
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-
-__device__ __forceinline__ double quad_sum(double x) {
-    x += quad_perm<0xB1>(x);   // lanes (1,0,3,2)
-    x += quad_perm<0x4E>(x);   // lanes (2,3,0,1)
-    return x;
-}
-
-// This lane's share of v^T a over the tile (v in LDS, row t at v[t]); four partial chains.
-__device__ __forceinline__ double dot_lane(const double* v, const double (&a)[RPL], int g) {
-    double p[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int i = 0; i < RPL; ++i) p[i & 3] = fma(v[i * LPC + g], a[i], p[i & 3]);
-    return (p[0] + p[1]) + (p[2] + p[3]);
-}
-
-__device__ __forceinline__ double norm2_lane(const double (&a)[RPL]) {
-    double p[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int i = 0; i < RPL; ++i) p[i & 3] = fma(a[i], a[i], p[i & 3]);
-    return (p[0] + p[1]) + (p[2] + p[3]);
-}
-
-// Reflector j from (slot[j][j], tile column j held by this quad): the tile part of v
-// overwrites a[], goes to vbuf, tau to tau_sh and taus_out[j].
-template <typename SlotT>
-__device__ __forceinline__ void make_reflector(SlotT* slot, double (&a)[RPL], int c, int j, int g, double* vbuf,
-                                               double* tau_sh, double* taus_out) {
-    const double xn2 = quad_sum(norm2_lane(a));
-    const int dj = tri_index(j, j, c);
-    const double rjj = (double)slot[dj];
-    double tau = 0.0;
-    if (xn2 > 0.0) {
-        // beta = -sign(rjj) |(rjj, x)|, tau = (beta - rjj) / beta, v = x / (rjj - beta).
-        // |beta| and |rjj - beta| are at least sqrt(xn2) >= 2^-537, so both reciprocals
-        // are of normal numbers.  (Their product is not: a chain whose tiles have fewer
-        // rows than columns drives the later columns' norms down to rounding noise of
-        // rounding noise, below 1e-300.)
-        const double t = fma(rjj, rjj, xn2);
-        const double beta = -copysign(t * rsqrt_refined(t), rjj);
-        const double u = rjj - beta;
-        tau = -u * rcp_refined(beta);
-        const double sc = rcp_refined(u);
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) a[i] *= sc;
-        if (g == 0) slot[dj] = (SlotT)beta;
-    }
-#pragma unroll
-    for (int i = 0; i < RPL; ++i) vbuf[i * LPC + g] = a[i];
-    if (g == 0) {
-        *tau_sh = tau;
-        taus_out[j] = tau;
-    }
-}
-
-// Apply reflector (v, tau) with slot row j to this quad's column col: slot[j][col] and a[].
-template <typename SlotT>
-__device__ __forceinline__ void reflect_column(SlotT* slot, double (&a)[RPL], int c, int j, int col, int g,
-                                               const double* v, double tau) {
-    const double s = quad_sum(dot_lane(v, a, g));
-    const int idx = tri_index(j, col, c);
-    const double r = (double)slot[idx];
-    const double w = (r + s) * tau;
-    if (g == 0) slot[idx] = (SlotT)(r - w);
-#pragma unroll
-    for (int i = 0; i < RPL; ++i) a[i] = fma(-w, v[i * LPC + g], a[i]);
-}
-
-// Forward: fold the tile (a[] = this quad's column, TR rows) into the slot with
-// reflectors jstart..c-1.  Reflector j's tile part replaces column j's a[].
-// Reflectors alternate between two LDS buffers so one barrier per reflector
-// suffices: the quad of column j+1 builds reflector j+1 as soon as it has applied
-// reflector j.
-template <typename SlotT>
-__device__ void fold_tile(SlotT* slot, double (&a)[RPL], int c, int jstart, double* vbuf, double* tau_sh,
-                          double* taus_out) {
-    const int col = threadIdx.x / LPC, g = threadIdx.x % LPC;
-    if (col == jstart) make_reflector(slot, a, c, jstart, g, vbuf, tau_sh, taus_out);
-    __syncthreads();
-    for (int j = jstart; j < c; ++j) {
-        const int buf = (j - jstart) & 1;
-        const double tau = tau_sh[buf];
-        if (col > j && col < c && tau != 0.0) reflect_column(slot, a, c, j, col, g, vbuf + buf * TR, tau);
-        if (col == j + 1 && j + 1 < c)
-            make_reflector(slot, a, c, j + 1, g, vbuf + (buf ^ 1) * TR, tau_sh + (buf ^ 1), taus_out);
-        __syncthreads();
-    }
-}
-
-// Backward: apply the tile's known reflectors j = c-1 .. jstart to (slot, a[] = tile
-// rows of this quad's column).  Reflector j's tile part is refl[j * TR + t]; its tau
-// taus[j].  Reflectors go through LDS in blocks of up to NB, double-buffered: the
-// next block is loaded into registers while the current one is applied.  No barrier
-// is needed between the reflectors of a block because a column is touched only by
-// its own quad.
-constexpr int UF_PF = 4;   // prefetched doubles per thread
-
-template <typename SlotT>
-__device__ void unfold_tile(SlotT* slot, double (&a)[RPL], int c, int jstart, const double* refl,
-                            const double* taus, double* vst, double* tst) {
-    const int col = threadIdx.x / LPC, g = threadIdx.x % LPC;
-    const int nbk = min(NB, (int)(UF_PF * blockDim.x) / TR);     // reflectors per block
-    const int nblocks = (c - jstart + nbk - 1) / nbk;
-    double pre[UF_PF];
-    double ptau = 0.0;
-#define UF_LOAD(B)                                                                 \
-    {                                                                              \
-        const int jhi_ = c - 1 - (B) * nbk, jlo_ = max(jstart, jhi_ - nbk + 1);    \
-        const int cnt_ = jhi_ - jlo_ + 1;                                          \
-        _Pragma("unroll") for (int q = 0; q < UF_PF; ++q) {                        \
-            const int e = threadIdx.x + q * blockDim.x;                            \
-            pre[q] = e < cnt_ * TR ? refl[(int64_t)jlo_ * TR + e] : 0.0;           \
-        }                                                                          \
-        ptau = threadIdx.x < cnt_ ? taus[jlo_ + threadIdx.x] : 0.0;                \
-    }
-#define UF_STORE(BUF)                                                              \
-    {                                                                              \
-        double* v_ = vst + (BUF) * NB * TR;                                        \
-        _Pragma("unroll") for (int q = 0; q < UF_PF; ++q) {                        \
-            const int e = threadIdx.x + q * blockDim.x;                            \
-            if (e < NB * TR) v_[e] = pre[q];                                       \
-        }                                                                          \
-        if (threadIdx.x < NB) tst[(BUF) * NB + threadIdx.x] = ptau;                \
-    }
-    __syncthreads();
-    UF_LOAD(0)
-    UF_STORE(0)
-    __syncthreads();
-    for (int b = 0; b < nblocks; ++b) {
-        if (b + 1 < nblocks) UF_LOAD(b + 1)
-        const int jhi = c - 1 - b * nbk, jlo = max(jstart, jhi - nbk + 1);
-        const double* vb = vst + (b & 1) * NB * TR;
-        const double* tb = tst + (b & 1) * NB;
-        if (col < c) {
-            for (int j = jhi; j >= jlo; --j) {
-                const double tau = tb[j - jlo];
-                if (tau == 0.0 || col < j) continue;   // uniform within the quad
-                reflect_column(slot, a, c, j, col, g, vb + (j - jlo) * TR, tau);
-            }
-        }
-        if (b + 1 < nblocks) UF_STORE((b + 1) & 1)
-        __syncthreads();
-    }
-#undef UF_LOAD
-#undef UF_STORE
-}
-
-template <typename SlotT>
-__device__ void slot_zero(SlotT* slot, int c) {
-    const int tri = c * (c + 1) / 2;
-    for (int e = threadIdx.x; e < tri; e += blockDim.x) slot[e] = (SlotT)0;
-    __syncthreads();
-}
-
-// Slot <-> dense row-major c x c float64 (upper triangle only).
-template <typename SlotT>
-__device__ void slot_load(SlotT* slot, const double* M, int c) {
-    for (int j = 0; j < c; ++j)
-        for (int col = j + threadIdx.x; col < c; col += blockDim.x) slot[tri_index(j, col, c)] = (SlotT)M[(int64_t)j * c + col];
-    __syncthreads();
-}
-
-template <typename SlotT>
-__device__ void slot_store(const SlotT* slot, double* M, int c) {
-    for (int j = 0; j < c; ++j)
-        for (int col = threadIdx.x; col < c; col += blockDim.x)
-            M[(int64_t)j * c + col] = col >= j ? (double)slot[tri_index(j, col, c)] : 0.0;
-    __syncthreads();
-}
-
-// LDS layout shared by the four TSQR kernels: two reflector panels (2 x PANEL x TR
-// doubles; the backward pass stages NB reflectors in the first), 2 x PANEL taus,
-// then the slot.
-constexpr int STAGE_DOUBLES = 2 * PANEL * TR + 2 * PANEL;
-static_assert(NB <= 2 * PANEL, "staging buffer too small");
-
-// ---------------------------------------------------------------------------
-// Leaf chains.  Reflectors are stored per tile, column-major: reflector j of
-// global tile gt has its tile part at refl[(gt * c + j) * TR + t]; taus[gt * c + j].
-// ---------------------------------------------------------------------------
-template <typename TE, typename SlotT>
-__global__ void __launch_bounds__(QR_MAX_THREADS) tsqr_leaf_forward(int64_t n, int c, int64_t rows_per_chain,
-                                                                    const TE* __restrict__ E, double* __restrict__ refl,
-                                                                    double* __restrict__ taus, double* __restrict__ Rs) {
-    extern __shared__ unsigned char smem_raw[];
-    double* vbuf = (double*)smem_raw;
-    double* tau_sh = vbuf + 2 * PANEL * TR;
-    SlotT* slot = (SlotT*)(vbuf + STAGE_DOUBLES);
-    const int ch = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
-    const int64_t r_begin = ch * rows_per_chain;
-    const int64_t r_end = min(n, r_begin + rows_per_chain);
-    const int tiles_per_chain = (int)(rows_per_chain / TR);
-    slot_zero(slot, c);
-    for (int tile = 0; r_begin + (int64_t)tile * TR < r_end; ++tile) {
-        const int64_t r0 = r_begin + (int64_t)tile * TR;
-        double a[RPL];
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            const int64_t r = r0 + i * LPC + g;
-            a[i] = (col < c && r < r_end) ? to_f64(E[(int64_t)col * n + r]) : 0.0;
-        }
-        const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
-        fold_tile(slot, a, c, 0, vbuf, tau_sh, taus + gtile * c);
-        if (col < c) {
-            double* dst = refl + (gtile * c + col) * TR;
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) dst[i * LPC + g] = a[i];
-        }
-    }
-    slot_store(slot, Rs + (int64_t)ch * c * c, c);
-}
-
-template <typename TQ, typename SlotT>
-__global__ void __launch_bounds__(QR_MAX_THREADS) tsqr_leaf_backward(int64_t n, int c, int64_t rows_per_chain,
-                                                                     const double* __restrict__ refl,
-                                                                     const double* __restrict__ taus,
-                                                                     const double* __restrict__ Qtop, TQ* __restrict__ Q) {
-    extern __shared__ unsigned char smem_raw[];
-    double* vst = (double*)smem_raw;
-    double* tst = vst + 2 * PANEL * TR;
-    SlotT* slot = (SlotT*)(vst + STAGE_DOUBLES);
-    const int ch = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
-    const int64_t r_begin = ch * rows_per_chain;
-    if (r_begin >= n) return;   // uniform: whole workgroup leaves
-    const int64_t r_end = min(n, r_begin + rows_per_chain);
-    const int tiles_per_chain = (int)(rows_per_chain / TR);
-    const int ntiles = (int)((r_end - r_begin + TR - 1) / TR);
-    slot_load(slot, Qtop + (int64_t)ch * c * c, c);
-    for (int tile = ntiles - 1; tile >= 0; --tile) {
-        const int64_t r0 = r_begin + (int64_t)tile * TR;
-        const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
-        double a[RPL];
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) a[i] = 0.0;
-        unfold_tile(slot, a, c, 0, refl + gtile * c * TR, taus + gtile * c, vst, tst);
-        if (col < c) {
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-                const int64_t r = r0 + i * LPC + g;
-                if (r < r_end) Q[(int64_t)col * n + r] = (TQ)a[i];
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Tree over the per-chain R factors.  At level l, combine i merges chain
-// a = i * 2^(l+1) with b = a + 2^l.  The reflectors of combine (l, i) live at
-// tree_refl[(off_l + i) * ntc * c * TR] (per row tile of R_b, as in the leaves)
-// and tree_tau[((off_l + i) * ntc + t) * c + j].
-// ---------------------------------------------------------------------------
-template <typename SlotT>
-__global__ void __launch_bounds__(QR_MAX_THREADS) tsqr_tree_forward(int c, int stride, int64_t comb_off,
-                                                                    double* __restrict__ Rs,
-                                                                    double* __restrict__ tree_refl,
-                                                                    double* __restrict__ tree_tau) {
-    extern __shared__ unsigned char smem_raw[];
-    double* vbuf = (double*)smem_raw;
-    double* tau_sh = vbuf + 2 * PANEL * TR;
-    SlotT* slot = (SlotT*)(vbuf + STAGE_DOUBLES);
-    const int i = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
-    const int a_idx = i * 2 * stride, b_idx = a_idx + stride;
-    const double* Rb = Rs + (int64_t)b_idx * c * c;
-    const int ntc = (c + TR - 1) / TR;
-    double* rf = tree_refl + (comb_off + i) * (int64_t)ntc * c * TR;
-    double* tt = tree_tau + (comb_off + i) * (int64_t)ntc * c;
-    slot_load(slot, Rs + (int64_t)a_idx * c * c, c);
-    for (int tile = 0; tile < ntc; ++tile) {
-        double a[RPL];
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-            const int row = tile * TR + q * LPC + g;
-            a[q] = (col < c && row < c && col >= row) ? Rb[(int64_t)row * c + col] : 0.0;
-        }
-        fold_tile(slot, a, c, tile * TR, vbuf, tau_sh, tt + (int64_t)tile * c);
-        if (col < c) {
-            double* dst = rf + ((int64_t)tile * c + col) * TR;
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) dst[q * LPC + g] = a[q];
-        }
-    }
-    slot_store(slot, Rs + (int64_t)a_idx * c * c, c);
-}
-
-template <typename SlotT>
-__global__ void __launch_bounds__(QR_MAX_THREADS) tsqr_tree_backward(int c, int stride, int64_t comb_off,
-                                                                     double* __restrict__ Qtop,
-                                                                     const double* __restrict__ tree_refl,
-                                                                     const double* __restrict__ tree_tau) {
-    extern __shared__ unsigned char smem_raw[];
-    double* vst = (double*)smem_raw;
-    double* tst = vst + 2 * PANEL * TR;
-    SlotT* slot = (SlotT*)(vst + STAGE_DOUBLES);
-    const int i = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
-    const int a_idx = i * 2 * stride, b_idx = a_idx + stride;
-    const int ntc = (c + TR - 1) / TR;
-    const double* rf = tree_refl + (comb_off + i) * (int64_t)ntc * c * TR;
-    const double* tt = tree_tau + (comb_off + i) * (int64_t)ntc * c;
-    double* Qb = Qtop + (int64_t)b_idx * c * c;
-    slot_load(slot, Qtop + (int64_t)a_idx * c * c, c);
-    for (int tile = ntc - 1; tile >= 0; --tile) {
-        double a[RPL];
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) a[q] = 0.0;
-        unfold_tile(slot, a, c, tile * TR, rf + (int64_t)tile * c * TR, tt + (int64_t)tile * c, vst, tst);
-        if (col < c) {
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-                const int row = tile * TR + q * LPC + g;
-                if (row < c) Qb[(int64_t)row * c + col] = a[q];
-            }
-        }
-    }
-    slot_store(slot, Qtop + (int64_t)a_idx * c * c, c);
 }
 
 // F = R2 R1 for upper-triangular row-major c x c factors.
@@ -406,67 +45,6 @@ __global__ void tri_mul(int c, const double* __restrict__ R2, const double* __re
 __global__ void set_identity(double* __restrict__ M, int c) {
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < c * c; e += gridDim.x * blockDim.x)
         M[e] = (e / c == e % c) ? 1.0 : 0.0;
-}
-
-// ---------------------------------------------------------------------------
-// T = Q^T X (tall-skinny, float64 partials per row chunk, then fixed-order sum)
-// ---------------------------------------------------------------------------
-constexpr int TN_T = 64, TN_R = 32;
-
-// c x 128 column block of A^T B for one row chunk: 512 threads as a 32 x 16 grid,
-// each owning an 8 x 8 block of outputs (i = ty + 32 u, j = j0 + tx + 16 v),
-// rows staged through LDS 16 at a time.  grid = (chunks, ceil(c / 128)).
-constexpr int FT_ROWS = 16;
-
-template <typename TA, typename TB>
-__global__ void __launch_bounds__(512) gemm_tn_full(int64_t n, int c, const TA* __restrict__ A,
-                                                    const TB* __restrict__ B, double* __restrict__ part,
-                                                    int64_t rows_per_chunk) {
-    __shared__ double As[FT_ROWS][256 + 1];
-    __shared__ double Bs[FT_ROWS][128 + 1];
-    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-    const int chunk = blockIdx.x, j0 = blockIdx.y * 128;
-    const int64_t rb = chunk * rows_per_chunk, re = min(n, rb + rows_per_chunk);
-    double acc[8][8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-#pragma unroll
-        for (int v = 0; v < 8; ++v) acc[u][v] = 0.0;
-    for (int64_t r0 = rb; r0 < re; r0 += FT_ROWS) {
-        for (int e = tid; e < FT_ROWS * 256; e += 512) {
-            const int rr = e % FT_ROWS, cc = e / FT_ROWS;
-            const int64_t r = r0 + rr;
-            As[rr][cc] = (r < re && cc < c) ? to_f64(A[(int64_t)cc * n + r]) : 0.0;
-        }
-        for (int e = tid; e < FT_ROWS * 128; e += 512) {
-            const int rr = e % FT_ROWS, cc = e / FT_ROWS;
-            const int64_t r = r0 + rr;
-            Bs[rr][cc] = (r < re && j0 + cc < c) ? to_f64(B[(int64_t)(j0 + cc) * n + r]) : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 2
-        for (int rr = 0; rr < FT_ROWS; ++rr) {
-            double a[8], b[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                a[u] = As[rr][ty + 32 * u];
-                b[u] = Bs[rr][tx + 16 * u];
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int v = 0; v < 8; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
-        }
-        __syncthreads();
-    }
-    double* dst = part + (int64_t)chunk * c * c;
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            const int i = ty + 32 * u, j = j0 + tx + 16 * v;
-            if (i < c && j < c) dst[(int64_t)j * c + i] = acc[u][v];
-        }
 }
 
 __global__ void sum_chunks(int64_t count, int nchunks, const double* __restrict__ part, double* __restrict__ out) {
@@ -1183,54 +761,6 @@ __global__ void __launch_bounds__(SMALL_THREADS) order_sign(int c, const double*
     }
 }
 
-// U = Q Us[:, :rank] (n x rank, column-major) from column-major Q (n x c) and Us (c x c).
-constexpr int BS_R = 64, BS_C = 64, BS_I = 16;
-
-template <typename TQ, typename TO>
-__global__ void __launch_bounds__(256) basis_gemm(int64_t n, int c, int rank, const TQ* __restrict__ Q,
-                                                  const double* __restrict__ Us, TO* __restrict__ U) {
-    __shared__ double Qs[BS_I][BS_R + 2];
-    __shared__ double Ms[BS_I][BS_C + 2];
-    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-    const int64_t r0 = (int64_t)blockIdx.y * BS_R;
-    const int j0 = blockIdx.x * BS_C;
-    double acc[4][4] = {};
-    for (int i0 = 0; i0 < c; i0 += BS_I) {
-        for (int q = tid; q < BS_I * BS_R; q += 256) {
-            const int rr = q % BS_R, ii = q / BS_R;
-            const int64_t r = r0 + rr;
-            Qs[ii][rr] = (r < n && i0 + ii < c) ? to_f64(Q[(int64_t)(i0 + ii) * n + r]) : 0.0;
-        }
-        for (int q = tid; q < BS_I * BS_C; q += 256) {
-            const int ii = q % BS_I, jj = q / BS_I;
-            Ms[ii][jj] = (i0 + ii < c && j0 + jj < rank) ? Us[(int64_t)(j0 + jj) * c + i0 + ii] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int ii = 0; ii < BS_I; ++ii) {
-            double qv[4], mv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                qv[u] = Qs[ii][tx * 4 + u];
-                mv[u] = Ms[ii][ty * 4 + u];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(qv[u], mv[v], acc[u][v]);
-        }
-        __syncthreads();
-    }
-    for (int v = 0; v < 4; ++v) {
-        const int j = j0 + ty * 4 + v;
-        if (j >= rank) continue;
-        for (int u = 0; u < 4; ++u) {
-            const int64_t r = r0 + tx * 4 + u;
-            if (r < n) U[(int64_t)j * n + r] = (TO)acc[u][v];
-        }
-    }
-}
-
 template <typename TO, typename Th>
 __global__ void posterior_diag_kernel(int64_t n, int rank, const TO* __restrict__ U, const double* __restrict__ lam,
                                       const Th* __restrict__ h0, TO* __restrict__ dout) {
@@ -1258,80 +788,6 @@ __global__ void zero_rsvd(int64_t n, int rank, TO* __restrict__ U, double* __res
 // ---------------------------------------------------------------------------
 // Host driver
 // ---------------------------------------------------------------------------
-inline int floor_pow2(int64_t x) {
-    int p = 1;
-    while ((int64_t)p * 2 <= x) p *= 2;
-    return p;
-}
-
-template <typename SlotT>
-size_t slot_smem(int c) {
-    return STAGE_DOUBLES * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
-}
-
-template <typename TO, typename SlotT>
-int tsqr(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
-    const int64_t n = h->n;
-    const int64_t tiles_total = (n + TR - 1) / TR;
-    const int nchains = (int)std::min<int64_t>(h->qr_chains, floor_pow2(std::max<int64_t>(1, tiles_total / 2)));
-    const int64_t rows_per_chain = round_up((n + nchains - 1) / nchains, TR);
-    const int tiles_per_chain = (int)(rows_per_chain / TR);
-    const int ntc = (c + TR - 1) / TR;
-    int rc;
-    const size_t refl_bytes = (size_t)nchains * rows_per_chain * c * 8;
-    const size_t tau_bytes = (size_t)nchains * tiles_per_chain * c * 8;
-    if ((rc = ensure_ws(h->refl, refl_bytes)) != BFGS_OK) return rc;
-    if ((rc = ensure_ws(h->tau, tau_bytes + (size_t)nchains * ntc * c * 8)) != BFGS_OK) return rc;
-    // Rtree: Rs (nchains c*c) + Qtop (nchains c*c) + tree reflectors (nchains ntc*c*TR)
-    if ((rc = ensure_ws(h->Rtree, ((size_t)2 * nchains * c * c + (size_t)nchains * ntc * c * TR) * 8)) != BFGS_OK)
-        return rc;
-    double* refl = (double*)h->refl.ptr;
-    double* taus = (double*)h->tau.ptr;
-    double* tree_tau = taus + (size_t)nchains * tiles_per_chain * c;
-    double* Rs = (double*)h->Rtree.ptr;
-    double* Qtop = Rs + (size_t)nchains * c * c;
-    double* tree_refl = Qtop + (size_t)nchains * c * c;
-    const size_t smem = slot_smem<SlotT>(c);
-    const int qr_threads = LPC * round_up(c, 16);
-    // Raise the dynamic-LDS limit once per instantiation (never while a graph is being captured).
-    static bool attr_done = false;
-    if (!attr_done) {
-        const int lim = 160 * 1024;
-        if (hipFuncSetAttribute((const void*)tsqr_leaf_forward<TO, SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
-            hipFuncSetAttribute((const void*)tsqr_leaf_backward<TO, SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
-            hipFuncSetAttribute((const void*)tsqr_tree_forward<SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
-            hipFuncSetAttribute((const void*)tsqr_tree_backward<SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
-            return BFGS_ERR_HIP;
-        attr_done = true;
-    }
-    ProfScope ps(h, "tsqr_leaf_fwd");
-    hipLaunchKernelGGL((tsqr_leaf_forward<TO, SlotT>), dim3(nchains), dim3(qr_threads), smem, h->stream, n, c,
-                       rows_per_chain, E, refl, taus, Rs);
-    prof_end(h);
-    prof_begin(h, "tsqr_tree");
-    int64_t off = 0;
-    int levels = 0;
-    for (int stride = 1; stride < nchains; stride *= 2, ++levels) {
-        const int ncomb = nchains / (2 * stride);
-        hipLaunchKernelGGL((tsqr_tree_forward<SlotT>), dim3(ncomb), dim3(qr_threads), smem, h->stream, c, stride, off, Rs,
-                           tree_refl, tree_tau);
-        off += ncomb;
-    }
-    hipLaunchKernelGGL(set_identity, dim3(64), dim3(256), 0, h->stream, Qtop, c);
-    for (int stride = nchains / 2; stride >= 1; stride /= 2) {
-        const int ncomb = nchains / (2 * stride);
-        off -= ncomb;
-        hipLaunchKernelGGL((tsqr_tree_backward<SlotT>), dim3(ncomb), dim3(qr_threads), smem, h->stream, c, stride, off,
-                           Qtop, tree_refl, tree_tau);
-    }
-    prof_end(h);
-    prof_begin(h, "tsqr_leaf_bwd");
-    hipLaunchKernelGGL((tsqr_leaf_backward<TO, SlotT>), dim3(nchains), dim3(qr_threads), smem, h->stream, n, c,
-                       rows_per_chain, refl, taus, Qtop, Q);
-    *R_out = Rs;   // chain 0 holds the final R (row-major, upper triangular)
-    return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
-}
-
 template <typename TS, typename TO, typename Th>
 int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, double* Sigma) {
     const int64_t n = h->n;

@@ -7,7 +7,11 @@
 // float64 matrix-core accumulator fragments: wave w owns column tile w (columns
 // 16w .. 16w + 15), lane l holds rows 16 rt + l/16 + 4 r of column 16 w + l%16.
 //
-// Fold of one tile (forward).  Panel p (column tile p) is factored by its owner
+// Leaves (forward).  One quad of lanes per column folds each tile with one
+// barrier per reflector (leaf_forward_q); the reflectors are stored in the panel
+// layout below and build_t computes each panel's T from them afterwards, in parallel.
+//
+// Tree fold (forward).  Panel p (column tile p) is factored by its owner
 // wave, one Householder reflector per column acting on (slot row j, tile rows);
 // the panel's reflectors form the compact WY block I - V T V^T (V: tile part,
 // the slot part of reflector j is the unit vector e_j; T upper triangular).  The
@@ -366,37 +370,178 @@ __device__ void unfold_tile(SlotT* slot, v4d (&A)[Layout<BT>::RT], int c, int p0
 }
 
 // ---------------------------------------------------------------------------
-// Kernels.  Leaf tile g of chain ch stores its panels at refl + (g * np + p) * PS.
+// Leaf fold with a quad of lanes per column (one barrier per reflector).  The
+// leaves' critical path is the chain of c reflectors per tile; handing each column
+// to its own quad (16 rows per lane, quad DPP reductions) and building reflector
+// j+1 in the quad of column j+1 right after it applies reflector j keeps that
+// chain shorter than the per-wave panel factorisation.  The reflectors are
+// written in the panel layout of the blocked backward pass (T's diagonal holds
+// the taus; build_t fills in the rest of T).
 // ---------------------------------------------------------------------------
-template <typename TE, typename SlotT, int BT>
-__global__ void __launch_bounds__(1024) leaf_forward(int64_t n, int c, int64_t rows_per_chain, const TE* __restrict__ E,
-                                                     double* __restrict__ refl, double* __restrict__ Rs) {
+constexpr int QT = 64;                 // tile rows (matches the blocked pass's BT = 64)
+constexpr int LPC = 4;                 // lanes per column
+constexpr int RPL = QT / LPC;          // rows per lane: row t = i * LPC + g
+
+template <int CTRL>
+__device__ __forceinline__ double quad_perm(double x) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double quad_sum(double x) {
+    x += quad_perm<0xB1>(x);   // lanes (1,0,3,2)
+    x += quad_perm<0x4E>(x);   // lanes (2,3,0,1)
+    return x;
+}
+
+// Reflector j from (slot[j][j], tile column j held by this quad): the tile part
+// overwrites a[], goes to vbuf; tau to tau_sh and taus_lds[j].
+template <typename SlotT>
+__device__ __forceinline__ void q_make_reflector(SlotT* slot, double (&a)[RPL], int c, int j, int g, double* vbuf,
+                                                 double* tau_sh, double* taus_lds) {
+    double p4[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) p4[i & 3] = fma(a[i], a[i], p4[i & 3]);
+    const double xn2 = quad_sum((p4[0] + p4[1]) + (p4[2] + p4[3]));
+    const int dj = tri_index(j, j, c);
+    const double rjj = (double)slot[dj];
+    double tau = 0.0;
+    if (xn2 > 0.0) {
+        // as in factor_panel: two reciprocals of normal-range numbers
+        const double t = fma(rjj, rjj, xn2);
+        const double beta = -copysign(t * rsqrt_nr(t), rjj);
+        const double u = rjj - beta;
+        tau = -u * rcp_nr(beta);
+        const double sc = rcp_nr(u);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) a[i] *= sc;
+        if (g == 0) slot[dj] = (SlotT)beta;
+    }
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) vbuf[i * LPC + g] = a[i];
+    if (g == 0) {
+        *tau_sh = tau;
+        taus_lds[j] = tau;
+    }
+}
+
+template <typename SlotT>
+__device__ __forceinline__ void q_reflect_column(SlotT* slot, double (&a)[RPL], int c, int j, int col, int g,
+                                                 const double* v, double tau) {
+    double p4[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) p4[i & 3] = fma(v[i * LPC + g], a[i], p4[i & 3]);
+    const double s = quad_sum((p4[0] + p4[1]) + (p4[2] + p4[3]));
+    const int idx = tri_index(j, col, c);
+    const double r = (double)slot[idx];
+    const double w = (r + s) * tau;
+    if (g == 0) slot[idx] = (SlotT)(r - w);
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) a[i] = fma(-w, v[i * LPC + g], a[i]);
+}
+
+// LDS of the quad fold: vbuf[2][QT] | tau_sh[2] | taus_lds[256] | slot
+constexpr int QF_HEAD = 2 * QT + 2 + 256;
+
+template <typename SlotT>
+size_t qf_lds_bytes(int c) {
+    return (size_t)QF_HEAD * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
+}
+
+template <typename TE, typename SlotT>
+__global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t rows_per_chain,
+                                                       const TE* __restrict__ E, double* __restrict__ refl,
+                                                       double* __restrict__ Rs) {
     extern __shared__ double lds[];
-    constexpr int RT = Layout<BT>::RT, PS = Layout<BT>::PS;
-    SlotT* slot = (SlotT*)(lds + Layout<BT>::HEAD);
-    const int ch = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6, jl = lane & 15, q = lane >> 4;
+    double* vbuf = lds;
+    double* tau_sh = vbuf + 2 * QT;
+    double* taus_lds = tau_sh + 2;
+    SlotT* slot = (SlotT*)(lds + QF_HEAD);
+    constexpr int PS = Layout<QT>::PS;
+    const int ch = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
     const int np = (c + PW - 1) / PW;
-    const int col = wave * PW + jl;
     const int64_t r_begin = ch * rows_per_chain;
     const int64_t r_end = min(n, r_begin + rows_per_chain);
-    const int tiles_per_chain = (int)(rows_per_chain / BT);
+    const int tiles_per_chain = (int)(rows_per_chain / QT);
     slot_zero(slot, c);
-    for (int tile = 0; r_begin + (int64_t)tile * BT < r_end; ++tile) {
-        const int64_t r0 = r_begin + (int64_t)tile * BT;
-        v4d A[RT];
+    for (int tile = 0; r_begin + (int64_t)tile * QT < r_end; ++tile) {
+        const int64_t r0 = r_begin + (int64_t)tile * QT;
+        double a[RPL];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = r0 + rt * 16 + q + 4 * r;
-                A[rt][r] = (col < c && row < r_end) ? to_f64(E[(int64_t)col * n + row]) : 0.0;
-            }
+        for (int i = 0; i < RPL; ++i) {
+            const int64_t r = r0 + i * LPC + g;
+            a[i] = (col < c && r < r_end) ? to_f64(E[(int64_t)col * n + r]) : 0.0;
+        }
+        if (col == 0) q_make_reflector(slot, a, c, 0, g, vbuf, tau_sh, taus_lds);
+        __syncthreads();
+        for (int j = 0; j < c; ++j) {
+            const int buf = j & 1;
+            const double tau = tau_sh[buf];
+            if (col > j && col < c && tau != 0.0) q_reflect_column(slot, a, c, j, col, g, vbuf + buf * QT, tau);
+            if (col == j + 1 && j + 1 < c)
+                q_make_reflector(slot, a, c, j + 1, g, vbuf + (buf ^ 1) * QT, tau_sh + (buf ^ 1), taus_lds);
+            __syncthreads();
+        }
+        // reflector col: tile part (rows t = i * LPC + g) and tau on T's diagonal
         const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
-        fold_tile<BT, SlotT>(slot, A, c, 0, lds, refl + gtile * np * PS);
+        if (col < np * PW) {
+            double* dst = refl + (gtile * np + col / PW) * PS;
+            const int jj = col % PW;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) dst[jj * QT + i * LPC + g] = a[i];
+            if (g == 0) dst[PW * QT + jj * PW + jj] = col < c ? taus_lds[col] : 0.0;
+        }
     }
     slot_store(slot, Rs + (int64_t)ch * c * c, c);
 }
 
+// T of every stored panel from its V and taus (diagonal): G = V^T V on the matrix
+// core, then row a of T by lane a.  One wave per panel.
+__global__ void __launch_bounds__(256) build_t(int64_t npanels, double* __restrict__ store) {
+    constexpr int PS = Layout<QT>::PS;
+    __shared__ double Vs[4][PW * (QT + 2)];
+    __shared__ double Gs[4][PW * TS_LD];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, jl = lane & 15, q = lane >> 4;
+    const int64_t pid = (int64_t)blockIdx.x * 4 + wave;
+    if (pid >= npanels) return;   // uniform per wave; no workgroup barrier below
+    double* base = store + pid * PS;
+    double* V = Vs[wave];
+    double* G = Gs[wave];
+    for (int e = lane; e < PW * QT; e += 64) V[(e / QT) * (QT + 2) + e % QT] = base[e];
+    wave_sync();
+    v4d gacc = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < QT / 4; ++ks) {
+        const double a = V[jl * (QT + 2) + ks * 4 + q];
+        gacc = mfma64(a, a, gacc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) G[(q + 4 * r) * TS_LD + jl] = gacc[r];
+    wave_sync();
+    if (lane < PW) {
+        double* T = base + PW * QT;
+        double tau[PW];
+#pragma unroll
+        for (int i = 0; i < PW; ++i) tau[i] = T[i * PW + i];
+        double trow[PW];
+#pragma unroll
+        for (int i = 0; i < PW; ++i) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int b = 0; b < i; ++b) sacc = fma(trow[b], G[b * TS_LD + i], sacc);
+            trow[i] = i < lane ? 0.0 : (i == lane ? tau[i] : -tau[i] * sacc);
+        }
+#pragma unroll
+        for (int i = 0; i < PW; ++i) T[lane * PW + i] = trow[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels of the blocked passes.  Leaf tile g of chain ch stores its panels at
+// refl + (g * np + p) * PS.
+// ---------------------------------------------------------------------------
 template <typename TQ, typename SlotT, int BT>
 __global__ void __launch_bounds__(1024) leaf_backward(int64_t n, int c, int64_t rows_per_chain,
                                                       const double* __restrict__ refl, const double* __restrict__ Qtop,
@@ -526,16 +671,26 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     static bool attr_done = false;
     if (!attr_done) {
         const int lim = 160 * 1024;
-        if (hipFuncSetAttribute((const void*)leaf_forward<TO, SlotT, BT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
-            hipFuncSetAttribute((const void*)leaf_backward<TO, SlotT, BT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
+        if (hipFuncSetAttribute((const void*)leaf_backward<TO, SlotT, BT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
             hipFuncSetAttribute((const void*)tree_forward<SlotT, BT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
             hipFuncSetAttribute((const void*)tree_backward<SlotT, BT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
             return BFGS_ERR_HIP;
         attr_done = true;
     }
+    static bool attr_q = false;
+    if (!attr_q) {
+        if (hipFuncSetAttribute((const void*)leaf_forward_q<TO, SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024) != hipSuccess)
+            return BFGS_ERR_HIP;
+        attr_q = true;
+    }
     prof_begin(h, "tsqr_leaf_fwd");
-    hipLaunchKernelGGL((leaf_forward<TO, SlotT, BT>), dim3(nchains), dim3(threads), smem, h->stream, n, c,
-                       rows_per_chain, E, refl, Rs);
+    hipLaunchKernelGGL((leaf_forward_q<TO, SlotT>), dim3(nchains), dim3(LPC * 16 * np), qf_lds_bytes<SlotT>(c),
+                       h->stream, n, c, rows_per_chain, E, refl, Rs);
+    {
+        const int64_t npanels = (int64_t)nchains * tiles_per_chain * np;
+        hipLaunchKernelGGL(build_t, dim3((unsigned)((npanels + 3) / 4)), dim3(256), 0, h->stream, npanels, refl);
+    }
     prof_end(h);
     prof_begin(h, "tsqr_tree");
     int64_t off = 0;
@@ -568,7 +723,8 @@ int tsqr_dispatch(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     // within 128 registers per lane (1024-thread workgroups); the slot is float64
     // whenever it fits in LDS (c <= 184) and float32 above that
     const size_t lim = 160 * 1024;
-    if (lds_bytes<64, double>(c) <= lim) return tsqr_impl<TO, double, 64>(h, c, E, Q, R_out);
+    if (lds_bytes<64, double>(c) <= lim && qf_lds_bytes<double>(c) <= lim)
+        return tsqr_impl<TO, double, 64>(h, c, E, Q, R_out);
     return tsqr_impl<TO, float, 64>(h, c, E, Q, R_out);
 }
 
