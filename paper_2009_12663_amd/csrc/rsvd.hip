@@ -107,7 +107,7 @@ constexpr int MT_K = 16;          // reduction depth staged per step
 // (nchunk, nblk, nblk): workgroup (ch, bi, bj) owns output rows bi * 128.. and
 // columns bj * 128..
 template <typename TQ, typename TX>
-__global__ void __launch_bounds__(256) qtx_mfma(int64_t n, int c, const TQ* __restrict__ Q, const TX* __restrict__ X,
+__global__ void __launch_bounds__(256, 2) qtx_mfma(int64_t n, int c, const TQ* __restrict__ Q, const TX* __restrict__ X,
                                                 double* __restrict__ part, int64_t rows_per_chunk) {
     __shared__ double Qs[MT_K][MT_LD];
     __shared__ double Xs[MT_K][MT_LD];
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(256) qtx_mfma(int64_t n, int c, const TQ* __re
 // U = Q Us[:, :rank] (n x rank, column-major, TO) from column-major Q (n x c) and
 // Us (c x c, column-major).  Grid (ceil(n / 128), ceil(rank / 128)).
 template <typename TQ, typename TO>
-__global__ void __launch_bounds__(256) basis_mfma(int64_t n, int c, int rank, const TQ* __restrict__ Q,
+__global__ void __launch_bounds__(256, 2) basis_mfma(int64_t n, int c, int rank, const TQ* __restrict__ Q,
                                                   const double* __restrict__ Us, TO* __restrict__ U) {
     __shared__ double stage_sh[MT_TILE * (MT_K + 1) + MT_K * MT_LD];
     double* Qs = stage_sh;                          // [128 rows][MT_K + 1]
