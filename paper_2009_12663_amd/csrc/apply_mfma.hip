@@ -82,31 +82,48 @@ __global__ void scatter_pair_layouts(int64_t n, int64_t rows_f1, int64_t rows_f2
 // ---------------------------------------------------------------------------
 // Pass 1
 // ---------------------------------------------------------------------------
-constexpr int G1_STAGE = 64;      // rows per stage (4 MFMA k-steps of 16)
-constexpr int VS_LD = 72;         // LDS row pitch (elements) of a staged V column: 64 rows + 8 pad
+// Rows per stage: 128 (8 MFMA k-steps of 16) while the register budget allows it,
+// 64 for eight column tiles; one stage is in flight while the previous one is used.
+template <int NT>
+struct G1Shape {
+    static constexpr int STAGE = NT >= 8 ? 64 : 128;
+    static constexpr int KS = STAGE / 16;
+    static constexpr int CPC = STAGE / 8;   // 16-byte chunks per staged V column
+    static constexpr int LD = STAGE + 8;    // LDS pitch (elements) of a staged V column
+};
+int g1_stage(int NT) { return NT >= 8 ? G1Shape<8>::STAGE : G1Shape<1>::STAGE; }
 
 // blockDim = 64 * MT (one 32-pair tile per wave); grid = 16 * ceil(nk / 8)
 template <int NT, bool DIAG>
 __global__ void __launch_bounds__(512) gemm1_mfma(int64_t n, int k, int kmax, int c, const bf16_t* __restrict__ S1,
                                                   const bf16_t* __restrict__ Y1, const float* __restrict__ h0,
                                                   const bf16_t* __restrict__ V, float* __restrict__ part,
-                                                  int64_t rows_per_wg, int64_t rows_f1, int nk, int v_aligned) {
+                                                  int64_t rows_per_xcd, int64_t rows_f1, int nk, int v_aligned) {
+    constexpr int G1_STAGE = G1Shape<NT>::STAGE, G1_KS = G1Shape<NT>::KS, G1_CPC = G1Shape<NT>::CPC;
+    constexpr int VS_LD = G1Shape<NT>::LD;
     extern __shared__ unsigned char smem_raw[];
     uint16_t* Vs = (uint16_t*)smem_raw;                 // [NT*32][VS_LD]
     uint16_t* Vl = Vs + NT * 32 * VS_LD;                // low halves (Y part, diagonal B_0)
+    // Workgroup g runs on XCD g % 8.  Each XCD owns a contiguous eighth of the rows
+    // (rows_per_xcd, a whole number of stages) and deals its stages round-robin to its
+    // nk / 8 row slots, so the slots of one XCD stream neighbouring rows of every V
+    // column together.  The S and Y workgroups of a slot (g and g + 8) share an XCD,
+    // and with it the V stage in L2.
     const int g = blockIdx.x;
-    const int kr = 8 * (g / 16) + (g % 8);
-    const int part_id = (g / 8) % 2;
-    if (kr >= nk) return;                                // whole workgroup
+    const int xcd = g % 8, slot = g / 8, nj = nk / 8;
+    const int part_id = slot % 2, j = slot / 2;
+    if (j >= nj) return;                                 // whole workgroup
+    const int kr = xcd * nj + j;                         // partial-sum index
     const bool scaled = DIAG && part_id == 1;
     const bf16_t* W = part_id ? Y1 : S1;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int p = wave * 32 + (lane & 31);               // pair owned by this lane in the A fragment
     const bool active = wave * 32 < k;                   // waves past the last pair tile only stage V
     const int half = lane >> 5;
-    const int64_t r_begin = (int64_t)kr * rows_per_wg;
-    int64_t r_end = r_begin + rows_per_wg;
+    const int64_t r_begin = (int64_t)xcd * rows_per_xcd + (int64_t)j * G1_STAGE;
+    int64_t r_end = (int64_t)(xcd + 1) * rows_per_xcd;
     if (r_end > rows_f1) r_end = rows_f1;
+    const int64_t r_step = (int64_t)nj * G1_STAGE;
 
     floatx16 acc[NT];
 #pragma unroll
@@ -114,17 +131,17 @@ __global__ void __launch_bounds__(512) gemm1_mfma(int64_t n, int k, int kmax, in
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
 
-    constexpr int VCH = NT * 32 * 8;                     // 16-byte chunks per staged V block
+    constexpr int VCH = NT * 32 * G1_CPC;                // 16-byte chunks per staged V block
     constexpr int VQ = (VCH + 511) / 512;                // per thread (512 threads)
     uint4 vreg[VQ];
-    uint4 areg[4];
+    uint4 areg[G1_KS];
 
     auto load_v = [&](int64_t r0) {
 #pragma unroll
         for (int q = 0; q < VQ; ++q) {
             const int idx = tid + q * 512;
             if (idx >= VCH) continue;
-            const int col = idx >> 3, ch = idx & 7;
+            const int col = idx / G1_CPC, ch = idx % G1_CPC;
             const int64_t r = r0 + ch * 8;
             uint4 val = make_uint4(0, 0, 0, 0);
             if (col < c && r < n) {
@@ -146,7 +163,7 @@ __global__ void __launch_bounds__(512) gemm1_mfma(int64_t n, int k, int kmax, in
         for (int q = 0; q < VQ; ++q) {
             const int idx = tid + q * 512;
             if (idx >= VCH) continue;
-            const int col = idx >> 3, ch = idx & 7;
+            const int col = idx / G1_CPC, ch = idx % G1_CPC;
             uint16_t* dst = Vs + col * VS_LD + ch * 8;
             if (!scaled) {
                 *(uint4*)dst = vreg[q];
@@ -168,7 +185,7 @@ __global__ void __launch_bounds__(512) gemm1_mfma(int64_t n, int k, int kmax, in
     };
     auto load_a = [&](int64_t r0) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < G1_KS; ++s) {
             const int64_t rr = r0 + 16 * s;
             if (active && p < k && rr < r_end)
                 areg[s] = *(const uint4*)(W + (rr / 16) * (int64_t)kmax * 16 + (int64_t)p * 16 + half * 8);
@@ -181,20 +198,20 @@ __global__ void __launch_bounds__(512) gemm1_mfma(int64_t n, int k, int kmax, in
         load_v(r_begin);
         load_a(r_begin);
     }
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += G1_STAGE) {
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += r_step) {
         __syncthreads();
         store_v(r0);
         __syncthreads();
-        uint4 acur[4];
+        uint4 acur[G1_KS];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acur[s] = areg[s];
-        if (r0 + G1_STAGE < r_end) {
-            load_v(r0 + G1_STAGE);
-            load_a(r0 + G1_STAGE);
+        for (int s = 0; s < G1_KS; ++s) acur[s] = areg[s];
+        if (r0 + r_step < r_end) {
+            load_v(r0 + r_step);
+            load_a(r0 + r_step);
         }
         if (active) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < G1_KS; ++s) {
             const bf16x8 a = as_bf16x8(acur[s]);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
@@ -262,10 +279,11 @@ __global__ void pack_small(int k, int c, int cpad, int Gp, const double* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Pass 2: 8 waves, one 32-row tile each (256 rows per workgroup), MT2 column tiles.
+// Pass 2: eight 32-row groups per workgroup (256 rows), MT2 column tiles.
 // ---------------------------------------------------------------------------
 constexpr int G2_ROWS = 256;
 constexpr int SM_LD = 40;        // LDS pitch of a staged small column: 32 pairs + 8 pad
+constexpr int G2_EP_LD = 264;    // LDS pitch (floats) of a staged output column: 256 rows + 8 pad
 
 // Two waves share each 32-row group (SPLIT = 2 when MT2 > 1), each owning MH of the
 // MT2 output column tiles: the W fragments are read by both (the second read hits
@@ -274,7 +292,7 @@ template <int MT2>
 struct G2Shape {
     static constexpr int SPLIT = MT2 > 1 ? 2 : 1;
     static constexpr int MH = (MT2 + SPLIT - 1) / SPLIT;
-    static constexpr int THREADS = 512 * SPLIT;
+    static constexpr int THREADS = 64 * (G2_ROWS / 32) * SPLIT;
 };
 
 template <int MT2, bool DIFF>
@@ -291,10 +309,18 @@ __global__ void __launch_bounds__(G2Shape<MT2>::THREADS) gemm2_mfma(int64_t n, i
     constexpr int BUF = MT2 * 32 * SM_LD;
     uint16_t* sm = (uint16_t*)smem_raw;   // buffer b: hi at sm + 2*b*BUF, lo at sm + (2*b+1)*BUF
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, half = lane >> 5;
-    const int rg = wave / SPLIT, cs = wave % SPLIT;        // row group, column share
+    // row group and column share; the share alternates between waves 4 apart, which
+    // sit on the same SIMD, so every SIMD gets one wave of each share
+    const int rg = wave / SPLIT, cs = SPLIT == 2 ? ((wave ^ (wave >> 2)) & 1) : 0;
     const int mt0 = cs * MH;                               // first column tile of this wave
     const int ntw = min(MH, MT2 - mt0);                    // tiles of this wave (uniform)
-    const int64_t row_base = (int64_t)blockIdx.x * G2_ROWS + rg * 32;
+    // Row block: workgroup g runs on XCD g % 8, and each XCD walks a contiguous eighth
+    // of the row blocks in order, so the column-major V reads and output writes of the
+    // workgroups an XCD runs at once form long runs per column.
+    const int nblk = (int)((n + G2_ROWS - 1) / G2_ROWS), per_xcd = (nblk + 7) / 8;
+    const int blk = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (blk >= nblk) return;                              // whole workgroup
+    const int64_t row_base = (int64_t)blk * G2_ROWS + rg * 32;
     const int64_t rb32 = row_base / 32;
     const int K2 = 2 * Gp * 16;
     const int nchunks = K2 / 32;
@@ -336,12 +362,15 @@ __global__ void __launch_bounds__(G2Shape<MT2>::THREADS) gemm2_mfma(int64_t n, i
             *(uint4*)(L_ + ((tid + NTH) >> 2) * SM_LD + (tid & 3) * 8) = sl1;               \
         }                                                                                   \
     }
+    // Every call issues a load: a chunk past the end re-reads the last chunk (unused), and a
+    // padding group past G re-reads group G - 1, whose product with the zero rows of the
+    // small operand is exactly zero.  With no branch or select on the result, each prefetch
+    // slot stays in one register set and the loop carries no copies (nor the wait for all
+    // outstanding loads that such copies would force at the back edge).
     auto load_b = [&](int t, int sg) -> uint4 {
-        const int gq = 2 * t + sg;
-        if (t >= nchunks) return make_uint4(0, 0, 0, 0);
+        const int gq = 2 * min(t, nchunks - 1) + sg;
         const int phase = gq >= Gp ? 1 : 0;
-        const int grp = gq - phase * Gp;
-        if (grp >= G) return make_uint4(0, 0, 0, 0);
+        const int grp = min(gq - phase * Gp, G - 1);
         const bf16_t* W = phase ? S2 : Y2;
         return *(const uint4*)(W + rb32 * (int64_t)G * 512 + (int64_t)grp * 512 + (lane & 31) * 16 + half * 8);
     };
@@ -356,24 +385,24 @@ __global__ void __launch_bounds__(G2Shape<MT2>::THREADS) gemm2_mfma(int64_t n, i
     }
     G2_LOAD_SMALL(0)
     G2_STORE_SMALL(0)
-    if (nchunks > 1) G2_LOAD_SMALL(1)
+    G2_LOAD_SMALL(min(1, nchunks - 1))
     __syncthreads();
     for (int t0 = 0; t0 < nchunks; t0 += DEPTH) {
 #pragma unroll
         for (int d = 0; d < DEPTH; ++d) {
             const int t = t0 + d;
-            if (t < nchunks) {
-                const int buf = t & 1;
-                if (t + 1 < nchunks) G2_STORE_SMALL(buf ^ 1)
-                if (t + 2 < nchunks) G2_LOAD_SMALL(t + 2)
-                const uint4 b0 = bq0[d], b1 = bq1[d];
-                bq0[d] = load_b(t + DEPTH, 0);
-                bq1[d] = load_b(t + DEPTH, 1);
-                const uint16_t* H = sm + 2 * buf * BUF;
-                const uint16_t* L = H + BUF;
+            // The loads run unconditionally (clamped chunk indices) so that the prefetch
+            // registers take the same path on every iteration; only the LDS store and the
+            // MFMAs are skipped for a chunk past the end.
+            const int buf = t & 1;
+            if (t + 1 < nchunks) G2_STORE_SMALL(buf ^ 1)
+            G2_LOAD_SMALL(min(t + 2, nchunks - 1))
+            const uint16_t* H = sm + 2 * buf * BUF;
+            const uint16_t* L = H + BUF;
 #pragma unroll
-                for (int sg = 0; sg < 2; ++sg) {
-                    const bf16x8 b = as_bf16x8(sg ? b1 : b0);
+            for (int sg = 0; sg < 2; ++sg) {
+                if (t < nchunks) {
+                    const bf16x8 b = as_bf16x8(sg ? bq1[d] : bq0[d]);
 #pragma unroll
                     for (int m = 0; m < MH; ++m) {
                         if (m < ntw) {
@@ -383,6 +412,12 @@ __global__ void __launch_bounds__(G2Shape<MT2>::THREADS) gemm2_mfma(int64_t n, i
                         }
                     }
                 }
+                // refill the slot just consumed: its register is free once the MFMAs
+                // above have read it, so the loop needs no register copies
+                if (sg) bq1[d] = load_b(t + DEPTH, 1);
+                else bq0[d] = load_b(t + DEPTH, 0);
+            }
+            if (t < nchunks) {
                 if (2 * t + 2 == Gp) {
                     // end of the Y phase: acc holds -(Y P)^T for this lane's row; scale by h0[row]
 #pragma unroll
@@ -396,59 +431,64 @@ __global__ void __launch_bounds__(G2Shape<MT2>::THREADS) gemm2_mfma(int64_t n, i
     }
 #undef G2_LOAD_SMALL
 #undef G2_STORE_SMALL
-    const int64_t row = row_base + (lane & 31);
+    // Output through LDS.  Pass p stages column tile p of each column share as
+    // [column][row] (256 rows per column), then every wave writes four whole columns:
+    // lane l covers rows 4l .. 4l+3 of the workgroup, so each column is one contiguous
+    // 1 KB store (16 bytes per lane) and its V rows one contiguous 512-byte load.  The
+    // small-operand buffers are free by now (last barrier of the loop).
+    float* ep = (float*)smem_raw;                        // [SPLIT * 32][G2_EP_LD]
+    const int64_t r4 = (int64_t)blk * G2_ROWS + lane * 4;
+    const bool vec = (n % 4) == 0 && (((uintptr_t)out) & 15) == 0 && (DIFF || (((uintptr_t)V) & 7) == 0);
+    float h4[4] = {0.f, 0.f, 0.f, 0.f};
     if (!DIFF) {
-        // V tile of this wave (32 columns x 32 rows per column tile) through LDS: each
-        // column's 32 rows are one 64-byte load (4 lanes x 16 bytes), then every lane
-        // reads its own row.  The small-operand buffers are free by now (last barrier).
-        uint16_t* vt = sm + wave * (32 * 40);             // [col][40] per wave, 2.5 KB
-        const bool vec_ok = (n % 8) == 0 && (((uintptr_t)V) & 15) == 0;
 #pragma unroll
-        for (int m = 0; m < MH; ++m) {
-            if (m >= ntw) continue;
-            const int mt = mt0 + m;
-            // lane -> (column q = lane / 4 + 16 * u, 8-row chunk lane % 4); two passes cover 32 columns
+        for (int e = 0; e < 4; ++e) h4[e] = r4 + e < n ? h0[r4 + e] : 0.f;
+    }
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int q = (lane >> 2) + 16 * u, ch = lane & 3;
-                const int col = mt * 32 + q;
-                const int64_t r = row_base + ch * 8;
-                uint4 val = make_uint4(0, 0, 0, 0);
-                if (col < c && r < n) {
-                    const bf16_t* src = V + (int64_t)col * n + r;
-                    if (vec_ok && r + 8 <= n) {
-                        val = *(const uint4*)src;
-                    } else {
-                        u16x8 tv;
+    for (int p = 0; p < MH; ++p) {
+        // V rows of this pass's four columns, issued before the staging barrier
+        uint2 vq[4];
+        if (!DIFF) {
 #pragma unroll
-                        for (int e = 0; e < 8; ++e) tv.v[e] = (r + e < n) ? src[e].bits : (uint16_t)0;
-                        val = __builtin_bit_cast(uint4, tv);
-                    }
-                }
-                *(uint4*)(vt + q * 40 + ch * 8) = val;
-            }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_s_waitcnt(0);
-            if (row_ok) {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int cl = 8 * (i / 4) + 4 * half + (i % 4);
-                    const int col = mt * 32 + cl;
-                    if (col < c) out[(int64_t)col * n + row] = acc[m][i] + h0r * bits_to_f32(vt[cl * 40 + (lane & 31)]);
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-    } else if (row_ok) {
-#pragma unroll
-        for (int m = 0; m < MH; ++m) {
-            if (m >= ntw) continue;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int col = (mt0 + m) * 32 + 8 * (i / 4) + 4 * half + (i % 4);
-                if (col < c) out[(int64_t)col * n + row] = acc[m][i];
+            for (int j = 0; j < 4; ++j) {
+                const int q = wave * 4 + j, qs = q / 32, col = (qs * MH + p) * 32 + q % 32;
+                vq[j] = make_uint2(0, 0);
+                const bool has = p < min(MH, MT2 - qs * MH) && col < c;
+                if (has && vec && r4 + 4 <= n) vq[j] = *(const uint2*)(V + (int64_t)col * n + r4);
             }
         }
+        if (p < ntw) {
+            float* dst = ep + cs * 32 * G2_EP_LD + rg * 32 + (lane & 31);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) dst[(8 * (i / 4) + 4 * half + (i % 4)) * G2_EP_LD] = acc[p][i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = wave * 4 + j, qs = q / 32, col = (qs * MH + p) * 32 + q % 32;
+            if (p >= min(MH, MT2 - qs * MH) || col >= c) continue;
+            const float4 a = *(const float4*)(ep + q * G2_EP_LD + lane * 4);
+            float o[4] = {a.x, a.y, a.z, a.w};
+            float* dst = out + (int64_t)col * n + r4;
+            if (vec && r4 + 4 <= n) {
+                if (!DIFF) {
+                    o[0] += h4[0] * bits_to_f32((uint16_t)(vq[j].x & 0xffffu));
+                    o[1] += h4[1] * bits_to_f32((uint16_t)(vq[j].x >> 16));
+                    o[2] += h4[2] * bits_to_f32((uint16_t)(vq[j].y & 0xffffu));
+                    o[3] += h4[3] * bits_to_f32((uint16_t)(vq[j].y >> 16));
+                }
+                *(float4*)dst = make_float4(o[0], o[1], o[2], o[3]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (r4 + e >= n) break;
+                    float v = o[e];
+                    if (!DIFF) v += h4[e] * bits_to_f32(V[(int64_t)col * n + r4 + e].bits);
+                    dst[e] = v;
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -459,7 +499,7 @@ void launch_g1(int grid, int threads, size_t smem, hipStream_t st, int64_t n, in
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void*)gemm1_mfma<NT, DIAG>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  2 * 8 * 32 * VS_LD * (int)sizeof(uint16_t));
+                                  2 * 8 * 32 * G1Shape<NT>::LD * (int)sizeof(uint16_t));
         attr = true;
     }
     hipLaunchKernelGGL((gemm1_mfma<NT, DIAG>), dim3(grid), dim3(threads), smem, st, n, k, kmax, c, S1, Y1, h0, V, part,
@@ -483,9 +523,10 @@ g1_fn pick_g1(int NT, bool diag) {
 template <int MT2, bool DIFF>
 void launch_g2(int grid, hipStream_t st, int64_t n, int c, int G, int Gp, const bf16_t* Y2, const bf16_t* S2,
                const uint16_t* shi, const uint16_t* slo, const float* h0, const bf16_t* V, float* out) {
-    // small-operand double buffer, reused by the epilogue for one V tile of 32 x 40 per wave
+    // small-operand double buffer, reused by the epilogue for SPLIT x 32 output columns
     constexpr int NTH = G2Shape<MT2>::THREADS;
-    const size_t smem = std::max((size_t)4 * MT2 * 32 * SM_LD, (size_t)(NTH / 64) * 32 * 40) * sizeof(uint16_t);
+    const size_t smem = std::max((size_t)4 * MT2 * 32 * SM_LD * sizeof(uint16_t),
+                                 (size_t)G2Shape<MT2>::SPLIT * 32 * G2_EP_LD * sizeof(float));
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void*)gemm2_mfma<MT2, DIFF>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -540,9 +581,9 @@ int mfma_apply(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
     const bf16_t* V = (const bf16_t*)Vv;
     float* out = (float*)outv;
     const int NT = (c + 31) / 32;
-    const int nk = h->g1_nk;                              // row ranges (multiple of 8, tunable)
+    const int nk = std::max(8, (h->g1_nk + 7) / 8 * 8);   // row slots, 1/8 per XCD (tunable)
     const int64_t rows_f1 = mfma_rows_f1(n);
-    const int64_t rows_per_wg = round_up((rows_f1 + nk - 1) / nk, G1_STAGE);
+    const int64_t rows_per_xcd = round_up((rows_f1 + 7) / 8, g1_stage(NT));
     const int twok = 2 * k;
     const int G = mfma_groups(h->kmax);
     const int Gk = (k + 15) / 16;                          // groups that hold pairs
@@ -562,11 +603,11 @@ int mfma_apply(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
     const bool diag = !h->gamma_mode;
     {
         ProfScope ps(h, "apply_gemm1");
-        const size_t smem = (size_t)(diag ? 2 : 1) * NT * 32 * VS_LD * sizeof(uint16_t);
-        const int grid = 16 * ((nk + 7) / 8);
+        const size_t smem = (size_t)(diag ? 2 : 1) * NT * 32 * (g1_stage(NT) + 8) * sizeof(uint16_t);
+        const int grid = 2 * nk;                           // S and Y workgroup per slot
         const int aligned = (n % 8 == 0) && (((uintptr_t)V) % 16 == 0);
         pick_g1(NT, diag)(grid, 512, smem, h->stream, n, k, h->kmax, c, (const bf16_t*)h->S1,
-                          (const bf16_t*)h->Y1, (const float*)h->h0, V, part, rows_per_wg, rows_f1, nk, aligned);
+                          (const bf16_t*)h->Y1, (const float*)h->h0, V, part, rows_per_xcd, rows_f1, nk, aligned);
     }
     {
         ProfScope ps(h, "apply_reduce");
@@ -583,7 +624,7 @@ int mfma_apply(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
     }
     {
         ProfScope ps(h, "apply_gemm2");
-        const int grid = ceil_div(n, G2_ROWS);
+        const int grid = 8 * ceil_div(ceil_div(n, G2_ROWS), 8);   // whole number of blocks per XCD
         pick_g2(NT, diff)(grid, h->stream, n, c, G, Gp, (const bf16_t*)h->Y2, (const bf16_t*)h->S2, shi, slo,
                           (const float*)h->h0, V, out);
     }
