@@ -61,17 +61,7 @@ __global__ void sum_chunks(int64_t count, int nchunks, const double* __restrict_
 // ---------------------------------------------------------------------------
 constexpr int SMALL_THREADS = 256;
 
-// sum_l x[l] * y[l] with eight independent partial sums
-__device__ __forceinline__ double dot8(const double* x, const double* y, int m) {
-    double p[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int l = 0;
-    for (; l + 8 <= m; l += 8)
-#pragma unroll
-        for (int u = 0; u < 8; ++u) p[u] = fma(x[l + u], y[l + u], p[u]);
-    for (; l < m; ++l) p[0] = fma(x[l], y[l], p[0]);
-    return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
-}
-
+template <int NTHR = SMALL_THREADS>
 __device__ double wg_sum(double v, double* red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -79,7 +69,7 @@ __device__ double wg_sum(double v, double* red) {
     if (lane == 0) red[w] = v;
     __syncthreads();
     double s = 0.0;
-    for (int i = 0; i < SMALL_THREADS / 64; ++i) s += red[i];
+    for (int i = 0; i < NTHR / 64; ++i) s += red[i];
     __syncthreads();
     return s;
 }
@@ -472,21 +462,29 @@ __global__ void __launch_bounds__(LU_THREADS) omega_solve(int c, double* __restr
 //                      recorded (sweep q: rows l..m, angles at rot[2 * (off + i - l)])
 //   apply_rotations    Z <- Z G (the recorded rotations), rows in parallel
 // Z: column-major c x c eigenvectors (Z[i*c + r] = component r of vector i).
-__global__ void __launch_bounds__(SMALL_THREADS) sym_tridiag(int c, double* __restrict__ A, double* __restrict__ V,
+__device__ __forceinline__ double wave_sum_d(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+constexpr int TRI_THREADS = 1024;
+
+__global__ void __launch_bounds__(TRI_THREADS) sym_tridiag(int c, double* __restrict__ A, double* __restrict__ V,
                                                              double* __restrict__ dg, double* __restrict__ eg,
                                                              double* __restrict__ taus) {
-    __shared__ double red[SMALL_THREADS / 64];
+    __shared__ double red[TRI_THREADS / 64];
     __shared__ double vsh[256];
     __shared__ double wsh[256];
     const int tid = threadIdx.x;
     for (int kk = 0; kk + 2 < c; ++kk) {
         const int m = c - kk - 1;   // length of x = A(kk+1:, kk)
         double part = 0.0;
-        for (int i = 1 + tid; i < m; i += SMALL_THREADS) {
+        for (int i = 1 + tid; i < m; i += TRI_THREADS) {
             const double x = A[(int64_t)(kk + 1 + i) * c + kk];
             part = fma(x, x, part);
         }
-        const double xn2 = wg_sum(part, red);
+        const double xn2 = wg_sum<TRI_THREADS>(part, red);
         const double alpha = A[(int64_t)(kk + 1) * c + kk];
         double tau = 0.0, beta = alpha, scale = 0.0;
         if (xn2 > 0.0) {
@@ -494,7 +492,7 @@ __global__ void __launch_bounds__(SMALL_THREADS) sym_tridiag(int c, double* __re
             tau = (beta - alpha) / beta;
             scale = 1.0 / (alpha - beta);
         }
-        for (int i = tid; i < m; i += SMALL_THREADS) {
+        for (int i = tid; i < m; i += TRI_THREADS) {
             const double v = (i == 0) ? 1.0 : A[(int64_t)(kk + 1 + i) * c + kk] * scale;
             vsh[i] = v;
             V[(int64_t)kk * c + kk + 1 + i] = v;
@@ -507,19 +505,25 @@ __global__ void __launch_bounds__(SMALL_THREADS) sym_tridiag(int c, double* __re
         }
         if (tau != 0.0) {
             // p = tau * A22 v;  w = p - (tau/2)(p^T v) v;  A22 -= v w^T + w v^T
-            for (int i = tid; i < m; i += SMALL_THREADS) {
+            // one wave per row, lanes across the row (coalesced), then a wave sum
+            for (int i = tid >> 6; i < m; i += TRI_THREADS / 64) {
                 const double* row = A + (int64_t)(kk + 1 + i) * c + (kk + 1);
-                wsh[i] = tau * dot8(row, vsh, m);
+                double sr = 0.0;
+                for (int l = tid & 63; l < m; l += 64) sr = fma(row[l], vsh[l], sr);
+                sr = wave_sum_d(sr);
+                if ((tid & 63) == 0) wsh[i] = tau * sr;
             }
             __syncthreads();
             double pp = 0.0;
-            for (int i = tid; i < m; i += SMALL_THREADS) pp = fma(wsh[i], vsh[i], pp);
-            const double K = 0.5 * tau * wg_sum(pp, red);
-            for (int i = tid; i < m; i += SMALL_THREADS) wsh[i] -= K * vsh[i];
+            for (int i = tid; i < m; i += TRI_THREADS) pp = fma(wsh[i], vsh[i], pp);
+            const double K = 0.5 * tau * wg_sum<TRI_THREADS>(pp, red);
+            for (int i = tid; i < m; i += TRI_THREADS) wsh[i] -= K * vsh[i];
             __syncthreads();
-            for (int q = tid; q < m * m; q += SMALL_THREADS) {
-                const int i = q / m, l = q % m;
-                A[(int64_t)(kk + 1 + i) * c + (kk + 1 + l)] -= vsh[i] * wsh[l] + wsh[i] * vsh[l];
+            for (int i = tid >> 6; i < m; i += TRI_THREADS / 64) {
+                double* row = A + (int64_t)(kk + 1 + i) * c + (kk + 1);
+                const double vi = vsh[i], wi = wsh[i];
+#pragma unroll 4
+                for (int l = tid & 63; l < m; l += 64) row[l] -= vi * wsh[l] + wi * vsh[l];
             }
         }
         __syncthreads();
@@ -533,12 +537,6 @@ __global__ void __launch_bounds__(SMALL_THREADS) sym_tridiag(int c, double* __re
         dg[c - 1] = A[(int64_t)(c - 1) * c + (c - 1)];
         eg[c - 1] = 0.0;
     }
-}
-
-__device__ __forceinline__ double wave_sum_d(double x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
 }
 
 // Column col of Z = H_0 H_1 ... H_{c-3} e_col: the reflectors are applied to e_col
@@ -880,7 +878,7 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     prof_end(h);
     prof_begin(h, "sym_eig");
     // Bm (the LU right-hand sides) is free after omega_solve: it holds the reflectors
-    hipLaunchKernelGGL(sym_tridiag, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, Om, Bm, dv, ev, tv);
+    hipLaunchKernelGGL(sym_tridiag, dim3(1), dim3(TRI_THREADS), 0, h->stream, c, Om, Bm, dv, ev, tv);
     hipLaunchKernelGGL(householder_accum, dim3(ceil_div(c, 4)), dim3(256), 0, h->stream, c, Bm, tv, Zm);
     hipLaunchKernelGGL(ql_tridiag, dim3(1), dim3(64), 0, h->stream, c, dv, ev, rotbuf, sweeps, nsweeps, max_rot,
                        max_sweeps, h->status);
