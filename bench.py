@@ -46,12 +46,17 @@ def source_digest(files):
 
 
 def kernel_models(n, k, c, rank, wb, vb, ob):
-    """Algorithmic bytes and flops per launch of each kernel group."""
+    """Algorithmic bytes and flops per launch of each kernel group: GEMM1 reads S, Y
+    (2 n k words), the block and h0; GEMM2 reads S, Y, the block (B_k V only: the h0 V
+    term) and h0, and writes the output; the rSVD groups are listed with their inputs
+    and outputs read and written once."""
     pass_bytes = 2 * n * k * wb
     return {
         "apply_gemm1": dict(bound="hbm", bytes=pass_bytes + n * c * vb + 4 * n, flops=2 * n * 2 * k * c),
         "apply_gemm2": dict(bound="hbm", bytes=pass_bytes + n * c * vb + n * c * ob + 4 * n,
                             flops=2 * n * 2 * k * c),
+        "hdiff_gemm1": dict(bound="hbm", bytes=pass_bytes + n * c * vb + 4 * n, flops=2 * n * 2 * k * c),
+        "hdiff_gemm2": dict(bound="hbm", bytes=pass_bytes + n * c * ob + 4 * n, flops=2 * n * 2 * k * c),
         "tsqr_leaf_fwd": dict(bound="alu", bytes=n * c * ob + n * c * 8, flops=2 * n * c * c),
         "tsqr_leaf_bwd": dict(bound="alu", bytes=n * c * 8 + n * c * ob, flops=2 * n * c * c),
         "proj_QtX": dict(bound="hbm", bytes=n * c * (ob + vb), flops=2 * n * c * c),
@@ -311,8 +316,9 @@ KERNEL_GROUPS = [
     ("gemm1_mfma", "apply_gemm1"), ("gemm1_generic", "apply_gemm1"), ("reduce_z", "apply_reduce"),
     ("reduce_partials", "apply_reduce"), ("small_solve", "apply_solve"), ("pack_small", "apply_pack"),
     ("gemm2_mfma", "apply_gemm2"), ("gemm2_generic", "apply_gemm2"), ("scale_by_h0", "apply_gemm2"),
-    ("probes_kernel", "probes"), ("tsqr_leaf_forward", "tsqr_leaf_fwd"), ("tsqr_tree", "tsqr_tree"),
-    ("set_identity", "tsqr_tree"), ("tsqr_leaf_backward", "tsqr_leaf_bwd"), ("tri_mul", "tsqr_tree"),
+    ("probes_kernel", "probes"), ("leaf_forward_q", "tsqr_leaf_fwd"), ("build_t", "tsqr_leaf_fwd"),
+    ("tree_forward", "tsqr_tree"), ("tree_backward", "tsqr_tree"), ("set_identity", "tsqr_tree"),
+    ("leaf_backward", "tsqr_leaf_bwd"), ("tri_mul", "tsqr_tree"),
     ("qtx_mfma", "proj_QtX"), ("sum_chunks", "proj_QtX"), ("omega_solve", "omega_lu"),
     ("sym_tridiag", "sym_eig"), ("householder_accum", "sym_eig"), ("ql_tridiag", "sym_eig"),
     ("apply_rotations", "sym_eig"), ("order_sign", "sym_eig"), ("basis_mfma", "basis_diag"),
@@ -322,7 +328,23 @@ KERNEL_GROUPS = [
 ]
 
 
+# Groups with a kernel that runs once per launch while others run less often.
+GROUP_ANCHORS = {"push_pair": "store_pair_kernel"}
+
+
+def group_launches(group, calls_by_kernel):
+    """Launches of a group in a trace: the anchor kernel's calls, else the fewest calls
+    of any of its kernels (each launch runs every kernel of the group at least once)."""
+    anchor = GROUP_ANCHORS.get(group)
+    for k, cn in calls_by_kernel:
+        if anchor and anchor in k:
+            return cn
+    return min(cn for _, cn in calls_by_kernel)
+
+
 def group_of(kernel_name):
+    if "gemm2_mfma<" in kernel_name and ", true>" in kernel_name:
+        return "hdiff_gemm2"            # the difference form inside the rSVD
     for key, grp in KERNEL_GROUPS:
         if key in kernel_name:
             return grp
@@ -352,24 +374,41 @@ def summarize_profiles(d, out_dir, digest, cmd_prefix):
              f"    {cmd_prefix} --kernel-trace --stats -d <dir> -o kt --output-format csv -- "
              "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline", "",
              "| kernel | group | calls | total ms | avg ms |", "|---|---|---|---|---|"]
+    groups = {}
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:40]:
         g = group_of(r["Name"])
         if g is None and float(r["TotalDurationNs"]) < 2e6:
             continue
         lines.append(f"| {short_name(r['Name'])[:70]} | {g or '(input generation, torch)'} | {r['Calls']} | "
                      f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['AverageNs']) / 1e6:.4f} |")
+    for r in stats:
+        g = group_of(r["Name"])
+        if g is not None:
+            groups.setdefault(g, []).append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"])))
+    # a group launch runs each of its kernels at least once: launches = fewest calls
+    lines += ["", "Per group (the library's profiling groups; `ms per launch` is what bench.py's "
+              "HIP-event timing of the same group measures):", "",
+              "| group | kernels | launches | ms per launch |", "|---|---|---|---|"]
+    for g, v in sorted(groups.items(), key=lambda kv: -sum(t for _, _, t in kv[1])):
+        launches = group_launches(g, [(k, cn) for k, cn, _ in v])
+        lines.append(f"| {g} | {len(v)} | {launches} | {sum(t for _, _, t in v) / launches / 1e6:.4f} |")
     open(os.path.join(out_dir, "kernels_grid3_bf16.md"), "w").write("\n".join(lines) + "\n")
 
-    def counter_means(pattern, counter):
+    def counter_values(pattern, counter):
         acc = {}
         for r in rows(pattern):
             if r.get("Counter_Name") != counter:
                 continue
             acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        return {k: sum(v) / len(v) for k, v in acc.items()}
+        return acc
 
-    fetch = counter_means("fetch_*counter_collection.csv", "FETCH_SIZE")
-    write = counter_means("write_*counter_collection.csv", "WRITE_SIZE")
+    def counter_means(pattern, counter):
+        return {k: sum(v) / len(v) for k, v in counter_values(pattern, counter).items()}
+
+    fetch_all = counter_values("fetch_*counter_collection.csv", "FETCH_SIZE")
+    write_all = counter_values("write_*counter_collection.csv", "WRITE_SIZE")
+    fetch = {k: sum(v) / len(v) for k, v in fetch_all.items()}
+    write = {k: sum(v) / len(v) for k, v in write_all.items()}
     cf = counter_means("cfetch_*counter_collection.csv", "FETCH_SIZE")
     cw = counter_means("cwrite_*counter_collection.csv", "WRITE_SIZE")
     copy_f = max([v for k, v in cf.items() if "copyBuffer" in k] or [0.0])
@@ -399,10 +438,19 @@ def summarize_profiles(d, out_dir, digest, cmd_prefix):
         fb = fetch.get(k, 0.0) * 1024 * (f_scale or 0)
         wb = write.get(k, 0.0) * 1024 * (w_scale or 0)
         lines.append(f"| {short_name(k)[:70]} | {g} | {fetch.get(k, 0):.0f} | {write.get(k, 0):.0f} | {fb + wb:.4g} |")
-        per_group.setdefault(g, []).append(fb + wb)
+        calls = max(len(fetch_all.get(k, [])), len(write_all.get(k, [])), 1)
+        per_group.setdefault(g, []).append((k, calls, (fb + wb) * calls))
+    # bytes per group launch: all dispatches of the group's kernels over the number of launches
+    traffic = {}
+    lines += ["", "Per group launch (sum over the group's kernels):", "",
+              "| group | launches | HBM bytes per launch |", "|---|---|---|"]
+    for g, v in sorted(per_group.items(), key=lambda kv: -sum(b for _, _, b in kv[1])):
+        launches = group_launches(g, [(k, cn) for k, cn, _ in v])
+        per_launch = sum(b for _, _, b in v) / launches
+        lines.append(f"| {g} | {launches} | {per_launch:.4g} |")
+        traffic[g] = {"hbm_bytes_per_launch": per_launch, "source_digest": digest,
+                      "fetch_scale": f_scale, "write_scale": w_scale}
     open(os.path.join(out_dir, "hbm_traffic_grid3_bf16.md"), "w").write("\n".join(lines) + "\n")
-    traffic = {g: {"hbm_bytes_per_launch": sum(v) / len(v), "source_digest": digest,
-                   "fetch_scale": f_scale, "write_scale": w_scale} for g, v in per_group.items()}
     json.dump(traffic, open(os.path.join(out_dir, "traffic.json"), "w"), indent=1)
     log(f"[bench] wrote profile summaries for {len(per_group)} kernel groups to {out_dir}")
 
@@ -527,11 +575,10 @@ def main():
     entries = []
     for name, (cnt, tot_ms) in prof.items():
         model = models.get(name)
-        if name.startswith("tsqr") or name in ("proj_QtX", "basis_diag", "probes"):
+        if name.startswith("tsqr") or name.startswith("hdiff") or name in ("proj_QtX", "basis_diag", "probes"):
             model = models_rsvd.get(name)
         if model is None:
             continue
-        # apply groups run twice per step (explicit apply, and E inside rsvd); both use c=ncols=c_rsvd here
         entries.append((tot_ms, name, cnt, model))
     entries.sort(reverse=True)
     dom = entries[0] if entries else None

@@ -342,7 +342,7 @@ int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
     double* Z = (double*)h->Z.ptr;
     double* P = (double*)h->PT.ptr;
     double* T = P + (size_t)k * c;
-    prof_begin(h, "apply_gemm1");
+    prof_begin(h, diff ? "hdiff_gemm1" : "apply_gemm1");
     hipLaunchKernelGGL((gemm1_generic<Ts, Th, Ts>), dim3(ptiles, ctiles, nchunks), dim3(256), 0, h->stream, n, h->ld,
                        k, c, (const Ts*)h->S, (const Ts*)h->Y, h0, V, part, rows_per_chunk);
     const int64_t count = (int64_t)twok * c;
@@ -351,7 +351,7 @@ int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
     hipLaunchKernelGGL(reduce_partials, dim3(ceil_div(count, 256)), dim3(256), 0, h->stream, count, nchunks, part, Z);
     prof_end(h);
     if (int rc2 = apply_small_solve(h, c, Z, P, T)) return rc2;
-    prof_begin(h, "apply_gemm2");
+    prof_begin(h, diff ? "hdiff_gemm2" : "apply_gemm2");
     hipLaunchKernelGGL((gemm2_generic<Ts, Th, Ts, To>), dim3(ceil_div(c, G2_TC), ceil_div(n, G2_TR)), dim3(256), 0,
                        h->stream, n, h->ld, k, c, (const Ts*)h->S, (const Ts*)h->Y, h0, V, P, T, out,
                        diff ? 1 : 0);

@@ -602,7 +602,7 @@ int mfma_apply(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
     uint16_t* slo = shi + (size_t)cpad * 2 * Gp * 16;
     const bool diag = !h->gamma_mode;
     {
-        ProfScope ps(h, "apply_gemm1");
+        ProfScope ps(h, diff ? "hdiff_gemm1" : "apply_gemm1");
         const size_t smem = (size_t)(diag ? 2 : 1) * NT * 32 * (g1_stage(NT) + 8) * sizeof(uint16_t);
         const int grid = 2 * nk;                           // S and Y workgroup per slot
         const int aligned = (n % 8 == 0) && (((uintptr_t)V) % 16 == 0);
@@ -623,7 +623,7 @@ int mfma_apply(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
                            k, c, cpad, Gp, P, T, shi, slo);
     }
     {
-        ProfScope ps(h, "apply_gemm2");
+        ProfScope ps(h, diff ? "hdiff_gemm2" : "apply_gemm2");
         const int grid = 8 * ceil_div(ceil_div(n, G2_ROWS), 8);   // whole number of blocks per XCD
         pick_g2(NT, diff)(grid, h->stream, n, c, G, Gp, (const bf16_t*)h->Y2, (const bf16_t*)h->S2, shi, slo,
                           (const float*)h->h0, V, out);
