@@ -9,7 +9,7 @@
 //
 // Leaves (forward).  One quad of lanes per column folds each tile with one
 // barrier per reflector (leaf_forward_q); the reflectors are stored in the panel
-// layout below and build_t computes each panel's T from them afterwards, in parallel.
+// layout below, with each panel's T formed from them while they are in registers.
 //
 // Tree fold (forward).  Panel p (column tile p) is factored by its owner
 // wave, one Householder reflector per column acting on (slot row j, tile rows);
@@ -100,6 +100,14 @@ __device__ __forceinline__ double read_lane(double x, int l) {
     const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, l);
     const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), l);
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// x of lane src (any lane, chosen per lane)
+__device__ __forceinline__ double bpermute_f64(double x, int src) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(unsigned)u);
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(unsigned)(u >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -374,9 +382,8 @@ __device__ void unfold_tile(SlotT* slot, v4d (&A)[Layout<BT>::RT], int c, int p0
 // leaves' critical path is the chain of c reflectors per tile; handing each column
 // to its own quad (16 rows per lane, quad DPP reductions) and building reflector
 // j+1 in the quad of column j+1 right after it applies reflector j keeps that
-// chain shorter than the per-wave panel factorisation.  The reflectors are
-// written in the panel layout of the blocked backward pass (T's diagonal holds
-// the taus; build_t fills in the rest of T).
+// chain shorter than the per-wave panel factorisation.  The reflectors and each
+// panel's T are written in the panel layout of the blocked backward pass.
 // ---------------------------------------------------------------------------
 constexpr int QT = 64;                 // tile rows (matches the blocked pass's BT = 64)
 constexpr int LPC = 4;                 // lanes per column
@@ -484,58 +491,43 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
                 q_make_reflector(slot, a, c, j + 1, g, vbuf + (buf ^ 1) * QT, tau_sh + (buf ^ 1), taus_lds);
             __syncthreads();
         }
-        // reflector col: tile part (rows t = i * LPC + g) and tau on T's diagonal
+        // reflector col: tile part (rows t = i * LPC + g) in the panel layout
         const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
-        if (col < np * PW) {
-            double* dst = refl + (gtile * np + col / PW) * PS;
-            const int jj = col % PW;
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;   // wave = panel
+        double* dst = refl + (gtile * np + wave) * PS;
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) dst[jj * QT + i * LPC + g] = a[i];
-            if (g == 0) dst[PW * QT + jj * PW + jj] = col < c ? taus_lds[col] : 0.0;
+        for (int i = 0; i < RPL; ++i) dst[(col % PW) * QT + i * LPC + g] = a[i];
+        // The panel's compact-WY factor T (I - V T V^T, T upper triangular) from the
+        // reflectors still in registers.  G = V^T V on the matrix cores: V's rows
+        // 4 ks .. 4 ks + 3 sit in a[ks] of the quads, one lane permutation away from the
+        // A/B operand layout.  Then T column by column: lane r < 16 keeps row r, and
+        // G(b, i) (accumulator element b / 4 of lane 16 (b % 4) + i) is broadcast.
+        {
+            const int src = 4 * (lane & 15) + (lane >> 4);
+            v4d gacc = {0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < RPL; ++ks) {
+                const double v = bpermute_f64(a[ks], src);
+                gacc = mfma64(v, v, gacc);
+            }
+            const int r = lane & 15;
+            double trow[PW];
+#pragma unroll
+            for (int i = 0; i < PW; ++i) {
+                const int ci = wave * PW + i;
+                const double tau_i = ci < c ? taus_lds[ci] : 0.0;
+                double sacc = 0.0;
+#pragma unroll
+                for (int b = 0; b < i; ++b) sacc = fma(trow[b], read_lane(gacc[b / 4], 16 * (b % 4) + i), sacc);
+                trow[i] = i < r ? 0.0 : (i == r ? tau_i : -tau_i * sacc);
+            }
+            if (lane < PW) {
+#pragma unroll
+                for (int i = 0; i < PW; ++i) dst[PW * QT + lane * PW + i] = trow[i];
+            }
         }
     }
     slot_store(slot, Rs + (int64_t)ch * c * c, c);
-}
-
-// T of every stored panel from its V and taus (diagonal): G = V^T V on the matrix
-// core, then row a of T by lane a.  One wave per panel.
-__global__ void __launch_bounds__(256) build_t(int64_t npanels, double* __restrict__ store) {
-    constexpr int PS = Layout<QT>::PS;
-    __shared__ double Vs[4][PW * (QT + 2)];
-    __shared__ double Gs[4][PW * TS_LD];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, jl = lane & 15, q = lane >> 4;
-    const int64_t pid = (int64_t)blockIdx.x * 4 + wave;
-    if (pid >= npanels) return;   // uniform per wave; no workgroup barrier below
-    double* base = store + pid * PS;
-    double* V = Vs[wave];
-    double* G = Gs[wave];
-    for (int e = lane; e < PW * QT; e += 64) V[(e / QT) * (QT + 2) + e % QT] = base[e];
-    wave_sync();
-    v4d gacc = {0, 0, 0, 0};
-#pragma unroll
-    for (int ks = 0; ks < QT / 4; ++ks) {
-        const double a = V[jl * (QT + 2) + ks * 4 + q];
-        gacc = mfma64(a, a, gacc);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) G[(q + 4 * r) * TS_LD + jl] = gacc[r];
-    wave_sync();
-    if (lane < PW) {
-        double* T = base + PW * QT;
-        double tau[PW];
-#pragma unroll
-        for (int i = 0; i < PW; ++i) tau[i] = T[i * PW + i];
-        double trow[PW];
-#pragma unroll
-        for (int i = 0; i < PW; ++i) {
-            double sacc = 0.0;
-#pragma unroll
-            for (int b = 0; b < i; ++b) sacc = fma(trow[b], G[b * TS_LD + i], sacc);
-            trow[i] = i < lane ? 0.0 : (i == lane ? tau[i] : -tau[i] * sacc);
-        }
-#pragma unroll
-        for (int i = 0; i < PW; ++i) T[lane * PW + i] = trow[i];
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -687,10 +679,6 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     prof_begin(h, "tsqr_leaf_fwd");
     hipLaunchKernelGGL((leaf_forward_q<TO, SlotT>), dim3(nchains), dim3(LPC * 16 * np), qf_lds_bytes<SlotT>(c),
                        h->stream, n, c, rows_per_chain, E, refl, Rs);
-    {
-        const int64_t npanels = (int64_t)nchains * tiles_per_chain * np;
-        hipLaunchKernelGGL(build_t, dim3((unsigned)((npanels + 3) / 4)), dim3(256), 0, h->stream, npanels, refl);
-    }
     prof_end(h);
     prof_begin(h, "tsqr_tree");
     int64_t off = 0;
