@@ -218,6 +218,98 @@ def bench_batch(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_sweep(args):
+    """The 1700 x 350 x 3 grid (k = 200) with bfloat16 and float32 storage side by side:
+    apply columns/s and HBM fraction over probe widths c, the bfloat16 path's relative
+    error against the float32 path on the same probe values, rSVD time of both (rank
+    200 + 20) with the bfloat16 Sigma and posterior variance against float32, and the
+    measured stream ceilings (device copy and fill) next to the 8 TB/s peak."""
+    import torch
+    import paper_2009_12663_amd as P
+    from workloads import quadratic as wq
+
+    cfg = wq.CONFIGS["grid3"]
+    k, rank, p = cfg["k"], cfg["rank"], cfg["oversample"]
+    prob = wq.make_problem("grid3", device="cuda")
+    S, Y, _ = wq.cg_pairs(prob, k)
+    n = prob.n
+    hs = {}
+    for st in ("bf16", "f32"):
+        H = P.Bfgs(n, k, None, st)
+        for s_, y_ in zip(S, Y):
+            H.push_pair(s_.float(), y_.float())
+        hs[st] = H
+    del S, Y
+    torch.cuda.synchronize()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def rel(a, b):
+        return float(torch.linalg.vector_norm((a - b).double()) / torch.linalg.vector_norm(b.double()))
+
+    widths = [1, 8, 32, 64, 128, 220, 256]
+    sweep = []
+    for c in widths:
+        v32 = hs["f32"].generate_probes(seed=2, ncols=c)
+        vb = v32.to(torch.bfloat16)
+        vf = vb.float()                                   # the same probe values for both paths
+        row = {"c": c}
+        outs = {}
+        for st, v in (("bf16", vb), ("f32", vf)):
+            out = torch.empty((c, n), dtype=torch.float32, device="cuda")
+            ms = timed(lambda: hs[st].apply_Hinv(v, out), max(3, args.steps))
+            wbytes = 2 if st == "bf16" else 4
+            bytes_ = 2 * 2 * n * k * wbytes + n * c * (2 * wbytes + 4) + 8 * n
+            row[st] = {"ms": round(ms, 4), "columns_per_s": round(c / (ms / 1e3), 1),
+                       "hbm_frac": round(bytes_ / (ms / 1e3) / HBM_PEAK, 4)}
+            outs[st] = out
+        row["bf16_rel_err_vs_f32"] = rel(outs["bf16"], outs["f32"])
+        row["speedup_bf16_over_f32"] = round(row["f32"]["ms"] / row["bf16"]["ms"], 3)
+        log(f"[sweep] c={c}: bf16 {row['bf16']['ms']:.3f} ms, f32 {row['f32']['ms']:.3f} ms, "
+            f"rel err {row['bf16_rel_err_vs_f32']:.2e}")
+        sweep.append(row)
+        del outs
+    rs = {}
+    for st in ("bf16", "f32"):
+        U = torch.empty((rank, n), dtype=torch.float32, device="cuda")
+        sg = torch.empty(rank, dtype=torch.float64, device="cuda")
+        dg = torch.empty(n, dtype=torch.float32, device="cuda")
+        ms = timed(lambda: hs[st].rsvd(rank, p, cfg["seed"], U, sg), 2)
+        hs[st].posterior_diag(dg)
+        torch.cuda.synchronize()
+        rs[st] = {"ms": round(ms, 3), "sigma": sg.clone(), "diag": dg.clone()}
+        log(f"[sweep] rsvd {st}: {ms:.2f} ms")
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    t_copy = timed(lambda: dst.copy_(src), 5)
+    t_fill = timed(lambda: dst.fill_(1.5), 5)
+    res = {
+        "metric": "B_k V columns/s over probe widths, bfloat16 vs float32 storage (1700 x 350 x 3, k = 200)",
+        "config": {"workload": "grid3 sweep", "n": n, "k": k, "rank": rank, "oversample": p},
+        "sweep": sweep,
+        "rsvd_ms": {st: rs[st]["ms"] for st in rs},
+        "rsvd_speedup_bf16_over_f32": round(rs["f32"]["ms"] / rs["bf16"]["ms"], 3),
+        "bf16_sigma_rel_err_vs_f32": rel(rs["bf16"]["sigma"], rs["f32"]["sigma"]),
+        "bf16_diag_rel_err_vs_f32": rel(rs["bf16"]["diag"], rs["f32"]["diag"]),
+        "stream_ceiling_GBps": {"copy_read_plus_write": round(2 * nbytes / (t_copy / 1e3) / 1e9, 1),
+                                "fill_write": round(nbytes / (t_fill / 1e3) / 1e9, 1),
+                                "peak": HBM_PEAK / 1e9},
+    }
+    for H in hs.values():
+        H.close()
+    print(json.dumps(res), flush=True)
+
+
 def bench_learned(args):
     """Learned diagonal B_0: train the network on the posterior variances of 32 runs
     of the 600 x 200 x 3 grid (k = 100, rank 100 + 20), then compare it with gamma I
@@ -493,14 +585,17 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU path "
-              "(multi-GPU sharding is a design note, not implemented). Use --gpus 1.", file=sys.stderr)
+        print("bench.py runs on one GPU only: the path's row sharding over several GPUs is "
+              "designed but not implemented. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.config == "batch":
         bench_batch(args)
         return
     if args.config == "learned":
         bench_learned(args)
+        return
+    if args.config == "sweep":
+        bench_sweep(args)
         return
 
     import torch
