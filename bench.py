@@ -405,9 +405,9 @@ def bench_learned(args):
 # rocprofv3 summaries (CSV output of --kernel-trace --stats and of --pmc runs)
 # ---------------------------------------------------------------------------
 KERNEL_GROUPS = [
-    ("gemm1_mfma", "apply_gemm1"), ("gemm1_generic", "apply_gemm1"), ("reduce_z", "apply_reduce"),
+    ("gemm1_mfma", "apply_gemm1"), ("gemm1_f64mfma", "apply_gemm1"), ("reduce_z", "apply_reduce"),
     ("reduce_partials", "apply_reduce"), ("small_solve", "apply_solve"), ("pack_small", "apply_pack"),
-    ("gemm2_mfma", "apply_gemm2"), ("gemm2_generic", "apply_gemm2"), ("scale_by_h0", "apply_gemm2"),
+    ("gemm2_mfma", "apply_gemm2"), ("gemm2_f64mfma", "apply_gemm2"), ("scale_by_h0", "apply_gemm2"),
     ("probes_kernel", "probes"), ("leaf_forward_q", "tsqr_leaf_fwd"), ("build_t", "tsqr_leaf_fwd"),
     ("tree_forward", "tsqr_tree"), ("tree_backward", "tsqr_tree"), ("set_identity", "tsqr_tree"),
     ("leaf_backward", "tsqr_leaf_bwd"), ("tri_mul", "tsqr_tree"),

@@ -12,81 +12,15 @@
 // small solve:     P = R^-1 Z_s,  T = R^-T ((D + Y^T B_0 Y) P - Z_y)     (float64)
 // Pass 2 (gemm2):  out = h0 o (V - Y P) + S T     (or - h0 o (Y P) + S T for B_k - B_0)
 //
-// This file holds the portable kernels that run every storage type with
-// float64 accumulation; the bfloat16 form has MFMA kernels in apply_mfma.hip.
+// This file holds the float64 matrix-core form of both passes (float32 and
+// float64 storage, and bfloat16 where its own MFMA form in apply_mfma.hip does not
+// apply) and the inner solve shared by all forms.
 #include <cmath>
 
 #include "common.h"
 
 namespace {
 
-constexpr int G1_TP = 64;   // pair-index tile
-constexpr int G1_TC = 64;   // probe-column tile
-constexpr int G1_TR = 32;   // rows per LDS stage
-
-template <typename Ts, typename Th, typename Tv>
-__global__ void __launch_bounds__(256) gemm1_generic(int64_t n, int64_t ld, int k, int c,
-                                                     const Ts* __restrict__ S, const Ts* __restrict__ Y,
-                                                     const Th* __restrict__ h0, const Tv* __restrict__ V,
-                                                     double* __restrict__ part, int64_t rows_per_chunk) {
-    __shared__ double As[G1_TR][G1_TP + 1];
-    __shared__ double Bs[G1_TR][G1_TC + 1];
-    const int tid = threadIdx.x;
-    const int tx = tid % 16, ty = tid / 16;
-    const int p0 = blockIdx.x * G1_TP, j0 = blockIdx.y * G1_TC;
-    const int chunk = blockIdx.z;
-    const int64_t r_begin = chunk * rows_per_chunk;
-    const int64_t r_end = min(n, r_begin + rows_per_chunk);
-    const int twok = 2 * k;
-    double acc[4][4] = {};
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += G1_TR) {
-        // A tile: pairs p0..p0+63 (S columns then h0-weighted Y columns), rows r0..r0+31
-        for (int e = tid; e < G1_TR * G1_TP; e += 256) {
-            const int rr = e % G1_TR, pp = e / G1_TR;
-            const int64_t r = r0 + rr;
-            const int p = p0 + pp;
-            double a = 0.0;
-            if (r < r_end && p < twok) {
-                if (p < k) a = to_f64(S[(int64_t)p * ld + r]);
-                else a = to_f64(h0[r]) * to_f64(Y[(int64_t)(p - k) * ld + r]);
-            }
-            As[rr][pp] = a;
-        }
-        for (int e = tid; e < G1_TR * G1_TC; e += 256) {
-            const int rr = e % G1_TR, jj = e / G1_TR;
-            const int64_t r = r0 + rr;
-            const int j = j0 + jj;
-            Bs[rr][jj] = (r < r_end && j < c) ? to_f64(V[(int64_t)j * n + r]) : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int rr = 0; rr < G1_TR; ++rr) {
-            double a[4], b[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] = As[rr][ty * 4 + u];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) b[u] = Bs[rr][tx * 4 + u];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
-        }
-        __syncthreads();
-    }
-    double* dst = part + (int64_t)chunk * twok * c;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int p = p0 + ty * 4 + u;
-        if (p >= twok) continue;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int j = j0 + tx * 4 + v;
-            if (j < c) dst[(int64_t)j * twok + p] = acc[u][v];
-        }
-    }
-}
-
-// Z(:, j) = sum over chunks, in chunk order.  Z is column-major 2k x c.
 __global__ void reduce_partials(int64_t count, int nchunks, const double* __restrict__ part,
                                 double* __restrict__ Z) {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -234,77 +168,6 @@ __global__ void __launch_bounds__(256) small_solve_blocks(int k, int kmax, int c
     if (bad) set_status(status, BFGS_ERR_NONFINITE);
 }
 
-constexpr int G2_TR = 64;   // output rows per tile
-constexpr int G2_TC = 64;   // output columns per tile
-constexpr int G2_TI = 16;   // pair index per LDS stage
-
-template <typename Ts, typename Th, typename Tv, typename To>
-__global__ void __launch_bounds__(256) gemm2_generic(int64_t n, int64_t ld, int k, int c, const Ts* __restrict__ S,
-                                                     const Ts* __restrict__ Y, const Th* __restrict__ h0,
-                                                     const Tv* __restrict__ V, const double* __restrict__ P,
-                                                     const double* __restrict__ T, To* __restrict__ out, int diff) {
-    __shared__ double Ss[G2_TI][G2_TR + 2];
-    __shared__ double Ys[G2_TI][G2_TR + 2];
-    __shared__ double Ts_[G2_TI][G2_TC + 2];
-    __shared__ double Ps[G2_TI][G2_TC + 2];
-    const int tid = threadIdx.x;
-    const int tx = tid % 16, ty = tid / 16;   // tx: 4 rows each, ty: 4 columns each
-    const int64_t r0 = (int64_t)blockIdx.y * G2_TR;
-    const int j0 = blockIdx.x * G2_TC;
-    double st[4][4] = {}, yp[4][4] = {};
-    for (int i0 = 0; i0 < k; i0 += G2_TI) {
-        for (int e = tid; e < G2_TI * G2_TR; e += 256) {
-            const int rr = e % G2_TR, ii = e / G2_TR;
-            const int64_t r = r0 + rr;
-            const int i = i0 + ii;
-            const bool ok = r < n && i < k;
-            Ss[ii][rr] = ok ? to_f64(S[(int64_t)i * ld + r]) : 0.0;
-            Ys[ii][rr] = ok ? to_f64(Y[(int64_t)i * ld + r]) : 0.0;
-        }
-        for (int e = tid; e < G2_TI * G2_TC; e += 256) {
-            const int ii = e % G2_TI, jj = e / G2_TI;
-            const int i = i0 + ii, j = j0 + jj;
-            const bool ok = i < k && j < c;
-            Ts_[ii][jj] = ok ? T[(int64_t)j * k + i] : 0.0;
-            Ps[ii][jj] = ok ? P[(int64_t)j * k + i] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int ii = 0; ii < G2_TI; ++ii) {
-            double s[4], y[4], t[4], p[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                s[u] = Ss[ii][tx * 4 + u];
-                y[u] = Ys[ii][tx * 4 + u];
-                t[u] = Ts_[ii][ty * 4 + u];
-                p[u] = Ps[ii][ty * 4 + u];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    st[u][v] = fma(s[u], t[v], st[u][v]);
-                    yp[u][v] = fma(y[u], p[v], yp[u][v]);
-                }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int j = j0 + ty * 4 + v;
-        if (j >= c) continue;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t r = r0 + tx * 4 + u;
-            if (r >= n) continue;
-            const double hr = to_f64(h0[r]);
-            double o = st[u][v] - hr * yp[u][v];
-            if (!diff) o += hr * to_f64(V[(int64_t)j * n + r]);
-            out[(int64_t)j * n + r] = (To)o;
-        }
-    }
-}
-
 template <typename Th, typename Tv, typename To>
 __global__ void scale_by_h0(int64_t n, int c, const Th* __restrict__ h0, const Tv* __restrict__ V,
                             To* __restrict__ out, int diff) {
@@ -312,6 +175,207 @@ __global__ void scale_by_h0(int64_t n, int c, const Th* __restrict__ h0, const T
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = e % n;
         out[e] = diff ? (To)0 : (To)(to_f64(h0[r]) * to_f64(V[e]));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Float64 matrix-core forms of both passes for float32 and float64 storage
+// (v_mfma_f64_16x16x4f64: lane l holds A(l % 16, l / 16), B(l / 16, l % 16) and
+// C(l / 16 + 4 r, l % 16) in accumulator element r).  Both read W = [S | h0 o Y]
+// (n x 2k), widened to float64 and scaled as it is staged:
+//   pass 1:  Z = W^T V                  (= [S^T V ; Y^T (h0 o V)])
+//   pass 2:  out = W [T ; -P] + h0 o V  (= h0 o (V - Y P) + S T; no h0 o V for B_k - B_0)
+// Tiles are 128 x 128 on four waves (2 x 2, 4 x 4 fragments each); the next
+// 16-deep stage is loaded into registers while the current one feeds the MFMAs.
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int FT = 128;          // output tile edge
+constexpr int FT_LD = FT + 4;    // LDS pitch of a staged row of 128
+constexpr int FK = 16;           // reduction depth per stage
+
+// Raw W entry (r, p) in the storage type: S's column p, or Y's column p - k (the h0
+// factor of the Y half is applied when the value is staged).
+template <typename Ts>
+__device__ __forceinline__ Ts w_raw(const Ts* S, const Ts* Y, int64_t ld, int k, int p, int64_t r) {
+    return p < k ? S[(int64_t)p * ld + r] : Y[(int64_t)(p - k) * ld + r];
+}
+
+// part[chunk][j * 2k + p] = sum over the chunk's rows of W(r, p) V(r, j).
+// Grid (nchunks, ceil(2k / 128), ceil(c / 128)).
+template <typename Ts, typename Th>
+__global__ void __launch_bounds__(256, 2) gemm1_f64mfma(int64_t n, int64_t ld, int k, int c, const Ts* __restrict__ S,
+                                                     const Ts* __restrict__ Y, const Th* __restrict__ h0,
+                                                     const Ts* __restrict__ V, double* __restrict__ part,
+                                                     int64_t rows_per_chunk) {
+    __shared__ double Ws[FK][FT_LD];
+    __shared__ double Vs[FK][FT_LD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wi = wave >> 1, wj = wave & 1;
+    const int twok = 2 * k;
+    const int pi0 = blockIdx.y * FT, cj0 = blockIdx.z * FT;
+    const int64_t rb = (int64_t)blockIdx.x * rows_per_chunk;
+    const int64_t re = min(n, rb + rows_per_chunk);
+    // staging map: element e = tid + 256 q (q < 8): row e % 16 (= tid % 16 for every q),
+    // column e / 16; values stay in the storage type until they are staged
+    Ts wreg[8], vreg[8];
+    double h0r = 0.0;
+#define G1F_LOAD_STAGE(R0)                                                                   \
+    {                                                                                      \
+        const int64_t r = (R0) + tid % FK;                                                 \
+        const bool rv = r < re;                                                            \
+        h0r = rv ? to_f64(h0[r]) : 0.0;                                                    \
+        _Pragma("unroll") for (int q = 0; q < 8; ++q) {                                    \
+            const int cc = (tid + 256 * q) / FK;                                           \
+            wreg[q] = (rv && pi0 + cc < twok) ? w_raw(S, Y, ld, k, pi0 + cc, r) : Ts{};     \
+            vreg[q] = (rv && cj0 + cc < c) ? V[(int64_t)(cj0 + cc) * n + r] : Ts{};          \
+        }                                                                                  \
+    }
+    v4d acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+    if (rb < re) { G1F_LOAD_STAGE(rb) }
+    for (int64_t r0 = rb; r0 < re; r0 += FK) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + 256 * q, rr = e % FK, cc = e / FK;
+            const double w = to_f64(wreg[q]);
+            Ws[rr][cc] = pi0 + cc < k ? w : w * h0r;
+            Vs[rr][cc] = to_f64(vreg[q]);
+        }
+        __syncthreads();
+        if (r0 + FK < re) { G1F_LOAD_STAGE(r0 + FK) }
+#pragma unroll
+        for (int kk = 0; kk < FK / 4; ++kk) {
+            const int kr = 4 * kk + lane / 16, m = lane % 16;
+            double a[4], b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                a[t] = Ws[kr][(wi * 4 + t) * 16 + m];
+                b[t] = Vs[kr][(wj * 4 + t) * 16 + m];
+            }
+#pragma unroll
+            for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < 4; ++tb) acc[ta][tb] = mfma64(a[ta], b[tb], acc[ta][tb]);
+        }
+        __syncthreads();
+    }
+#undef G1F_LOAD_STAGE
+    double* dst = part + (int64_t)blockIdx.x * twok * c;
+#pragma unroll
+    for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gp = pi0 + (wi * 4 + ta) * 16 + lane / 16 + 4 * r;
+                const int gj = cj0 + (wj * 4 + tb) * 16 + lane % 16;
+                if (gp < twok && gj < c) dst[(int64_t)gj * twok + gp] = acc[ta][tb][r];
+            }
+}
+
+// out (column-major n x c) = W [T ; -P] (+ h0 o V unless diff); P, T column-major k x c.
+// Grid (ceil(n / 128), ceil(c / 128)).
+template <typename Ts, typename Th, typename To>
+__global__ void __launch_bounds__(256, 2) gemm2_f64mfma(int64_t n, int64_t ld, int k, int c, const Ts* __restrict__ S,
+                                                     const Ts* __restrict__ Y, const Th* __restrict__ h0,
+                                                     const Ts* __restrict__ V, const double* __restrict__ P,
+                                                     const double* __restrict__ T, To* __restrict__ out, int diff) {
+    __shared__ double stage_sh[FT * (FK + 1) + FK * FT_LD];
+    double* Wsh = stage_sh;                     // [128 rows][FK + 1]
+    double* Ms = stage_sh + FT * (FK + 1);      // [FK][FT_LD]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wi = wave >> 1, wj = wave & 1;
+    const int twok = 2 * k;
+    const int64_t row0 = (int64_t)blockIdx.x * FT;
+    const int col0 = blockIdx.y * FT;
+    // W stage element e = tid + 256 q: row e % 128 (= tid % 128 for every q), pair
+    // e / 128; M stage: pair e % 16, column e / 16
+    Ts wreg[8];
+    double mreg[8];
+    const int64_t wr = row0 + tid % FT;
+    const double h0w = wr < n ? to_f64(h0[wr]) : 0.0;
+#define G2F_LOAD_STAGE(K0)                                                                       \
+    _Pragma("unroll") for (int q = 0; q < 8; ++q) {                                            \
+        const int e = tid + 256 * q;                                                           \
+        const int kq = e / FT;                                                                 \
+        wreg[q] = (wr < n && (K0) + kq < twok) ? w_raw(S, Y, ld, k, (K0) + kq, wr) : Ts{};      \
+        const int pm = (K0) + e % FK, j = col0 + e / FK;                                       \
+        double mv = 0.0;                                                                       \
+        if (pm < twok && j < c) mv = pm < k ? T[(int64_t)j * k + pm] : -P[(int64_t)j * k + pm - k]; \
+        mreg[q] = mv;                                                                          \
+    }
+    v4d acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+    G2F_LOAD_STAGE(0)
+    for (int k0 = 0; k0 < twok; k0 += FK) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + 256 * q;
+            const double w = to_f64(wreg[q]);
+            Wsh[(e % FT) * (FK + 1) + e / FT] = k0 + e / FT < k ? w : w * h0w;
+            Ms[(e % FK) * FT_LD + e / FK] = mreg[q];
+        }
+        __syncthreads();
+        if (k0 + FK < twok) { G2F_LOAD_STAGE(k0 + FK) }
+#pragma unroll
+        for (int kk = 0; kk < FK / 4; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                a[t] = Wsh[((wi * 4 + t) * 16 + lane % 16) * (FK + 1) + 4 * kk + lane / 16];
+                b[t] = Ms[(4 * kk + lane / 16) * FT_LD + (wj * 4 + t) * 16 + lane % 16];
+            }
+#pragma unroll
+            for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < 4; ++tb) acc[ta][tb] = mfma64(a[ta], b[tb], acc[ta][tb]);
+        }
+        __syncthreads();
+    }
+#undef G2F_LOAD_STAGE
+    // Transpose through LDS in groups of EC columns (Os[column][row], float64, so the
+    // output is rounded once) so that each column's 128 rows are written, and V's
+    // read, contiguously.
+    constexpr int EC = 32;
+    double* Os = stage_sh;
+    static_assert(EC * (FT + 1) * sizeof(double) <= sizeof(stage_sh), "epilogue tile exceeds LDS");
+    for (int g0 = 0; g0 < FT; g0 += EC) {
+#pragma unroll
+        for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < 4; ++tb) {
+                const int jj = (wj * 4 + tb) * 16 + lane % 16 - g0;
+                if (jj >= 0 && jj < EC) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int rr = (wi * 4 + ta) * 16 + lane / 16 + 4 * r;
+                        Os[jj * (FT + 1) + rr] = acc[ta][tb][r];
+                    }
+                }
+            }
+        __syncthreads();
+        for (int e = tid; e < EC * FT; e += 256) {
+            const int rr = e % FT, jj = e / FT;
+            const int64_t r = row0 + rr;
+            const int j = col0 + g0 + jj;
+            if (r < n && j < c) {
+                double o = Os[jj * (FT + 1) + rr];
+                if (!diff) o += to_f64(h0[r]) * to_f64(V[(int64_t)j * n + r]);
+                out[(int64_t)j * n + r] = (To)o;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -329,10 +393,11 @@ int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
         return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
     }
     const int twok = 2 * k;
-    const int ptiles = ceil_div(twok, G1_TP), ctiles = ceil_div(c, G1_TC);
-    const int64_t max_chunks = std::max<int64_t>(1, (n + G1_TR - 1) / G1_TR);
+    const int ptiles = ceil_div(twok, FT), ctiles = ceil_div(c, FT);
+    // row chunks: about 2048 pass-1 workgroups, each chunk a whole number of stages
+    const int64_t max_chunks = std::max<int64_t>(1, (n + FK - 1) / FK);
     int nchunks = (int)std::min<int64_t>(max_chunks, std::max(1, 2048 / (ptiles * ctiles)));
-    const int64_t rows_per_chunk = round_up((n + nchunks - 1) / nchunks, G1_TR);
+    const int64_t rows_per_chunk = round_up((n + nchunks - 1) / nchunks, FK);
     nchunks = (int)((n + rows_per_chunk - 1) / rows_per_chunk);
     int rc;
     if ((rc = ensure_ws(h->part, (size_t)nchunks * twok * c * 8)) != BFGS_OK) return rc;
@@ -343,8 +408,8 @@ int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
     double* P = (double*)h->PT.ptr;
     double* T = P + (size_t)k * c;
     prof_begin(h, diff ? "hdiff_gemm1" : "apply_gemm1");
-    hipLaunchKernelGGL((gemm1_generic<Ts, Th, Ts>), dim3(ptiles, ctiles, nchunks), dim3(256), 0, h->stream, n, h->ld,
-                       k, c, (const Ts*)h->S, (const Ts*)h->Y, h0, V, part, rows_per_chunk);
+    hipLaunchKernelGGL((gemm1_f64mfma<Ts, Th>), dim3(nchunks, ptiles, ctiles), dim3(256), 0, h->stream, n, h->ld, k,
+                       c, (const Ts*)h->S, (const Ts*)h->Y, h0, V, part, rows_per_chunk);
     const int64_t count = (int64_t)twok * c;
     prof_end(h);
     prof_begin(h, "apply_reduce");
@@ -352,7 +417,7 @@ int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
     prof_end(h);
     if (int rc2 = apply_small_solve(h, c, Z, P, T)) return rc2;
     prof_begin(h, diff ? "hdiff_gemm2" : "apply_gemm2");
-    hipLaunchKernelGGL((gemm2_generic<Ts, Th, Ts, To>), dim3(ceil_div(c, G2_TC), ceil_div(n, G2_TR)), dim3(256), 0,
+    hipLaunchKernelGGL((gemm2_f64mfma<Ts, Th, To>), dim3((unsigned)ceil_div(n, (int64_t)FT), ctiles), dim3(256), 0,
                        h->stream, n, h->ld, k, c, (const Ts*)h->S, (const Ts*)h->Y, h0, V, P, T, out,
                        diff ? 1 : 0);
     prof_end(h);
