@@ -469,15 +469,27 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 }
 
 constexpr int TRI_THREADS = 1024;
+constexpr int TRI_LDS_MAX = 191;   // trailing matrices up to this size run from LDS (packed lower triangle)
 
+__host__ __device__ constexpr size_t tri_lds_bytes() { return (size_t)TRI_LDS_MAX * (TRI_LDS_MAX + 1) / 2 * 8; }
+
+__device__ __forceinline__ int ptri(int i, int l) { return i * (i + 1) / 2 + l; }   // (i, l), l <= i
+
+// Householder tridiagonalisation.  While the trailing matrix is larger than
+// TRI_LDS_MAX the steps work on A in global memory (full symmetric storage); the
+// remaining steps work on the packed lower triangle of A[b0:, b0:] in LDS, where
+// the rank-2 update touches only the lower triangle.
 __global__ void __launch_bounds__(TRI_THREADS) sym_tridiag(int c, double* __restrict__ A, double* __restrict__ V,
                                                              double* __restrict__ dg, double* __restrict__ eg,
                                                              double* __restrict__ taus) {
+    extern __shared__ double Tl[];   // packed lower triangle of A[b0:, b0:]
     __shared__ double red[TRI_THREADS / 64];
     __shared__ double vsh[256];
     __shared__ double wsh[256];
-    const int tid = threadIdx.x;
-    for (int kk = 0; kk + 2 < c; ++kk) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NW = TRI_THREADS / 64;
+    const int b0 = c > TRI_LDS_MAX ? c - TRI_LDS_MAX : 0;
+    for (int kk = 0; kk < b0 && kk + 2 < c; ++kk) {
         const int m = c - kk - 1;   // length of x = A(kk+1:, kk)
         double part = 0.0;
         for (int i = 1 + tid; i < m; i += TRI_THREADS) {
@@ -506,12 +518,12 @@ __global__ void __launch_bounds__(TRI_THREADS) sym_tridiag(int c, double* __rest
         if (tau != 0.0) {
             // p = tau * A22 v;  w = p - (tau/2)(p^T v) v;  A22 -= v w^T + w v^T
             // one wave per row, lanes across the row (coalesced), then a wave sum
-            for (int i = tid >> 6; i < m; i += TRI_THREADS / 64) {
+            for (int i = wave; i < m; i += NW) {
                 const double* row = A + (int64_t)(kk + 1 + i) * c + (kk + 1);
                 double sr = 0.0;
-                for (int l = tid & 63; l < m; l += 64) sr = fma(row[l], vsh[l], sr);
+                for (int l = lane; l < m; l += 64) sr = fma(row[l], vsh[l], sr);
                 sr = wave_sum_d(sr);
-                if ((tid & 63) == 0) wsh[i] = tau * sr;
+                if (lane == 0) wsh[i] = tau * sr;
             }
             __syncthreads();
             double pp = 0.0;
@@ -519,22 +531,87 @@ __global__ void __launch_bounds__(TRI_THREADS) sym_tridiag(int c, double* __rest
             const double K = 0.5 * tau * wg_sum<TRI_THREADS>(pp, red);
             for (int i = tid; i < m; i += TRI_THREADS) wsh[i] -= K * vsh[i];
             __syncthreads();
-            for (int i = tid >> 6; i < m; i += TRI_THREADS / 64) {
+            for (int i = wave; i < m; i += NW) {
                 double* row = A + (int64_t)(kk + 1 + i) * c + (kk + 1);
                 const double vi = vsh[i], wi = wsh[i];
 #pragma unroll 4
-                for (int l = tid & 63; l < m; l += 64) row[l] -= vi * wsh[l] + wi * vsh[l];
+                for (int l = lane; l < m; l += 64) row[l] -= vi * wsh[l] + wi * vsh[l];
+            }
+        }
+        __syncthreads();
+    }
+    // the trailing (c - b0) x (c - b0) matrix moves to LDS
+    const int s0 = c - b0;
+    for (int e = tid; e < s0 * (s0 + 1) / 2; e += TRI_THREADS) {
+        int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while (ptri(i + 1, 0) <= e) ++i;
+        while (ptri(i, 0) > e) --i;
+        const int l = e - ptri(i, 0);
+        Tl[e] = A[(int64_t)(b0 + i) * c + b0 + l];
+    }
+    __syncthreads();
+    for (int kk = b0; kk + 2 < c; ++kk) {
+        const int o = kk - b0;      // local index of the column being eliminated
+        const int m = c - kk - 1;
+        double part = 0.0;
+        for (int i = 1 + tid; i < m; i += TRI_THREADS) {
+            const double x = Tl[ptri(o + 1 + i, o)];
+            part = fma(x, x, part);
+        }
+        const double xn2 = wg_sum<TRI_THREADS>(part, red);
+        const double alpha = Tl[ptri(o + 1, o)];
+        double tau = 0.0, beta = alpha, scale = 0.0;
+        if (xn2 > 0.0) {
+            beta = -copysign(sqrt(fma(alpha, alpha, xn2)), alpha);
+            tau = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        for (int i = tid; i < m; i += TRI_THREADS) {
+            const double v = (i == 0) ? 1.0 : Tl[ptri(o + 1 + i, o)] * scale;
+            vsh[i] = v;
+            V[(int64_t)kk * c + kk + 1 + i] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            taus[kk] = tau;
+            dg[kk] = Tl[ptri(o, o)];
+            eg[kk] = beta;
+        }
+        if (tau != 0.0) {
+            // p_i = tau sum_l A22(i, l) v_l: row i up to the diagonal, then column i below it
+            const int q0 = o + 1;
+            for (int i = wave; i < m; i += NW) {
+                const int gi = q0 + i, rbase = ptri(gi, q0);
+                double sr = 0.0;
+                for (int l = lane; l < m; l += 64) {
+                    const double aval = l <= i ? Tl[rbase + l] : Tl[ptri(q0 + l, gi)];
+                    sr = fma(aval, vsh[l], sr);
+                }
+                sr = wave_sum_d(sr);
+                if (lane == 0) wsh[i] = tau * sr;
+            }
+            __syncthreads();
+            double pp = 0.0;
+            for (int i = tid; i < m; i += TRI_THREADS) pp = fma(wsh[i], vsh[i], pp);
+            const double K = 0.5 * tau * wg_sum<TRI_THREADS>(pp, red);
+            for (int i = tid; i < m; i += TRI_THREADS) wsh[i] -= K * vsh[i];
+            __syncthreads();
+            // lower triangle of A22 -= v w^T + w v^T
+            for (int i = wave; i < m; i += NW) {
+                double* row = Tl + ptri(q0 + i, q0);
+                const double vi = vsh[i], wi = wsh[i];
+                for (int l = lane; l <= i; l += 64) row[l] -= vi * wsh[l] + wi * vsh[l];
             }
         }
         __syncthreads();
     }
     if (tid == 0) {
         if (c >= 2) {
-            dg[c - 2] = A[(int64_t)(c - 2) * c + (c - 2)];
-            eg[c - 2] = A[(int64_t)(c - 1) * c + (c - 2)];
+            dg[c - 2] = Tl[ptri(c - 2 - b0, c - 2 - b0)];
+            eg[c - 2] = Tl[ptri(c - 1 - b0, c - 2 - b0)];
             taus[c - 2] = 0.0;
         }
-        dg[c - 1] = A[(int64_t)(c - 1) * c + (c - 1)];
+        dg[c - 1] = Tl[ptri(c - 1 - b0, c - 1 - b0)];
         eg[c - 1] = 0.0;
     }
 }
@@ -878,7 +955,16 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     prof_end(h);
     prof_begin(h, "sym_eig");
     // Bm (the LU right-hand sides) is free after omega_solve: it holds the reflectors
-    hipLaunchKernelGGL(sym_tridiag, dim3(1), dim3(TRI_THREADS), 0, h->stream, c, Om, Bm, dv, ev, tv);
+    {
+        static bool attr = false;
+        if (!attr) {
+            if (hipFuncSetAttribute((const void*)sym_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)tri_lds_bytes()) != hipSuccess)
+                return BFGS_ERR_HIP;
+            attr = true;
+        }
+        hipLaunchKernelGGL(sym_tridiag, dim3(1), dim3(TRI_THREADS), tri_lds_bytes(), h->stream, c, Om, Bm, dv, ev, tv);
+    }
     hipLaunchKernelGGL(householder_accum, dim3(ceil_div(c, 4)), dim3(256), 0, h->stream, c, Bm, tv, Zm);
     hipLaunchKernelGGL(ql_tridiag, dim3(1), dim3(64), 0, h->stream, c, dv, ev, rotbuf, sweeps, nsweeps, max_rot,
                        max_sweeps, h->status);
