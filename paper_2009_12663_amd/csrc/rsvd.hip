@@ -755,23 +755,53 @@ __global__ void __launch_bounds__(64) ql_tridiag(int c, double* __restrict__ dg,
 }
 
 // Applies the recorded QL rotations to the rows of Z (column-major c x c); one
-// 64-lane workgroup per 64 rows, rows resident in LDS ([i][lane] layout), each
-// sweep's angles staged in LDS.  A sweep's rotations form a chain through the
-// shared column, carried in a register.
+// 64-lane workgroup per 64 rows, rows resident in LDS ([i][lane] layout).  A sweep's
+// rotations form a chain through the shared column, carried in a register.  The
+// angles of sweep q + 1 (and the bounds of sweep q + 2) are loaded while the chain
+// of sweep q runs, into the other of two LDS angle buffers, so a sweep never waits
+// for memory.
+constexpr int ROT_PF = 8;   // angle values per lane of one sweep: 2 (c - 1) / 64 <= 8 for c <= 256
+
+size_t rot_lds_bytes(int c) { return ((size_t)c * 64 + 4 * (size_t)c) * sizeof(double); }
+
 __global__ void __launch_bounds__(64) apply_rotations(int c, const int* __restrict__ nsweeps_p,
                                                       const int* __restrict__ sweeps, const double* __restrict__ rot,
                                                       double* __restrict__ Z) {
-    extern __shared__ double zr[];   // [c][64], then 2 * c staged angles
-    double* rs = zr + (size_t)c * 64;
+    extern __shared__ double zr[];   // [c][64], then two angle buffers of 2 c
+    double* rsb = zr + (size_t)c * 64;
     const int lane = threadIdx.x;
     const int r = blockIdx.x * 64 + lane;
     for (int i = 0; i < c; ++i) zr[i * 64 + lane] = r < c ? Z[(int64_t)i * c + r] : 0.0;
     const int nsw = nsweeps_p[0];
+    int l0 = 0, m0 = 0, l1 = 0, m1 = 0, o1 = 0;
+    if (nsw > 0) {
+        l0 = sweeps[0];
+        m0 = sweeps[1];
+        const int o0 = sweeps[2];
+        for (int e = lane; e < 2 * (m0 - l0); e += 64) rsb[e] = rot[2 * (int64_t)o0 + e];
+    }
+    if (nsw > 1) {
+        l1 = sweeps[3];
+        m1 = sweeps[4];
+        o1 = sweeps[5];
+    }
+    __syncthreads();
     for (int q = 0; q < nsw; ++q) {
-        const int l = sweeps[3 * q], m = sweeps[3 * q + 1], off = sweeps[3 * q + 2];
-        __syncthreads();
-        for (int e = lane; e < 2 * (m - l); e += 64) rs[e] = rot[2 * (int64_t)off + e];
-        __syncthreads();
+        const int n1 = q + 1 < nsw ? 2 * (m1 - l1) : 0;
+        double pf[ROT_PF];
+#pragma unroll
+        for (int u = 0; u < ROT_PF; ++u) {
+            const int e = lane + 64 * u;
+            pf[u] = e < n1 ? rot[2 * (int64_t)o1 + e] : 0.0;
+        }
+        int l2 = 0, m2 = 0, o2 = 0;
+        if (q + 2 < nsw) {
+            l2 = sweeps[3 * (q + 2)];
+            m2 = sweeps[3 * (q + 2) + 1];
+            o2 = sweeps[3 * (q + 2) + 2];
+        }
+        const double* rs = rsb + (q & 1) * 2 * c;
+        const int l = l0, m = m0;
         double carry = zr[m * 64 + lane];
         int i = m - 1;
         // blocks of 8: the operands of 8 steps are loaded before any of them stores
@@ -784,19 +814,36 @@ __global__ void __launch_bounds__(64) apply_rotations(int c, const int* __restri
                 cb[u] = rs[2 * (i - u - l)];
                 sb[u] = rs[2 * (i - u - l) + 1];
             }
+            // only one operation per step depends on the carry: cs * z is formed off the chain
+            double cz[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) cz[u] = cb[u] * zb[u];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 zr[(i - u + 1) * 64 + lane] = fma(sb[u], zb[u], cb[u] * carry);
-                carry = fma(cb[u], zb[u], -sb[u] * carry);
+                carry = fma(-sb[u], carry, cz[u]);
             }
         }
         for (; i >= l; --i) {
             const double cs = rs[2 * (i - l)], sn = rs[2 * (i - l) + 1];
             const double zi = zr[i * 64 + lane];
             zr[(i + 1) * 64 + lane] = fma(sn, zi, cs * carry);
-            carry = fma(cs, zi, -sn * carry);
+            carry = fma(-sn, carry, cs * zi);
         }
         zr[l * 64 + lane] = carry;
+        // buffer (q + 1) & 1 was last read in sweep q - 1, before the barrier that ended it
+        double* nb = rsb + ((q + 1) & 1) * 2 * c;
+#pragma unroll
+        for (int u = 0; u < ROT_PF; ++u) {
+            const int e = lane + 64 * u;
+            if (e < n1) nb[e] = pf[u];
+        }
+        __syncthreads();
+        l0 = l1;
+        m0 = m1;
+        l1 = l2;
+        m1 = m2;
+        o1 = o2;
     }
     if (r < c)
         for (int i = 0; i < c; ++i) Z[(int64_t)i * c + r] = zr[i * 64 + lane];
@@ -969,11 +1016,11 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     hipLaunchKernelGGL(ql_tridiag, dim3(1), dim3(64), 0, h->stream, c, dv, ev, rotbuf, sweeps, nsweeps, max_rot,
                        max_sweeps, h->status);
     {
-        const size_t smem_rot = (size_t)c * 66 * sizeof(double);
+        const size_t smem_rot = rot_lds_bytes(c);
         static bool attr = false;
         if (!attr) {
             (void)hipFuncSetAttribute((const void*)apply_rotations, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      256 * 66 * (int)sizeof(double));
+                                      (int)rot_lds_bytes(256));
             attr = true;
         }
         hipLaunchKernelGGL(apply_rotations, dim3(ceil_div(c, 64)), dim3(64), smem_rot, h->stream, c, nsweeps, sweeps,
