@@ -157,6 +157,12 @@ int rsvd_run(bfgsuq_ctx* h, int32_t rank, int32_t oversample, uint64_t seed, voi
 // the handle's workspace).  tsqr.hip.
 int tsqr_run(bfgsuq_ctx* h, int c, const float* E, float* Q, double** R_out);
 int tsqr_run(bfgsuq_ctx* h, int c, const double* E, double* Q, double** R_out);
+// Eigenpairs of the symmetric tridiagonal (d, e), c <= 256, by divide and conquer:
+// *w_out -> the eigenvalues (in work), Z = Qh Y with Y their eigenvectors (c x c
+// column-major device arrays); work holds tridiag_dc_workspace(c) bytes.
+size_t tridiag_dc_workspace(int c);
+int tridiag_dc(hipStream_t st, int c, const double* d, const double* e, const double* Qh, double* work, double** w_out,
+               double* Z, int32_t* status);
 int probes_run(bfgsuq_ctx* h, uint64_t seed, int32_t ncols, void* X);
 int64_t mfma_rows_f1(int64_t n);
 int64_t mfma_rows_f2(int64_t n);

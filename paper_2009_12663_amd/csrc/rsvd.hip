@@ -936,12 +936,10 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     const size_t cc = (size_t)c * c;
     if ((rc = ensure_ws(h->small, ((size_t)nchunks * cc + 8 * cc + 6 * (size_t)c) * 8 + (size_t)c * 4)) != BFGS_OK)
         return rc;
-    const int max_sweeps = 64 * c;
-    const int64_t max_rot = (int64_t)32 * c * c;
-    if ((rc = ensure_ws(h->lam, (size_t)max_rot * 2 * 8 + (size_t)(3 * max_sweeps + 4) * 4)) != BFGS_OK) return rc;
-    double* rotbuf = (double*)h->lam.ptr;
-    int* sweeps = (int*)(rotbuf + 2 * max_rot);
-    int* nsweeps = sweeps + 3 * max_sweeps;
+    // tridiagonal eigensolver workspace, then Z = Q_H Y (c x c)
+    if ((rc = ensure_ws(h->lam, tridiag_dc_workspace(c) + cc * sizeof(double))) != BFGS_OK) return rc;
+    double* dcwork = (double*)h->lam.ptr;
+    double* Zt = dcwork + tridiag_dc_workspace(c) / sizeof(double);
     double* part = (double*)h->small.ptr;
     double* Tm = part + (size_t)nchunks * cc;
     double* Bm = Tm + cc;
@@ -1013,20 +1011,9 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
         hipLaunchKernelGGL(sym_tridiag, dim3(1), dim3(TRI_THREADS), tri_lds_bytes(), h->stream, c, Om, Bm, dv, ev, tv);
     }
     hipLaunchKernelGGL(householder_accum, dim3(ceil_div(c, 4)), dim3(256), 0, h->stream, c, Bm, tv, Zm);
-    hipLaunchKernelGGL(ql_tridiag, dim3(1), dim3(64), 0, h->stream, c, dv, ev, rotbuf, sweeps, nsweeps, max_rot,
-                       max_sweeps, h->status);
-    {
-        const size_t smem_rot = rot_lds_bytes(c);
-        static bool attr = false;
-        if (!attr) {
-            (void)hipFuncSetAttribute((const void*)apply_rotations, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)rot_lds_bytes(256));
-            attr = true;
-        }
-        hipLaunchKernelGGL(apply_rotations, dim3(ceil_div(c, 64)), dim3(64), smem_rot, h->stream, c, nsweeps, sweeps,
-                           rotbuf, Zm);
-    }
-    hipLaunchKernelGGL(order_sign, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, dv, Zm, lam, Usm);
+    double* wv = nullptr;
+    if ((rc = tridiag_dc(h->stream, c, dv, ev, Zm, dcwork, &wv, Zt, h->status)) != BFGS_OK) return rc;
+    hipLaunchKernelGGL(order_sign, dim3(1), dim3(SMALL_THREADS), 0, h->stream, c, wv, Zt, lam, Usm);
     if (hipMemcpyAsync(Sigma, lam, (size_t)rank * 8, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
         return BFGS_ERR_HIP;
     prof_end(h);

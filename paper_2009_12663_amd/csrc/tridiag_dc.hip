@@ -1,0 +1,286 @@
+// Eigenpairs of the symmetric tridiagonal T (diagonal d, off-diagonal e, e[i] =
+// T(i, i+1)) from the Householder reduction of Omega, for Alg. 3's small symmetric
+// eigenproblem (Omega = U_s Lambda U_s^T), by divide and conquer (Cuppen 1981):
+//
+//   T = diag(T_A - b e_last e_last^T, T_B - b e_1 e_1^T) + b u u^T,  u = e_last + e_1,
+//
+// so with T_A = Q_A D_A Q_A^T and T_B = Q_B D_B Q_B^T the merged problem is
+// diag(D_A, D_B) + rho z z^T with rho = 2 b and z = [Q_A's last row, Q_B's first row]
+// / sqrt 2.  Its eigenvalues are the roots of the secular equation
+// f(x) = 1 + rho sum_i z_i^2 / (d_i - x), one between consecutive poles and one above
+// the last (rho > 0; a negative rho is handled by negating D).  Steps of a merge:
+//   * sort the poles; deflate components with |rho z_i| <= tol, and close poles by a
+//     Givens rotation that moves one pole's weight onto its neighbour;
+//   * each root by bisection on f, measured from the nearer pole (x = d_o + tau), so
+//     that differences x - d_i keep their relative accuracy;
+//   * z recomputed from the roots (Loewner's formula; Gu and Eisenstat 1994), which
+//     makes the eigenvectors z_i / (d_i - x_j) numerically orthogonal;
+//   * the merged basis: the sorted, rotated columns of diag(Q_A, Q_B) times those
+//     eigenvectors.
+// The merges run bottom-up over power-of-two blocks (leaf i starts at d_i - e_{i-1}
+// - e_i, since every adjacent pair is split at some level), one workgroup per merge,
+// all merges of a level in one launch.  Z = Q_H Y then gives the eigenvectors of Omega.
+#include <cmath>
+
+#include "common.h"
+
+namespace {
+
+constexpr double EPS = 2.220446049250313e-16;   // 2^-52
+constexpr int DC_MAX = 256;
+constexpr int DC_THREADS = 256;
+
+// Leaves: lam_i = d_i - e_{i-1} - e_i, Q = I.
+__global__ void dc_leaves(int c, const double* __restrict__ d, const double* __restrict__ e, double* __restrict__ lam,
+                          double* __restrict__ Q, int32_t* __restrict__ status) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < c * c; i += gridDim.x * blockDim.x) {
+        const int col = i / c, row = i % c;
+        Q[i] = col == row ? 1.0 : 0.0;
+        if (row == 0) {
+            const double el = col > 0 ? e[col - 1] : 0.0, er = col + 1 < c ? e[col] : 0.0;
+            const double v = d[col] - el - er;
+            lam[col] = v;
+            if (!isfinite(d[col]) || !isfinite(el) || !isfinite(er)) set_status(status, BFGS_ERR_NUMERIC);
+        }
+    }
+}
+
+// One merge of blocks [s, s + h) and [s + h, s + h + hb) per workgroup.  Qin/lam_in hold
+// the blocks' eigenvectors (block-diagonal, column-major c x c) and eigenvalues;
+// Qout/lam_out receive the merged ones.  R and U are c x c scratch (block regions).
+__global__ void __launch_bounds__(DC_THREADS) dc_merge(int c, int h, const double* __restrict__ e,
+                                                       const double* __restrict__ lam_in, const double* __restrict__ Qin,
+                                                       double* __restrict__ lam_out, double* __restrict__ Qout,
+                                                       double* __restrict__ R, double* __restrict__ U) {
+    __shared__ double Dv[DC_MAX], zv[DC_MAX], ds[DC_MAX], zs[DC_MAX];
+    __shared__ int pcol[DC_MAX], ndx[DC_MAX], slot_of[DC_MAX];
+    __shared__ unsigned char defl[DC_MAX];
+    __shared__ double dn[DC_MAX], z2n[DC_MAX], zn[DC_MAX], taun[DC_MAX], zh[DC_MAX], lamn[DC_MAX];
+    __shared__ int orgn[DC_MAX];
+    __shared__ int rot_a[DC_MAX], rot_b[DC_MAX];
+    __shared__ double rot_c[DC_MAX], rot_s[DC_MAX];
+    __shared__ int nrot_sh, K_sh;
+    const int tid = threadIdx.x;
+    const int s = blockIdx.x * 2 * h;
+    if (s >= c) return;                                   // whole workgroup
+    const int ha = min(h, c - s);
+    const int hb = min(h, c - s - ha);
+    const int n = ha + hb;
+    if (hb == 0) {
+        // nothing to merge: copy the block
+        for (int t = tid; t < n * n; t += DC_THREADS) {
+            const int col = s + t / n, row = s + t % n;
+            Qout[(int64_t)col * c + row] = Qin[(int64_t)col * c + row];
+        }
+        for (int t = tid; t < n; t += DC_THREADS) lam_out[s + t] = lam_in[s + t];
+        return;
+    }
+    const double beta = e[s + ha - 1];
+    const bool neg = beta < 0.0;
+    const double rho = 2.0 * fabs(beta);
+    const double r2 = 0.7071067811865476;   // 1 / sqrt 2
+    // poles and weights (negated when beta < 0, so that rho > 0)
+    for (int t = tid; t < n; t += DC_THREADS) {
+        const double dv = lam_in[s + t];
+        Dv[t] = neg ? -dv : dv;
+        zv[t] = r2 * (t < ha ? Qin[(int64_t)(s + t) * c + s + ha - 1] : Qin[(int64_t)(s + t) * c + s + ha]);
+    }
+    __syncthreads();
+    // sort by rank (ties by index)
+    for (int t = tid; t < n; t += DC_THREADS) {
+        const double dt = Dv[t];
+        int rk = 0;
+        for (int u = 0; u < n; ++u) {
+            const double du = Dv[u];
+            rk += (du < dt || (du == dt && u < t)) ? 1 : 0;
+        }
+        ds[rk] = dt;
+        zs[rk] = zv[t];
+        pcol[rk] = t;
+    }
+    __syncthreads();
+    // deflation scan (one lane)
+    if (tid == 0) {
+        double dmax = rho;
+        for (int p = 0; p < n; ++p) dmax = fmax(dmax, fabs(ds[p]));
+        const double tol = 8.0 * EPS * dmax;
+        int nrot = 0, last = -1, K = 0;
+        for (int p = 0; p < n; ++p) {
+            defl[p] = fabs(rho * zs[p]) <= tol ? 1 : 0;
+            if (defl[p]) continue;
+            if (last >= 0) {
+                const double zl = zs[last], zi = zs[p];
+                const double tau = sqrt(fma(zl, zl, zi * zi));
+                const double cc = zi / tau, sn = -zl / tau;
+                if (fabs((ds[p] - ds[last]) * cc * sn) <= tol) {
+                    zs[p] = tau;
+                    zs[last] = 0.0;
+                    const double dl = ds[last], di = ds[p];
+                    ds[last] = dl * cc * cc + di * sn * sn;
+                    ds[p] = dl * sn * sn + di * cc * cc;
+                    defl[last] = 1;
+                    rot_a[nrot] = last;
+                    rot_b[nrot] = p;
+                    rot_c[nrot] = cc;
+                    rot_s[nrot] = sn;
+                    ++nrot;
+                }
+            }
+            last = p;
+        }
+        for (int p = 0; p < n; ++p) {
+            if (!defl[p]) {
+                ndx[K] = p;
+                slot_of[p] = K;
+                ++K;
+            } else {
+                slot_of[p] = -1;
+            }
+        }
+        nrot_sh = nrot;
+        K_sh = K;
+    }
+    __syncthreads();
+    const int K = K_sh, nrot = nrot_sh;
+    for (int j = tid; j < K; j += DC_THREADS) {
+        const double zj = zs[ndx[j]];
+        dn[j] = ds[ndx[j]];
+        zn[j] = zj;
+        z2n[j] = zj * zj;
+    }
+    __syncthreads();
+    // secular roots: lane j finds root j by bisection from its nearer pole
+    double z2sum = 0.0;
+    for (int i = 0; i < K; ++i) z2sum += z2n[i];
+    for (int j = tid; j < K; j += DC_THREADS) {
+        int o;
+        double a, b;
+        if (j < K - 1) {
+            const double mid = 0.5 * (dn[j] + dn[j + 1]);
+            double f = 1.0;
+            for (int i = 0; i < K; ++i) f += rho * z2n[i] / (dn[i] - mid);
+            if (f > 0.0) {
+                o = j;
+                a = 0.0;
+                b = mid - dn[j];
+            } else {
+                o = j + 1;
+                a = mid - dn[j + 1];
+                b = 0.0;
+            }
+        } else {
+            o = K - 1;
+            a = 0.0;
+            b = rho * z2sum;
+        }
+        const double dorg = dn[o];
+        for (int it = 0; it < 256; ++it) {
+            const double t = 0.5 * (a + b);
+            if (b - a <= 2.0 * EPS * fmax(fabs(a), fabs(b)) || t == a || t == b) break;
+            double f = 1.0;
+            for (int i = 0; i < K; ++i) f += rho * z2n[i] / ((dn[i] - dorg) - t);
+            if (f > 0.0) b = t;
+            else a = t;
+        }
+        orgn[j] = o;
+        taun[j] = 0.5 * (a + b);
+        lamn[j] = dorg + taun[j];
+    }
+    __syncthreads();
+    // Loewner: zh_i^2 = prod_j (x_j - d_i) / prod_{j != i} (d_j - d_i) / rho
+    for (int i = tid; i < K; i += DC_THREADS) {
+        const double di = dn[i];
+        double p = (dn[orgn[K - 1]] - di) + taun[K - 1];
+        for (int j = 0; j < K - 1; ++j) {
+            const double lj = (dn[orgn[j]] - di) + taun[j];
+            const double dd = j >= i ? dn[j + 1] - di : dn[j] - di;
+            p *= lj / dd;
+        }
+        p /= rho;
+        zh[i] = copysign(sqrt(fmax(p, 0.0)), zn[i]);
+    }
+    __syncthreads();
+    // U (K x K, column j = normalised zh / (d - x_j)) in the block region of U
+    for (int j = tid; j < K; j += DC_THREADS) {
+        double ss = 0.0;
+        for (int i = 0; i < K; ++i) {
+            const double v = zh[i] / ((dn[i] - dn[orgn[j]]) - taun[j]);
+            ss = fma(v, v, ss);
+        }
+        const double inv = 1.0 / sqrt(ss);
+        for (int i = 0; i < K; ++i) U[(int64_t)(s + j) * c + s + i] = zh[i] / ((dn[i] - dn[orgn[j]]) - taun[j]) * inv;
+    }
+    // rotated basis R: row r, sorted column p = column pcol[p] of diag(Q_A, Q_B) (only the
+    // diagonal blocks of Qin are current; the rest is zero), then the deflation
+    // rotations in order (one thread per row)
+    for (int r = tid; r < n; r += DC_THREADS) {
+        double* Rr = R + s + r;   // R[(s + p) * c + s + r]
+        for (int p = 0; p < n; ++p) {
+            const int q = pcol[p];
+            Rr[(int64_t)(s + p) * c] = (q < ha) == (r < ha) ? Qin[(int64_t)(s + q) * c + s + r] : 0.0;
+        }
+        for (int q = 0; q < nrot; ++q) {
+            const int pa = rot_a[q], pb = rot_b[q];
+            const double cc = rot_c[q], sn = rot_s[q];
+            const double xa = Rr[(int64_t)(s + pa) * c], xb = Rr[(int64_t)(s + pb) * c];
+            Rr[(int64_t)(s + pa) * c] = cc * xa + sn * xb;
+            Rr[(int64_t)(s + pb) * c] = -sn * xa + cc * xb;
+        }
+    }
+    __syncthreads();   // orders the R and U writes (global) before they are read below
+    // merged basis: deflated columns as rotated, the others R[:, ndx] U
+    for (int t = tid; t < n * n; t += DC_THREADS) {
+        const int p = t / n, r = t % n;
+        const int j = slot_of[p];
+        double v;
+        if (j < 0) {
+            v = R[(int64_t)(s + p) * c + s + r];
+        } else {
+            v = 0.0;
+            for (int i = 0; i < K; ++i) v = fma(R[(int64_t)(s + ndx[i]) * c + s + r], U[(int64_t)(s + j) * c + s + i], v);
+        }
+        Qout[(int64_t)(s + p) * c + s + r] = v;
+    }
+    for (int p = tid; p < n; p += DC_THREADS) {
+        const int j = slot_of[p];
+        const double v = j < 0 ? ds[p] : lamn[j];
+        lam_out[s + p] = neg ? -v : v;
+    }
+}
+
+// C = A B, all c x c column-major; block (ceil(c / 64), c): lane -> row, y -> column.
+__global__ void __launch_bounds__(64) dc_gemm_nn(int c, const double* __restrict__ A, const double* __restrict__ B,
+                                                 double* __restrict__ C) {
+    const int r = blockIdx.x * 64 + threadIdx.x, col = blockIdx.y;
+    if (r >= c) return;
+    const double* bc = B + (int64_t)col * c;
+    double acc = 0.0;
+    for (int k = 0; k < c; ++k) acc = fma(A[(int64_t)k * c + r], bc[k], acc);
+    C[(int64_t)col * c + r] = acc;
+}
+
+}  // namespace
+
+size_t tridiag_dc_workspace(int c) { return ((size_t)4 * c * c + 2 * (size_t)c) * sizeof(double); }
+
+int tridiag_dc(hipStream_t st, int c, const double* d, const double* e, const double* Qh, double* work, double** w_out,
+               double* Z, int32_t* status) {
+    if (c < 1 || c > DC_MAX) return BFGS_ERR_ARG;
+    const size_t cc = (size_t)c * c;
+    double* Qa = work;
+    double* Qb = Qa + cc;
+    double* R = Qb + cc;
+    double* U = R + cc;
+    double* la = U + cc;
+    double* lb = la + c;
+    hipLaunchKernelGGL(dc_leaves, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, st, c, d, e, la, Qa, status);
+    for (int h = 1; h < c; h *= 2) {
+        const int nb = ceil_div(c, 2 * h);
+        hipLaunchKernelGGL(dc_merge, dim3(nb), dim3(DC_THREADS), 0, st, c, h, e, la, Qa, lb, Qb, R, U);
+        std::swap(Qa, Qb);
+        std::swap(la, lb);
+    }
+    hipLaunchKernelGGL(dc_gemm_nn, dim3(ceil_div(c, 64), c), dim3(64), 0, st, c, Qh, Qa, Z);
+    *w_out = la;
+    return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+}
