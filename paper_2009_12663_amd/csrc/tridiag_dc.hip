@@ -173,18 +173,52 @@ __global__ void __launch_bounds__(DC_THREADS) dc_merge(int c, int h, const doubl
             a = 0.0;
             b = rho * z2sum;
         }
+        // Newton on h(t) = t f(t), which has the same root but no pole at the origin
+        // (that term of t f is the constant -rho z_o^2; the other pole is at least twice
+        // as far as the root).  The iterate stays inside the bracket [a, b] that each
+        // evaluation's sign of f narrows (f increases in t); a step that leaves it is
+        // replaced by the bracket's midpoint.
         const double dorg = dn[o];
+        double t = 0.5 * (a + b);
         for (int it = 0; it < 256; ++it) {
-            const double t = 0.5 * (a + b);
-            if (b - a <= 2.0 * EPS * fmax(fabs(a), fabs(b)) || t == a || t == b) break;
-            double f = 1.0;
-            for (int i = 0; i < K; ++i) f += rho * z2n[i] / ((dn[i] - dorg) - t);
+            double f0 = 0.0, f1 = 0.0, f2 = 0.0, f3 = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+            int i = 0;
+            for (; i + 4 <= K; i += 4) {
+                const double q0 = 1.0 / ((dn[i] - dorg) - t), q1 = 1.0 / ((dn[i + 1] - dorg) - t);
+                const double q2 = 1.0 / ((dn[i + 2] - dorg) - t), q3 = 1.0 / ((dn[i + 3] - dorg) - t);
+                const double w0 = z2n[i] * q0, w1 = z2n[i + 1] * q1, w2 = z2n[i + 2] * q2, w3 = z2n[i + 3] * q3;
+                f0 += w0;
+                f1 += w1;
+                f2 += w2;
+                f3 += w3;
+                g0 = fma(w0, q0, g0);
+                g1 = fma(w1, q1, g1);
+                g2 = fma(w2, q2, g2);
+                g3 = fma(w3, q3, g3);
+            }
+            for (; i < K; ++i) {
+                const double q = 1.0 / ((dn[i] - dorg) - t), w = z2n[i] * q;
+                f0 += w;
+                g0 = fma(w, q, g0);
+            }
+            const double f = fma(rho, (f0 + f1) + (f2 + f3), 1.0);
+            const double fp = rho * ((g0 + g1) + (g2 + g3));
+            if (f == 0.0) break;
             if (f > 0.0) b = t;
             else a = t;
+            const double step = t * f / fma(t, fp, f);
+            double tn = t - step;
+            if (fabs(step) <= 2.0 * EPS * fabs(t)) {
+                t = tn;
+                break;
+            }
+            if (!(tn > a && tn < b)) tn = 0.5 * (a + b);
+            t = tn;
+            if (b - a <= 2.0 * EPS * fmax(fabs(a), fabs(b))) break;
         }
         orgn[j] = o;
-        taun[j] = 0.5 * (a + b);
-        lamn[j] = dorg + taun[j];
+        taun[j] = t;
+        lamn[j] = dorg + t;
     }
     __syncthreads();
     // Loewner: zh_i^2 = prod_j (x_j - d_i) / prod_{j != i} (d_j - d_i) / rho
