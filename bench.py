@@ -412,8 +412,8 @@ KERNEL_GROUPS = [
     ("tree_forward", "tsqr_tree"), ("tree_backward", "tsqr_tree"), ("set_identity", "tsqr_tree"),
     ("leaf_backward", "tsqr_leaf_bwd"), ("tri_mul", "tsqr_tree"),
     ("qtx_mfma", "proj_QtX"), ("sum_chunks", "proj_QtX"), ("omega_solve", "omega_lu"),
-    ("sym_tridiag", "sym_eig"), ("householder_accum", "sym_eig"), ("ql_tridiag", "sym_eig"),
-    ("apply_rotations", "sym_eig"), ("order_sign", "sym_eig"), ("basis_mfma", "basis_diag"),
+    ("sym_tridiag", "sym_eig"), ("householder_accum", "sym_eig"), ("dc_leaves", "sym_eig"),
+    ("dc_merge_gemm", "sym_eig"), ("dc_merge", "sym_eig"), ("order_sign", "sym_eig"), ("basis_mfma", "basis_diag"),
     ("posterior_diag_kernel", "basis_diag"), ("store_pair_kernel", "push_pair"), ("gram_partial_kernel", "push_pair"),
     ("gram_finish_kernel", "push_pair"), ("rinv_update_kernel", "push_pair"), ("scatter_pair_layouts", "push_pair"),
     ("fill_h0_kernel", "push_pair"), ("upcast_kernel", "push_pair"),

@@ -5,7 +5,7 @@
 //   E = (B_k - B_0) X                                  apply.hip, "difference" form
 //   E = Q R                                            Householder TSQR (tsqr.hip)
 //   Omega (Q^T X) = Q^T E = R                          LU with partial pivoting, float64
-//   Omega <- (Omega + Omega^T) / 2;  Omega = U_s Lambda U_s^T     tridiagonal QL, float64
+//   Omega <- (Omega + Omega^T) / 2;  Omega = U_s Lambda U_s^T     tridiagonal divide and conquer, float64
 //   U = Q U_s[:, :rank],  Sigma = lambda[:rank],  d = h0 + sum_i lambda_i U_i^2
 //
 // Q^T E equals R exactly for E = Q R, so the R of the factorisation is used
@@ -451,16 +451,14 @@ __global__ void __launch_bounds__(LU_THREADS) omega_solve(int c, double* __restr
     if (tid == 0 && bad) set_status(status, BFGS_ERR_NUMERIC);
 }
 
-// Symmetric eigendecomposition of A (row-major c x c, overwritten), in four kernels:
+// Symmetric eigendecomposition of A (row-major c x c, overwritten):
 //   sym_tridiag        Householder tridiagonalisation (one workgroup); reflector kk
 //                      (unit first entry, acting on rows kk+1..c-1) is stored
 //                      contiguously at V[kk * c + r] with tau in taus[kk]
 //   householder_accum  Z = H_0 H_1 ... H_{c-3} explicitly, one wave per column
-//   ql_tridiag         implicit QL with Wilkinson-type shifts on (d, e), one wave:
-//                      deflation tests in parallel (ballot), the sweep itself is
-//                      evaluated uniformly by the wave; every sweep's rotations are
-//                      recorded (sweep q: rows l..m, angles at rot[2 * (off + i - l)])
-//   apply_rotations    Z <- Z G (the recorded rotations), rows in parallel
+//   tridiag_dc         eigenpairs of the tridiagonal (d, e) by divide and conquer,
+//                      eigenvectors of A = Z times those of the tridiagonal
+//                      (tridiag_dc.hip)
 // Z: column-major c x c eigenvectors (Z[i*c + r] = component r of vector i).
 __device__ __forceinline__ double wave_sum_d(double x) {
 #pragma unroll
@@ -646,207 +644,6 @@ __global__ void __launch_bounds__(256) householder_accum(int c, const double* __
         const int r = lane + 64 * q;
         if (r < c) Z[(int64_t)col * c + r] = z[q];
     }
-}
-
-__global__ void __launch_bounds__(64) ql_tridiag(int c, double* __restrict__ dg, const double* __restrict__ eg,
-                                                 double* __restrict__ rot, int* __restrict__ sweeps,
-                                                 int* __restrict__ nsweeps_out, int64_t max_rot, int max_sweeps,
-                                                 int32_t* __restrict__ status) {
-    // d[-1] and e[-1] exist so that the sweep can read one entry ahead unconditionally
-    __shared__ double d_pad[257], e_pad[257];
-    double* d = d_pad + 1;
-    double* e = e_pad + 1;
-    const int lane = threadIdx.x;
-    for (int i = lane; i < c; i += 64) {
-        d[i] = dg[i];
-        e[i] = eg[i];
-    }
-    if (lane == 0) {
-        d_pad[0] = 0.0;
-        e_pad[0] = 0.0;
-    }
-    __syncthreads();
-    int nsw = 0;
-    int64_t off = 0;
-    int fail = 0;
-    for (int l = 0; l < c && !fail; ++l) {
-        int iter = 0;
-        while (true) {
-            // smallest m >= l with m == c-1 or e[m] negligible against d[m], d[m+1]
-            int m = c - 1;
-            for (int base = l; base < c - 1; base += 64) {
-                const int mm = base + lane;
-                bool hit = true;
-                if (mm < c - 1) {
-                    const double dd = fabs(d[mm]) + fabs(d[mm + 1]);
-                    hit = (fabs(e[mm]) + dd == dd);
-                }
-                const unsigned long long bal = __ballot(hit);
-                if (bal) {
-                    m = min(c - 1, base + __ffsll((long long)bal) - 1);
-                    break;
-                }
-            }
-            if (m == l) break;
-            if (++iter > 60 || nsw >= max_sweeps || off + (m - l) > max_rot) {
-                fail = 1;
-                break;
-            }
-            // one lane runs the sweep (single-lane LDS traffic, no exec changes inside)
-            if (lane == 0) {
-                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-                const double r0 = sqrt(fma(g, g, 1.0));
-                g = d[m] - d[l] + e[l] / (g + copysign(r0, g));
-                double sn = 1.0, cs = 1.0, p = 0.0;
-                bool early = false;
-                double ei = e[m - 1], di = d[m - 1], dip1 = d[m];
-                double* rr = rot + 2 * off;
-                for (int i = m - 1; i >= l; --i) {
-                    const double ei_next = e[i - 1];   // i - 1 >= -1: padded
-                    const double di_next = d[i - 1];
-                    const double f = sn * ei;
-                    const double b = cs * ei;
-                    const double t = fma(f, f, g * g);
-                    if (t == 0.0) {
-                        d[i + 1] = dip1 - p;
-                        e[m] = 0.0;
-                        early = true;
-                        for (int q = 0; q <= i - l; ++q) {
-                            rr[2 * q] = 1.0;
-                            rr[2 * q + 1] = 0.0;
-                        }
-                        break;
-                    }
-                    const double ri = rsqrt_refined(t);
-                    e[i + 1] = t * ri;
-                    sn = f * ri;
-                    cs = g * ri;
-                    g = dip1 - p;
-                    const double r = fma(di - g, sn, 2.0 * cs * b);
-                    p = sn * r;
-                    d[i + 1] = g + p;
-                    g = fma(cs, r, -b);
-                    rr[2 * (i - l)] = cs;
-                    rr[2 * (i - l) + 1] = sn;
-                    dip1 = di;
-                    di = di_next;
-                    ei = ei_next;
-                }
-                if (!early) {
-                    d[l] -= p;
-                    e[l] = g;
-                    e[m] = 0.0;
-                }
-                sweeps[3 * nsw + 0] = l;
-                sweeps[3 * nsw + 1] = m;
-                sweeps[3 * nsw + 2] = (int)off;
-            }
-            __syncthreads();
-            ++nsw;
-            off += m - l;
-        }
-    }
-    __syncthreads();
-    if (lane == 0) {
-        nsweeps_out[0] = nsw;
-        if (fail) set_status(status, BFGS_ERR_NUMERIC);
-    }
-    for (int i = lane; i < c; i += 64) dg[i] = d[i];
-}
-
-// Applies the recorded QL rotations to the rows of Z (column-major c x c); one
-// 64-lane workgroup per 64 rows, rows resident in LDS ([i][lane] layout).  A sweep's
-// rotations form a chain through the shared column, carried in a register.  The
-// angles of sweep q + 1 (and the bounds of sweep q + 2) are loaded while the chain
-// of sweep q runs, into the other of two LDS angle buffers, so a sweep never waits
-// for memory.
-constexpr int ROT_PF = 8;   // angle values per lane of one sweep: 2 (c - 1) / 64 <= 8 for c <= 256
-
-size_t rot_lds_bytes(int c) { return ((size_t)c * 64 + 4 * (size_t)c) * sizeof(double); }
-
-__global__ void __launch_bounds__(64) apply_rotations(int c, const int* __restrict__ nsweeps_p,
-                                                      const int* __restrict__ sweeps, const double* __restrict__ rot,
-                                                      double* __restrict__ Z) {
-    extern __shared__ double zr[];   // [c][64], then two angle buffers of 2 c
-    double* rsb = zr + (size_t)c * 64;
-    const int lane = threadIdx.x;
-    const int r = blockIdx.x * 64 + lane;
-    for (int i = 0; i < c; ++i) zr[i * 64 + lane] = r < c ? Z[(int64_t)i * c + r] : 0.0;
-    const int nsw = nsweeps_p[0];
-    int l0 = 0, m0 = 0, l1 = 0, m1 = 0, o1 = 0;
-    if (nsw > 0) {
-        l0 = sweeps[0];
-        m0 = sweeps[1];
-        const int o0 = sweeps[2];
-        for (int e = lane; e < 2 * (m0 - l0); e += 64) rsb[e] = rot[2 * (int64_t)o0 + e];
-    }
-    if (nsw > 1) {
-        l1 = sweeps[3];
-        m1 = sweeps[4];
-        o1 = sweeps[5];
-    }
-    __syncthreads();
-    for (int q = 0; q < nsw; ++q) {
-        const int n1 = q + 1 < nsw ? 2 * (m1 - l1) : 0;
-        double pf[ROT_PF];
-#pragma unroll
-        for (int u = 0; u < ROT_PF; ++u) {
-            const int e = lane + 64 * u;
-            pf[u] = e < n1 ? rot[2 * (int64_t)o1 + e] : 0.0;
-        }
-        int l2 = 0, m2 = 0, o2 = 0;
-        if (q + 2 < nsw) {
-            l2 = sweeps[3 * (q + 2)];
-            m2 = sweeps[3 * (q + 2) + 1];
-            o2 = sweeps[3 * (q + 2) + 2];
-        }
-        const double* rs = rsb + (q & 1) * 2 * c;
-        const int l = l0, m = m0;
-        double carry = zr[m * 64 + lane];
-        int i = m - 1;
-        // blocks of 8: the operands of 8 steps are loaded before any of them stores
-        // (step j overwrites entry j + 1, which step j + 1 has already read)
-        for (; i - 7 >= l; i -= 8) {
-            double zb[8], cb[8], sb[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                zb[u] = zr[(i - u) * 64 + lane];
-                cb[u] = rs[2 * (i - u - l)];
-                sb[u] = rs[2 * (i - u - l) + 1];
-            }
-            // only one operation per step depends on the carry: cs * z is formed off the chain
-            double cz[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) cz[u] = cb[u] * zb[u];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                zr[(i - u + 1) * 64 + lane] = fma(sb[u], zb[u], cb[u] * carry);
-                carry = fma(-sb[u], carry, cz[u]);
-            }
-        }
-        for (; i >= l; --i) {
-            const double cs = rs[2 * (i - l)], sn = rs[2 * (i - l) + 1];
-            const double zi = zr[i * 64 + lane];
-            zr[(i + 1) * 64 + lane] = fma(sn, zi, cs * carry);
-            carry = fma(-sn, carry, cs * zi);
-        }
-        zr[l * 64 + lane] = carry;
-        // buffer (q + 1) & 1 was last read in sweep q - 1, before the barrier that ended it
-        double* nb = rsb + ((q + 1) & 1) * 2 * c;
-#pragma unroll
-        for (int u = 0; u < ROT_PF; ++u) {
-            const int e = lane + 64 * u;
-            if (e < n1) nb[e] = pf[u];
-        }
-        __syncthreads();
-        l0 = l1;
-        m0 = m1;
-        l1 = l2;
-        m1 = m2;
-        o1 = o2;
-    }
-    if (r < c)
-        for (int i = 0; i < c; ++i) Z[(int64_t)i * c + r] = zr[i * 64 + lane];
 }
 
 // Order eigenpairs by |lambda| descending (ties: lambda descending, then index),

@@ -51,7 +51,9 @@ __global__ void dc_leaves(int c, const double* __restrict__ d, const double* __r
 __global__ void __launch_bounds__(DC_THREADS) dc_merge(int c, int h, const double* __restrict__ e,
                                                        const double* __restrict__ lam_in, const double* __restrict__ Qin,
                                                        double* __restrict__ lam_out, double* __restrict__ Qout,
-                                                       double* __restrict__ R, double* __restrict__ U) {
+                                                       double* __restrict__ R, double* __restrict__ U,
+                                                       int* __restrict__ Kg, int* __restrict__ ndx_g,
+                                                       int* __restrict__ slot_g) {
     __shared__ double Dv[DC_MAX], zv[DC_MAX], ds[DC_MAX], zs[DC_MAX];
     __shared__ int pcol[DC_MAX], ndx[DC_MAX], slot_of[DC_MAX];
     __shared__ unsigned char defl[DC_MAX];
@@ -67,7 +69,8 @@ __global__ void __launch_bounds__(DC_THREADS) dc_merge(int c, int h, const doubl
     const int hb = min(h, c - s - ha);
     const int n = ha + hb;
     if (hb == 0) {
-        // nothing to merge: copy the block
+        // nothing to merge: copy the block (dc_merge_gemm skips it)
+        if (tid == 0) Kg[blockIdx.x] = -1;
         for (int t = tid; t < n * n; t += DC_THREADS) {
             const int col = s + t / n, row = s + t % n;
             Qout[(int64_t)col * c + row] = Qin[(int64_t)col * c + row];
@@ -261,24 +264,72 @@ __global__ void __launch_bounds__(DC_THREADS) dc_merge(int c, int h, const doubl
             Rr[(int64_t)(s + pb) * c] = -sn * xa + cc * xb;
         }
     }
-    __syncthreads();   // orders the R and U writes (global) before they are read below
-    // merged basis: deflated columns as rotated, the others R[:, ndx] U
-    for (int t = tid; t < n * n; t += DC_THREADS) {
-        const int p = t / n, r = t % n;
-        const int j = slot_of[p];
-        double v;
-        if (j < 0) {
-            v = R[(int64_t)(s + p) * c + s + r];
-        } else {
-            v = 0.0;
-            for (int i = 0; i < K; ++i) v = fma(R[(int64_t)(s + ndx[i]) * c + s + r], U[(int64_t)(s + j) * c + s + i], v);
-        }
-        Qout[(int64_t)(s + p) * c + s + r] = v;
+    // the merged basis (R[:, ndx] U, deflated columns as rotated) is formed by dc_merge_gemm
+    if (tid == 0) Kg[blockIdx.x] = K;
+    for (int p = tid; p < n; p += DC_THREADS) {
+        slot_g[s + p] = slot_of[p];
+        ndx_g[s + p] = p < K ? ndx[p] : 0;
     }
     for (int p = tid; p < n; p += DC_THREADS) {
         const int j = slot_of[p];
         const double v = j < 0 ? ds[p] : lamn[j];
         lam_out[s + p] = neg ? -v : v;
+    }
+}
+
+// Merged basis of each merge of the level: column p of the block is R[:, p] when p was
+// deflated, else R[:, ndx] U[:, slot(p)].  Grid (merges, tiles of 64 x 64 outputs);
+// thread = 4 x 4 outputs; the reduction is staged 16 deep in LDS.
+constexpr int MG_T = 64, MG_K = 16;
+
+__global__ void __launch_bounds__(256) dc_merge_gemm(int c, int h, const double* __restrict__ R,
+                                                     const double* __restrict__ U, const int* __restrict__ Kg,
+                                                     const int* __restrict__ ndx_g, const int* __restrict__ slot_g,
+                                                     double* __restrict__ Qout) {
+    __shared__ double As[MG_K][MG_T + 1];   // As[k][r] = R(r, ndx[k])
+    __shared__ double Bs[MG_K][MG_T + 1];   // Bs[k][p] = U(k, slot(p))
+    const int b = blockIdx.x, K = Kg[b];
+    if (K < 0) return;                      // whole workgroup: block copied by dc_merge
+    const int s = b * 2 * h, n = min(2 * h, c - s);
+    const int tpd = (2 * h + MG_T - 1) / MG_T;
+    const int r0 = (blockIdx.y / tpd) * MG_T, p0 = (blockIdx.y % tpd) * MG_T;
+    if (r0 >= n || p0 >= n) return;         // whole workgroup
+    const int tid = threadIdx.x, tr = tid / 16, tp = tid % 16;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += MG_K) {
+        for (int e = tid; e < MG_K * MG_T; e += 256) {
+            const int kk = e / MG_T, rr = e % MG_T, k = k0 + kk;
+            As[kk][rr] = (k < K && r0 + rr < n) ? R[(int64_t)(s + ndx_g[s + k]) * c + s + r0 + rr] : 0.0;
+            const int pp = e % MG_T, kb = e / MG_T, kq = k0 + kb;
+            int j = p0 + pp < n ? slot_g[s + p0 + pp] : -1;
+            Bs[kb][pp] = (kq < K && j >= 0) ? U[(int64_t)(s + j) * c + s + kq] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < MG_K; ++kk) {
+            double a[4], bb[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = As[kk][tr * 4 + u];
+                bb[u] = Bs[kk][tp * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], bb[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int p = p0 + tp * 4 + v;
+        if (p >= n) continue;
+        const bool defl = slot_g[s + p] < 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + tr * 4 + u;
+            if (r < n) Qout[(int64_t)(s + p) * c + s + r] = defl ? R[(int64_t)(s + p) * c + s + r] : acc[u][v];
+        }
     }
 }
 
@@ -295,7 +346,7 @@ __global__ void __launch_bounds__(64) dc_gemm_nn(int c, const double* __restrict
 
 }  // namespace
 
-size_t tridiag_dc_workspace(int c) { return ((size_t)4 * c * c + 2 * (size_t)c) * sizeof(double); }
+size_t tridiag_dc_workspace(int c) { return ((size_t)4 * c * c + 2 * (size_t)c) * sizeof(double) + (size_t)4 * c * sizeof(int); }
 
 int tridiag_dc(hipStream_t st, int c, const double* d, const double* e, const double* Qh, double* work, double** w_out,
                double* Z, int32_t* status) {
@@ -307,10 +358,16 @@ int tridiag_dc(hipStream_t st, int c, const double* d, const double* e, const do
     double* U = R + cc;
     double* la = U + cc;
     double* lb = la + c;
+    int* Kg = (int*)(lb + c);
+    int* ndx_g = Kg + c;
+    int* slot_g = ndx_g + c;
     hipLaunchKernelGGL(dc_leaves, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, st, c, d, e, la, Qa, status);
     for (int h = 1; h < c; h *= 2) {
         const int nb = ceil_div(c, 2 * h);
-        hipLaunchKernelGGL(dc_merge, dim3(nb), dim3(DC_THREADS), 0, st, c, h, e, la, Qa, lb, Qb, R, U);
+        const int tpd = ceil_div(2 * h, MG_T);
+        hipLaunchKernelGGL(dc_merge, dim3(nb), dim3(DC_THREADS), 0, st, c, h, e, la, Qa, lb, Qb, R, U, Kg, ndx_g,
+                           slot_g);
+        hipLaunchKernelGGL(dc_merge_gemm, dim3(nb, tpd * tpd), dim3(256), 0, st, c, h, R, U, Kg, ndx_g, slot_g, Qb);
         std::swap(Qa, Qb);
         std::swap(la, lb);
     }
