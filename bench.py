@@ -414,6 +414,7 @@ KERNEL_GROUPS = [
     ("qtx_mfma", "proj_QtX"), ("sum_chunks", "proj_QtX"), ("omega_solve", "omega_lu"),
     ("sym_tridiag", "sym_eig"), ("householder_accum", "sym_eig"), ("dc_leaves", "sym_eig"),
     ("dc_merge_gemm", "sym_eig"), ("dc_merge", "sym_eig"), ("order_sign", "sym_eig"), ("basis_mfma", "basis_diag"),
+    ("basis_bf16", "basis_diag"), ("split_us", "basis_diag"),
     ("posterior_diag_kernel", "basis_diag"), ("store_pair_kernel", "push_pair"), ("gram_partial_kernel", "push_pair"),
     ("gram_finish_kernel", "push_pair"), ("rinv_update_kernel", "push_pair"), ("scatter_pair_layouts", "push_pair"),
     ("fill_h0_kernel", "push_pair"), ("upcast_kernel", "push_pair"),

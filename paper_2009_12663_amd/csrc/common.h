@@ -161,6 +161,12 @@ int tsqr_run(bfgsuq_ctx* h, int c, const double* E, double* Q, double** R_out);
 // *w_out -> the eigenvalues (in work), Z = Qh Y with Y their eigenvectors (c x c
 // column-major device arrays); work holds tridiag_dc_workspace(c) bytes.
 size_t tridiag_dc_workspace(int c);
+// bfloat16-storage form of the rSVD basis U = Q Us[:, :rank] and the posterior
+// diagonal dout = h0 + sum_j lam_j U_j^2 (rsvd_bf16.hip); ush holds
+// basis_bf16_workspace(c, rank) bytes of split Us.
+size_t basis_bf16_workspace(int c, int rank);
+int basis_bf16_launch(hipStream_t st, int64_t n, int c, int rank, const float* Q, const double* Us, uint16_t* ush,
+                      const double* lam, const float* h0, float* U, float* dout);
 int tridiag_dc(hipStream_t st, int c, const double* d, const double* e, const double* Qh, double* work, double** w_out,
                double* Z, int32_t* status);
 int probes_run(bfgsuq_ctx* h, uint64_t seed, int32_t ncols, void* X);

@@ -9,8 +9,12 @@
 //   U = Q U_s[:, :rank],  Sigma = lambda[:rank],  d = h0 + sum_i lambda_i U_i^2
 //
 // Q^T E equals R exactly for E = Q R, so the R of the factorisation is used
-// instead of a second product with E.
+// instead of a second product with E.  Q^T X runs on the float64 matrix cores
+// (float64 sums).  Q U_s does too, except for bfloat16 storage, where it runs on
+// the bfloat16 matrix cores with Q and U_s split into bfloat16 terms
+// (rsvd_bf16.hip).
 #include <cmath>
+#include <type_traits>
 #include <utility>
 
 #include "common.h"
@@ -734,9 +738,13 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     if ((rc = ensure_ws(h->small, ((size_t)nchunks * cc + 8 * cc + 6 * (size_t)c) * 8 + (size_t)c * 4)) != BFGS_OK)
         return rc;
     // tridiagonal eigensolver workspace, then Z = Q_H Y (c x c)
-    if ((rc = ensure_ws(h->lam, tridiag_dc_workspace(c) + cc * sizeof(double))) != BFGS_OK) return rc;
+    constexpr bool bf16_path = std::is_same<TS, bf16_t>::value;
+    const size_t ush_bytes = bf16_path ? basis_bf16_workspace(c, rank) : 0;
+    const size_t ush_off = round_up((int64_t)(tridiag_dc_workspace(c) + cc * sizeof(double)), 256);
+    if ((rc = ensure_ws(h->lam, ush_off + ush_bytes)) != BFGS_OK) return rc;
     double* dcwork = (double*)h->lam.ptr;
     double* Zt = dcwork + tridiag_dc_workspace(c) / sizeof(double);
+    uint16_t* ush = (uint16_t*)((char*)h->lam.ptr + ush_off);   // 16-byte fragment loads
     double* part = (double*)h->small.ptr;
     double* Tm = part + (size_t)nchunks * cc;
     double* Bm = Tm + cc;
@@ -775,6 +783,7 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     }
     ProfScope ps(h, "proj_QtX");
     {
+        // float64 sums: Omega = F T^-1 amplifies the rounding of T by about cond(T)
         const int nblk = ceil_div(c, MT_TILE);
         hipLaunchKernelGGL((qtx_mfma<TO, TS>), dim3(nchunks, nblk, nblk), dim3(256), 0, h->stream, n, c, Q, X, part,
                            rows_per_chunk);
@@ -815,9 +824,13 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
         return BFGS_ERR_HIP;
     prof_end(h);
     prof_begin(h, "basis_diag");
-    hipLaunchKernelGGL((basis_mfma<TO, TO>), dim3((unsigned)ceil_div(n, (int64_t)MT_TILE), ceil_div(rank, MT_TILE)),
-                       dim3(256), 0, h->stream, n, c, rank, Q, Usm, U);
-    {
+    if constexpr (bf16_path) {
+        // the posterior diagonal is formed in the same pass
+        if ((rc = basis_bf16_launch(h->stream, n, c, rank, Q, Usm, ush, lam, (const float*)h->h0, U, dout)) != BFGS_OK)
+            return rc;
+    } else {
+        hipLaunchKernelGGL((basis_mfma<TO, TO>), dim3((unsigned)ceil_div(n, (int64_t)MT_TILE), ceil_div(rank, MT_TILE)),
+                           dim3(256), 0, h->stream, n, c, rank, Q, Usm, U);
         const int g = (int)std::min<int64_t>(4096, (n + 255) / 256);
         hipLaunchKernelGGL((posterior_diag_kernel<TO, Th>), dim3(g), dim3(256), 0, h->stream, n, rank, U, lam,
                            (const Th*)h->h0, dout);
