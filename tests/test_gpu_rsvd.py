@@ -158,3 +158,49 @@ def test_rsvd_deterministic():
     U2, S2 = H.rsvd(25, 10, 3)
     assert torch.equal(U1, U2) and torch.equal(S1, S2)
     H.close()
+
+
+@pytest.mark.parametrize("storage,config", [("f32", "grid2"), ("bf16", "grid3")])
+def test_rsvd_full_size(storage, config):
+    """The full-size workloads of the two paths, gamma I, seed 5: float32 on the
+    600 x 200 x 3 grid (n = 360,000, k = 100 exact-line-search pairs, rank 100 +
+    oversample 20) and bfloat16 on the 1700 x 350 x 3 grid (n = 1,785,000, k = 200,
+    rank 200 + 20, the configuration the benchmark times).  Sigma, U and the posterior
+    diagonal against the oracle (Alg. 3 in float64 on the same stored S, Y and
+    probes).  Sigma is compared relative to Sigma_0 (as in the cases above) and, for
+    the significant eigenvalues (|Sigma_i| >= 1e-3 |Sigma_0|), relative to itself: E
+    and Q are stored in float32 on both paths (relative rounding 6e-8), and the
+    Omega solve amplifies that by about cond(Q^T X), so the smaller significant
+    eigenvalues carry relative errors of order 1e-5 (float32) and 1e-4 (bfloat16)."""
+    cfg = wq.CONFIGS[config]
+    rank, p = cfg["rank"], cfg["oversample"]
+    print(f"\n[rsvd full size] {storage} {config}: k={cfg['k']} rank={rank} p={p}", flush=True)
+    prob = wq.make_problem(config, device="cuda")
+    S, Y, _ = wq.cg_pairs(prob, cfg["k"])
+    S, Y = S.cpu(), Y.cpu()
+    del prob
+    H = build_handle(storage, S, Y)
+    U, Sig = H.rsvd(rank, p, 5)
+    d = H.posterior_diag()
+    assert H.get_status() == 0
+    Ud = U.double()
+    orth = float((Ud @ Ud.T - torch.eye(rank, dtype=torch.float64, device="cuda")).abs().max())
+    Sig = Sig.cpu().numpy()
+    d = d.double().cpu().numpy()
+    H.close()
+    del U, Ud
+    h = oracle_h0(storage, S, Y, None)
+    X = oprobes.round_to(oprobes.normal_block(S.shape[1], rank + p, 5), storage)
+    ref = orsvd.rsvd(h, oracle_input(S, storage), oracle_input(Y, storage), X, rank)
+    dref = orsvd.posterior_diag(h, ref["U"], ref["Sigma"])
+    s0 = abs(ref["Sigma"][0])
+    sig_err = np.abs(Sig - ref["Sigma"]).max() / s0
+    big = np.abs(ref["Sigma"]) >= 1e-3 * s0
+    rel_big = (np.abs(Sig - ref["Sigma"])[big] / np.abs(ref["Sigma"][big])).max()
+    diag_max = np.abs(d - dref).max() / np.abs(dref).max()
+    print(f"  sigma {sig_err:.2e}, significant ({big.sum()}) relative {rel_big:.2e}; diag_max {diag_max:.2e}; "
+          f"orth {orth:.2e}", flush=True)
+    assert sig_err <= SIG_TOL[storage]
+    assert diag_max <= SIG_TOL[storage]
+    assert orth <= 1e-5
+    assert rel_big <= (3e-5 if storage == "f32" else 1e-2)
