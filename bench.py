@@ -411,7 +411,7 @@ KERNEL_GROUPS = [
     ("probes_kernel", "probes"), ("leaf_forward_q", "tsqr_leaf_fwd"), ("build_t", "tsqr_leaf_fwd"),
     ("tree_forward", "tsqr_tree"), ("tree_backward", "tsqr_tree"), ("set_identity", "tsqr_tree"),
     ("leaf_backward", "tsqr_leaf_bwd"), ("tri_mul", "tsqr_tree"),
-    ("qtx_mfma", "proj_QtX"), ("sum_chunks", "proj_QtX"), ("omega_solve", "omega_lu"),
+    ("qtx_mfma", "proj_QtX"), ("qtx_bf16", "proj_QtX"), ("sum_chunks", "proj_QtX"), ("omega_solve", "omega_lu"),
     ("sym_tridiag", "sym_eig"), ("householder_accum", "sym_eig"), ("dc_leaves", "sym_eig"),
     ("dc_merge_gemm", "sym_eig"), ("dc_merge", "sym_eig"), ("order_sign", "sym_eig"), ("basis_mfma", "basis_diag"),
     ("basis_bf16", "basis_diag"), ("split_us", "basis_diag"),

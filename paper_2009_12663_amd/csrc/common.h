@@ -161,9 +161,12 @@ int tsqr_run(bfgsuq_ctx* h, int c, const double* E, double* Q, double** R_out);
 // *w_out -> the eigenvalues (in work), Z = Qh Y with Y their eigenvectors (c x c
 // column-major device arrays); work holds tridiag_dc_workspace(c) bytes.
 size_t tridiag_dc_workspace(int c);
-// bfloat16-storage form of the rSVD basis U = Q Us[:, :rank] and the posterior
-// diagonal dout = h0 + sum_j lam_j U_j^2 (rsvd_bf16.hip); ush holds
+// bfloat16-storage forms of the rSVD's tall products (rsvd_bf16.hip): Q^T X chunk
+// partials (float64, the layout qtx_mfma writes), and the basis U = Q Us[:, :rank]
+// with the posterior diagonal dout = h0 + sum_j lam_j U_j^2; ush holds
 // basis_bf16_workspace(c, rank) bytes of split Us.
+int qtx_bf16_launch(hipStream_t st, int64_t n, int c, const float* Q, const bf16_t* X, double* part, int nchunks,
+                    int64_t rows_per_chunk);
 size_t basis_bf16_workspace(int c, int rank);
 int basis_bf16_launch(hipStream_t st, int64_t n, int c, int rank, const float* Q, const double* Us, uint16_t* ush,
                       const double* lam, const float* h0, float* U, float* dout);

@@ -9,10 +9,9 @@
 //   U = Q U_s[:, :rank],  Sigma = lambda[:rank],  d = h0 + sum_i lambda_i U_i^2
 //
 // Q^T E equals R exactly for E = Q R, so the R of the factorisation is used
-// instead of a second product with E.  Q^T X runs on the float64 matrix cores
-// (float64 sums).  Q U_s does too, except for bfloat16 storage, where it runs on
-// the bfloat16 matrix cores with Q and U_s split into bfloat16 terms
-// (rsvd_bf16.hip).
+// instead of a second product with E.  Q^T X and Q U_s run on the float64 matrix
+// cores, except for bfloat16 storage, where they run on the bfloat16 matrix cores
+// with Q and U_s split into bfloat16 terms (rsvd_bf16.hip).
 #include <cmath>
 #include <type_traits>
 #include <utility>
@@ -782,8 +781,9 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
         R = Fm;
     }
     ProfScope ps(h, "proj_QtX");
-    {
-        // float64 sums: Omega = F T^-1 amplifies the rounding of T by about cond(T)
+    if constexpr (bf16_path) {
+        if ((rc = qtx_bf16_launch(h->stream, n, c, Q, X, part, nchunks, rows_per_chunk)) != BFGS_OK) return rc;
+    } else {
         const int nblk = ceil_div(c, MT_TILE);
         hipLaunchKernelGGL((qtx_mfma<TO, TS>), dim3(nchunks, nblk, nblk), dim3(256), 0, h->stream, n, c, Q, X, part,
                            rows_per_chunk);

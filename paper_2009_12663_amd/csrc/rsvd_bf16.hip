@@ -1,14 +1,19 @@
-// U = Q Us[:, :rank] of Alg. 3 for bfloat16 storage on the bfloat16 matrix cores
-// (v_mfma_f32_32x32x16_bf16, float32 accumulation), with the posterior diagonal
-// of eqs. (10) and (14) formed in the same pass.
+// The tall products of Alg. 3 for bfloat16 storage on the bfloat16 matrix cores
+// (v_mfma_f32_32x32x16_bf16):
+//   T = Q^T X           the projection (Q float32, X the bfloat16 probes)
+//   U = Q Us[:, :rank]  the basis (Us the float64 eigenvectors), with the
+//                       posterior diagonal of eqs. (10) and (14) in the same pass
 //
 // A value q is carried as three bfloat16 terms, q_hi = rne(q), q_mid =
 // rne(q - q_hi), q_lo = rne(q - q_hi - q_mid), which hold a float32 value to
 // 2^-25 (in practice exactly); bfloat16 products are exact in float32.
+//   T = (Q_hi + Q_mid + Q_lo)^T X, X exact: each matrix-core step sums 16 exact
+//       products in float32 and every 32 rows the float32 partial is added to
+//       float64 accumulators, so T carries about one float32 rounding (Omega =
+//       F T^-1 amplifies the rounding of T by about cond(T); float32 sums over
+//       whole row chunks would grow with the chunk length).
 //   U = Us_hi Q_hi + Us_hi Q_mid + Us_mid Q_hi + Us_hi Q_lo + Us_mid Q_mid + Us_lo Q_hi,
-//   accumulated over c in float32 (the dropped products are below 2^-25).
-// The projection Q^T X is not done this way: Omega = F (Q^T X)^-1 amplifies the
-// rounding of Q^T X by about its condition number, so its sums stay float64.
+//       accumulated over c in float32 (the dropped products are below 2^-25).
 //
 // Fragment layout of the 32x32x16 product C += A B on a wave: lane l holds
 // A(l % 32, 8 (l / 32) + e) and B(8 (l / 32) + e, l % 32) for e = 0..7, and
@@ -26,6 +31,8 @@ __device__ __forceinline__ floatx16 mma(bf16x8 a, bf16x8 b, floatx16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
+__device__ __forceinline__ uint32_t pack2(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+
 // q -> (hi, mid, lo) bfloat16 bit patterns
 __device__ __forceinline__ void split_bits(float q, uint16_t& hi, uint16_t& mid, uint16_t& lo) {
     const bf16_t h = float_to_bf16(q);
@@ -34,6 +41,163 @@ __device__ __forceinline__ void split_bits(float q, uint16_t& hi, uint16_t& mid,
     hi = h.bits;
     mid = m.bits;
     lo = float_to_bf16(r1 - bf16_to_float(m)).bits;
+}
+
+// eight float32 values -> hi, mid and lo fragments whose sum is exact: each term
+// keeps the top 8 significant bits of what is left (truncation), and a float32
+// significand has 24
+__device__ __forceinline__ uint32_t top16(float x) { return __builtin_bit_cast(uint32_t, x) & 0xffff0000u; }
+
+__device__ __forceinline__ void split8x3(const float (&q)[8], bf16x8& hi, bf16x8& mid, bf16x8& lo) {
+    uint32_t h[4], m[4], l[4];
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+        uint32_t th[2], tm[2], tl[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const float x = q[e + u];
+            th[u] = top16(x);
+            const float r1 = x - __builtin_bit_cast(float, th[u]);
+            tm[u] = top16(r1);
+            tl[u] = top16(r1 - __builtin_bit_cast(float, tm[u]));
+        }
+        h[e / 2] = (th[0] >> 16) | th[1];
+        m[e / 2] = (tm[0] >> 16) | tm[1];
+        l[e / 2] = (tl[0] >> 16) | tl[1];
+    }
+    hi = __builtin_bit_cast(bf16x8, make_uint4(h[0], h[1], h[2], h[3]));
+    mid = __builtin_bit_cast(bf16x8, make_uint4(m[0], m[1], m[2], m[3]));
+    lo = __builtin_bit_cast(bf16x8, make_uint4(l[0], l[1], l[2], l[3]));
+}
+
+// ---------------------------------------------------------------------------
+// T = Q^T X.  Workgroup (chunk, jg) = one row chunk and the QX_NJ column tiles
+// jg * QX_NJ .. of X; wave ti owns the 32-row block ti of T (columns 32 ti.. of Q).
+// The jgroups workgroups of a chunk sit on one XCD (workgroup g runs on XCD
+// g % 8), so the chunk's Q rows come from HBM once.  Each 16-row step loads the
+// lane's 8 rows of one Q column (32 bytes) and of QX_NJ X columns (16 bytes each)
+// straight from HBM; steps alternate between two register sets.
+// part[ch * c * c + j * c + i] = the chunk's float64 sums.
+// ---------------------------------------------------------------------------
+constexpr int QX_NJ = 2;
+constexpr int QX_PF = 4;   // 16-row steps loaded ahead (even: the float64 flush is every second step)
+
+struct QxStep {
+    float q[8];
+    uint4 x[QX_NJ];
+    bool qv, xv[QX_NJ];   // row and column in range (out-of-range values are zeroed at use)
+};
+
+// Loads are unconditional, from addresses clamped into the arrays, so no branch
+// separates a prefetch slot from its use and each step waits only for its own loads.
+template <bool VEC>
+__device__ __forceinline__ void qx_load(QxStep& s, int64_t n, int c, const float* __restrict__ Q,
+                                        const bf16_t* __restrict__ X, int64_t row, int64_t rb, int64_t re, int icol,
+                                        int jt0, int m) {
+    // VEC: n % 8 == 0 and chunks end at multiples of 8, so a lane's 8 rows are all in
+    // or all out, and re - 8 >= rb
+    const int64_t rowc = min(row, re - 8 >= rb ? re - 8 : rb);
+    s.qv = row < re && icol < c;
+    const int ic = min(icol, c - 1);
+    if (VEC) {
+        const float4* p = (const float4*)(Q + (int64_t)ic * n + rowc);
+        const float4 a0 = p[0], a1 = p[1];
+        s.q[0] = a0.x; s.q[1] = a0.y; s.q[2] = a0.z; s.q[3] = a0.w;
+        s.q[4] = a1.x; s.q[5] = a1.y; s.q[6] = a1.z; s.q[7] = a1.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s.q[e] = Q[(int64_t)ic * n + min(row + e, n - 1)];
+    }
+#pragma unroll
+    for (int t = 0; t < QX_NJ; ++t) {
+        const int jc = (jt0 + t) * 32 + m;
+        s.xv[t] = row < re && jc < c;
+        const int jcc = min(jc, c - 1);
+        if (VEC) {
+            s.x[t] = *(const uint4*)(X + (int64_t)jcc * n + rowc);
+        } else {
+            uint16_t b[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) b[e] = X[(int64_t)jcc * n + min(row + e, n - 1)].bits;
+            s.x[t] = make_uint4(pack2(b[0], b[1]), pack2(b[2], b[3]), pack2(b[4], b[5]), pack2(b[6], b[7]));
+        }
+    }
+}
+
+// Rows past re are zeroed element by element in the scalar path (a lane's 8 rows can
+// straddle re there).
+template <bool VEC>
+__device__ __forceinline__ void qx_mma(const QxStep& s, floatx16 (&acc)[QX_NJ], int64_t row, int64_t re) {
+    float q[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) q[e] = (s.qv && (VEC || row + e < re)) ? s.q[e] : 0.f;
+    bf16x8 hi, mid, lo;
+    split8x3(q, hi, mid, lo);
+#pragma unroll
+    for (int t = 0; t < QX_NJ; ++t) {
+        const uint4 xr = s.xv[t] ? s.x[t] : make_uint4(0, 0, 0, 0);
+        const bf16x8 b = __builtin_bit_cast(bf16x8, xr);
+        acc[t] = mma(lo, b, acc[t]);
+        acc[t] = mma(mid, b, acc[t]);
+        acc[t] = mma(hi, b, acc[t]);
+    }
+}
+
+template <bool VEC>
+__global__ void __launch_bounds__(512, 2) qtx_bf16(int64_t n, int c, const float* __restrict__ Q,
+                                                   const bf16_t* __restrict__ X, double* __restrict__ part,
+                                                   int nchunks, int64_t rows_per_chunk) {
+    const int lane = threadIdx.x & 63, half = lane >> 5, m = lane & 31;
+    const int ntj = (c + 31) / 32, jgroups = (ntj + QX_NJ - 1) / QX_NJ;
+    const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+    const int chunk = (slot / jgroups) * 8 + xcd, jt0 = (slot % jgroups) * QX_NJ;
+    if (chunk >= nchunks) return;   // whole workgroup (padding of the grid to 8 x jgroups)
+    const int ti = threadIdx.x >> 6;
+    const int icol = ti * 32 + m;
+    const int64_t rb = (int64_t)chunk * rows_per_chunk;
+    const int64_t re = min(n, rb + rows_per_chunk);
+    floatx16 acc[QX_NJ];
+    double accd[QX_NJ][16];
+#pragma unroll
+    for (int t = 0; t < QX_NJ; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            acc[t][i] = 0.f;
+            accd[t][i] = 0.0;
+        }
+    // QX_PF register slots of 16-row steps, each refilled after its step's products
+    // (the compiler places the loads; pinning them as a deeper prefetch measured slower)
+    QxStep buf[QX_PF];
+#pragma unroll
+    for (int d = 0; d < QX_PF; ++d) qx_load<VEC>(buf[d], n, c, Q, X, rb + 16 * d + 8 * half, rb, re, icol, jt0, m);
+    for (int64_t r0 = rb; r0 < re; r0 += 16 * QX_PF) {
+#pragma unroll
+        for (int d = 0; d < QX_PF; ++d) {
+            qx_mma<VEC>(buf[d], acc, r0 + 16 * d + 8 * half, re);
+            qx_load<VEC>(buf[d], n, c, Q, X, r0 + 16 * (d + QX_PF) + 8 * half, rb, re, icol, jt0, m);
+            if (d & 1) {
+                // the 32-row float32 partial into the float64 sums
+#pragma unroll
+                for (int t = 0; t < QX_NJ; ++t)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        accd[t][i] += (double)acc[t][i];
+                        acc[t][i] = 0.f;
+                    }
+            }
+        }
+    }
+    double* out = part + (int64_t)chunk * c * c;
+#pragma unroll
+    for (int t = 0; t < QX_NJ; ++t) {
+        const int jc = (jt0 + t) * 32 + m;
+        if (jt0 + t >= ntj || jc >= c) continue;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int ic = ti * 32 + 8 * (i / 4) + 4 * half + i % 4;
+            if (ic < c) out[(int64_t)jc * c + ic] = accd[t][i];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -211,6 +375,19 @@ __global__ void __launch_bounds__(512, 4) basis_bf16(int64_t n, int c, int rank,
 }
 
 }  // namespace
+
+int qtx_bf16_launch(hipStream_t st, int64_t n, int c, const float* Q, const bf16_t* X, double* part, int nchunks,
+                    int64_t rows_per_chunk) {
+    if (c < 1 || c > 256 || rows_per_chunk % 16 != 0) return BFGS_ERR_ARG;
+    const int ntj = (c + 31) / 32, jgroups = (ntj + QX_NJ - 1) / QX_NJ;
+    const dim3 block(64 * ntj);   // <= 8 waves
+    const dim3 grid((unsigned)(ceil_div((int64_t)nchunks, 8) * 8 * jgroups));
+    if (n % 8 == 0)
+        hipLaunchKernelGGL(qtx_bf16<true>, grid, block, 0, st, n, c, Q, X, part, nchunks, rows_per_chunk);
+    else
+        hipLaunchKernelGGL(qtx_bf16<false>, grid, block, 0, st, n, c, Q, X, part, nchunks, rows_per_chunk);
+    return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+}
 
 size_t basis_bf16_workspace(int c, int rank) {
     const int nks = (c + 15) / 16, ntj = (rank + 31) / 32;
