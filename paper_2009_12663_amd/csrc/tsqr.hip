@@ -313,10 +313,11 @@ __device__ void fold_tile(SlotT* slot, v4d (&A)[Layout<BT>::RT], int c, int p0, 
 }
 
 // Apply the stored panels np-1 .. p0 (backward) to (slot, A).  Each panel's V and T
-// are staged through LDS; the next panel is loaded into registers meanwhile.
-constexpr int UB_PF = 8;   // staged doubles per thread and panel (PS <= UB_PF * 256 for BT <= 128)
-
-template <int BT, typename SlotT>
+// are staged through LDS (two buffers); the global loads run two panels ahead of the
+// panel being applied, in two register sets of PF doubles per thread.  When PF values
+// per thread cannot hold a panel (few columns, so few threads), a panel is copied
+// straight to LDS instead.
+template <int BT, typename SlotT, int PF>
 __device__ void unfold_tile(SlotT* slot, v4d (&A)[Layout<BT>::RT], int c, int p0, double* lds, const double* store) {
     constexpr int VLD = Layout<BT>::VLD, VP = Layout<BT>::VP, TSZ = Layout<BT>::TSZ, PS = Layout<BT>::PS;
     const int wave = threadIdx.x >> 6;
@@ -324,57 +325,58 @@ __device__ void unfold_tile(SlotT* slot, v4d (&A)[Layout<BT>::RT], int c, int p0
     double* Vbuf = lds;
     double* Tbuf = lds + 2 * VP;
     const int nthr = blockDim.x;
-    double pre[UB_PF];
-#define UB_LOAD(P)                                                                 \
-    {                                                                              \
-        const double* src_ = store + (int64_t)(P) * PS;                            \
-        _Pragma("unroll") for (int k = 0; k < UB_PF; ++k) {                        \
-            const int e = threadIdx.x + k * nthr;                                  \
-            pre[k] = e < PS ? src_[e] : 0.0;                                       \
-        }                                                                          \
-    }
-#define UB_STORE(B)                                                                \
-    {                                                                              \
-        double* v_ = Vbuf + (B) * VP;                                              \
-        double* t_ = Tbuf + (B) * TSZ;                                             \
-        _Pragma("unroll") for (int k = 0; k < UB_PF; ++k) {                        \
-            const int e = threadIdx.x + k * nthr;                                  \
-            if (e < PW * BT) v_[(e / BT) * VLD + e % BT] = pre[k];                 \
-            else if (e < PS) t_[((e - PW * BT) / PW) * TS_LD + (e - PW * BT) % PW] = pre[k]; \
-        }                                                                          \
-    }
-    // a panel of stored V and T must fit the per-thread staging
-    const bool staged = UB_PF * nthr >= PS;
+    const bool staged = PF * nthr >= PS;
+    auto ld = [&](int P, double (&pre)[PF]) {
+        const double* src = store + (int64_t)P * PS;
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int e = threadIdx.x + k * nthr;
+            pre[k] = e < PS ? src[e] : 0.0;
+        }
+    };
+    auto st = [&](int B, const double (&pre)[PF]) {
+        double* v = Vbuf + B * VP;
+        double* t = Tbuf + B * TSZ;
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int e = threadIdx.x + k * nthr;
+            if (e < PW * BT) v[(e / BT) * VLD + e % BT] = pre[k];
+            else if (e < PS) t[((e - PW * BT) / PW) * TS_LD + (e - PW * BT) % PW] = pre[k];
+        }
+    };
+    auto copy = [&](int P, int B) {
+        for (int e = threadIdx.x; e < PS; e += nthr) {
+            const double x = store[(int64_t)P * PS + e];
+            if (e < PW * BT) Vbuf[B * VP + (e / BT) * VLD + e % BT] = x;
+            else Tbuf[B * TSZ + ((e - PW * BT) / PW) * TS_LD + (e - PW * BT) % PW] = x;
+        }
+    };
+    double pa[PF], pb[PF];
     __syncthreads();
     if (staged) {
-        UB_LOAD(np - 1)
-        UB_STORE(0)
+        ld(np - 1, pa);
+        st(0, pa);
+        if (np - 2 >= p0) ld(np - 2, pb);
     } else {
-        for (int e = threadIdx.x; e < PS; e += nthr) {
-            const double v = store[(int64_t)(np - 1) * PS + e];
-            if (e < PW * BT) Vbuf[(e / BT) * VLD + e % BT] = v;
-            else Tbuf[((e - PW * BT) / PW) * TS_LD + (e - PW * BT) % PW] = v;
-        }
+        copy(np - 1, 0);
     }
     __syncthreads();
-    for (int p = np - 1, b = 0; p >= p0; --p, b ^= 1) {
-        if (staged && p - 1 >= p0) UB_LOAD(p - 1)
+    // panel p from buffer b; x holds panel p - 1 (loaded two panels ago), y receives p - 2
+    auto step = [&](int p, int b, double (&x)[PF], double (&y)[PF]) {
+        if (staged && p - 2 >= p0) ld(p - 2, y);
         if (wave >= p) apply_panel<BT, SlotT, false>(slot, A, c, p, wave, Vbuf + b * VP, Tbuf + b * TSZ);
         if (p - 1 >= p0) {
-            if (staged) {
-                UB_STORE(b ^ 1)
-            } else {
-                for (int e = threadIdx.x; e < PS; e += nthr) {
-                    const double v = store[(int64_t)(p - 1) * PS + e];
-                    if (e < PW * BT) Vbuf[(b ^ 1) * VP + (e / BT) * VLD + e % BT] = v;
-                    else Tbuf[(b ^ 1) * TSZ + ((e - PW * BT) / PW) * TS_LD + (e - PW * BT) % PW] = v;
-                }
-            }
+            if (staged) st(b ^ 1, x);
+            else copy(p - 1, b ^ 1);
         }
         __syncthreads();
+    };
+    // panel np - 1 - 2i uses buffer 0, the one after it buffer 1
+    for (int p = np - 1; p >= p0; p -= 2) {
+        step(p, 0, pb, pa);
+        if (p - 1 < p0) break;
+        step(p - 1, 1, pa, pb);
     }
-#undef UB_LOAD
-#undef UB_STORE
 }
 
 // ---------------------------------------------------------------------------
@@ -534,7 +536,7 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
 // Kernels of the blocked passes.  Leaf tile g of chain ch stores its panels at
 // refl + (g * np + p) * PS.
 // ---------------------------------------------------------------------------
-template <typename TQ, typename SlotT, int BT>
+template <typename TQ, typename SlotT, int BT, int PF>
 __global__ void __launch_bounds__(1024) leaf_backward(int64_t n, int c, int64_t rows_per_chain,
                                                       const double* __restrict__ refl, const double* __restrict__ Qtop,
                                                       TQ* __restrict__ Q) {
@@ -556,7 +558,7 @@ __global__ void __launch_bounds__(1024) leaf_backward(int64_t n, int c, int64_t 
         v4d A[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) A[rt] = v4d{0, 0, 0, 0};
-        unfold_tile<BT, SlotT>(slot, A, c, 0, lds, refl + gtile * np * PS);
+        unfold_tile<BT, SlotT, PF>(slot, A, c, 0, lds, refl + gtile * np * PS);
         if (col < c) {
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
@@ -597,7 +599,7 @@ __global__ void __launch_bounds__(1024) tree_forward(int c, int stride, int64_t 
     slot_store(slot, Rs + (int64_t)a_idx * c * c, c);
 }
 
-template <typename SlotT, int BT>
+template <typename SlotT, int BT, int PF>
 __global__ void __launch_bounds__(1024) tree_backward(int c, int stride, int64_t comb_off, double* __restrict__ Qtop,
                                                       const double* __restrict__ tree) {
     extern __shared__ double lds[];
@@ -613,7 +615,7 @@ __global__ void __launch_bounds__(1024) tree_backward(int c, int stride, int64_t
         v4d A[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) A[rt] = v4d{0, 0, 0, 0};
-        unfold_tile<BT, SlotT>(slot, A, c, (t * BT) / PW, lds, tree + ((comb_off + i) * ntt + t) * np * PS);
+        unfold_tile<BT, SlotT, PF>(slot, A, c, (t * BT) / PW, lds, tree + ((comb_off + i) * ntt + t) * np * PS);
         if (col < c) {
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
@@ -638,7 +640,8 @@ inline int floor_pow2(int64_t x) {
     return p;
 }
 
-template <typename TO, typename SlotT, int BT>
+// PF: doubles per thread that stage one stored panel in the backward passes.
+template <typename TO, typename SlotT, int BT, int PF>
 int tsqr_impl(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     constexpr int PS = Layout<BT>::PS;
     const int64_t n = h->n;
@@ -663,9 +666,9 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     static bool attr_done = false;
     if (!attr_done) {
         const int lim = 160 * 1024;
-        if (hipFuncSetAttribute((const void*)leaf_backward<TO, SlotT, BT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
+        if (hipFuncSetAttribute((const void*)leaf_backward<TO, SlotT, BT, PF>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
             hipFuncSetAttribute((const void*)tree_forward<SlotT, BT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
-            hipFuncSetAttribute((const void*)tree_backward<SlotT, BT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
+            hipFuncSetAttribute((const void*)tree_backward<SlotT, BT, PF>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
             return BFGS_ERR_HIP;
         attr_done = true;
     }
@@ -692,12 +695,12 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     for (int stride = nchains / 2; stride >= 1; stride /= 2) {
         const int ncomb = nchains / (2 * stride);
         off -= ncomb;
-        hipLaunchKernelGGL((tree_backward<SlotT, BT>), dim3(ncomb), dim3(threads), smem, h->stream, c, stride, off,
+        hipLaunchKernelGGL((tree_backward<SlotT, BT, PF>), dim3(ncomb), dim3(threads), smem, h->stream, c, stride, off,
                            Qtop, tree);
     }
     prof_end(h);
     prof_begin(h, "tsqr_leaf_bwd");
-    hipLaunchKernelGGL((leaf_backward<TO, SlotT, BT>), dim3(nchains), dim3(threads), smem, h->stream, n, c,
+    hipLaunchKernelGGL((leaf_backward<TO, SlotT, BT, PF>), dim3(nchains), dim3(threads), smem, h->stream, n, c,
                        rows_per_chain, refl, Qtop, Q);
     prof_end(h);
     *R_out = Rs;   // chain 0 holds the final R (row-major, upper triangular)
@@ -711,9 +714,14 @@ int tsqr_dispatch(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     // within 128 registers per lane (1024-thread workgroups); the slot is float64
     // whenever it fits in LDS (c <= 184) and float32 above that
     const size_t lim = 160 * 1024;
-    if (lds_bytes<64, double>(c) <= lim && qf_lds_bytes<double>(c) <= lim)
-        return tsqr_impl<TO, double, 64>(h, c, E, Q, R_out);
-    return tsqr_impl<TO, float, 64>(h, c, E, Q, R_out);
+    const bool dslot = lds_bytes<64, double>(c) <= lim && qf_lds_bytes<double>(c) <= lim;
+    // staging doubles per thread for one stored panel (64 * ceil(c / 16) threads); more
+    // than 8 (c <= 32) copies panels straight to LDS
+    const int pf = ceil_div(Layout<64>::PS, 64 * ceil_div(c, PW));
+    if (pf <= 2) return dslot ? tsqr_impl<TO, double, 64, 2>(h, c, E, Q, R_out) : tsqr_impl<TO, float, 64, 2>(h, c, E, Q, R_out);
+    if (pf <= 3) return dslot ? tsqr_impl<TO, double, 64, 3>(h, c, E, Q, R_out) : tsqr_impl<TO, float, 64, 3>(h, c, E, Q, R_out);
+    if (pf <= 5) return dslot ? tsqr_impl<TO, double, 64, 5>(h, c, E, Q, R_out) : tsqr_impl<TO, float, 64, 5>(h, c, E, Q, R_out);
+    return dslot ? tsqr_impl<TO, double, 64, 8>(h, c, E, Q, R_out) : tsqr_impl<TO, float, 64, 8>(h, c, E, Q, R_out);
 }
 
 }  // namespace
