@@ -50,7 +50,6 @@ template <typename T>
 __global__ void probes_kernel(int64_t n, int c, uint64_t seed, T* __restrict__ X) {
     const int64_t quads = (n + 3) / 4;
     const int64_t total = quads * c;
-    const double two_pi = 6.283185307179586476925286766559;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t q = e % quads;
         const int j = (int)(e / quads);
@@ -59,9 +58,12 @@ __global__ void probes_kernel(int64_t n, int c, uint64_t seed, T* __restrict__ X
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             const double rad = sqrt(-2.0 * log(unit_open0(x.v[2 * half])));
-            const double ang = two_pi * unit_open0(x.v[2 * half + 1]);
-            z[2 * half] = rad * cos(ang);
-            z[2 * half + 1] = rad * sin(ang);
+            // angle 2 pi u as pi (2u): 2u is exact and lies in (0, 2], so sincospi needs
+            // no range reduction beyond its own
+            double sn, cs;
+            sincospi(2.0 * unit_open0(x.v[2 * half + 1]), &sn, &cs);
+            z[2 * half] = rad * cs;
+            z[2 * half + 1] = rad * sn;
         }
         T* col = X + (int64_t)j * n;
 #pragma unroll
