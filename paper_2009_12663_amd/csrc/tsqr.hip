@@ -1,32 +1,27 @@
-// Blocked Householder TSQR of E (n x c, column-major, c <= 256) for Alg. 3's
-// "E = Q R": Q explicit (n x c, column-major), R upper triangular (c x c, row-major).
+// Householder TSQR of E (n x c, column-major, c <= 256) for Alg. 3's "E = Q R":
+// Q explicit (n x c, column-major), R upper triangular (c x c, row-major).
 //
 // Layout.  E is split into `nchains` contiguous row ranges, one workgroup each.
 // A workgroup keeps an upper-triangular c x c slot (packed, LDS) and folds its
-// rows in, BT rows at a time.  The BT x c tile lives in registers as 16 x 16
-// float64 matrix-core accumulator fragments: wave w owns column tile w (columns
-// 16w .. 16w + 15), lane l holds rows 16 rt + l/16 + 4 r of column 16 w + l%16.
+// rows in, 64 at a time.  The slot starts at zero, so a column's first non-zero
+// tile swaps into the slot (tau = 1) and the slot rows carry no part of Q.
 //
-// Leaves (forward).  One quad of lanes per column folds each tile with one
-// barrier per reflector (leaf_forward_q); the reflectors are stored in the panel
-// layout below, with each panel's T formed from them while they are in registers.
+// Forward (leaf_forward_q, tree_forward_q).  One quad of lanes per column holds
+// the column's 64 tile rows (16 per lane) and folds the tile with one barrier per
+// reflector: reflector j acts on (slot row j, tile rows); the quad that owns column
+// j+1 builds reflector j+1 right after it applies reflector j.  Each wave's 16
+// columns form a panel whose reflectors are stored with the panel's compact-WY
+// factor T (I - V T V^T, V the tile parts; the slot part of reflector j is the unit
+// vector e_j; T upper triangular), formed while the reflectors are still in
+// registers.  The per-chain R factors are combined by a binary tree with the same
+// fold, R_b read as tile rows (tile t is zero left of column 64 t).
 //
-// Tree fold (forward).  Panel p (column tile p) is factored by its owner
-// wave, one Householder reflector per column acting on (slot row j, tile rows);
-// the panel's reflectors form the compact WY block I - V T V^T (V: tile part,
-// the slot part of reflector j is the unit vector e_j; T upper triangular).  The
-// waves right of the panel then apply its transpose to their columns on the
-// matrix cores:  W = S_p + V^T A,  W' = T^T W,  S_p -= W',  A -= V W', where S_p
-// is the panel's 16 slot rows.  Panels and T alternate between two LDS buffers,
-// so panel p+1 is factored while the other waves still apply panel p.
-// The slot starts at zero, so a column's first non-zero tile swaps into the slot
-// (tau = 1) and the slot rows carry no part of Q.
-//
-// Q (backward).  The per-chain R factors are combined by a binary tree with the
-// same fold (reading the second R as tile rows).  Q is then formed by applying the
-// stored blocks in reverse to the identity at the root and to zero tile rows at
-// the leaves: W = S_p + V^T A,  W' = T W,  S_p -= W',  A -= V W'.  Every slot met
-// on the way stays upper triangular.
+// Backward (tree_backward, leaf_backward).  Q is formed by applying the stored
+// panels in reverse to the identity at the root and to zero tile rows at the
+// leaves, on the float64 matrix cores from register-resident accumulator tiles
+// (wave w owns column tile w; lane l holds rows 16 rt + l/16 + 4 r of column
+// 16 w + l%16):  W = S_p + V^T A,  W' = T W,  S_p -= W',  A -= V W', with S_p the
+// panel's 16 slot rows.  Every slot met on the way stays upper triangular.
 #include <algorithm>
 #include <cmath>
 
@@ -72,29 +67,6 @@ __device__ __forceinline__ double rcp_nr(double x) {
     return y;
 }
 
-// x + x(lane ^ 16) + x(lane ^ 32) + x(lane ^ 48): the sum over the four 16-lane rows
-// that share lane % 16.  v_permlane{16,32}_swap with both operands equal to x
-// returns, across its two results, each lane's own value and its partner's.
-__device__ __forceinline__ double add_perm16(double x) {
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
-    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
-    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
-    const double a = __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | lo[0]);
-    const double b = __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | lo[1]);
-    return a + b;
-}
-
-__device__ __forceinline__ double add_perm32(double x) {
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
-    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
-    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
-    const double a = __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | lo[0]);
-    const double b = __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | lo[1]);
-    return a + b;
-}
-
-__device__ __forceinline__ double row_sum4(double x) { return add_perm32(add_perm16(x)); }
-
 __device__ __forceinline__ double read_lane(double x, int l) {
     const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
     const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, l);
@@ -110,19 +82,14 @@ __device__ __forceinline__ double bpermute_f64(double x, int src) {
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-// LDS: Vp[2][PW][VLD] | Ts[2][PW][TS_LD] | Gs[PW][TS_LD] | tau[PW] | slot
+// LDS of the backward passes: Vp[2][PW][VLD] | Ts[2][PW][TS_LD] | slot
 template <int BT>
 struct Layout {
     static constexpr int RT = BT / 16;
     static constexpr int VLD = BT + 2;
     static constexpr int VP = PW * VLD;            // doubles per panel buffer
     static constexpr int TSZ = PW * TS_LD;
-    static constexpr int HEAD = 2 * VP + 2 * TSZ + TSZ + PW;
+    static constexpr int HEAD = 2 * VP + 2 * TSZ;
     static constexpr int PS = PW * BT + PW * PW;   // doubles per stored panel (V then T)
 };
 
@@ -131,111 +98,8 @@ size_t lds_bytes(int c) {
     return (size_t)Layout<BT>::HEAD * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
 }
 
-// Factor panel p (owner wave): 16 reflectors on (slot rows 16p.., tile columns).
-// Leaves V in Vp ([refl][row]), T in Ts, copies both to `store` (V: [refl][BT], then T).
-template <int BT, typename SlotT>
-__device__ void factor_panel(SlotT* slot, v4d (&A)[Layout<BT>::RT], int c, int p, double* Vp, double* Ts,
-                             double* Gs, double* tau_s, double* store) {
-    constexpr int RT = Layout<BT>::RT, VLD = Layout<BT>::VLD;
-    const int lane = threadIdx.x & 63, jl = lane & 15, q = lane >> 4;
-    const int j0 = p * PW, col = j0 + jl;
-    __builtin_amdgcn_s_setprio(3);   // the panel is the critical path
-    for (int jj = 0; jj < PW; ++jj) {
-        const int j = j0 + jj;
-        // slot(j, j) and slot(j, col): no earlier reflector of this panel touches row j
-        const int dj = j < c ? tri_index(j, j, c) : 0;
-        const bool mine = jl > jj && col < c;
-        const int ij = mine ? tri_index(j, col, c) : 0;
-        const double rjj_pre = (double)slot[dj];
-        const double rr_pre = mine ? (double)slot[ij] : 0.0;
-        // norm^2 of column jj's tile part (every lane computes its own column's);
-        // four independent partial sums keep the FMA chains short
-        double pp[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) pp[r] = fma(A[rt][r], A[rt][r], pp[r]);
-        const double part = row_sum4((pp[0] + pp[1]) + (pp[2] + pp[3]));
-        const double xn2 = read_lane(part, jj);
-        double tau = 0.0, beta = 0.0, sc = 0.0;
-        if (j < c && xn2 > 0.0) {
-            // beta = -sign(rjj) |(rjj, x)|, tau = (beta - rjj) / beta, v = x / (rjj - beta);
-            // |beta| and |rjj - beta| are >= sqrt(xn2) >= 2^-537: both reciprocals are of
-            // normal numbers (their product need not be)
-            const double rjj = rjj_pre;
-            const double t = fma(rjj, rjj, xn2);
-            beta = -copysign(t * rsqrt_nr(t), rjj);
-            const double u = rjj - beta;
-            tau = -u * rcp_nr(beta);
-            sc = rcp_nr(u);
-        }
-        if (jl == jj) {
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    A[rt][r] *= sc;
-                    Vp[jj * VLD + rt * 16 + q + 4 * r] = A[rt][r];
-                }
-        }
-        if (lane == 0) {
-            if (tau != 0.0) slot[dj] = (SlotT)beta;
-            tau_s[jj] = tau;
-        }
-        wave_sync();
-        if (tau != 0.0) {
-            double dp[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) dp[r] = fma(Vp[jj * VLD + rt * 16 + q + 4 * r], A[rt][r], dp[r]);
-            const double d = row_sum4((dp[0] + dp[1]) + (dp[2] + dp[3]));
-            if (mine) {
-                const double rr = rr_pre;
-                const double w = (rr + d) * tau;
-                if (q == 0) slot[ij] = (SlotT)(rr - w);
-#pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) A[rt][r] = fma(-w, Vp[jj * VLD + rt * 16 + q + 4 * r], A[rt][r]);
-            }
-        }
-        wave_sync();
-    }
-    __builtin_amdgcn_s_setprio(0);
-    // G = V^T V (tile parts; the slot parts are distinct unit vectors) on the matrix core
-    v4d g = {0, 0, 0, 0};
-#pragma unroll
-    for (int ks = 0; ks < BT / 4; ++ks) {
-        const double a = Vp[jl * VLD + ks * 4 + q];
-        g = mfma64(a, a, g);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Gs[(q + 4 * r) * TS_LD + jl] = g[r];
-    wave_sync();
-    // T(a, i) = -tau_i sum_{a <= b < i} T(a, b) G(b, i), T(a, a) = tau_a: row a of T
-    // depends only on row a, so lane a builds it alone, in registers.
-    if (lane < PW) {
-        double trow[PW];
-#pragma unroll
-        for (int i = 0; i < PW; ++i) {
-            double sacc = 0.0;
-#pragma unroll
-            for (int b = 0; b < i; ++b) sacc = fma(trow[b], Gs[b * TS_LD + i], sacc);
-            const double ti = tau_s[i];
-            trow[i] = i < lane ? 0.0 : (i == lane ? ti : -ti * sacc);
-        }
-#pragma unroll
-        for (int i = 0; i < PW; ++i) Ts[lane * TS_LD + i] = trow[i];
-    }
-    // copy V and T out for the backward pass (coalesced)
-    for (int e = lane; e < PW * BT; e += 64) store[e] = Vp[(e / BT) * VLD + e % BT];
-    for (int e = lane; e < PW * PW; e += 64) store[PW * BT + e] = Ts[(e / PW) * TS_LD + e % PW];
-    wave_sync();
-}
-
 // Apply panel p's block to this wave's column tile w:
-//   W = S_p + V^T A;  W' = op(T) W (op = transpose in the fold);  S_p -= W';  A -= V W'.
+//   W = S_p + V^T A;  W' = op(T) W (op = transpose for Q^T, identity for Q);  S_p -= W';  A -= V W'.
 template <int BT, typename SlotT, bool TRANS>
 __device__ __forceinline__ void apply_panel(SlotT* slot, v4d (&A)[Layout<BT>::RT], int c, int p, int w,
                                             const double* Vp, const double* Ts) {
@@ -289,26 +153,6 @@ __device__ void slot_store(const SlotT* slot, double* M, int c) {
     for (int j = 0; j < c; ++j)
         for (int col = threadIdx.x; col < c; col += blockDim.x)
             M[(int64_t)j * c + col] = col >= j ? (double)slot[tri_index(j, col, c)] : 0.0;
-    __syncthreads();
-}
-
-// Fold the tile in A into the slot, panels p0 .. np-1; panel p's V and T go to
-// store + p * PS.
-template <int BT, typename SlotT>
-__device__ void fold_tile(SlotT* slot, v4d (&A)[Layout<BT>::RT], int c, int p0, double* lds, double* store) {
-    constexpr int VP = Layout<BT>::VP, TSZ = Layout<BT>::TSZ, PS = Layout<BT>::PS;
-    const int wave = threadIdx.x >> 6;
-    const int np = (c + PW - 1) / PW;
-    double* Vbuf = lds;
-    double* Tbuf = lds + 2 * VP;
-    double* Gs = Tbuf + 2 * TSZ;
-    double* tau_s = Gs + TSZ;
-    for (int p = p0; p < np; ++p) {
-        const int b = (p - p0) & 1;
-        if (wave == p) factor_panel<BT, SlotT>(slot, A, c, p, Vbuf + b * VP, Tbuf + b * TSZ, Gs, tau_s, store + (int64_t)p * PS);
-        __syncthreads();
-        if (wave > p) apply_panel<BT, SlotT, true>(slot, A, c, p, wave, Vbuf + b * VP, Tbuf + b * TSZ);
-    }
     __syncthreads();
 }
 
@@ -459,6 +303,59 @@ size_t qf_lds_bytes(int c) {
     return (size_t)QF_HEAD * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
 }
 
+// Fold the tile held in a[] (this quad's column) into the slot with reflectors
+// j0 .. c-1 (the tile's columns below j0 are zero): one barrier per reflector.
+template <typename SlotT>
+__device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int j0, int col, int g, double* vbuf,
+                                       double* tau_sh, double* taus_lds) {
+    if (col == j0 && j0 < c) q_make_reflector(slot, a, c, j0, g, vbuf + (j0 & 1) * QT, tau_sh + (j0 & 1), taus_lds);
+    __syncthreads();
+    for (int j = j0; j < c; ++j) {
+        const int buf = j & 1;
+        const double tau = tau_sh[buf];
+        if (col > j && col < c && tau != 0.0) q_reflect_column(slot, a, c, j, col, g, vbuf + buf * QT, tau);
+        if (col == j + 1 && j + 1 < c)
+            q_make_reflector(slot, a, c, j + 1, g, vbuf + (buf ^ 1) * QT, tau_sh + (buf ^ 1), taus_lds);
+        __syncthreads();
+    }
+}
+
+// After a fold, this wave's reflectors (its 16 columns = one panel) go to dst in the
+// panel layout: the tile part (rows t = i * LPC + g), then the panel's compact-WY
+// factor T (I - V T V^T, T upper triangular) formed from the reflectors still in
+// registers.  G = V^T V on the matrix cores: V's rows 4 ks .. 4 ks + 3 sit in a[ks]
+// of the quads, one lane permutation away from the A/B operand layout.  Then T
+// column by column: lane r < 16 keeps row r, and G(b, i) (accumulator element b / 4
+// of lane 16 (b % 4) + i) is broadcast.
+__device__ __forceinline__ void q_store_panel(const double (&a)[RPL], int c, int col, int g,
+                                              const double* taus_lds, double* dst) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) dst[(col % PW) * QT + i * LPC + g] = a[i];
+    const int src = 4 * (lane & 15) + (lane >> 4);
+    v4d gacc = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < RPL; ++ks) {
+        const double v = bpermute_f64(a[ks], src);
+        gacc = mfma64(v, v, gacc);
+    }
+    const int r = lane & 15;
+    double trow[PW];
+#pragma unroll
+    for (int i = 0; i < PW; ++i) {
+        const int ci = wave * PW + i;
+        const double tau_i = ci < c ? taus_lds[ci] : 0.0;
+        double sacc = 0.0;
+#pragma unroll
+        for (int b = 0; b < i; ++b) sacc = fma(trow[b], read_lane(gacc[b / 4], 16 * (b % 4) + i), sacc);
+        trow[i] = i < r ? 0.0 : (i == r ? tau_i : -tau_i * sacc);
+    }
+    if (lane < PW) {
+#pragma unroll
+        for (int i = 0; i < PW; ++i) dst[PW * QT + lane * PW + i] = trow[i];
+    }
+}
+
 template <typename TE, typename SlotT>
 __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t rows_per_chain,
                                                        const TE* __restrict__ E, double* __restrict__ refl,
@@ -483,53 +380,42 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
             const int64_t r = r0 + i * LPC + g;
             a[i] = (col < c && r < r_end) ? to_f64(E[(int64_t)col * n + r]) : 0.0;
         }
-        if (col == 0) q_make_reflector(slot, a, c, 0, g, vbuf, tau_sh, taus_lds);
-        __syncthreads();
-        for (int j = 0; j < c; ++j) {
-            const int buf = j & 1;
-            const double tau = tau_sh[buf];
-            if (col > j && col < c && tau != 0.0) q_reflect_column(slot, a, c, j, col, g, vbuf + buf * QT, tau);
-            if (col == j + 1 && j + 1 < c)
-                q_make_reflector(slot, a, c, j + 1, g, vbuf + (buf ^ 1) * QT, tau_sh + (buf ^ 1), taus_lds);
-            __syncthreads();
-        }
-        // reflector col: tile part (rows t = i * LPC + g) in the panel layout
+        q_fold(slot, a, c, 0, col, g, vbuf, tau_sh, taus_lds);
         const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;   // wave = panel
-        double* dst = refl + (gtile * np + wave) * PS;
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) dst[(col % PW) * QT + i * LPC + g] = a[i];
-        // The panel's compact-WY factor T (I - V T V^T, T upper triangular) from the
-        // reflectors still in registers.  G = V^T V on the matrix cores: V's rows
-        // 4 ks .. 4 ks + 3 sit in a[ks] of the quads, one lane permutation away from the
-        // A/B operand layout.  Then T column by column: lane r < 16 keeps row r, and
-        // G(b, i) (accumulator element b / 4 of lane 16 (b % 4) + i) is broadcast.
-        {
-            const int src = 4 * (lane & 15) + (lane >> 4);
-            v4d gacc = {0, 0, 0, 0};
-#pragma unroll
-            for (int ks = 0; ks < RPL; ++ks) {
-                const double v = bpermute_f64(a[ks], src);
-                gacc = mfma64(v, v, gacc);
-            }
-            const int r = lane & 15;
-            double trow[PW];
-#pragma unroll
-            for (int i = 0; i < PW; ++i) {
-                const int ci = wave * PW + i;
-                const double tau_i = ci < c ? taus_lds[ci] : 0.0;
-                double sacc = 0.0;
-#pragma unroll
-                for (int b = 0; b < i; ++b) sacc = fma(trow[b], read_lane(gacc[b / 4], 16 * (b % 4) + i), sacc);
-                trow[i] = i < r ? 0.0 : (i == r ? tau_i : -tau_i * sacc);
-            }
-            if (lane < PW) {
-#pragma unroll
-                for (int i = 0; i < PW; ++i) dst[PW * QT + lane * PW + i] = trow[i];
-            }
-        }
+        q_store_panel(a, c, col, g, taus_lds, refl + (gtile * np + (threadIdx.x >> 6)) * PS);
     }
     slot_store(slot, Rs + (int64_t)ch * c * c, c);
+}
+
+// Tree fold with the quad scheme: combine i of a level folds R_b (chain a + stride)
+// into the slot holding R_a, 64 rows at a time; tile t of R_b is zero left of
+// column 64 t, so its reflectors start there.  Its panels p >= 64 t / 16 go to
+// tree + ((comb_off + i) * ntt + t) * np * PS + p * PS, as the backward pass reads them.
+template <typename SlotT>
+__global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_t comb_off, double* __restrict__ Rs,
+                                                       double* __restrict__ tree) {
+    extern __shared__ double lds[];
+    double* vbuf = lds;
+    double* tau_sh = vbuf + 2 * QT;
+    double* taus_lds = tau_sh + 2;
+    SlotT* slot = (SlotT*)(lds + QF_HEAD);
+    constexpr int PS = Layout<QT>::PS;
+    const int i = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC, wave = threadIdx.x >> 6;
+    const int np = (c + PW - 1) / PW, ntt = (c + QT - 1) / QT;
+    const int a_idx = i * 2 * stride, b_idx = a_idx + stride;
+    const double* Rb = Rs + (int64_t)b_idx * c * c;
+    slot_load(slot, Rs + (int64_t)a_idx * c * c, c);
+    for (int t = 0; t < ntt; ++t) {
+        double a[RPL];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const int row = t * QT + q * LPC + g;
+            a[q] = (col < c && row < c && col >= row) ? Rb[(int64_t)row * c + col] : 0.0;
+        }
+        q_fold(slot, a, c, t * QT, col, g, vbuf, tau_sh, taus_lds);
+        if (wave >= (t * QT) / PW) q_store_panel(a, c, col, g, taus_lds, tree + (((comb_off + i) * ntt + t) * np + wave) * PS);
+    }
+    slot_store(slot, Rs + (int64_t)a_idx * c * c, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -571,34 +457,8 @@ __global__ void __launch_bounds__(1024) leaf_backward(int64_t n, int c, int64_t 
     }
 }
 
-// Tree: combine i of a level merges chain a = i * 2 * stride with b = a + stride;
-// its tile t (rows t * BT .. of R_b) stores panels at tree + ((comb_off + i) * ntt + t) * np * PS.
-template <typename SlotT, int BT>
-__global__ void __launch_bounds__(1024) tree_forward(int c, int stride, int64_t comb_off, double* __restrict__ Rs,
-                                                     double* __restrict__ tree) {
-    extern __shared__ double lds[];
-    constexpr int RT = Layout<BT>::RT, PS = Layout<BT>::PS;
-    SlotT* slot = (SlotT*)(lds + Layout<BT>::HEAD);
-    const int i = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6, jl = lane & 15, q = lane >> 4;
-    const int np = (c + PW - 1) / PW, ntt = (c + BT - 1) / BT;
-    const int col = wave * PW + jl;
-    const int a_idx = i * 2 * stride, b_idx = a_idx + stride;
-    const double* Rb = Rs + (int64_t)b_idx * c * c;
-    slot_load(slot, Rs + (int64_t)a_idx * c * c, c);
-    for (int t = 0; t < ntt; ++t) {
-        v4d A[RT];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = t * BT + rt * 16 + q + 4 * r;
-                A[rt][r] = (col < c && row < c && col >= row) ? Rb[(int64_t)row * c + col] : 0.0;
-            }
-        fold_tile<BT, SlotT>(slot, A, c, (t * BT) / PW, lds, tree + ((comb_off + i) * ntt + t) * np * PS);
-    }
-    slot_store(slot, Rs + (int64_t)a_idx * c * c, c);
-}
-
+// Tree backward: combine i of a level (chain a = i * 2 * stride, b = a + stride)
+// applies the panels tree_forward_q stored for its tiles t (rows t * BT .. of R_b).
 template <typename SlotT, int BT, int PF>
 __global__ void __launch_bounds__(1024) tree_backward(int c, int stride, int64_t comb_off, double* __restrict__ Qtop,
                                                       const double* __restrict__ tree) {
@@ -667,7 +527,7 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     if (!attr_done) {
         const int lim = 160 * 1024;
         if (hipFuncSetAttribute((const void*)leaf_backward<TO, SlotT, BT, PF>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
-            hipFuncSetAttribute((const void*)tree_forward<SlotT, BT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
+            hipFuncSetAttribute((const void*)tree_forward_q<SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
             hipFuncSetAttribute((const void*)tree_backward<SlotT, BT, PF>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
             return BFGS_ERR_HIP;
         attr_done = true;
@@ -687,8 +547,8 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     int64_t off = 0;
     for (int stride = 1; stride < nchains; stride *= 2) {
         const int ncomb = nchains / (2 * stride);
-        hipLaunchKernelGGL((tree_forward<SlotT, BT>), dim3(ncomb), dim3(threads), smem, h->stream, c, stride, off, Rs,
-                           tree);
+        hipLaunchKernelGGL((tree_forward_q<SlotT>), dim3(ncomb), dim3(threads), qf_lds_bytes<SlotT>(c), h->stream, c,
+                           stride, off, Rs, tree);
         off += ncomb;
     }
     hipLaunchKernelGGL(set_identity_kernel, dim3(64), dim3(256), 0, h->stream, Qtop, c);
