@@ -408,8 +408,8 @@ KERNEL_GROUPS = [
     ("gemm1_mfma", "apply_gemm1"), ("gemm1_f64mfma", "apply_gemm1"), ("reduce_z", "apply_reduce"),
     ("reduce_partials", "apply_reduce"), ("small_solve", "apply_solve"), ("pack_small", "apply_pack"),
     ("gemm2_mfma", "apply_gemm2"), ("gemm2_f64mfma", "apply_gemm2"), ("scale_by_h0", "apply_gemm2"),
-    ("probes_kernel", "probes"), ("leaf_forward_q", "tsqr_leaf_fwd"), ("build_t", "tsqr_leaf_fwd"),
-    ("tree_forward", "tsqr_tree"), ("tree_backward", "tsqr_tree"), ("set_identity", "tsqr_tree"),
+    ("probes_kernel", "probes"), ("leaf_forward_q", "tsqr_leaf_fwd"),
+    ("tree_forward_q", "tsqr_tree"), ("tree_backward", "tsqr_tree"), ("set_identity", "tsqr_tree"),
     ("leaf_backward", "tsqr_leaf_bwd"), ("tri_mul", "tsqr_tree"),
     ("qtx_mfma", "proj_QtX"), ("qtx_bf16", "proj_QtX"), ("sum_chunks", "proj_QtX"), ("omega_solve", "omega_lu"),
     ("sym_tridiag", "sym_eig"), ("householder_accum", "sym_eig"), ("dc_leaves", "sym_eig"),

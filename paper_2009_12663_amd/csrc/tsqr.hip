@@ -262,7 +262,9 @@ __device__ __forceinline__ void q_make_reflector(SlotT* slot, double (&a)[RPL], 
     const double rjj = (double)slot[dj];
     double tau = 0.0;
     if (xn2 > 0.0) {
-        // as in factor_panel: two reciprocals of normal-range numbers
+        // beta = -sign(rjj) |(rjj, x)|, tau = (beta - rjj) / beta, v = x / (rjj - beta);
+        // |beta| and |rjj - beta| are >= sqrt(xn2) >= 2^-537, so both reciprocals are of
+        // normal numbers (their product need not be)
         const double t = fma(rjj, rjj, xn2);
         const double beta = -copysign(t * rsqrt_nr(t), rjj);
         const double u = rjj - beta;
