@@ -463,14 +463,45 @@ __global__ void __launch_bounds__(LU_THREADS) omega_solve(int c, double* __restr
 //                      eigenvectors of A = Z times those of the tridiagonal
 //                      (tridiag_dc.hip)
 // Z: column-major c x c eigenvectors (Z[i*c + r] = component r of vector i).
+// x summed over the wave, in every lane (all lanes active): quad and 16-lane row sums
+// by DPP (quad permutations, row rotations by 4 and 8), then the four rows by the
+// permlane swaps, which return across their two results each lane's own value and
+// that of the same lane in the partner row.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double swap_sum16(double x) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | lo[0]) +
+           __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | lo[1]);
+}
+
+__device__ __forceinline__ double swap_sum32(double x) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi[0] << 32) | lo[0]) +
+           __builtin_bit_cast(double, ((unsigned long long)hi[1] << 32) | lo[1]);
+}
+
 __device__ __forceinline__ double wave_sum_d(double x) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+    x += dpp_f64<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+    x += dpp_f64<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+    x += dpp_f64<0x124>(x);   // row_ror:4
+    x += dpp_f64<0x128>(x);   // row_ror:8
+    return swap_sum32(swap_sum16(x));
 }
 
 constexpr int TRI_THREADS = 1024;
 constexpr int TRI_LDS_MAX = 191;   // trailing matrices up to this size run from LDS (packed lower triangle)
+static_assert(TRI_LDS_MAX <= 193, "LDS-phase rows are covered by three 64-lane passes");
 
 __host__ __device__ constexpr size_t tri_lds_bytes() { return (size_t)TRI_LDS_MAX * (TRI_LDS_MAX + 1) / 2 * 8; }
 
@@ -484,7 +515,7 @@ __global__ void __launch_bounds__(TRI_THREADS) sym_tridiag(int c, double* __rest
                                                              double* __restrict__ dg, double* __restrict__ eg,
                                                              double* __restrict__ taus) {
     extern __shared__ double Tl[];   // packed lower triangle of A[b0:, b0:]
-    __shared__ double red[TRI_THREADS / 64];
+    __shared__ double red[2 * (TRI_THREADS / 64)];
     __shared__ double vsh[256];
     __shared__ double wsh[256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -519,12 +550,26 @@ __global__ void __launch_bounds__(TRI_THREADS) sym_tridiag(int c, double* __rest
         if (tau != 0.0) {
             // p = tau * A22 v;  w = p - (tau/2)(p^T v) v;  A22 -= v w^T + w v^T
             // one wave per row, lanes across the row (coalesced), then a wave sum
-            for (int i = wave; i < m; i += NW) {
-                const double* row = A + (int64_t)(kk + 1 + i) * c + (kk + 1);
-                double sr = 0.0;
-                for (int l = lane; l < m; l += 64) sr = fma(row[l], vsh[l], sr);
-                sr = wave_sum_d(sr);
-                if (lane == 0) wsh[i] = tau * sr;
+            // two rows per pass, all loads of a pass first (m <= 255: four per lane and row)
+            for (int i0 = wave; i0 < m; i0 += 2 * NW) {
+                double sr[2] = {0.0, 0.0};
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int i = i0 + r * NW;
+                    const double* row = A + (int64_t)(kk + 1 + i) * c + (kk + 1);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int l = lane + 64 * u;
+                        if (i < m && l < m) sr[r] = fma(row[l], vsh[l], sr[r]);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int i = i0 + r * NW;
+                    if (i >= m) break;   // uniform
+                    const double p = wave_sum_d(sr[r]);
+                    if (lane == 0) wsh[i] = tau * p;
+                }
             }
             __syncthreads();
             double pp = 0.0;
@@ -532,11 +577,30 @@ __global__ void __launch_bounds__(TRI_THREADS) sym_tridiag(int c, double* __rest
             const double K = 0.5 * tau * wg_sum<TRI_THREADS>(pp, red);
             for (int i = tid; i < m; i += TRI_THREADS) wsh[i] -= K * vsh[i];
             __syncthreads();
-            for (int i = wave; i < m; i += NW) {
-                double* row = A + (int64_t)(kk + 1 + i) * c + (kk + 1);
-                const double vi = vsh[i], wi = wsh[i];
-#pragma unroll 4
-                for (int l = lane; l < m; l += 64) row[l] -= vi * wsh[l] + wi * vsh[l];
+            for (int i0 = wave; i0 < m; i0 += 2 * NW) {
+                double x[2][4];
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int i = i0 + r * NW;
+                    const double* row = A + (int64_t)(kk + 1 + i) * c + (kk + 1);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int l = lane + 64 * u;
+                        x[r][u] = (i < m && l < m) ? row[l] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int i = i0 + r * NW;
+                    if (i >= m) break;   // uniform
+                    double* row = A + (int64_t)(kk + 1 + i) * c + (kk + 1);
+                    const double vi = vsh[i], wi = wsh[i];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int l = lane + 64 * u;
+                        if (l < m) row[l] = x[r][u] - (vi * wsh[l] + wi * vsh[l]);
+                    }
+                }
             }
         }
         __syncthreads();
@@ -551,15 +615,24 @@ __global__ void __launch_bounds__(TRI_THREADS) sym_tridiag(int c, double* __rest
         Tl[e] = A[(int64_t)(b0 + i) * c + b0 + l];
     }
     __syncthreads();
+    // Three barriers per step: (v written) (p and the partials of p^T v written)
+    // (A22 updated and the partials of the next column's norm written).  w = p - K v
+    // is formed on the fly in the update, whose lane 0 of each row also sums the
+    // squares of the next column below its subdiagonal.
+    double* red2 = red + NW;
+    double xn2 = 0.0;
+    if (b0 + 2 < c) {
+        const int m = c - b0 - 1;
+        double part = 0.0;
+        for (int i = 1 + tid; i < m; i += TRI_THREADS) {
+            const double x = Tl[ptri(1 + i, 0)];
+            part = fma(x, x, part);
+        }
+        xn2 = wg_sum<TRI_THREADS>(part, red);
+    }
     for (int kk = b0; kk + 2 < c; ++kk) {
         const int o = kk - b0;      // local index of the column being eliminated
         const int m = c - kk - 1;
-        double part = 0.0;
-        for (int i = 1 + tid; i < m; i += TRI_THREADS) {
-            const double x = Tl[ptri(o + 1 + i, o)];
-            part = fma(x, x, part);
-        }
-        const double xn2 = wg_sum<TRI_THREADS>(part, red);
         const double alpha = Tl[ptri(o + 1, o)];
         double tau = 0.0, beta = alpha, scale = 0.0;
         if (xn2 > 0.0) {
@@ -572,39 +645,101 @@ __global__ void __launch_bounds__(TRI_THREADS) sym_tridiag(int c, double* __rest
             vsh[i] = v;
             V[(int64_t)kk * c + kk + 1 + i] = v;
         }
-        __syncthreads();
         if (tid == 0) {
             taus[kk] = tau;
             dg[kk] = Tl[ptri(o, o)];
             eg[kk] = beta;
         }
+        __syncthreads();
+        const int q0 = o + 1;
         if (tau != 0.0) {
-            // p_i = tau sum_l A22(i, l) v_l: row i up to the diagonal, then column i below it
-            const int q0 = o + 1;
-            for (int i = wave; i < m; i += NW) {
-                const int gi = q0 + i, rbase = ptri(gi, q0);
-                double sr = 0.0;
-                for (int l = lane; l < m; l += 64) {
-                    const double aval = l <= i ? Tl[rbase + l] : Tl[ptri(q0 + l, gi)];
-                    sr = fma(aval, vsh[l], sr);
+            // p_i = tau sum_l A22(i, l) v_l: row i up to the diagonal, then column i below
+            // it; each wave also sums p_i v_i over its rows
+            double pv = 0.0, vl[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int l = lane + 64 * u;
+                vl[u] = l < m ? vsh[l] : 0.0;
+            }
+            for (int i0 = wave; i0 < m; i0 += 2 * NW) {
+                double sr[2] = {0.0, 0.0};
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int i = i0 + r * NW, gi = q0 + i, rbase = ptri(gi, q0);
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) {
+                        const int l = lane + 64 * u;
+                        const double aval = (i < m && l < m) ? (l <= i ? Tl[rbase + l] : Tl[ptri(q0 + l, gi)]) : 0.0;
+                        sr[r] = fma(aval, vl[u], sr[r]);
+                    }
                 }
-                sr = wave_sum_d(sr);
-                if (lane == 0) wsh[i] = tau * sr;
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int i = i0 + r * NW;
+                    if (i >= m) break;   // uniform
+                    const double p = tau * wave_sum_d(sr[r]);
+                    if (lane == 0) wsh[i] = p;
+                    pv = fma(p, vsh[i], pv);
+                }
             }
+            if (lane == 0) red[wave] = pv;
             __syncthreads();
-            double pp = 0.0;
-            for (int i = tid; i < m; i += TRI_THREADS) pp = fma(wsh[i], vsh[i], pp);
-            const double K = 0.5 * tau * wg_sum<TRI_THREADS>(pp, red);
-            for (int i = tid; i < m; i += TRI_THREADS) wsh[i] -= K * vsh[i];
-            __syncthreads();
-            // lower triangle of A22 -= v w^T + w v^T
-            for (int i = wave; i < m; i += NW) {
-                double* row = Tl + ptri(q0 + i, q0);
-                const double vi = vsh[i], wi = wsh[i];
-                for (int l = lane; l <= i; l += 64) row[l] -= vi * wsh[l] + wi * vsh[l];
+            double ps = 0.0;
+            for (int w = 0; w < NW; ++w) ps += red[w];
+            const double K = 0.5 * tau * ps;
+            // lower triangle of A22 -= v w^T + w v^T with w = p - K v; two rows per pass,
+            // every load of a pass issued before its stores (rows do not overlap, which
+            // the compiler cannot see)
+            double nrm = 0.0;
+            for (int i0 = wave; i0 < m; i0 += 2 * NW) {
+                double x[2][3], vl[3], wl[3];
+#pragma unroll
+                for (int u = 0; u < 3; ++u) {
+                    const int l = lane + 64 * u;
+                    vl[u] = l < m ? vsh[l] : 0.0;
+                    wl[u] = l < m ? fma(-K, vl[u], wsh[l]) : 0.0;
+                }
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int i = i0 + r * NW;
+                    const double* row = Tl + ptri(q0 + i, q0);
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) {
+                        const int l = lane + 64 * u;
+                        x[r][u] = (i < m && l <= i) ? row[l] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int i = i0 + r * NW;
+                    if (i >= m) break;   // uniform
+                    double* row = Tl + ptri(q0 + i, q0);
+                    const double vi = vsh[i], wi = fma(-K, vi, wsh[i]);
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) {
+                        const int l = lane + 64 * u;
+                        if (l <= i) {
+                            const double y = x[r][u] - (vi * wl[u] + wi * vl[u]);
+                            row[l] = y;
+                            if (l == 0 && i >= 2) nrm = fma(y, y, nrm);
+                        }
+                    }
+                }
             }
+            if (lane == 0) red2[wave] = nrm;
+        } else {
+            // A22 unchanged: the next column's norm directly
+            double nrm = 0.0;
+            for (int i = 2 + wave; i < m; i += NW)
+                if (lane == 0) {
+                    const double x = Tl[ptri(q0 + i, q0)];
+                    nrm = fma(x, x, nrm);
+                }
+            if (lane == 0) red2[wave] = nrm;
         }
         __syncthreads();
+        xn2 = 0.0;
+        for (int w = 0; w < NW; ++w) xn2 += red2[w];
     }
     if (tid == 0) {
         if (c >= 2) {
