@@ -249,18 +249,22 @@ __device__ __forceinline__ double quad_sum(double x) {
     return x;
 }
 
-// Reflector j from (slot[j][j], tile column j held by this quad): the tile part
-// overwrites a[], goes to vbuf; tau to tau_sh and taus_lds[j].
+// Reflector j from (slot[j][j], tile column j held by this quad).  The column goes to
+// vbuf unscaled, first, so that its LDS writes overlap the norm and the scalars; the
+// scale sc (v = sc x) and tau follow in ts[0..1], tau also in taus_lds[j].  The
+// scaled tile part v overwrites a[] (for the panel store).
 template <typename SlotT>
 __device__ __forceinline__ void q_make_reflector(SlotT* slot, double (&a)[RPL], int c, int j, int g, double* vbuf,
-                                                 double* tau_sh, double* taus_lds) {
+                                                 double* ts, double* taus_lds) {
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) vbuf[i * LPC + g] = a[i];
     double p4[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < RPL; ++i) p4[i & 3] = fma(a[i], a[i], p4[i & 3]);
     const double xn2 = quad_sum((p4[0] + p4[1]) + (p4[2] + p4[3]));
     const int dj = tri_index(j, j, c);
     const double rjj = (double)slot[dj];
-    double tau = 0.0;
+    double tau = 0.0, sc = 0.0;
     if (xn2 > 0.0) {
         // beta = -sign(rjj) |(rjj, x)|, tau = (beta - rjj) / beta, v = x / (rjj - beta);
         // |beta| and |rjj - beta| are >= sqrt(xn2) >= 2^-537, so both reciprocals are of
@@ -269,36 +273,37 @@ __device__ __forceinline__ void q_make_reflector(SlotT* slot, double (&a)[RPL], 
         const double beta = -copysign(t * rsqrt_nr(t), rjj);
         const double u = rjj - beta;
         tau = -u * rcp_nr(beta);
-        const double sc = rcp_nr(u);
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) a[i] *= sc;
+        sc = rcp_nr(u);
         if (g == 0) slot[dj] = (SlotT)beta;
     }
-#pragma unroll
-    for (int i = 0; i < RPL; ++i) vbuf[i * LPC + g] = a[i];
     if (g == 0) {
-        *tau_sh = tau;
+        ts[0] = tau;
+        ts[1] = sc;
         taus_lds[j] = tau;
     }
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) a[i] *= sc;   // zero stays zero when xn2 = 0
 }
 
+// Reflector j (v = sc x, x the unscaled tile part in LDS) applied to column col.
 template <typename SlotT>
 __device__ __forceinline__ void q_reflect_column(SlotT* slot, double (&a)[RPL], int c, int j, int col, int g,
-                                                 const double* v, double tau) {
+                                                 const double* x, double tau, double sc) {
     double p4[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) p4[i & 3] = fma(v[i * LPC + g], a[i], p4[i & 3]);
-    const double s = quad_sum((p4[0] + p4[1]) + (p4[2] + p4[3]));
+    for (int i = 0; i < RPL; ++i) p4[i & 3] = fma(x[i * LPC + g], a[i], p4[i & 3]);
+    const double s = sc * quad_sum((p4[0] + p4[1]) + (p4[2] + p4[3]));
     const int idx = tri_index(j, col, c);
     const double r = (double)slot[idx];
     const double w = (r + s) * tau;
     if (g == 0) slot[idx] = (SlotT)(r - w);
+    const double ws = w * sc;
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) a[i] = fma(-w, v[i * LPC + g], a[i]);
+    for (int i = 0; i < RPL; ++i) a[i] = fma(-ws, x[i * LPC + g], a[i]);
 }
 
-// LDS of the quad fold: vbuf[2][QT] | tau_sh[2] | taus_lds[256] | slot
-constexpr int QF_HEAD = 2 * QT + 2 + 256;
+// LDS of the quad fold: vbuf[2][QT] | (tau, sc)[2] | taus_lds[256] | slot
+constexpr int QF_HEAD = 2 * QT + 4 + 256;
 
 template <typename SlotT>
 size_t qf_lds_bytes(int c) {
@@ -310,14 +315,15 @@ size_t qf_lds_bytes(int c) {
 template <typename SlotT>
 __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int j0, int col, int g, double* vbuf,
                                        double* tau_sh, double* taus_lds) {
-    if (col == j0 && j0 < c) q_make_reflector(slot, a, c, j0, g, vbuf + (j0 & 1) * QT, tau_sh + (j0 & 1), taus_lds);
+    if (col == j0 && j0 < c)
+        q_make_reflector(slot, a, c, j0, g, vbuf + (j0 & 1) * QT, tau_sh + 2 * (j0 & 1), taus_lds);
     __syncthreads();
     for (int j = j0; j < c; ++j) {
         const int buf = j & 1;
-        const double tau = tau_sh[buf];
-        if (col > j && col < c && tau != 0.0) q_reflect_column(slot, a, c, j, col, g, vbuf + buf * QT, tau);
+        const double tau = tau_sh[2 * buf], sc = tau_sh[2 * buf + 1];
+        if (col > j && col < c && tau != 0.0) q_reflect_column(slot, a, c, j, col, g, vbuf + buf * QT, tau, sc);
         if (col == j + 1 && j + 1 < c)
-            q_make_reflector(slot, a, c, j + 1, g, vbuf + (buf ^ 1) * QT, tau_sh + (buf ^ 1), taus_lds);
+            q_make_reflector(slot, a, c, j + 1, g, vbuf + (buf ^ 1) * QT, tau_sh + 2 * (buf ^ 1), taus_lds);
         __syncthreads();
     }
 }
@@ -365,7 +371,7 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
     extern __shared__ double lds[];
     double* vbuf = lds;
     double* tau_sh = vbuf + 2 * QT;
-    double* taus_lds = tau_sh + 2;
+    double* taus_lds = tau_sh + 4;
     SlotT* slot = (SlotT*)(lds + QF_HEAD);
     constexpr int PS = Layout<QT>::PS;
     const int ch = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
@@ -399,7 +405,7 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
     extern __shared__ double lds[];
     double* vbuf = lds;
     double* tau_sh = vbuf + 2 * QT;
-    double* taus_lds = tau_sh + 2;
+    double* taus_lds = tau_sh + 4;
     SlotT* slot = (SlotT*)(lds + QF_HEAD);
     constexpr int PS = Layout<QT>::PS;
     const int i = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC, wave = threadIdx.x >> 6;
