@@ -235,6 +235,14 @@ constexpr int QT = 64;                 // tile rows (matches the blocked pass's 
 constexpr int LPC = 4;                 // lanes per column
 constexpr int RPL = QT / LPC;          // rows per lane: row t = i * LPC + g
 
+// An LDS read issued where it is written: the compiler otherwise moves such reads
+// down to their first use, which puts their latency on the reflector chain.
+template <typename T>
+__device__ __forceinline__ double lds_early(const T* p) {
+    typedef __attribute__((address_space(3))) const volatile T lds_t;
+    return (double)*(lds_t*)p;
+}
+
 template <int CTRL>
 __device__ __forceinline__ double quad_perm(double x) {
     const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
@@ -251,28 +259,31 @@ __device__ __forceinline__ double quad_sum(double x) {
 
 // Reflector j from (slot[j][j], tile column j held by this quad).  The column goes to
 // vbuf unscaled, first, so that its LDS writes overlap the norm and the scalars; the
-// scale sc (v = sc x) and tau follow in ts[0..1], tau also in taus_lds[j].  The
-// scaled tile part v overwrites a[] (for the panel store).
+// scale sc (v = sc x) and tau follow in ts[0..1], tau also in taus_lds[j].  Returns
+// sc: a[] keeps x, and the fold scales it to v once the tile is done (the column
+// takes no further reflector).
 template <typename SlotT>
-__device__ __forceinline__ void q_make_reflector(SlotT* slot, double (&a)[RPL], int c, int j, int g, double* vbuf,
-                                                 double* ts, double* taus_lds) {
+__device__ __forceinline__ double q_make_reflector(SlotT* slot, const double (&a)[RPL], int c, int j, int g,
+                                                   double* vbuf, double* ts, double* taus_lds) {
+    const int dj = tri_index(j, j, c);
+    const double rjj = lds_early(slot + dj);
 #pragma unroll
     for (int i = 0; i < RPL; ++i) vbuf[i * LPC + g] = a[i];
     double p4[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < RPL; ++i) p4[i & 3] = fma(a[i], a[i], p4[i & 3]);
     const double xn2 = quad_sum((p4[0] + p4[1]) + (p4[2] + p4[3]));
-    const int dj = tri_index(j, j, c);
-    const double rjj = (double)slot[dj];
     double tau = 0.0, sc = 0.0;
     if (xn2 > 0.0) {
-        // beta = -sign(rjj) |(rjj, x)|, tau = (beta - rjj) / beta, v = x / (rjj - beta);
-        // |beta| and |rjj - beta| are >= sqrt(xn2) >= 2^-537, so both reciprocals are of
-        // normal numbers (their product need not be)
+        // beta = -sign(rjj) |(rjj, x)|, tau = (beta - rjj) / beta = (|rjj| + |beta|) / |beta|,
+        // v = x / (rjj - beta).  1 / |beta| is the reciprocal square root already formed;
+        // |rjj - beta| = |rjj| + |beta| >= sqrt(xn2) >= 2^-537, so its reciprocal is of a
+        // normal number
         const double t = fma(rjj, rjj, xn2);
-        const double beta = -copysign(t * rsqrt_nr(t), rjj);
+        const double y = rsqrt_nr(t);
+        const double beta = -copysign(t * y, rjj);
         const double u = rjj - beta;
-        tau = -u * rcp_nr(beta);
+        tau = fabs(u) * y;
         sc = rcp_nr(u);
         if (g == 0) slot[dj] = (SlotT)beta;
     }
@@ -281,20 +292,19 @@ __device__ __forceinline__ void q_make_reflector(SlotT* slot, double (&a)[RPL], 
         ts[1] = sc;
         taus_lds[j] = tau;
     }
-#pragma unroll
-    for (int i = 0; i < RPL; ++i) a[i] *= sc;   // zero stays zero when xn2 = 0
+    return sc;
 }
 
 // Reflector j (v = sc x, x the unscaled tile part in LDS) applied to column col.
 template <typename SlotT>
 __device__ __forceinline__ void q_reflect_column(SlotT* slot, double (&a)[RPL], int c, int j, int col, int g,
                                                  const double* x, double tau, double sc) {
+    const int idx = tri_index(j, col, c);
+    const double r = lds_early(slot + idx);
     double p4[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < RPL; ++i) p4[i & 3] = fma(x[i * LPC + g], a[i], p4[i & 3]);
     const double s = sc * quad_sum((p4[0] + p4[1]) + (p4[2] + p4[3]));
-    const int idx = tri_index(j, col, c);
-    const double r = (double)slot[idx];
     const double w = (r + s) * tau;
     if (g == 0) slot[idx] = (SlotT)(r - w);
     const double ws = w * sc;
@@ -315,17 +325,22 @@ size_t qf_lds_bytes(int c) {
 template <typename SlotT>
 __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int j0, int col, int g, double* vbuf,
                                        double* tau_sh, double* taus_lds) {
+    double sc_own = 0.0;   // the scale of this quad's reflector (columns j0 .. c-1)
     if (col == j0 && j0 < c)
-        q_make_reflector(slot, a, c, j0, g, vbuf + (j0 & 1) * QT, tau_sh + 2 * (j0 & 1), taus_lds);
+        sc_own = q_make_reflector(slot, a, c, j0, g, vbuf + (j0 & 1) * QT, tau_sh + 2 * (j0 & 1), taus_lds);
     __syncthreads();
     for (int j = j0; j < c; ++j) {
         const int buf = j & 1;
-        const double tau = tau_sh[2 * buf], sc = tau_sh[2 * buf + 1];
-        if (col > j && col < c && tau != 0.0) q_reflect_column(slot, a, c, j, col, g, vbuf + buf * QT, tau, sc);
+        const double tau = lds_early(tau_sh + 2 * buf), sc = lds_early(tau_sh + 2 * buf + 1);
+        // tau = 0 (a zero column) leaves the column and the slot as they are
+        if (col > j && col < c) q_reflect_column(slot, a, c, j, col, g, vbuf + buf * QT, tau, sc);
         if (col == j + 1 && j + 1 < c)
-            q_make_reflector(slot, a, c, j + 1, g, vbuf + (buf ^ 1) * QT, tau_sh + 2 * (buf ^ 1), taus_lds);
+            sc_own = q_make_reflector(slot, a, c, j + 1, g, vbuf + (buf ^ 1) * QT, tau_sh + 2 * (buf ^ 1), taus_lds);
         __syncthreads();
     }
+    // x -> v (zero stays zero for a zero column, sc = 0; columns left of j0 are zero)
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) a[i] *= sc_own;
 }
 
 // After a fold, this wave's reflectors (its 16 columns = one panel) go to dst in the
