@@ -89,13 +89,18 @@ __global__ void __launch_bounds__(DC_THREADS) dc_merge(int c, int h, const doubl
         zv[t] = r2 * (t < ha ? Qin[(int64_t)(s + t) * c + s + ha - 1] : Qin[(int64_t)(s + t) * c + s + ha]);
     }
     __syncthreads();
-    // sort by rank (ties by index)
+    // sort by rank (ties by index).  The order is total even for NaN (after every
+    // number, among themselves by index), so the ranks are a permutation and every
+    // pcol entry is written: a non-finite input gives wrong values, never an index
+    // out of range.
     for (int t = tid; t < n; t += DC_THREADS) {
         const double dt = Dv[t];
+        const bool nt = isnan(dt);
         int rk = 0;
         for (int u = 0; u < n; ++u) {
             const double du = Dv[u];
-            rk += (du < dt || (du == dt && u < t)) ? 1 : 0;
+            const bool before = isnan(du) ? (nt && u < t) : (nt || du < dt || (du == dt && u < t));
+            rk += before ? 1 : 0;
         }
         ds[rk] = dt;
         zs[rk] = zv[t];

@@ -308,32 +308,75 @@ __device__ __forceinline__ void q_reflect_column(SlotT* slot, double (&a)[RPL], 
     for (int i = 0; i < RPL; ++i) a[i] = fma(-ws, x[i * LPC + g], a[i]);
 }
 
-// LDS of the quad fold: vbuf[2][QT] | (tau, sc)[2] | taus_lds[256] | slot
-constexpr int QF_HEAD = 2 * QT + 4 + 256;
+// LDS of the quad fold: x ring[PW][QT] (a group's unscaled reflectors) |
+// (tau, sc)[PW] | taus_lds[256] | ready counter | slot
+constexpr int QF_TS = PW * QT;
+constexpr int QF_TAUS = QF_TS + 2 * PW;
+constexpr int QF_READY = QF_TAUS + 256;
+constexpr int QF_HEAD = QF_READY + 2;
 
 template <typename SlotT>
 size_t qf_lds_bytes(int c) {
     return (size_t)QF_HEAD * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
 }
 
+// Publication of reflectors inside a workgroup: `ready` counts the reflectors
+// published since the kernel began (wrapping; compared by difference).  The release
+// store orders the reflector's LDS writes before the count, the acquire load orders
+// the count before the reader's loads of the reflector.
+typedef __attribute__((address_space(3))) unsigned lds_u32;
+
+__device__ __forceinline__ void q_publish(unsigned* ready, unsigned count) {
+    __hip_atomic_store((lds_u32*)ready, count, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void q_wait(unsigned* ready, unsigned count) {
+    while ((int)(__hip_atomic_load((lds_u32*)ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) - count) < 0)
+        __builtin_amdgcn_s_sleep(1);
+}
+
 // Fold the tile held in a[] (this quad's column) into the slot with reflectors
-// j0 .. c-1 (the tile's columns below j0 are zero): one barrier per reflector.
+// j0 .. c-1 (the tile's columns below j0 are zero; j0 is a multiple of PW).
+// Reflectors come in groups of PW: group k (reflectors PW k .. PW k + PW - 1) is
+// built by wave k, which owns those columns, one reflector after the other, each
+// applied to the wave's later columns at once (a wave's LDS operations complete in
+// order, so its own writes need no synchronisation).  Every reflector is published
+// as soon as it is written, and the waves to the right apply it then: the chain of
+// reflectors waits for nobody inside a group.  One barrier per group: after it every
+// wave has applied the group, so the next group may reuse the ring, and the next
+// wave has all it needs.  Each wait is for a reflector that the group's own wave
+// publishes before that barrier, so every wait ends.  `published` counts this
+// workgroup's publications so far (the same in every thread).
 template <typename SlotT>
-__device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int j0, int col, int g, double* vbuf,
-                                       double* tau_sh, double* taus_lds) {
-    double sc_own = 0.0;   // the scale of this quad's reflector (columns j0 .. c-1)
-    if (col == j0 && j0 < c)
-        sc_own = q_make_reflector(slot, a, c, j0, g, vbuf + (j0 & 1) * QT, tau_sh + 2 * (j0 & 1), taus_lds);
-    __syncthreads();
-    for (int j = j0; j < c; ++j) {
-        const int buf = j & 1;
-        const double tau = lds_early(tau_sh + 2 * buf), sc = lds_early(tau_sh + 2 * buf + 1);
-        // tau = 0 (a zero column) leaves the column and the slot as they are
-        if (col > j && col < c) q_reflect_column(slot, a, c, j, col, g, vbuf + buf * QT, tau, sc, tau * sc);
-        if (col == j + 1 && j + 1 < c)
-            sc_own = q_make_reflector(slot, a, c, j + 1, g, vbuf + (buf ^ 1) * QT, tau_sh + 2 * (buf ^ 1), taus_lds);
+__device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int j0, int col, int g, double* xring,
+                                       double* tsring, double* taus_lds, unsigned* ready, unsigned& published) {
+    const int wave = threadIdx.x >> 6;   // = col / PW
+    const int np = (c + PW - 1) / PW;
+    double sc_own = 0.0;                 // the scale of this quad's reflector (columns j0 .. c-1)
+    for (int k = j0 / PW; k < np; ++k) {
+        const int jb = k * PW, je = min(jb + PW, c);
+        if (wave == k) {
+            for (int j = jb; j < je; ++j) {
+                const int sl = j - jb;
+                if (col == j) {
+                    sc_own = q_make_reflector(slot, a, c, j, g, xring + sl * QT, tsring + 2 * sl, taus_lds);
+                    if (g == 0) q_publish(ready, published + (unsigned)(j - j0 + 1));
+                }
+                const double tau = lds_early(tsring + 2 * sl), sc = lds_early(tsring + 2 * sl + 1);
+                // tau = 0 (a zero column) leaves the column and the slot as they are
+                if (col > j && col < c) q_reflect_column(slot, a, c, j, col, g, xring + sl * QT, tau, sc, tau * sc);
+            }
+        } else if (wave > k) {
+            for (int j = jb; j < je; ++j) {
+                const int sl = j - jb;
+                q_wait(ready, published + (unsigned)(j - j0 + 1));
+                const double tau = lds_early(tsring + 2 * sl), sc = lds_early(tsring + 2 * sl + 1);
+                if (col < c) q_reflect_column(slot, a, c, j, col, g, xring + sl * QT, tau, sc, tau * sc);
+            }
+        }
         __syncthreads();
     }
+    published += (unsigned)(c - j0);
     // x -> v (zero stays zero for a zero column, sc = 0; columns left of j0 are zero)
 #pragma unroll
     for (int i = 0; i < RPL; ++i) a[i] *= sc_own;
@@ -380,10 +423,13 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
                                                        const TE* __restrict__ E, double* __restrict__ refl,
                                                        double* __restrict__ Rs) {
     extern __shared__ double lds[];
-    double* vbuf = lds;
-    double* tau_sh = vbuf + 2 * QT;
-    double* taus_lds = tau_sh + 4;
+    double* xring = lds;
+    double* tsring = lds + QF_TS;
+    double* taus_lds = lds + QF_TAUS;
+    unsigned* ready = (unsigned*)(lds + QF_READY);
     SlotT* slot = (SlotT*)(lds + QF_HEAD);
+    unsigned published = 0;
+    if (threadIdx.x == 0) *ready = 0;   // the slot set-up's barrier follows
     constexpr int PS = Layout<QT>::PS;
     const int ch = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
     const int np = (c + PW - 1) / PW;
@@ -393,13 +439,17 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
     slot_zero(slot, c);
     for (int tile = 0; r_begin + (int64_t)tile * QT < r_end; ++tile) {
         const int64_t r0 = r_begin + (int64_t)tile * QT;
+        // every load is issued (clamped to an element of E), and masked after it: a
+        // conditional load would wait for each one in turn
         double a[RPL];
+        const int colc = min(col, c - 1);
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const int64_t r = r0 + i * LPC + g;
-            a[i] = (col < c && r < r_end) ? to_f64(E[(int64_t)col * n + r]) : 0.0;
+            const double v = to_f64(E[(int64_t)colc * n + min(r, r_end - 1)]);
+            a[i] = (col < c && r < r_end) ? v : 0.0;
         }
-        q_fold(slot, a, c, 0, col, g, vbuf, tau_sh, taus_lds);
+        q_fold(slot, a, c, 0, col, g, xring, tsring, taus_lds, ready, published);
         const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
         q_store_panel(a, c, col, g, taus_lds, refl + (gtile * np + (threadIdx.x >> 6)) * PS);
     }
@@ -414,10 +464,13 @@ template <typename SlotT>
 __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_t comb_off, double* __restrict__ Rs,
                                                        double* __restrict__ tree) {
     extern __shared__ double lds[];
-    double* vbuf = lds;
-    double* tau_sh = vbuf + 2 * QT;
-    double* taus_lds = tau_sh + 4;
+    double* xring = lds;
+    double* tsring = lds + QF_TS;
+    double* taus_lds = lds + QF_TAUS;
+    unsigned* ready = (unsigned*)(lds + QF_READY);
     SlotT* slot = (SlotT*)(lds + QF_HEAD);
+    unsigned published = 0;
+    if (threadIdx.x == 0) *ready = 0;   // the slot set-up's barrier follows
     constexpr int PS = Layout<QT>::PS;
     const int i = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC, wave = threadIdx.x >> 6;
     const int np = (c + PW - 1) / PW, ntt = (c + QT - 1) / QT;
@@ -426,12 +479,14 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
     slot_load(slot, Rs + (int64_t)a_idx * c * c, c);
     for (int t = 0; t < ntt; ++t) {
         double a[RPL];
+        const int colc = min(col, c - 1);
 #pragma unroll
         for (int q = 0; q < RPL; ++q) {
             const int row = t * QT + q * LPC + g;
-            a[q] = (col < c && row < c && col >= row) ? Rb[(int64_t)row * c + col] : 0.0;
+            const double v = Rb[(int64_t)min(row, c - 1) * c + colc];   // clamped, masked below
+            a[q] = (col < c && row < c && col >= row) ? v : 0.0;
         }
-        q_fold(slot, a, c, t * QT, col, g, vbuf, tau_sh, taus_lds);
+        q_fold(slot, a, c, t * QT, col, g, xring, tsring, taus_lds, ready, published);
         if (wave >= (t * QT) / PW) q_store_panel(a, c, col, g, taus_lds, tree + (((comb_off + i) * ntt + t) * np + wave) * PS);
     }
     slot_store(slot, Rs + (int64_t)a_idx * c * c, c);

@@ -157,6 +157,25 @@ def test_rsvd_zero_pairs_and_errors():
     H.close()
 
 
+def test_rsvd_nonfinite_is_reported():
+    # A pair that passes the curvature check but makes E = (B_k - B_0) X overflow
+    # float32: with y = a s, B_1 - B_0 = (1/a - 1) s s^T / |s|^2, about 1e42 P here.
+    # The deferred status reports it; every kernel on the way (the eigensolver's
+    # sorts included) keeps its indices in range on the non-finite values.
+    P = lib()
+    n = 600
+    g = torch.Generator().manual_seed(4)
+    s = torch.randn(n, generator=g, dtype=torch.float64) * 1e21
+    y = s * 1e-42
+    H = P.Bfgs(n, 2, torch.ones(n, device="cuda"), "f32")
+    H.push_pair(s.float().cuda(), y.float().cuda())
+    assert H.get_status() == 0
+    H.rsvd(1, 8, 3)
+    torch.cuda.synchronize()
+    assert H.get_status() != 0
+    H.close()
+
+
 def test_rsvd_deterministic():
     prob, S, Y, h0 = make_pairs("cg", 30, 20, 25, seed=5, precond=True)
     H = build_handle("bf16", S, Y, h0)
