@@ -308,75 +308,99 @@ __device__ __forceinline__ void q_reflect_column(SlotT* slot, double (&a)[RPL], 
     for (int i = 0; i < RPL; ++i) a[i] = fma(-ws, x[i * LPC + g], a[i]);
 }
 
-// LDS of the quad fold: x ring[PW][QT] (a group's unscaled reflectors) |
-// (tau, sc)[PW] | taus_lds[256] | ready counter | slot
-constexpr int QF_TS = PW * QT;
-constexpr int QF_TAUS = QF_TS + 2 * PW;
-constexpr int QF_READY = QF_TAUS + 256;
-constexpr int QF_HEAD = QF_READY + 2;
+// LDS of the quad fold: x ring[2][PW][QT] (two groups' unscaled reflectors) |
+// (tau, sc)[2][PW] | taus_lds[256] | counters ready[2], done[2] | slot
+constexpr int QF_TS = 2 * PW * QT;
+constexpr int QF_TAUS = QF_TS + 4 * PW;
+constexpr int QF_CNT = QF_TAUS + 256;
+constexpr int QF_HEAD = QF_CNT + 2;
 
 template <typename SlotT>
 size_t qf_lds_bytes(int c) {
     return (size_t)QF_HEAD * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
 }
 
-// Publication of reflectors inside a workgroup: `ready` counts the reflectors
-// published since the kernel began (wrapping; compared by difference).  The release
-// store orders the reflector's LDS writes before the count, the acquire load orders
-// the count before the reader's loads of the reflector.
+// Counters in LDS shared by the waves of a workgroup (wrapping, compared by
+// difference).  The release operations order a wave's LDS accesses before the
+// count, the acquire loads order the count before the waiter's accesses.
 typedef __attribute__((address_space(3))) unsigned lds_u32;
 
-__device__ __forceinline__ void q_publish(unsigned* ready, unsigned count) {
-    __hip_atomic_store((lds_u32*)ready, count, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+__device__ __forceinline__ void q_publish(unsigned* cnt, unsigned value) {
+    __hip_atomic_store((lds_u32*)cnt, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ void q_wait(unsigned* ready, unsigned count) {
-    while ((int)(__hip_atomic_load((lds_u32*)ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) - count) < 0)
+__device__ __forceinline__ void q_arrive(unsigned* cnt) {
+    __hip_atomic_fetch_add((lds_u32*)cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void q_wait(unsigned* cnt, unsigned value) {
+    while ((int)(__hip_atomic_load((lds_u32*)cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) - value) < 0)
         __builtin_amdgcn_s_sleep(1);
 }
+
+// Progress of a workgroup's folds, the same in every thread: groups started, and per
+// ring half the arrivals owed by its groups so far.
+struct QfSeq {
+    unsigned groups = 0;
+    unsigned owed0 = 0, owed1 = 0;   // ring halves 0 and 1
+};
 
 // Fold the tile held in a[] (this quad's column) into the slot with reflectors
 // j0 .. c-1 (the tile's columns below j0 are zero; j0 is a multiple of PW).
 // Reflectors come in groups of PW: group k (reflectors PW k .. PW k + PW - 1) is
 // built by wave k, which owns those columns, one reflector after the other, each
 // applied to the wave's later columns at once (a wave's LDS operations complete in
-// order, so its own writes need no synchronisation).  Every reflector is published
-// as soon as it is written, and the waves to the right apply it then: the chain of
-// reflectors waits for nobody inside a group.  One barrier per group: after it every
-// wave has applied the group, so the next group may reuse the ring, and the next
-// wave has all it needs.  Each wait is for a reflector that the group's own wave
-// publishes before that barrier, so every wait ends.  `published` counts this
-// workgroup's publications so far (the same in every thread).
+// order, so its own writes need no synchronisation).  The groups alternate between
+// two ring halves.  Each reflector is published in its half's ready counter (value
+// 256 G + slot + 1 for the workgroup's G-th group) as soon as it is written, and the
+// waves to the right apply it then.  Every wave that used a group (its builder and
+// the waves to its right) arrives at the half's done counter afterwards; the wave
+// that next fills the half first waits for all of them, so one builder at a time
+// writes a half and its ready counter only grows.  No wave shares slot entries with
+// another (an entry belongs to its column's quad), so there is no barrier: each wait
+// is for an event of an earlier group, whose waves wait only for still earlier
+// ones, so every wait ends.
 template <typename SlotT>
 __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int j0, int col, int g, double* xring,
-                                       double* tsring, double* taus_lds, unsigned* ready, unsigned& published) {
+                                       double* tsring, double* taus_lds, unsigned* cnt, QfSeq& sq) {
     const int wave = threadIdx.x >> 6;   // = col / PW
     const int np = (c + PW - 1) / PW;
     double sc_own = 0.0;                 // the scale of this quad's reflector (columns j0 .. c-1)
-    for (int k = j0 / PW; k < np; ++k) {
+    for (int k = j0 / PW; k < np; ++k, ++sq.groups) {
         const int jb = k * PW, je = min(jb + PW, c);
-        if (wave == k) {
-            for (int j = jb; j < je; ++j) {
-                const int sl = j - jb;
-                if (col == j) {
-                    sc_own = q_make_reflector(slot, a, c, j, g, xring + sl * QT, tsring + 2 * sl, taus_lds);
-                    if (g == 0) q_publish(ready, published + (unsigned)(j - j0 + 1));
+        const int half = sq.groups & 1;
+        double* xb = xring + half * PW * QT;
+        double* tb = tsring + half * 2 * PW;
+        unsigned* ready = cnt + half;
+        unsigned* done = cnt + 2 + half;
+        const unsigned tag = sq.groups * 256u + 1u;
+        if (wave >= k) {
+            if (wave == k) {
+                q_wait(done, half ? sq.owed1 : sq.owed0);   // the half's previous group is used up
+                for (int j = jb; j < je; ++j) {
+                    const int sl = j - jb;
+                    if (col == j) {
+                        sc_own = q_make_reflector(slot, a, c, j, g, xb + sl * QT, tb + 2 * sl, taus_lds);
+                        if (g == 0) q_publish(ready, tag + (unsigned)sl);
+                    }
+                    const double tau = lds_early(tb + 2 * sl), sc = lds_early(tb + 2 * sl + 1);
+                    // tau = 0 (a zero column) leaves the column and the slot as they are
+                    if (col > j && col < c) q_reflect_column(slot, a, c, j, col, g, xb + sl * QT, tau, sc, tau * sc);
                 }
-                const double tau = lds_early(tsring + 2 * sl), sc = lds_early(tsring + 2 * sl + 1);
-                // tau = 0 (a zero column) leaves the column and the slot as they are
-                if (col > j && col < c) q_reflect_column(slot, a, c, j, col, g, xring + sl * QT, tau, sc, tau * sc);
+            } else {
+                for (int j = jb; j < je; ++j) {
+                    const int sl = j - jb;
+                    q_wait(ready, tag + (unsigned)sl);
+                    const double tau = lds_early(tb + 2 * sl), sc = lds_early(tb + 2 * sl + 1);
+                    if (col < c) q_reflect_column(slot, a, c, j, col, g, xb + sl * QT, tau, sc, tau * sc);
+                }
             }
-        } else if (wave > k) {
-            for (int j = jb; j < je; ++j) {
-                const int sl = j - jb;
-                q_wait(ready, published + (unsigned)(j - j0 + 1));
-                const double tau = lds_early(tsring + 2 * sl), sc = lds_early(tsring + 2 * sl + 1);
-                if (col < c) q_reflect_column(slot, a, c, j, col, g, xring + sl * QT, tau, sc, tau * sc);
-            }
+            if (threadIdx.x % 64 == 0) q_arrive(done);
         }
-        __syncthreads();
+        const unsigned users = (unsigned)(np - k);   // wave k and the waves to its right
+        if (half) sq.owed1 += users;
+        else sq.owed0 += users;
     }
-    published += (unsigned)(c - j0);
     // x -> v (zero stays zero for a zero column, sc = 0; columns left of j0 are zero)
 #pragma unroll
     for (int i = 0; i < RPL; ++i) a[i] *= sc_own;
@@ -426,10 +450,10 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
     double* xring = lds;
     double* tsring = lds + QF_TS;
     double* taus_lds = lds + QF_TAUS;
-    unsigned* ready = (unsigned*)(lds + QF_READY);
+    unsigned* cnt = (unsigned*)(lds + QF_CNT);
     SlotT* slot = (SlotT*)(lds + QF_HEAD);
-    unsigned published = 0;
-    if (threadIdx.x == 0) *ready = 0;   // the slot set-up's barrier follows
+    QfSeq sq;
+    if (threadIdx.x < 4) cnt[threadIdx.x] = 0;   // the slot set-up's barrier follows
     constexpr int PS = Layout<QT>::PS;
     const int ch = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
     const int np = (c + PW - 1) / PW;
@@ -449,10 +473,11 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
             const double v = to_f64(E[(int64_t)colc * n + min(r, r_end - 1)]);
             a[i] = (col < c && r < r_end) ? v : 0.0;
         }
-        q_fold(slot, a, c, 0, col, g, xring, tsring, taus_lds, ready, published);
+        q_fold(slot, a, c, 0, col, g, xring, tsring, taus_lds, cnt, sq);
         const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
         q_store_panel(a, c, col, g, taus_lds, refl + (gtile * np + (threadIdx.x >> 6)) * PS);
     }
+    __syncthreads();   // the folds have no barrier; slot_store reads every column's entries
     slot_store(slot, Rs + (int64_t)ch * c * c, c);
 }
 
@@ -467,10 +492,10 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
     double* xring = lds;
     double* tsring = lds + QF_TS;
     double* taus_lds = lds + QF_TAUS;
-    unsigned* ready = (unsigned*)(lds + QF_READY);
+    unsigned* cnt = (unsigned*)(lds + QF_CNT);
     SlotT* slot = (SlotT*)(lds + QF_HEAD);
-    unsigned published = 0;
-    if (threadIdx.x == 0) *ready = 0;   // the slot set-up's barrier follows
+    QfSeq sq;
+    if (threadIdx.x < 4) cnt[threadIdx.x] = 0;   // the slot set-up's barrier follows
     constexpr int PS = Layout<QT>::PS;
     const int i = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC, wave = threadIdx.x >> 6;
     const int np = (c + PW - 1) / PW, ntt = (c + QT - 1) / QT;
@@ -486,9 +511,10 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
             const double v = Rb[(int64_t)min(row, c - 1) * c + colc];   // clamped, masked below
             a[q] = (col < c && row < c && col >= row) ? v : 0.0;
         }
-        q_fold(slot, a, c, t * QT, col, g, xring, tsring, taus_lds, ready, published);
+        q_fold(slot, a, c, t * QT, col, g, xring, tsring, taus_lds, cnt, sq);
         if (wave >= (t * QT) / PW) q_store_panel(a, c, col, g, taus_lds, tree + (((comb_off + i) * ntt + t) * np + wave) * PS);
     }
+    __syncthreads();   // the folds have no barrier; slot_store reads every column's entries
     slot_store(slot, Rs + (int64_t)a_idx * c * c, c);
 }
 

@@ -1,0 +1,129 @@
+"""CPU model of the synchronisation inside the TSQR quad fold (tsqr.hip, q_fold).
+
+The fold's waves share two LDS ring halves of reflectors and four counters.
+Group k of 16 reflectors is built by wave k: it waits until its ring half's done
+counter has every arrival owed by the half's earlier groups, then writes and
+publishes each reflector (the half's ready counter takes 256 G + slot + 1 for the
+workgroup's G-th group) and finally arrives at done.  The waves to its right wait
+for each reflector, apply it, and arrive at done after the group.
+
+Here each wave is a generator that follows exactly that control flow, and a
+seeded random scheduler interleaves them.  The model fails on a deadlock, on a
+reflector read from a ring half that has since been refilled by another group,
+and on a ring half refilled while some wave still reads the previous group in it.
+"""
+import random
+
+import pytest
+
+PW = 16
+
+
+def wave_program(w, c, tiles, st):
+    """Wave w's accesses over `tiles` tiles of leaf folds (starts) or tree folds."""
+    np_ = (c + PW - 1) // PW
+    groups = 0
+    owed = [0, 0]
+    for j0 in tiles:
+        for k in range(j0 // PW, np_):
+            jb, je = PW * k, min(PW * k + PW, c)
+            half = groups & 1
+            if w >= k:
+                if w == k:
+                    while st["done"][half] - owed[half] < 0:
+                        yield "wait"
+                    st["users"][groups] = st["users"].get(groups, 0) + 1
+                    for j in range(jb, je):
+                        prev = st["owner"][half]
+                        if prev is not None and prev != groups:
+                            assert st["users"].get(prev, 0) == 0, ("ring half refilled while in use", w, k)
+                        st["owner"][half] = groups
+                        st["ready"][half] = groups * 256 + (j - jb + 1)
+                        yield "step"
+                else:
+                    st["users"][groups] = st["users"].get(groups, 0) + 1
+                    for j in range(jb, je):
+                        while st["ready"][half] - (groups * 256 + (j - jb + 1)) < 0:
+                            yield "wait"
+                        assert st["owner"][half] == groups, ("stale reflector", w, k)
+                        yield "step"
+                st["users"][groups] -= 1
+                st["done"][half] += 1
+            owed[half] += np_ - k
+            groups += 1
+
+
+def run(c, tiles, seed):
+    rnd = random.Random(seed)
+    np_ = (c + PW - 1) // PW
+    st = {"ready": [0, 0], "done": [0, 0], "owner": [None, None], "users": {}}
+    progs = {w: wave_program(w, c, tiles, st) for w in range(np_)}
+    alive = set(progs)
+    idle = 0
+    while alive:
+        w = rnd.choice(sorted(alive))
+        try:
+            r = next(progs[w])
+        except StopIteration:
+            alive.discard(w)
+            continue
+        idle = idle + 1 if r == "wait" else 0
+        if idle > 20000:
+            return False
+    return True
+
+
+@pytest.mark.parametrize("c", [1, 15, 16, 17, 26, 32, 40, 64, 100, 220, 256])
+def test_fold_protocol_leaf_and_tree(c):
+    leaf = [0, 0, 0]                                  # three leaf tiles
+    tree = [64 * t for t in range((c + 63) // 64)]    # one tree combine: tile t starts at 64 t
+    for seed in range(30):
+        assert run(c, leaf, seed), ("deadlock", c, "leaf", seed)
+        assert run(c, tree + tree, seed), ("deadlock", c, "tree", seed)
+
+
+def test_fold_protocol_detects_a_shared_counter():
+    """The model itself catches the earlier design, in which the producers of all
+    groups published into one counter with plain stores: two producers of
+    consecutive groups can then run at once and move the counter back."""
+
+    def shared_counter_program(w, c, tiles, st):
+        np_ = (c + PW - 1) // PW
+        groups = published = 0
+        owed = [0, 0]
+        for j0 in tiles:
+            for k in range(j0 // PW, np_):
+                jb, je = PW * k, min(PW * k + PW, c)
+                half = groups & 1
+                if w == k:
+                    while st["done"][half] - owed[half] < 0:
+                        yield "wait"
+                    for j in range(jb, je):
+                        st["ready"] = published + (j - j0 + 1)
+                        yield "step"
+                elif w > k:
+                    for j in range(jb, je):
+                        while st["ready"] - (published + (j - j0 + 1)) < 0:
+                            yield "wait"
+                        yield "step"
+                    st["done"][half] += 1
+                owed[half] += np_ - 1 - k
+                groups += 1
+            published += c - j0
+
+    found = False
+    for seed in range(40):
+        rnd = random.Random(seed)
+        st = {"ready": 0, "done": [0, 0]}
+        progs = {w: shared_counter_program(w, 26, [0, 0, 0], st) for w in range(2)}
+        alive, idle = set(progs), 0
+        while alive and idle <= 20000:
+            w = rnd.choice(sorted(alive))
+            try:
+                r = next(progs[w])
+            except StopIteration:
+                alive.discard(w)
+                continue
+            idle = idle + 1 if r == "wait" else 0
+        found |= bool(alive)
+    assert found
