@@ -377,6 +377,8 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
         if (wave >= k) {
             if (wave == k) {
                 q_wait(done, half ? sq.owed1 : sq.owed0);   // the half's previous group is used up
+                // the builder carries the chain of reflectors: it goes first on its SIMD
+                __builtin_amdgcn_s_setprio(2);
                 for (int j = jb; j < je; ++j) {
                     const int sl = j - jb;
                     if (col == j) {
@@ -387,6 +389,7 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
                     // tau = 0 (a zero column) leaves the column and the slot as they are
                     if (col > j && col < c) q_reflect_column(slot, a, c, j, col, g, xb + sl * QT, tau, sc, tau * sc);
                 }
+                __builtin_amdgcn_s_setprio(0);
             } else {
                 for (int j = jb; j < je; ++j) {
                     const int sl = j - jb;
@@ -461,17 +464,32 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
     const int64_t r_end = min(n, r_begin + rows_per_chain);
     const int tiles_per_chain = (int)(rows_per_chain / QT);
     slot_zero(slot, c);
+    // Every load of E is issued (clamped to an element of E) and masked after it: a
+    // conditional load would be waited for on its own.  A float32 E has the next
+    // tile's loads in flight during the current fold (16 registers; a float64 E would
+    // not fit in 128 and is loaded at the tile's start).
+    const int colc = min(col, c - 1);
+    constexpr bool prefetch = sizeof(TE) == 4;
+    TE nx[RPL];
+    if (prefetch && r_begin < r_end) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) nx[i] = E[(int64_t)colc * n + min(r_begin + i * LPC + g, r_end - 1)];
+    }
     for (int tile = 0; r_begin + (int64_t)tile * QT < r_end; ++tile) {
         const int64_t r0 = r_begin + (int64_t)tile * QT;
-        // every load is issued (clamped to an element of E), and masked after it: a
-        // conditional load would wait for each one in turn
+        if (!prefetch) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) nx[i] = E[(int64_t)colc * n + min(r0 + i * LPC + g, r_end - 1)];
+        }
         double a[RPL];
-        const int colc = min(col, c - 1);
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const int64_t r = r0 + i * LPC + g;
-            const double v = to_f64(E[(int64_t)colc * n + min(r, r_end - 1)]);
-            a[i] = (col < c && r < r_end) ? v : 0.0;
+            a[i] = (col < c && r < r_end) ? to_f64(nx[i]) : 0.0;
+        }
+        if (prefetch && r0 + QT < r_end) {
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) nx[i] = E[(int64_t)colc * n + min(r0 + QT + i * LPC + g, r_end - 1)];
         }
         q_fold(slot, a, c, 0, col, g, xring, tsring, taus_lds, cnt, sq);
         const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
