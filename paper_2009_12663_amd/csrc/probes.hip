@@ -45,14 +45,20 @@ __device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
 
 __device__ __forceinline__ double unit_open0(uint64_t x) { return (double)((x >> 11) + 1) * 0x1.0p-53; }
 
-// One thread per group of four rows of one column.
 template <typename T>
-__global__ void probes_kernel(int64_t n, int c, uint64_t seed, T* __restrict__ X) {
+struct alignas(4 * sizeof(T)) quad_of {
+    T v[4];
+};
+
+// One thread per group of four rows of one column; column j = blockIdx.y (no
+// division of a flat index).  `vec`: n % 4 == 0 and X is aligned, so every group of
+// four rows is whole and one store writes it.
+template <typename T>
+__global__ void probes_kernel(int64_t n, uint64_t seed, T* __restrict__ X, int vec) {
     const int64_t quads = (n + 3) / 4;
-    const int64_t total = quads * c;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t q = e % quads;
-        const int j = (int)(e / quads);
+    const int j = blockIdx.y;
+    T* col = X + (int64_t)j * n;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < quads; q += (int64_t)gridDim.x * blockDim.x) {
         const u64x4 x = philox4x64_10((uint64_t)q, (uint64_t)j, 0, 0, seed, 0);
         double z[4];
 #pragma unroll
@@ -65,11 +71,17 @@ __global__ void probes_kernel(int64_t n, int c, uint64_t seed, T* __restrict__ X
             z[2 * half] = rad * cs;
             z[2 * half + 1] = rad * sn;
         }
-        T* col = X + (int64_t)j * n;
+        if (vec) {
+            quad_of<T> w;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int64_t r = 4 * q + t;
-            if (r < n) col[r] = from_f64<T>(z[t]);
+            for (int t = 0; t < 4; ++t) w.v[t] = from_f64<T>(z[t]);
+            *(quad_of<T>*)(col + 4 * q) = w;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t r = 4 * q + t;
+                if (r < n) col[r] = from_f64<T>(z[t]);
+            }
         }
     }
 }
@@ -77,17 +89,21 @@ __global__ void probes_kernel(int64_t n, int c, uint64_t seed, T* __restrict__ X
 }  // namespace
 
 int probes_launch(bfgsuq_ctx* h, uint64_t seed, int32_t c, void* X, hipStream_t stream) {
-    const int64_t total = (h->n + 3) / 4 * c;
-    const int grid = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (total + 255) / 256));
+    const int64_t quads = (h->n + 3) / 4;
+    // columns on grid.y; along a column enough workgroups that c of them fill the GPU
+    const int gx = (int)std::min<int64_t>(std::max<int64_t>(1, 16384 / c), (quads + 255) / 256);
+    const dim3 grid(gx, c);
+    const size_t tsz = dtype_size(h->storage);
+    const int vec = h->n % 4 == 0 && (uintptr_t)X % (4 * tsz) == 0;
     switch (h->storage) {
         case BFGS_F64:
-            hipLaunchKernelGGL(probes_kernel<double>, dim3(grid), dim3(256), 0, stream, h->n, c, seed, (double*)X);
+            hipLaunchKernelGGL(probes_kernel<double>, grid, dim3(256), 0, stream, h->n, seed, (double*)X, vec);
             break;
         case BFGS_F32:
-            hipLaunchKernelGGL(probes_kernel<float>, dim3(grid), dim3(256), 0, stream, h->n, c, seed, (float*)X);
+            hipLaunchKernelGGL(probes_kernel<float>, grid, dim3(256), 0, stream, h->n, seed, (float*)X, vec);
             break;
         case BFGS_BF16:
-            hipLaunchKernelGGL(probes_kernel<bf16_t>, dim3(grid), dim3(256), 0, stream, h->n, c, seed, (bf16_t*)X);
+            hipLaunchKernelGGL(probes_kernel<bf16_t>, grid, dim3(256), 0, stream, h->n, seed, (bf16_t*)X, vec);
             break;
     }
     return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;

@@ -218,12 +218,12 @@ __device__ void unfold_tile(SlotT* slot, v4d (&A)[Layout<BT>::RT], int c, int p0
 }
 
 // ---------------------------------------------------------------------------
-// Leaf fold with a quad of lanes per column (one barrier per reflector).  The
-// leaves' critical path is the chain of c reflectors per tile; handing each column
-// to its own quad (16 rows per lane, quad DPP reductions) and building reflector
-// j+1 in the quad of column j+1 right after it applies reflector j keeps that
-// chain shorter than the per-wave panel factorisation.  The reflectors and each
-// panel's T are written in the panel layout of the blocked backward pass.
+// Leaf fold with a quad of lanes per column (16 rows per lane, quad DPP
+// reductions).  The leaves' critical path is the chain of c reflectors per tile:
+// the wave that owns a group of 16 columns builds their reflectors one after the
+// other, and the other waves apply each one as it is published (q_fold).  The
+// reflectors and each panel's T are written in the panel layout of the blocked
+// backward pass.
 // ---------------------------------------------------------------------------
 constexpr int QT = 64;                 // tile rows (matches the blocked pass's BT = 64)
 constexpr int LPC = 4;                 // lanes per column
