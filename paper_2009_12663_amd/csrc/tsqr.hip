@@ -308,16 +308,29 @@ __device__ __forceinline__ void q_reflect_column(SlotT* slot, double (&a)[RPL], 
     for (int i = 0; i < RPL; ++i) a[i] = fma(-ws, x[i * LPC + g], a[i]);
 }
 
-// LDS of the quad fold: x ring[2][PW][QT] (two groups' unscaled reflectors) |
-// (tau, sc)[2][PW] | taus_lds[256] | counters ready[2], done[2] | slot
-constexpr int QF_TS = 2 * PW * QT;
-constexpr int QF_TAUS = QF_TS + 4 * PW;
+// LDS of the quad fold: taus_lds[256] | counters ready[QF_RMAX], done[QF_RMAX] |
+// (tau, sc)[QF_RMAX][PW] | x ring[R][PW][QT] (R groups' unscaled reflectors) | slot.
+// The ring takes what LDS leaves beside the slot, 2 to QF_RMAX groups.
+constexpr int QF_RMAX = 8;
+constexpr int QF_TAUS = 0;
 constexpr int QF_CNT = QF_TAUS + 256;
-constexpr int QF_HEAD = QF_CNT + 2;
+constexpr int QF_TS = QF_CNT + QF_RMAX;             // 2 QF_RMAX unsigned counters
+constexpr int QF_X = QF_TS + 2 * PW * QF_RMAX;
+constexpr size_t QF_LDS_LIMIT = 160 * 1024;
 
 template <typename SlotT>
-size_t qf_lds_bytes(int c) {
-    return (size_t)QF_HEAD * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
+size_t qf_lds_bytes(int c, int ring) {
+    return (size_t)(QF_X + ring * PW * QT) * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
+}
+
+// The deepest ring that fits beside the slot, and no deeper than a tile's groups
+// plus one (LDS left free lets small problems share a CU); 0 if not even 2 fit.
+template <typename SlotT>
+int qf_ring(int c) {
+    const int want = std::min(QF_RMAX, std::max(2, (c + PW - 1) / PW + 1));
+    for (int r = want; r >= 2; --r)
+        if (qf_lds_bytes<SlotT>(c, r) <= QF_LDS_LIMIT) return r;
+    return 0;
 }
 
 // Counters in LDS shared by the waves of a workgroup (wrapping, compared by
@@ -338,11 +351,23 @@ __device__ __forceinline__ void q_wait(unsigned* cnt, unsigned value) {
         __builtin_amdgcn_s_sleep(1);
 }
 
-// Progress of a workgroup's folds, the same in every thread: groups started, and per
-// ring half the arrivals owed by its groups so far.
+// Progress of a workgroup's folds, the same in every thread: groups started, the
+// ring slot of the next one, and per ring slot the arrivals owed by its groups so
+// far (registers: every index below is a constant after unrolling).
 struct QfSeq {
     unsigned groups = 0;
-    unsigned owed0 = 0, owed1 = 0;   // ring halves 0 and 1
+    int slot = 0;
+    unsigned owed[QF_RMAX] = {0, 0, 0, 0, 0, 0, 0, 0};
+    __device__ unsigned owed_at(int r) const {
+        unsigned v = 0;
+#pragma unroll
+        for (int i = 0; i < QF_RMAX; ++i) v = i == r ? owed[i] : v;
+        return v;
+    }
+    __device__ void add_owed(int r, unsigned n) {
+#pragma unroll
+        for (int i = 0; i < QF_RMAX; ++i) owed[i] += i == r ? n : 0u;
+    }
 };
 
 // Fold the tile held in a[] (this quad's column) into the slot with reflectors
@@ -350,33 +375,35 @@ struct QfSeq {
 // Reflectors come in groups of PW: group k (reflectors PW k .. PW k + PW - 1) is
 // built by wave k, which owns those columns, one reflector after the other, each
 // applied to the wave's later columns at once (a wave's LDS operations complete in
-// order, so its own writes need no synchronisation).  The groups alternate between
-// two ring halves.  Each reflector is published in its half's ready counter (value
-// 256 G + slot + 1 for the workgroup's G-th group) as soon as it is written, and the
-// waves to the right apply it then.  Every wave that used a group (its builder and
-// the waves to its right) arrives at the half's done counter afterwards; the wave
-// that next fills the half first waits for all of them, so one builder at a time
-// writes a half and its ready counter only grows.  No wave shares slot entries with
+// order, so its own writes need no synchronisation).  The groups take the `ring`
+// slots of the LDS ring in turn.  Each reflector is published in its slot's ready
+// counter (value 256 G + slot + 1 for the workgroup's G-th group) as soon as it is
+// written, and the waves to the right apply it then.  Every wave that used a group
+// (its builder and the waves to its right) arrives at the slot's done counter
+// afterwards; the wave that next fills the slot first waits for all of them, so one
+// builder at a time writes a slot and its ready counter only grows.  A wave is done
+// with a tile once it has built its own group, and goes on to the next tile: the
+// tiles' chains overlap as far as the ring allows.  No wave shares slot entries with
 // another (an entry belongs to its column's quad), so there is no barrier: each wait
 // is for an event of an earlier group, whose waves wait only for still earlier
 // ones, so every wait ends.
 template <typename SlotT>
 __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int j0, int col, int g, double* xring,
-                                       double* tsring, double* taus_lds, unsigned* cnt, QfSeq& sq) {
+                                       double* tsring, double* taus_lds, unsigned* cnt, int ring, QfSeq& sq) {
     const int wave = threadIdx.x >> 6;   // = col / PW
     const int np = (c + PW - 1) / PW;
     double sc_own = 0.0;                 // the scale of this quad's reflector (columns j0 .. c-1)
-    for (int k = j0 / PW; k < np; ++k, ++sq.groups) {
+    for (int k = j0 / PW; k < np; ++k) {
         const int jb = k * PW, je = min(jb + PW, c);
-        const int half = sq.groups & 1;
-        double* xb = xring + half * PW * QT;
-        double* tb = tsring + half * 2 * PW;
-        unsigned* ready = cnt + half;
-        unsigned* done = cnt + 2 + half;
+        const int r = sq.slot;
+        double* xb = xring + r * PW * QT;
+        double* tb = tsring + r * 2 * PW;
+        unsigned* ready = cnt + r;
+        unsigned* done = cnt + QF_RMAX + r;
         const unsigned tag = sq.groups * 256u + 1u;
         if (wave >= k) {
             if (wave == k) {
-                q_wait(done, half ? sq.owed1 : sq.owed0);   // the half's previous group is used up
+                q_wait(done, sq.owed_at(r));   // the slot's previous group is used up
                 // the builder carries the chain of reflectors: it goes first on its SIMD
                 __builtin_amdgcn_s_setprio(2);
                 for (int j = jb; j < je; ++j) {
@@ -400,9 +427,9 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
             }
             if (threadIdx.x % 64 == 0) q_arrive(done);
         }
-        const unsigned users = (unsigned)(np - k);   // wave k and the waves to its right
-        if (half) sq.owed1 += users;
-        else sq.owed0 += users;
+        sq.add_owed(r, (unsigned)(np - k));   // wave k and the waves to its right
+        ++sq.groups;
+        sq.slot = r + 1 == ring ? 0 : r + 1;
     }
     // x -> v (zero stays zero for a zero column, sc = 0; columns left of j0 are zero)
 #pragma unroll
@@ -448,15 +475,15 @@ __device__ __forceinline__ void q_store_panel(const double (&a)[RPL], int c, int
 template <typename TE, typename SlotT>
 __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t rows_per_chain,
                                                        const TE* __restrict__ E, double* __restrict__ refl,
-                                                       double* __restrict__ Rs) {
+                                                       double* __restrict__ Rs, int ring) {
     extern __shared__ double lds[];
-    double* xring = lds;
+    double* xring = lds + QF_X;
     double* tsring = lds + QF_TS;
     double* taus_lds = lds + QF_TAUS;
     unsigned* cnt = (unsigned*)(lds + QF_CNT);
-    SlotT* slot = (SlotT*)(lds + QF_HEAD);
+    SlotT* slot = (SlotT*)(lds + QF_X + ring * PW * QT);
     QfSeq sq;
-    if (threadIdx.x < 4) cnt[threadIdx.x] = 0;   // the slot set-up's barrier follows
+    if (threadIdx.x < 2 * QF_RMAX) cnt[threadIdx.x] = 0;   // the slot set-up's barrier follows
     constexpr int PS = Layout<QT>::PS;
     const int ch = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
     const int np = (c + PW - 1) / PW;
@@ -491,7 +518,7 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
 #pragma unroll
             for (int i = 0; i < RPL; ++i) nx[i] = E[(int64_t)colc * n + min(r0 + QT + i * LPC + g, r_end - 1)];
         }
-        q_fold(slot, a, c, 0, col, g, xring, tsring, taus_lds, cnt, sq);
+        q_fold(slot, a, c, 0, col, g, xring, tsring, taus_lds, cnt, ring, sq);
         const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
         q_store_panel(a, c, col, g, taus_lds, refl + (gtile * np + (threadIdx.x >> 6)) * PS);
     }
@@ -505,15 +532,15 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
 // tree + ((comb_off + i) * ntt + t) * np * PS + p * PS, as the backward pass reads them.
 template <typename SlotT>
 __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_t comb_off, double* __restrict__ Rs,
-                                                       double* __restrict__ tree) {
+                                                       double* __restrict__ tree, int ring) {
     extern __shared__ double lds[];
-    double* xring = lds;
+    double* xring = lds + QF_X;
     double* tsring = lds + QF_TS;
     double* taus_lds = lds + QF_TAUS;
     unsigned* cnt = (unsigned*)(lds + QF_CNT);
-    SlotT* slot = (SlotT*)(lds + QF_HEAD);
+    SlotT* slot = (SlotT*)(lds + QF_X + ring * PW * QT);
     QfSeq sq;
-    if (threadIdx.x < 4) cnt[threadIdx.x] = 0;   // the slot set-up's barrier follows
+    if (threadIdx.x < 2 * QF_RMAX) cnt[threadIdx.x] = 0;   // the slot set-up's barrier follows
     constexpr int PS = Layout<QT>::PS;
     const int i = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC, wave = threadIdx.x >> 6;
     const int np = (c + PW - 1) / PW, ntt = (c + QT - 1) / QT;
@@ -529,7 +556,7 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
             const double v = Rb[(int64_t)min(row, c - 1) * c + colc];   // clamped, masked below
             a[q] = (col < c && row < c && col >= row) ? v : 0.0;
         }
-        q_fold(slot, a, c, t * QT, col, g, xring, tsring, taus_lds, cnt, sq);
+        q_fold(slot, a, c, t * QT, col, g, xring, tsring, taus_lds, cnt, ring, sq);
         if (wave >= (t * QT) / PW) q_store_panel(a, c, col, g, taus_lds, tree + (((comb_off + i) * ntt + t) * np + wave) * PS);
     }
     __syncthreads();   // the folds have no barrier; slot_store reads every column's entries
@@ -657,16 +684,17 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
             return BFGS_ERR_HIP;
         attr_q = true;
     }
+    const int ring = qf_ring<SlotT>(c);   // >= 2: the slot type was chosen for that
     prof_begin(h, "tsqr_leaf_fwd");
-    hipLaunchKernelGGL((leaf_forward_q<TO, SlotT>), dim3(nchains), dim3(LPC * 16 * np), qf_lds_bytes<SlotT>(c),
-                       h->stream, n, c, rows_per_chain, E, refl, Rs);
+    hipLaunchKernelGGL((leaf_forward_q<TO, SlotT>), dim3(nchains), dim3(LPC * 16 * np), qf_lds_bytes<SlotT>(c, ring),
+                       h->stream, n, c, rows_per_chain, E, refl, Rs, ring);
     prof_end(h);
     prof_begin(h, "tsqr_tree");
     int64_t off = 0;
     for (int stride = 1; stride < nchains; stride *= 2) {
         const int ncomb = nchains / (2 * stride);
-        hipLaunchKernelGGL((tree_forward_q<SlotT>), dim3(ncomb), dim3(threads), qf_lds_bytes<SlotT>(c), h->stream, c,
-                           stride, off, Rs, tree);
+        hipLaunchKernelGGL((tree_forward_q<SlotT>), dim3(ncomb), dim3(threads), qf_lds_bytes<SlotT>(c, ring),
+                           h->stream, c, stride, off, Rs, tree, ring);
         off += ncomb;
     }
     hipLaunchKernelGGL(set_identity_kernel, dim3(64), dim3(256), 0, h->stream, Qtop, c);
@@ -692,7 +720,7 @@ int tsqr_dispatch(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     // within 128 registers per lane (1024-thread workgroups); the slot is float64
     // whenever it fits in LDS (c <= 184) and float32 above that
     const size_t lim = 160 * 1024;
-    const bool dslot = lds_bytes<64, double>(c) <= lim && qf_lds_bytes<double>(c) <= lim;
+    const bool dslot = lds_bytes<64, double>(c) <= lim && qf_ring<double>(c) >= 2;
     // staging doubles per thread for one stored panel (64 * ceil(c / 16) threads); more
     // than 8 (c <= 32) copies panels straight to LDS
     const int pf = ceil_div(Layout<64>::PS, 64 * ceil_div(c, PW));

@@ -1,16 +1,18 @@
 """CPU model of the synchronisation inside the TSQR quad fold (tsqr.hip, q_fold).
 
-The fold's waves share two LDS ring halves of reflectors and four counters.
-Group k of 16 reflectors is built by wave k: it waits until its ring half's done
-counter has every arrival owed by the half's earlier groups, then writes and
-publishes each reflector (the half's ready counter takes 256 G + slot + 1 for the
-workgroup's G-th group) and finally arrives at done.  The waves to its right wait
-for each reflector, apply it, and arrive at done after the group.
+The fold's waves share a ring of R group slots of reflectors in LDS, each with a
+ready and a done counter.  Group k of 16 reflectors is built by wave k: it waits
+until its slot's done counter has every arrival owed by the slot's earlier
+groups, then writes and publishes each reflector (the slot's ready counter takes
+256 G + slot + 1 for the workgroup's G-th group) and finally arrives at done.
+The waves to its right wait for each reflector, apply it, and arrive at done
+after the group.  A wave that has built its group goes on to the next tile, so
+the tiles' chains overlap as far as the ring allows.
 
 Here each wave is a generator that follows exactly that control flow, and a
 seeded random scheduler interleaves them.  The model fails on a deadlock, on a
-reflector read from a ring half that has since been refilled by another group,
-and on a ring half refilled while some wave still reads the previous group in it.
+reflector read from a slot that has since been refilled by another group, and
+on a slot refilled while some wave still reads the previous group in it.
 """
 import random
 
@@ -19,15 +21,15 @@ import pytest
 PW = 16
 
 
-def wave_program(w, c, tiles, st):
+def wave_program(w, c, tiles, st, R):
     """Wave w's accesses over `tiles` tiles of leaf folds (starts) or tree folds."""
     np_ = (c + PW - 1) // PW
     groups = 0
-    owed = [0, 0]
+    owed = [0] * R
     for j0 in tiles:
         for k in range(j0 // PW, np_):
             jb, je = PW * k, min(PW * k + PW, c)
-            half = groups & 1
+            half = groups % R
             if w >= k:
                 if w == k:
                     while st["done"][half] - owed[half] < 0:
@@ -53,11 +55,11 @@ def wave_program(w, c, tiles, st):
             groups += 1
 
 
-def run(c, tiles, seed):
+def run(c, tiles, seed, R=2):
     rnd = random.Random(seed)
     np_ = (c + PW - 1) // PW
-    st = {"ready": [0, 0], "done": [0, 0], "owner": [None, None], "users": {}}
-    progs = {w: wave_program(w, c, tiles, st) for w in range(np_)}
+    st = {"ready": [0] * R, "done": [0] * R, "owner": [None] * R, "users": {}}
+    progs = {w: wave_program(w, c, tiles, st, R) for w in range(np_)}
     alive = set(progs)
     idle = 0
     while alive:
@@ -73,13 +75,14 @@ def run(c, tiles, seed):
     return True
 
 
-@pytest.mark.parametrize("c", [1, 15, 16, 17, 26, 32, 40, 64, 100, 220, 256])
-def test_fold_protocol_leaf_and_tree(c):
-    leaf = [0, 0, 0]                                  # three leaf tiles
+@pytest.mark.parametrize("c", [1, 15, 16, 17, 26, 32, 40, 64, 100, 184, 220, 256])
+@pytest.mark.parametrize("R", [1, 2, 3, 7, 8])
+def test_fold_protocol_leaf_and_tree(c, R):
+    leaf = [0, 0, 0, 0]                               # four leaf tiles
     tree = [64 * t for t in range((c + 63) // 64)]    # one tree combine: tile t starts at 64 t
-    for seed in range(30):
-        assert run(c, leaf, seed), ("deadlock", c, "leaf", seed)
-        assert run(c, tree + tree, seed), ("deadlock", c, "tree", seed)
+    for seed in range(12):
+        assert run(c, leaf, seed, R), ("deadlock", c, R, "leaf", seed)
+        assert run(c, tree + tree, seed, R), ("deadlock", c, R, "tree", seed)
 
 
 def test_fold_protocol_detects_a_shared_counter():
