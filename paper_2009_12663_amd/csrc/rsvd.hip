@@ -384,17 +384,37 @@ __global__ void __launch_bounds__(LU_THREADS) omega_solve(int c, double* __restr
             }
         }
         __syncthreads();
-        // --- trailing update of rows kb + nb .. c-1 over M's right columns and B ---
-        const int trows = rows - nb;
-        const int wcols = right + c;
-        for (int e = tid; e < trows * wcols; e += LU_THREADS) {
-            const int rr = e / wcols, ec = e % wcols;
-            double* dst = ec < right ? M + (int64_t)(kb + nb + rr) * c + kb + nb + ec
-                                     : B + (int64_t)(kb + nb + rr) * c + (ec - right);
-            const double* lrow = P + (nb + rr) * LU_PLD;
-            double acc = *dst;
-            for (int i = 0; i < nb; ++i) acc = fma(-lrow[i], Ub[i * LU_ULD + ec], acc);
-            *dst = acc;
+        // --- trailing update of rows kb + nb .. c-1 over M's right columns and B:
+        // C -= L21 U12, a rank-nb product on the float64 matrix cores, one wave per
+        // 16 x 16 tile of C (A = L21 rows from the panel, B = U12 from the row block;
+        // loads from clamped indices, stores only inside C) ---
+        {
+            const int trows = rows - nb;
+            const int wcols = right + c;
+            const int ntr = (trows + 15) / 16, ntc = (wcols + 15) / 16;
+            const int lane = tid & 63, lm = lane & 15, lk = lane >> 4;
+            for (int tile = tid >> 6; tile < ntr * ntc; tile += LU_THREADS / 64) {
+                const int ti = tile / ntc, tj = tile % ntc;
+                const int ec = tj * 16 + lm, ecc = min(ec, wcols - 1);
+                double* colp = ecc < right ? M + (int64_t)(kb + nb) * c + kb + nb + ecc
+                                           : B + (int64_t)(kb + nb) * c + (ecc - right);
+                v4d acc;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = colp[(int64_t)min(ti * 16 + lk + 4 * q, trows - 1) * c];
+                const int ar = min(ti * 16 + lm, trows - 1);
+#pragma unroll
+                for (int ks = 0; ks < LU_NB / 4; ++ks) {
+                    const int k = 4 * ks + lk;
+                    const double a = k < nb ? -P[(nb + ar) * LU_PLD + k] : 0.0;
+                    const double b = k < nb ? Ub[k * LU_ULD + ecc] : 0.0;
+                    acc = mfma64(a, b, acc);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int rr = ti * 16 + lk + 4 * q;
+                    if (rr < trows && ec < wcols) colp[(int64_t)rr * c] = acc[q];
+                }
+            }
         }
         __syncthreads();
     }
@@ -434,12 +454,30 @@ __global__ void __launch_bounds__(LU_THREADS) omega_solve(int c, double* __restr
                 if (ii < nb) X[ii * LU_ULD + col] = x[ii];
         }
         __syncthreads();
-        for (int e = tid; e < kb * c; e += LU_THREADS) {
-            const int r = e / c, col = e % c;
-            const double* urow = P + r * LU_PLD;
-            double acc = B[(int64_t)r * c + col];
-            for (int i = 0; i < nb; ++i) acc = fma(-urow[i], X[i * LU_ULD + col], acc);
-            B[(int64_t)r * c + col] = acc;
+        // B[0:kb, :] -= U[0:kb, kb:kb+nb] X on the matrix cores, as above
+        {
+            const int ntr = (kb + 15) / 16, ntc = (c + 15) / 16;
+            const int lane = tid & 63, lm = lane & 15, lk = lane >> 4;
+            for (int tile = tid >> 6; tile < ntr * ntc; tile += LU_THREADS / 64) {
+                const int ti = tile / ntc, tj = tile % ntc;
+                const int col = tj * 16 + lm, colc = min(col, c - 1);
+                v4d acc;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = B[(int64_t)min(ti * 16 + lk + 4 * q, kb - 1) * c + colc];
+                const int ar = min(ti * 16 + lm, kb - 1);
+#pragma unroll
+                for (int ks = 0; ks < LU_NB / 4; ++ks) {
+                    const int k = 4 * ks + lk;
+                    const double a = k < nb ? -P[ar * LU_PLD + k] : 0.0;
+                    const double b = k < nb ? X[k * LU_ULD + colc] : 0.0;
+                    acc = mfma64(a, b, acc);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = ti * 16 + lk + 4 * q;
+                    if (r < kb && col < c) B[(int64_t)r * c + col] = acc[q];
+                }
+            }
         }
         __syncthreads();
     }
