@@ -269,6 +269,51 @@ __global__ void __launch_bounds__(256, 2) basis_mfma(int64_t n, int c, int rank,
 // unit-lower block (one thread per column); the trailing rows are updated from
 // the panel (L21) and the new U row block, both in LDS.  The backward
 // substitution with U is blocked the same way.
+// (value, index) of the largest value over a wave, ties to the lower index, in every
+// lane (all lanes active).  Quad and 16-lane row steps by DPP, then the rows by the
+// permlane swaps; each swap returns the lane's own pair and its partner's, and both
+// are offered (the own one changes nothing).  The order does not matter: the
+// selection is associative and commutative.
+__device__ __forceinline__ void argmax_take(double& best, int& bi, double v, int i) {
+    if (v > best || (v == best && i < bi)) {
+        best = v;
+        bi = i;
+    }
+}
+
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(double& best, int& bi) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, best);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    const int i2 = __builtin_amdgcn_update_dpp(0, bi, CTRL, 0xF, 0xF, false);
+    argmax_take(best, bi, __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo), i2);
+}
+
+template <bool ROWS32>
+__device__ __forceinline__ void argmax_swap(double& best, int& bi) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, best);
+    const unsigned l0 = (unsigned)u, h0 = (unsigned)(u >> 32), i0 = (unsigned)bi;
+    const auto lo = ROWS32 ? __builtin_amdgcn_permlane32_swap(l0, l0, false, false)
+                           : __builtin_amdgcn_permlane16_swap(l0, l0, false, false);
+    const auto hi = ROWS32 ? __builtin_amdgcn_permlane32_swap(h0, h0, false, false)
+                           : __builtin_amdgcn_permlane16_swap(h0, h0, false, false);
+    const auto ix = ROWS32 ? __builtin_amdgcn_permlane32_swap(i0, i0, false, false)
+                           : __builtin_amdgcn_permlane16_swap(i0, i0, false, false);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+        argmax_take(best, bi, __builtin_bit_cast(double, ((unsigned long long)hi[t] << 32) | lo[t]), (int)ix[t]);
+}
+
+__device__ __forceinline__ void wave_argmax(double& best, int& bi) {
+    argmax_dpp<0xB1>(best, bi);    // quad_perm [1, 0, 3, 2]
+    argmax_dpp<0x4E>(best, bi);    // quad_perm [2, 3, 0, 1]
+    argmax_dpp<0x124>(best, bi);   // row_ror:4
+    argmax_dpp<0x128>(best, bi);   // row_ror:8
+    argmax_swap<false>(best, bi);  // rows 0 <-> 1, 2 <-> 3
+    argmax_swap<true>(best, bi);   // halves
+}
+
 constexpr int LU_NB = 16;
 constexpr int LU_THREADS = 1024;
 constexpr int LU_PLD = LU_NB + 1;        // panel row stride (doubles)
@@ -310,12 +355,7 @@ __global__ void __launch_bounds__(LU_THREADS) omega_solve(int c, double* __restr
                     const double v = fabs(P[r * LU_PLD + j]);
                     if (v > best) { best = v; bi = r; }
                 }
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    const double v2 = __shfl_xor(best, off, 64);
-                    const int i2 = __shfl_xor(bi, off, 64);
-                    if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
-                }
+                wave_argmax(best, bi);
                 if (tid == 0) {
                     pivl[j] = bi;
                     piv[kb + j] = kb + bi;
