@@ -124,6 +124,26 @@ def test_rsvd_parity(storage, kind, nx, nz, k, rank, p, precond):
     assert r["orth"] <= (1e-12 if storage == "f64" else 1e-5)
 
 
+@pytest.mark.parametrize("storage,c", [("f64", 184), ("f32", 185)])
+def test_rsvd_fold_configuration_edges(storage, c):
+    """The TSQR fold's configuration edges: c = 184 is the largest block with a
+    float64 slot, whose reflector ring then holds two groups (float64 E: no
+    prefetch); c = 185 takes the float32 slot and a ring of eight.  Conjugate-
+    gradient pairs, rank = the pairs' count, p = the rest of c: c >= k + 1, so the
+    sketch is exact (as in the other float32 cases)."""
+    prob, S, Y, h0 = make_pairs("cg", 60, 40, c - 10, seed=c)
+    rank = S.shape[0]
+    p = c - rank
+    print(f"\n[rsvd fold edge] {storage} c={c} rank={rank} p={p}", flush=True)
+    r = run_case(storage, S, Y, h0, rank, p, seed=5)
+    print(f"  sigma {r['sig']:.2e} rec {r['rec']:.2e} diag_max {r['diag_max']:.2e} orth {r['orth']:.2e}", flush=True)
+    tol = SIG_TOL[storage]
+    assert r["sig"] <= tol
+    assert r["rec"] <= (10 * tol if storage != "f64" else 1e-10)
+    assert r["diag_max"] <= tol
+    assert r["orth"] <= (1e-12 if storage == "f64" else 1e-5)
+
+
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_rsvd_max_columns_and_ragged(storage):
     """c = 256 (the largest block) on n = 1443 rows (not a multiple of 4 or 8: the
