@@ -351,6 +351,16 @@ __device__ __forceinline__ void q_wait(unsigned* cnt, unsigned value) {
         __builtin_amdgcn_s_sleep(1);
 }
 
+// q_wait for a counter whose last value seen by this wave is `seen`: no load when
+// that already covers `value` (an acquire that saw a count orders everything
+// released up to it); otherwise wait and keep the new value.
+__device__ __forceinline__ void q_wait_seen(unsigned* cnt, unsigned value, unsigned& seen) {
+    while ((int)(seen - value) < 0) {
+        seen = __hip_atomic_load((lds_u32*)cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if ((int)(seen - value) < 0) __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 // Progress of a workgroup's folds, the same in every thread: groups started, the
 // ring slot of the next one, and per ring slot the arrivals owed by its groups so
 // far (registers: every index below is a constant after unrolling).
@@ -418,9 +428,10 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
                 }
                 __builtin_amdgcn_s_setprio(0);
             } else {
+                unsigned seen = tag - 1u;   // nothing of this group seen yet
                 for (int j = jb; j < je; ++j) {
                     const int sl = j - jb;
-                    q_wait(ready, tag + (unsigned)sl);
+                    q_wait_seen(ready, tag + (unsigned)sl, seen);
                     const double tau = lds_early(tb + 2 * sl), sc = lds_early(tb + 2 * sl + 1);
                     if (col < c) q_reflect_column(slot, a, c, j, col, g, xb + sl * QT, tau, sc, tau * sc);
                 }
