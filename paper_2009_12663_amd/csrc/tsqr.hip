@@ -429,12 +429,16 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
                 __builtin_amdgcn_s_setprio(0);
             } else {
                 unsigned seen = tag - 1u;   // nothing of this group seen yet
+                // the next group's builder must apply this group before it can start:
+                // it goes before the other waves that apply it
+                if (wave == k + 1) __builtin_amdgcn_s_setprio(1);
                 for (int j = jb; j < je; ++j) {
                     const int sl = j - jb;
                     q_wait_seen(ready, tag + (unsigned)sl, seen);
                     const double tau = lds_early(tb + 2 * sl), sc = lds_early(tb + 2 * sl + 1);
                     if (col < c) q_reflect_column(slot, a, c, j, col, g, xb + sl * QT, tau, sc, tau * sc);
                 }
+                if (wave == k + 1) __builtin_amdgcn_s_setprio(0);
             }
             if (threadIdx.x % 64 == 0) q_arrive(done);
         }
