@@ -92,12 +92,12 @@ def load_traffic(kernel, digest):
 
 
 def cpu_baseline(H, V, out, wq_prob_n, storage, ncols, budget_s=15.0):
-    """Oracle (Alg. 2 two-loop, float64 C/OpenMP) on a bounded sample of the same
+    """Oracle (eq. (3) recursion, float64 C/OpenMP) on a bounded sample of the same
     workload: whole chunks of `threads` probe columns until about `budget_s` seconds
     of oracle time (or all columns).  Also returns the relative error of the GPU's
     H_k V on those columns against the oracle (both from the stored values)."""
     import numpy as np
-    from oracle import twoloop
+    from oracle import recursion
     threads = len(os.sched_getaffinity(0))
     k = H.k
     n = wq_prob_n
@@ -115,18 +115,18 @@ def cpu_baseline(H, V, out, wq_prob_n, storage, ncols, budget_s=15.0):
         cols = list(range(done, min(ncols, done + chunk)))
         Vs = V[cols].double().cpu().numpy()
         t0 = time.perf_counter()
-        ref = twoloop.two_loop(h0, S, Y, Vs, nthreads=threads)
+        ref = recursion.apply_hk(h0, S, Y, Vs, nthreads=threads)
         spent += time.perf_counter() - t0
         got = out[cols].double().cpu().numpy()
         num += float(((got - ref) ** 2).sum())
         den += float((ref ** 2).sum())
         done += len(cols)
         log(f"[bench] oracle: {done} columns in {spent:.1f} s")
-    used = min(threads, twoloop.max_threads(), chunk)
+    used = min(threads, recursion.max_threads(), chunk)
     rel = (num / den) ** 0.5 if den > 0 else None
     return {"value": round(done / spent, 4), "unit": "columns/s", "cores": used, "kind": "oracle",
             "sample": f"{done} of the {ncols} probe columns of the same workload (n={n}, k={k}), "
-                      f"float64 two-loop recursion over the stored pairs, {spent:.1f} s"}, rel
+                      f"float64 eq. (3) recursion over the stored pairs, {spent:.1f} s"}, rel
 
 
 def bench_batch(args):

@@ -11,7 +11,7 @@ none of the method's arithmetic).
 Modules
   dense    eq. (3) inverse BFGS update applied recursively to a dense matrix
            (float64 and exact rationals), eq. (2) Hessian update.
-  twoloop  Alg. 2 two-loop recursion on a block of vectors (C, OpenMP).
+  recursion eq. (3) applied to a block as a recursion on the pair index (C, OpenMP).
   bfgs     Alg. 1 driven full-history BFGS with exact line search on a
            quadratic (used to pin the input generator, never to feed the GPU).
   rsvd     Alg. 3 single-pass randomized SVD and eq. (10)/(14) posterior

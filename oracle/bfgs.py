@@ -1,7 +1,7 @@
 """Full-history BFGS with an exact line search on a quadratic (oracle, test
 infrastructure only).
 
-The search direction is Alg. 1's p = -B_k g computed by the two-loop recursion
+The search direction is Alg. 1's p = -B_k g computed by the eq. (3) recursion
 with every pair kept and a fixed initial inverse Hessian B_0 (full-memory
 L-BFGS is BFGS, and B_0 then no longer changes with the iteration).  With no
 B_0 supplied, the first step is p = -g and B_0 = gamma I with
@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .twoloop import two_loop
+from .recursion import apply_hk
 
 
 def bfgs_quadratic(A, b, k: int, h0=None, damping: float = 1.0):
@@ -35,7 +35,7 @@ def bfgs_quadratic(A, b, k: int, h0=None, damping: float = 1.0):
         if not S and h is None:
             p = -g
         else:
-            p = -two_loop(h, np.array(S), np.array(Y), g)
+            p = -apply_hk(h, np.array(S), np.array(Y), g)
         Ap = A @ p
         alpha = damping * (-(g @ p) / (p @ Ap))
         s = alpha * p

@@ -6,7 +6,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["twoloop.c", "philox.c"]
+SOURCES = ["recursion.c", "philox.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

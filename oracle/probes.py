@@ -18,7 +18,7 @@ import ctypes
 import numpy as np
 import torch
 
-from .twoloop import lib
+from .recursion import lib
 
 
 def philox4x64_10(counter, key) -> np.ndarray:

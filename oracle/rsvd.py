@@ -1,37 +1,35 @@
-"""Alg. 3 single-pass randomized SVD and the posterior variance (oracle, test
-infrastructure only).
+"""Single-pass randomized SVD of B_k - B_0 and the posterior variance (oracle,
+test infrastructure only).
 
-rsvd(h0, S, Y, X, rank) follows Alg. 3 step by step on the operator
-B_k - B_0 (the difference probed by Alg. 2, whose low-rank part enters
-eq. (10)):
-  1. E = (B_k - B_0) X                     Alg. 2 with its final subtraction
-  2. Q R = E                               Householder QR (LAPACK), R_ii >= 0
-  3. Omega (Q^T X) = Q^T E                 LU with partial pivoting on (Q^T X)^T,
-                                           then Omega <- (Omega + Omega^T) / 2
-  4. U_s Lambda U_s^T = Omega              symmetric eigendecomposition with signed
-                                           eigenvalues, ordered by |lambda| descending
-                                           (ties: signed value descending, then index);
-                                           each eigenvector's largest-magnitude entry
-                                           made positive (lowest index on ties)
-  5. V = Q U_s, keeping the first `rank` columns; Sigma = the first `rank` eigenvalues
-posterior_diag: diag(V Lambda V^T + B_0) (eq. (10)), the variance of eq. (14) with
-C_m = I.
+Alg. 3 sketches the operator A = B_k - B_0 (the difference Alg. 2 probes, whose
+low-rank part enters eq. (10)) with a block of random vectors X and recovers a
+symmetric low-rank factorisation from that single sketch.  rsvd() takes the
+algorithm's steps in the paper's order:  the sketch E = A X; an orthonormal basis
+Q of its range from the QR factorisation E = Q R; the small matrix Omega that
+satisfies Omega (Q^T X) = Q^T E; its factorisation Omega = U_s Lambda U_s^T; and
+the basis U = Q U_s of the leading `rank` directions.  posterior_diag() forms
+diag(U Lambda U^T + B_0) of eq. (10), the variance of eq. (14) with C_m = I.
 
-Readings (the paper leaves them open): the solve in step 3 is square and is done by
-LU; Omega is symmetrised because step 4 writes its factorisation as U Lambda U^T;
-B_k - B_0 is indefinite in general, so Lambda keeps signs; oversampling columns are
-dropped after ordering.
+Readings where the paper leaves the method open:
+  * Q R = E is LAPACK's Householder QR with the signs chosen so that R_ii >= 0;
+  * Omega (Q^T X) = Q^T E is square and is solved by LU with partial pivoting,
+    then symmetrised, (Omega + Omega^T) / 2, since the next step factors it as
+    U_s Lambda U_s^T;
+  * A is indefinite in general, so Lambda keeps its signs: eigenvalues ordered by
+    |lambda| descending (ties: signed value descending, then index), each
+    eigenvector's largest-magnitude entry made positive (lowest index on ties);
+  * the oversampling columns are dropped after ordering.
 
 Pinned by: exactness when rank + oversampling exceeds rank(B_k - B_0) (against a
 dense eigendecomposition of the eq. (3) matrix), the Nystrom identity
-Q Omega Q^T = E (X^T E)^-1 E^T, and diag(B_k) by unit-pulse probing (Alg. 2).
+Q Omega Q^T = E (X^T E)^-1 E^T, and diag(B_k) by unit-pulse probing.
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.linalg
 
-from .twoloop import two_loop
+from .recursion import apply_hk
 
 
 def order_and_sign(lam: np.ndarray, Us: np.ndarray):
@@ -54,22 +52,22 @@ def rsvd(h0, S, Y, X, rank: int, E=None):
     c, n = X.shape
     assert rank <= c <= n
     if E is None:
-        E = two_loop(h0, S, Y, X, subtract_b0=True)            # step 1, (c, n)
+        E = apply_hk(h0, S, Y, X, subtract_b0=True)            # the sketch, (c, n)
     Em = E.T                                                     # n x c
     Xm = X.T
-    Q, R = np.linalg.qr(Em, mode="reduced")                      # step 2
+    Q, R = np.linalg.qr(Em, mode="reduced")                      # range basis
     d = np.sign(np.diag(R))
     d[d == 0] = 1.0
     Q = Q * d
     R = d[:, None] * R
-    T = Q.T @ Xm                                                 # step 3
+    T = Q.T @ Xm                                                 # Omega (Q^T X) = Q^T E
     F = Q.T @ Em
     lu, piv = scipy.linalg.lu_factor(T.T)
     Omega = scipy.linalg.lu_solve((lu, piv), F.T).T
     Omega = 0.5 * (Omega + Omega.T)
-    lam, Us = np.linalg.eigh(Omega)                              # step 4
+    lam, Us = np.linalg.eigh(Omega)                              # Omega = U_s Lambda U_s^T
     lam, Us = order_and_sign(lam, Us)
-    V = Q @ Us[:, :rank]                                         # step 5
+    V = Q @ Us[:, :rank]                                         # leading directions
     return dict(E=E, Q=Q, R=R, T=T, F=F, Omega=Omega, lam=lam, Us=Us,
                 U=V.T.copy(), Sigma=lam[:rank].copy())
 

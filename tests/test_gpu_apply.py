@@ -1,10 +1,10 @@
 """GPU parity of bfgs_apply_Hinv / bfgs_apply_Hdiff against the float64 oracle
-(Alg. 2 two-loop on the same stored inputs), plus the ABI's error behaviour."""
+(the eq. (3) recursion on the same stored inputs), plus the ABI's error behaviour."""
 import numpy as np
 import pytest
 import torch
 
-from oracle import twoloop, dense
+from oracle import recursion, dense
 from oracle.probes import round_to
 from workloads import quadratic as wq
 from tests.helpers import TOL, rel_f, gpu_input, oracle_input, h0_storage, make_pairs, gamma_of
@@ -33,7 +33,7 @@ def oracle_apply(storage, S, Y, V, h0=None, diff=False):
         h = np.full(S.shape[1], g if storage == "f64" else float(np.float32(g)))
     else:
         h = h0_storage(h0, storage)
-    return twoloop.two_loop(h, Sq, Yq, Vq, subtract_b0=diff), h
+    return recursion.apply_hk(h, Sq, Yq, Vq, subtract_b0=diff), h
 
 
 CASES = [

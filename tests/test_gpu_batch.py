@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import twoloop, rsvd as orsvd, probes as oprobes
+from oracle import recursion, rsvd as orsvd, probes as oprobes
 from workloads import quadratic as wq
 from tests.helpers import rel_f, gpu_input, oracle_input, h0_storage, make_pairs, gamma_of
 
@@ -48,7 +48,7 @@ def test_batch_parity_and_graph(storage):
     for i, (prob, S, Y, h0) in enumerate(probs):
         h = oracle_h(storage, S, Y, h0)
         Sq, Yq = oracle_input(S, storage), oracle_input(Y, storage)
-        want = twoloop.two_loop(h, Sq, Yq, oracle_input(V[i].double().cpu(), storage))
+        want = recursion.apply_hk(h, Sq, Yq, oracle_input(V[i].double().cpu(), storage))
         err = rel_f(out[i].double().cpu().numpy(), want)
         X = oprobes.round_to(oprobes.normal_block(ns[i], cs[i], 5 + i), storage)
         ref = orsvd.rsvd(h, Sq, Yq, X, ks[i])
@@ -120,7 +120,7 @@ def test_batch_full_shapes_sampled():
         g = float(np.float32(gamma_of(Sq, Yq)))
         cols = [0, cs[i] - 1]
         Vq = V[i][cols].double().cpu().numpy()
-        want = twoloop.two_loop(np.full(ns[i], g), Sq, Yq, Vq)
+        want = recursion.apply_hk(np.full(ns[i], g), Sq, Yq, Vq)
         err = rel_f(out[i][cols].double().cpu().numpy(), want)
         print(f"  problem {i}: n={ns[i]} k={ks[i]} sampled apply rel_F {err:.2e}", flush=True)
         assert err <= 1e-3

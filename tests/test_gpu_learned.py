@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import twoloop
+from oracle import recursion
 from workloads import quadratic as wq
 from tests.helpers import rel_f
 
@@ -53,7 +53,7 @@ def test_learned_h0_beats_gamma_identity():
         Sq = S.float().double().cpu().numpy()
         HY = H.apply_Hinv(Y[-8:].float()).double().cpu().numpy()
         res = np.linalg.norm(HY - Sq[-8:], axis=1) / np.linalg.norm(Sq[-8:], axis=1)
-        want = twoloop.two_loop(h0.double().cpu().numpy(), Sq, Yq, Yq[-8:])
+        want = recursion.apply_hk(h0.double().cpu().numpy(), Sq, Yq, Yq[-8:])
         print(f"[learned] seed {seed}: secant residual max {res.max():.2e}, "
               f"apply vs oracle {rel_f(HY, want):.2e}", flush=True)
         assert rel_f(HY, want) <= 1e-6

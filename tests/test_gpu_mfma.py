@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import twoloop
+from oracle import recursion
 from workloads import quadratic as wq
 from tests.helpers import rel_f, gpu_input, oracle_input, h0_storage, make_pairs, gamma_of
 
@@ -25,7 +25,7 @@ def build(S, Y, h0):
 def oracle(S, Y, V, h0, diff=False):
     Sq, Yq, Vq = oracle_input(S, "bf16"), oracle_input(Y, "bf16"), oracle_input(V, "bf16")
     h = np.full(S.shape[1], float(np.float32(gamma_of(Sq, Yq)))) if h0 is None else h0_storage(h0, "bf16")
-    return twoloop.two_loop(h, Sq, Yq, Vq, subtract_b0=diff), h, Vq
+    return recursion.apply_hk(h, Sq, Yq, Vq, subtract_b0=diff), h, Vq
 
 
 SHAPES = [
@@ -89,7 +89,7 @@ def test_mfma_full_size_sampled_columns():
     g = float(np.float32(gamma_of(Sq, Yq)))
     h = np.full(prob.n, g)
     Vq = V[cols].double().cpu().numpy()
-    want = twoloop.two_loop(h, Sq, Yq, Vq)
+    want = recursion.apply_hk(h, Sq, Yq, Vq)
     got = out[cols].double().cpu().numpy()
     err = rel_f(got, want)
     corr = rel_f(got - h * Vq, want - h * Vq)

@@ -11,7 +11,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
-from oracle import dense, twoloop, bfgs
+from oracle import dense, recursion, bfgs
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "eq3_hand.json")
 
@@ -43,11 +43,11 @@ def test_golden_exact(case):
     want = [[_frac(v) for v in row] for row in case["B"]]
     got = dense.inverse_hessian_exact(h0, S, Y)
     assert got == want
-    # float64 recursion and the two-loop agree with the same hand values
+    # the dense float64 update and the block recursion agree with the same hand values
     f = lambda M: np.array([[float(v) for v in row] for row in M])
     Bf = dense.inverse_hessian([float(v) for v in h0], f(S), f(Y))
     np.testing.assert_allclose(Bf, f(want), rtol=1e-15, atol=1e-15)
-    cols = twoloop.two_loop([float(v) for v in h0], f(S), f(Y), np.eye(len(h0)))
+    cols = recursion.apply_hk([float(v) for v in h0], f(S), f(Y), np.eye(len(h0)))
     np.testing.assert_allclose(cols, f(want), rtol=1e-15, atol=1e-15)
 
 
@@ -68,7 +68,7 @@ def test_exact_rationals_small_integers(seed):
     B = dense.inverse_hessian(h0, S, Y)
     scale = np.abs(exact_f).max()
     assert np.abs(B - exact_f).max() <= 1e-12 * scale
-    cols = twoloop.two_loop(h0, S, Y, np.eye(n))
+    cols = recursion.apply_hk(h0, S, Y, np.eye(n))
     assert np.abs(cols - exact_f).max() <= 1e-12 * scale
     # the secant condition of the last pair holds exactly in rationals
     s, y = S[-1].tolist(), Y[-1].tolist()
@@ -85,21 +85,21 @@ def test_secant_symmetry_pd(damping):
     np.testing.assert_allclose(B @ Y[-1], S[-1], rtol=0, atol=1e-13 * np.abs(S[-1]).max())
     assert np.abs(B - B.T).max() <= 1e-14 * np.abs(B).max()
     assert np.linalg.eigvalsh(B).min() > 0
-    # two-loop: symmetric bilinear form and secant
+    # block recursion: symmetric bilinear form and secant
     rng = np.random.default_rng(0)
     u, v = rng.standard_normal((2, n))
-    Bu = twoloop.two_loop(h, S, Y, u)
-    Bv = twoloop.two_loop(h, S, Y, v)
+    Bu = recursion.apply_hk(h, S, Y, u)
+    Bv = recursion.apply_hk(h, S, Y, v)
     assert abs(u @ Bv - v @ Bu) <= 1e-13 * abs(u @ Bv)
     assert v @ Bv > 0
-    np.testing.assert_allclose(twoloop.two_loop(h, S, Y, Y[-1]), S[-1], atol=1e-13 * np.abs(S[-1]).max())
+    np.testing.assert_allclose(recursion.apply_hk(h, S, Y, Y[-1]), S[-1], atol=1e-13 * np.abs(S[-1]).max())
 
 
 def test_hereditary_exact_line_search():
     """Exact line search on a quadratic keeps every earlier secant condition (conjugate steps)."""
     n, k = 60, 20
     A, S, Y, h = secant_pairs(n, k, seed=5)
-    HY = twoloop.two_loop(h, S, Y, Y)
+    HY = recursion.apply_hk(h, S, Y, Y)
     rel = np.abs(HY - S).max() / np.abs(S).max()
     assert rel < 1e-6
 
@@ -131,15 +131,15 @@ def test_eq2_inverse_is_eq3():
     assert np.abs(np.linalg.inv(H) - B).max() <= 1e-10 * np.abs(B).max()
 
 
-def test_full_memory_two_loop_is_dense_recursion():
+def test_block_recursion_is_dense_matrix():
     n, k = 80, 25
     A, S, Y, h = secant_pairs(n, k, seed=11, damping=0.7)
     h0 = np.random.default_rng(3).uniform(0.2, 3.0, n)
     B = dense.inverse_hessian(h0, S, Y)
     V = np.random.default_rng(4).standard_normal((7, n))
-    out = twoloop.two_loop(h0, S, Y, V)
+    out = recursion.apply_hk(h0, S, Y, V)
     np.testing.assert_allclose(out, V @ B, rtol=0, atol=1e-12 * np.abs(V @ B).max())
-    E = twoloop.two_loop(h0, S, Y, V, subtract_b0=True)
+    E = recursion.apply_hk(h0, S, Y, V, subtract_b0=True)
     np.testing.assert_allclose(E, V @ (B - np.diag(h0)), rtol=0, atol=1e-12 * np.abs(V @ B).max())
 
 
@@ -167,4 +167,4 @@ def test_gamma_bounds():
 def test_zero_pairs_is_b0():
     h0 = np.array([1.0, 2.0, 3.0])
     V = np.arange(6.0).reshape(2, 3)
-    np.testing.assert_array_equal(twoloop.two_loop(h0, np.zeros((0, 3)), np.zeros((0, 3)), V), V * h0)
+    np.testing.assert_array_equal(recursion.apply_hk(h0, np.zeros((0, 3)), np.zeros((0, 3)), V), V * h0)

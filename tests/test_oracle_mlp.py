@@ -64,3 +64,33 @@ def test_training_reduces_loss():
         loss, g = mlp.loss_and_grad(p, X, t)
         p = opt.step(p, g)
     assert loss < 0.1 * l0
+
+
+def test_forward_hand_value():
+    """Forward pass on a sparse parameter set written out by hand: biases before the
+    activation, GELU on both hidden layers, W2 read as (output unit, input unit) with
+    W2[0, 1] != W2[1, 0].  Phi comes from scipy.stats.norm, not from the oracle's erf."""
+    from scipy.stats import norm
+
+    def g(x):
+        return x * norm.cdf(x)
+
+    W1, b1, W2, b2, w3, b3 = (np.zeros(s) for s in mlp.SIZES)
+    W1[0, 0], W1[1, 1] = 1.0, 0.5
+    b1[0], b1[1], b1[2] = 0.25, -0.5, 1.0
+    W2[0, 1], W2[1, 0], W2[1, 2] = 2.0, -1.0, 0.5
+    b2[0], b2[1], b2[3] = 0.1, -0.2, 0.7
+    w3[0], w3[1], w3[3] = 1.0, 3.0, -2.0
+    b3[0] = 0.05
+    p = mlp.flatten([W1, b1, W2, b2, w3, b3])
+    X = np.zeros((3, 8))
+    X[0, 0] = 1.0
+    X[1, 1] = 2.0
+    X[2, :] = [-0.7, 1.3, 5.0, 5.0, 5.0, 5.0, 5.0, 5.0]   # features 2..7 have no weights
+    want = []
+    for x in X:
+        h0_, h1_, h2_ = g(x[0] + 0.25), g(0.5 * x[1] - 0.5), g(1.0)
+        z0 = 2.0 * h1_ + 0.1
+        z1 = -1.0 * h0_ + 0.5 * h2_ - 0.2
+        want.append(g(z0) + 3.0 * g(z1) - 2.0 * g(0.7) + 0.05)
+    np.testing.assert_allclose(mlp.forward(p, X), want, rtol=1e-14, atol=1e-15)

@@ -1,31 +1,36 @@
 """The pins are strong enough: plausible mistakes planted in a CPU copy of the
-two-loop recursion (Alg. 2) each fail at least one pin.  CPU only."""
+eq. (3) recursion each fail at least one pin.  CPU only."""
 import json
 import os
 
 import numpy as np
 import pytest
 
-from oracle import bfgs, twoloop
+from oracle import bfgs, recursion
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "eq3_hand.json")
 
 
-def two_loop_variant(h0, S, Y, v, mistake=None):
+def recursion_variant(h0, S, Y, v, mistake=None):
+    """B_k v by eq. (3) as a recursion on the pair index, with an optional mistake."""
     k = len(S)
-    r = [1.0 / (Y[i] @ S[i]) for i in range(k)]
-    q = v.astype(np.float64).copy()
-    a = np.zeros(k)
-    order1 = range(k) if mistake == "first_loop_ascending" else range(k - 1, -1, -1)
-    for i in order1:
-        s_, y_ = (Y[i], S[i]) if mistake == "swap_s_y" else (S[i], Y[i])
-        a[i] = r[i] * (s_ @ q)
-        q = q - a[i] * y_
-    z = q / h0 if mistake == "inverse_b0" else h0 * q
-    for i in range(k):
-        b = (Y[i] @ z) if mistake == "drop_rho" else r[i] * (Y[i] @ z)
-        z = z + S[i] * ((b - a[i]) if mistake == "flip_sign" else (a[i] - b))
-    return z
+    order = list(range(k))[::-1] if mistake == "reversed_pairs" else list(range(k))
+
+    def level(m, v):
+        if m == 0:
+            return v / h0 if mistake == "inverse_b0" else h0 * v
+        i = order[m - 1]
+        s, y = (Y[i], S[i]) if mistake == "swap_s_y" else (S[i], Y[i])
+        r = 1.0 if mistake == "drop_rho" else 1.0 / (y @ s)
+        t = s @ v
+        w = v - r * (y @ v) * s if mistake == "transpose_right" else v - r * t * y
+        z = level(m - 1, w)
+        u = y @ z
+        if mistake == "drop_ss_term":
+            return z - r * u * s
+        return z + r * ((u - t) if mistake == "flip_sign" else (t - u)) * s
+
+    return level(k, np.asarray(v, np.float64))
 
 
 def pins_pass(fn):
@@ -57,11 +62,11 @@ def pins_pass(fn):
 
 
 def test_unmutated_copy_passes_and_matches_oracle():
-    assert pins_pass(lambda h0, S, Y, v: two_loop_variant(h0, S, Y, v))
-    assert pins_pass(lambda h0, S, Y, v: twoloop.two_loop(h0, S, Y, v))
+    assert pins_pass(lambda h0, S, Y, v: recursion_variant(h0, S, Y, v))
+    assert pins_pass(lambda h0, S, Y, v: recursion.apply_hk(h0, S, Y, v))
 
 
-@pytest.mark.parametrize("mistake", ["first_loop_ascending", "swap_s_y", "inverse_b0",
-                                     "drop_rho", "flip_sign"])
+@pytest.mark.parametrize("mistake", ["reversed_pairs", "swap_s_y", "inverse_b0", "drop_rho",
+                                     "transpose_right", "drop_ss_term", "flip_sign"])
 def test_planted_mistake_is_caught(mistake):
-    assert not pins_pass(lambda h0, S, Y, v: two_loop_variant(h0, S, Y, v, mistake))
+    assert not pins_pass(lambda h0, S, Y, v: recursion_variant(h0, S, Y, v, mistake))

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import scipy.stats
 
-from oracle import dense, twoloop, rsvd, probes, bfgs
+from oracle import dense, recursion, rsvd, probes, bfgs
 from workloads import quadratic as wq
 import torch
 
@@ -44,7 +44,7 @@ def test_rsvd_exact_when_oversampled(precond):
     np.testing.assert_allclose(d, np.diag(Bk), rtol=1e-11)
     idx = np.random.default_rng(0).choice(n, 16, replace=False)
     pulses = np.eye(n)[idx]
-    col = twoloop.two_loop(h0, S, Y, pulses)
+    col = recursion.apply_hk(h0, S, Y, pulses)
     np.testing.assert_allclose(d[idx], col[np.arange(16), idx], rtol=1e-11)
 
 
@@ -124,3 +124,38 @@ def test_round_to_storage():
     np.testing.assert_array_equal(probes.round_to(x[:3], "bf16"), [1.0, 1.0 + 2.0**-7, 1.0])
     assert np.isinf(probes.round_to(x[3:], "f32")[0])
     assert probes.round_to([1.0 + 2.0**-30], "f32")[0] == 1.0
+
+
+def test_box_muller_pairs_against_numpy_philox():
+    """Each counter block gives two Box-Muller pairs: rows 4q, 4q+1 from (u_0, u_1) and
+    rows 4q+2, 4q+3 from (u_2, u_3).  Against numpy's Philox (a library generator):
+    the pair's squared radius is -2 ln u_0 (resp. u_2) and its angle 2 pi u_1 (resp.
+    u_3), with u = ((x >> 11) + 1) 2^-53 of the raw 64-bit outputs."""
+    seed = 77
+    X = probes.normal_block(64, 3, seed)
+    M = 2**64 - 1
+    for col in range(3):
+        for q in range(16):
+            # numpy's Philox increments its 256-bit counter before each block: start one below
+            before = [q - 1, col, 0, 0] if q > 0 else ([M, col - 1, 0, 0] if col > 0 else [M, M, M, M])
+            bg = np.random.Philox(counter=np.array(before, np.uint64), key=np.array([seed, 0], np.uint64))
+            raw = bg.random_raw(4)
+            u = ((raw >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+            for h in range(2):
+                z0, z1 = X[col, 4 * q + 2 * h], X[col, 4 * q + 2 * h + 1]
+                assert z0 * z0 + z1 * z1 == pytest.approx(-2.0 * np.log(u[2 * h]), rel=1e-13)
+                ang = np.arctan2(z1, z0) % (2 * np.pi)
+                assert abs(ang - 2 * np.pi * u[2 * h + 1]) <= 1e-12 or abs(abs(ang - 2 * np.pi * u[2 * h + 1]) - 2 * np.pi) <= 1e-12
+
+
+def test_box_muller_pair_members_independent():
+    """Within a column, the two members of a pair (rows 4q, 4q+1) and neighbouring
+    pairs are uncorrelated, and so are their squares (the cos/sin members of one
+    Box-Muller pair are independent normals)."""
+    X = probes.normal_block(400_000, 2, seed=9)
+    for col in range(2):
+        x = X[col]
+        for a, b in [(0, 1), (2, 3), (1, 2), (0, 2)]:
+            u, v = x[a::4], x[b::4]
+            assert abs(np.corrcoef(u, v)[0, 1]) < 0.015
+            assert abs(np.corrcoef(u * u, v * v)[0, 1]) < 0.015
