@@ -111,6 +111,7 @@ def cpu_baseline(H, V, out, wq_prob_n, storage, ncols, budget_s=15.0):
     chunk = max(1, min(threads, ncols))
     done, spent = 0, 0.0
     num = den = 0.0
+    elem_max = 0.0
     while done < ncols and (done == 0 or spent < budget_s):
         cols = list(range(done, min(ncols, done + chunk)))
         Vs = V[cols].double().cpu().numpy()
@@ -120,13 +121,75 @@ def cpu_baseline(H, V, out, wq_prob_n, storage, ncols, budget_s=15.0):
         got = out[cols].double().cpu().numpy()
         num += float(((got - ref) ** 2).sum())
         den += float((ref ** 2).sum())
+        elem_max = max(elem_max, float((np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)).max()))
         done += len(cols)
         log(f"[bench] oracle: {done} columns in {spent:.1f} s")
     used = min(threads, recursion.max_threads(), chunk)
     rel = (num / den) ** 0.5 if den > 0 else None
     return {"value": round(done / spent, 4), "unit": "columns/s", "cores": used, "kind": "oracle",
             "sample": f"{done} of the {ncols} probe columns of the same workload (n={n}, k={k}), "
-                      f"float64 eq. (3) recursion over the stored pairs, {spent:.1f} s"}, rel
+                      f"float64 eq. (3) recursion over the stored pairs, {spent:.1f} s"}, \
+        {"apply_rel_F": rel, "apply_elem_max": elem_max}, (S, Y, h0)
+
+
+def oracle_rsvd_errors(S, Y, h0, storage, seed, rank, p, Sig, dg):
+    """The rSVD of the timed step against the float64 oracle (Alg. 3 on the same
+    stored pairs and probes): max |Sigma - Sigma_ref| / |Sigma_ref,0| and the
+    posterior variance's relative Frobenius and element-wise errors."""
+    import numpy as np
+    from oracle import rsvd as orsvd, probes as oprobes
+    t0 = time.perf_counter()
+    n = h0.shape[0]
+    X = oprobes.round_to(oprobes.normal_block(n, rank + p, seed), storage)
+    ref = orsvd.rsvd(h0, S, Y, X, rank)
+    del X
+    dref = orsvd.posterior_diag(h0, ref["U"], ref["Sigma"])
+    sig = Sig.cpu().numpy()
+    d = dg.double().cpu().numpy()
+    out = {"sigma_rel_err": float(np.abs(sig - ref["Sigma"]).max() / abs(ref["Sigma"][0])),
+           "diag_rel_F": float(np.linalg.norm(d - dref) / np.linalg.norm(dref)),
+           "diag_elem_max": float(np.abs(d - dref).max() / np.abs(dref).max()),
+           "oracle_rsvd_s": round(time.perf_counter() - t0, 1)}
+    log(f"[bench] oracle rSVD: {out}")
+    return out
+
+
+def fp32_path(P, S, Y, n, k, V, out, rank, p, seed, Sig, dg, ncols, apply_ms_bf16):
+    """The plain float32 form on the same pairs and probe values: its apply time (the
+    speedup baseline of the bfloat16 form) and the bfloat16 results against it."""
+    import torch
+    Hf = P.Bfgs(n, k, None, "f32")
+    for s_, y_ in zip(S, Y):
+        Hf.push_pair(s_.float(), y_.float())
+    Vf = V.float()                          # the bfloat16 probe values, exact in float32
+    of = torch.empty((ncols, n), dtype=torch.float32, device="cuda")
+    Hf.apply_Hinv(Vf, of)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        Hf.apply_Hinv(Vf, of)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    Uf = torch.empty((rank, n), dtype=torch.float32, device="cuda")
+    Sf = torch.empty(rank, dtype=torch.float64, device="cuda")
+    Hf.rsvd(rank, p, seed, Uf, Sf)
+    df = Hf.posterior_diag()
+    torch.cuda.synchronize()
+    status = Hf.get_status()
+    Hf.close()
+
+    def rel(a, b):
+        return float(torch.linalg.vector_norm((a - b).double()) / torch.linalg.vector_norm(b.double()))
+    res = {"apply_ms": round(ms, 4), "columns_per_s": round(ncols / (ms / 1e3), 2),
+           "speedup_bf16_over_fp32": round(ms / apply_ms_bf16, 3),
+           "bf16_apply_rel_F_vs_fp32": rel(out, of),
+           "bf16_sigma_rel_err_vs_fp32": float((Sig - Sf).abs().max() / Sf[0].abs()),
+           "bf16_diag_rel_F_vs_fp32": rel(dg, df), "device_status": status}
+    log(f"[bench] fp32 path: {res}")
+    return res
 
 
 def bench_batch(args):
@@ -563,6 +626,8 @@ def main():
     ap.add_argument("--ncols", type=int, default=220)
     ap.add_argument("--config", default="grid3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32-path", action="store_true",
+                    help="skip the float32-storage comparison run after the timed region")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (counter calibration)")
     ap.add_argument("--summarize", default="", metavar="DIR",
@@ -616,7 +681,8 @@ def main():
     H = P.Bfgs(n, k, None, args.storage)
     for s, y in zip(S, Y):
         H.push_pair(s.float() if args.storage != "f64" else s, y.float() if args.storage != "f64" else y)
-    del S, Y
+    if args.storage != "bf16" or args.no_fp32_path:
+        del S, Y
     V = H.generate_probes(seed=2, ncols=args.ncols)
     out = torch.empty((args.ncols, n), dtype=H.rdt, device="cuda")
     U = torch.empty((rank, n), dtype=H.rdt, device="cuda")
@@ -714,10 +780,16 @@ def main():
         "kernels_ms_per_step": {name: round(v[1] / args.steps, 4) for name, v in prof.items()},
         "source_digest": digest,
     }
+    if args.storage == "bf16" and not args.no_fp32_path:
+        result["fp32_path"] = fp32_path(P, S, Y, n, k, V, out, rank, p, seed, Sig, dg, args.ncols, apply_ms)
+        del S, Y
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
-        result["cpu_baseline"], rel = cpu_baseline(H, V, out, n, args.storage, args.ncols)
-        result["rel_err_vs_oracle"] = {"apply_rel_F": rel, "sample": result["cpu_baseline"]["sample"]}
+        result["cpu_baseline"], errs, (So, Yo, h0o) = cpu_baseline(H, V, out, n, args.storage, args.ncols)
+        errs.update(oracle_rsvd_errors(So, Yo, h0o, args.storage, seed, rank, p, Sig, dg))
+        errs["sample"] = result["cpu_baseline"]["sample"] + "; rSVD: all of Sigma and the posterior variance"
+        result["rel_err_vs_oracle"] = errs
+        del So, Yo
         log(f"[bench] cpu baseline: {result['cpu_baseline']['value']} columns/s "
             f"({result['cpu_baseline']['cores']} threads)")
     else:

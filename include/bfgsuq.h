@@ -189,6 +189,17 @@ int bfgs_batch_create(int32_t nprob, const int64_t* n, const int32_t* k_max, con
                       void* stream, bfgs_batch_t* out);
 /* The handle of problem i (for bfgs_push_pair and inspection; owned by the batch). */
 int bfgs_batch_handle(bfgs_batch_t b, int32_t i, bfgs_t* h_out);
+/* bfgs_batch_push_pairs — appends kcount[i] pairs to problem i (definitions after
+ * eq. (2)): S[i], Y[i] (device) are n_i x kcount[i] column-major blocks (column j
+ * = pair j, leading dimension n_i) of in_dtype (BFGS_F64 or BFGS_F32), pushed in
+ * column order exactly as bfgs_push_pair would push them.  The problems' pushes
+ * run on their own streams and overlap.  A pair that fails the curvature or
+ * finiteness check is dropped and the following pairs are still pushed; the
+ * return value is the first error met (bfgs_num_pairs tells how many pairs each
+ * problem holds).  BFGS_ERR_FULL (nothing pushed) if some problem would exceed
+ * its k_max.  Synchronous.                                                      */
+int bfgs_batch_push_pairs(bfgs_batch_t b, const void* const* S, const void* const* Y, const int32_t* kcount,
+                          bfgs_dtype in_dtype);
 int bfgs_batch_apply_Hinv(bfgs_batch_t b, const void* const* V, const int32_t* ncols, void* const* out);
 int bfgs_batch_rsvd(bfgs_batch_t b, const int32_t* rank, int32_t oversample, uint64_t seed, void* const* U,
                     double* const* Sigma);
@@ -196,11 +207,15 @@ int bfgs_batch_rsvd(bfgs_batch_t b, const int32_t* rank, int32_t oversample, uin
 int bfgs_batch_autotune(bfgs_batch_t b, const void* const* V, const int32_t* ncols, void* const* out,
                         const int32_t* rank, int32_t oversample, void* const* U, double* const* Sigma);
 /* Runs apply + rSVD of every problem once, then captures the same sequence into a
- * hipGraph on `stream` (synchronous).  The buffers passed are baked into the graph. */
+ * hipGraph on `stream` (synchronous).  The buffers passed are baked into the graph,
+ * and so are the problems' pair counts, launch shapes and workspaces. */
 int bfgs_batch_graph_build(bfgs_batch_t b, const void* const* V, const int32_t* ncols, void* const* out,
                            const int32_t* rank, int32_t oversample, uint64_t seed, void* const* U,
                            double* const* Sigma);
-/* Replays the captured graph on `stream` (BFGS_ERR_STATE if none was built). */
+/* Replays the captured graph on `stream`.  BFGS_ERR_STATE if none was built, or
+ * if any problem's handle changed since the capture (a pair pushed, a retune, a
+ * workspace grown by a call with more columns): the graph is then discarded,
+ * nothing is launched, and bfgs_batch_graph_build must be called again.        */
 int bfgs_batch_graph_launch(bfgs_batch_t b);
 int bfgs_batch_destroy(bfgs_batch_t b);
 
@@ -246,6 +261,12 @@ int bfgs_mlp_train_step(bfgs_mlp_t m, const float* X, const float* target, int64
  *   record.  BFGS_ERR_ARG if buf is too small.                               */
 int bfgs_profile(bfgs_t h, int32_t enable);
 int bfgs_profile_report(bfgs_t h, char* buf, int32_t len);
+
+/* bfgs_tsqr_shape — the configuration the tall-skinny QR of a c-column block
+ *   takes (host outputs, either may be NULL): slot_f64 = 1 when the per-chain
+ *   c x c triangle is kept in float64 in LDS (0: float32), ring = the number of
+ *   16-reflector groups in flight per chain.  BFGS_ERR_ARG unless 1 <= c <= 256. */
+int bfgs_tsqr_shape(int32_t c, int32_t* slot_f64, int32_t* ring);
 
 /* bfgs_sync — waits until all work enqueued on the handle's stream is done. */
 int bfgs_sync(bfgs_t h);

@@ -19,4 +19,12 @@ from ._lib import (  # noqa: F401
     load,
     LIB_PATH,
     EXPORTS,
+    BFGS_OK,
+    BFGS_ERR_ARG,
+    BFGS_ERR_FULL,
+    BFGS_ERR_STATE,
+    BFGS_ERR_CURVATURE,
+    BFGS_ERR_NONFINITE,
+    BFGS_ERR_NUMERIC,
+    tsqr_shape,
 )

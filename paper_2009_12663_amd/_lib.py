@@ -35,8 +35,8 @@ EXPORTS = [
     "bfgs_create", "bfgs_destroy", "bfgs_push_pair", "bfgs_num_pairs", "bfgs_apply_Hinv",
     "bfgs_apply_Hdiff", "bfgs_generate_probes", "bfgs_rsvd", "bfgs_posterior_diag",
     "bfgs_get_pair", "bfgs_get_h0", "bfgs_get_status", "bfgs_status_string",
-    "bfgs_profile", "bfgs_profile_report", "bfgs_autotune", "bfgs_tuning", "bfgs_sync",
-    "bfgs_batch_create", "bfgs_batch_handle", "bfgs_batch_apply_Hinv", "bfgs_batch_rsvd",
+    "bfgs_profile", "bfgs_profile_report", "bfgs_autotune", "bfgs_tuning", "bfgs_sync", "bfgs_tsqr_shape",
+    "bfgs_batch_create", "bfgs_batch_handle", "bfgs_batch_push_pairs", "bfgs_batch_apply_Hinv", "bfgs_batch_rsvd",
     "bfgs_batch_autotune", "bfgs_batch_graph_build", "bfgs_batch_graph_launch", "bfgs_batch_destroy",
     "bfgs_mlp_create", "bfgs_mlp_destroy", "bfgs_mlp_set_params", "bfgs_mlp_get_params", "bfgs_mlp_features",
     "bfgs_mlp_forward", "bfgs_mlp_grad", "bfgs_mlp_train_step",
@@ -80,8 +80,10 @@ def load(path: str = LIB_PATH):
         "bfgs_autotune": [vp, i32, i32, i32, vp, vp, vp, vp],
         "bfgs_tuning": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "bfgs_sync": [vp],
+        "bfgs_tsqr_shape": [i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "bfgs_batch_create": [i32, vp, vp, vp, ctypes.c_int, vp, ctypes.POINTER(vp)],
         "bfgs_batch_handle": [vp, i32, ctypes.POINTER(vp)],
+        "bfgs_batch_push_pairs": [vp, vp, vp, vp, ctypes.c_int],
         "bfgs_batch_apply_Hinv": [vp, vp, vp, vp],
         "bfgs_batch_rsvd": [vp, vp, i32, u64, vp, vp],
         "bfgs_batch_autotune": [vp, vp, vp, vp, vp, i32, vp, vp],
@@ -116,6 +118,13 @@ def _check(code: int, where: str) -> int:
     if code < 0:
         raise BfgsError(code, where)
     return code
+
+
+def tsqr_shape(c: int):
+    """(slot_f64, ring) of the tall-skinny QR for a c-column block."""
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().bfgs_tsqr_shape(int(c), ctypes.byref(a), ctypes.byref(b)), "bfgs_tsqr_shape")
+    return bool(a.value), int(b.value)
 
 
 def _ptr(t):
@@ -254,6 +263,17 @@ class Bfgs:
         self._leave()
         return s, y
 
+    def get_pairs(self):
+        """All stored pairs, upcast exactly: (S, Y) of shape (k, n) on the device."""
+        k = self.k
+        S = torch.empty((k, self.n), dtype=self.rdt, device="cuda")
+        Y = torch.empty((k, self.n), dtype=self.rdt, device="cuda")
+        self._enter()
+        for j in range(k):
+            _check(self.L.bfgs_get_pair(self.h, j, _ptr(S[j]), _ptr(Y[j])), "bfgs_get_pair")
+        self._leave()
+        return S, Y
+
     def get_h0(self) -> torch.Tensor:
         out = torch.empty(self.n, dtype=self.hdt, device="cuda")
         self._enter()
@@ -344,6 +364,22 @@ class BfgsBatch:
             self.close()
         except Exception:
             pass
+
+    def push_pairs(self, S: list, Y: list):
+        """S[i], Y[i]: (k_i, n_i) float32 or float64 tensors on the device (row j = pair j).
+        Returns the status of bfgs_batch_push_pairs (0, or the first pair error met;
+        rejected pairs are dropped); argument and capacity errors raise."""
+        dt = S[0].dtype
+        code = F64 if dt == torch.float64 else F32
+        S = [s.to(dt).contiguous() for s in S]
+        Y = [y.to(dt).contiguous() for y in Y]
+        for p, s, y in zip(self.problems, S, Y):
+            assert s.shape == y.shape and (s.numel() == 0 or s.shape[1] == p.n)
+        rc = self.L.bfgs_batch_push_pairs(self.b, _ptr_array(S), _ptr_array(Y), _i32_array([s.shape[0] for s in S]),
+                                          code)
+        if rc in (BFGS_ERR_ARG, BFGS_ERR_FULL, BFGS_ERR_HIP, BFGS_ERR_ALLOC):
+            raise BfgsError(rc, "bfgs_batch_push_pairs")
+        return rc
 
     def apply_Hinv(self, V: list, out: list | None = None) -> list:
         V = [p._block(v) for p, v in zip(self.problems, V)]

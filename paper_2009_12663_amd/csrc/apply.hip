@@ -168,14 +168,19 @@ __global__ void __launch_bounds__(256) small_solve_blocks(int k, int kmax, int c
     if (bad) set_status(status, BFGS_ERR_NONFINITE);
 }
 
+// k = 0: B_0 V (or zero for B_k - B_0); a non-finite input sets the deferred status.
 template <typename Th, typename Tv, typename To>
 __global__ void scale_by_h0(int64_t n, int c, const Th* __restrict__ h0, const Tv* __restrict__ V,
-                            To* __restrict__ out, int diff) {
+                            To* __restrict__ out, int diff, int32_t* __restrict__ status) {
     const int64_t total = n * c;
+    bool bad = false;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = e % n;
-        out[e] = diff ? (To)0 : (To)(to_f64(h0[r]) * to_f64(V[e]));
+        const double v = to_f64(h0[r]) * to_f64(V[e]);
+        bad |= !isfinite(v);
+        out[e] = diff ? (To)0 : (To)v;
     }
+    if (bad) set_status(status, BFGS_ERR_NONFINITE);
 }
 
 // ---------------------------------------------------------------------------
@@ -380,7 +385,7 @@ __global__ void __launch_bounds__(256, 2) gemm2_f64mfma(int64_t n, int64_t ld, i
 }
 
 template <typename Ts, typename Th, typename To>
-int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
+int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff, const ApplyWs* fixed) {
     const int64_t n = h->n;
     const int k = h->k;
     const Th* h0 = (const Th*)h->h0;
@@ -389,7 +394,7 @@ int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
     if (k == 0) {
         int64_t g = std::min<int64_t>(4096, (n * c + 255) / 256);
         hipLaunchKernelGGL((scale_by_h0<Th, Ts, To>), dim3((int)g), dim3(256), 0, h->stream, n, c, h0, V, out,
-                           diff ? 1 : 0);
+                           diff ? 1 : 0, h->status);
         return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
     }
     const int twok = 2 * k;
@@ -397,15 +402,28 @@ int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
     // row chunks: about 2048 pass-1 workgroups, each chunk a whole number of stages
     const int64_t max_chunks = std::max<int64_t>(1, (n + FK - 1) / FK);
     int nchunks = (int)std::min<int64_t>(max_chunks, std::max(1, 2048 / (ptiles * ctiles)));
+    const size_t chunk_bytes = (size_t)twok * c * 8;
+    if (fixed) {
+        const int cap = (int)std::min<size_t>(fixed->part_bytes / chunk_bytes, 1 << 20);
+        if (cap < 1) return BFGS_ERR_ARG;
+        nchunks = std::min(nchunks, cap);
+    }
     const int64_t rows_per_chunk = round_up((n + nchunks - 1) / nchunks, FK);
     nchunks = (int)((n + rows_per_chunk - 1) / rows_per_chunk);
-    int rc;
-    if ((rc = ensure_ws(h->part, (size_t)nchunks * twok * c * 8)) != BFGS_OK) return rc;
-    if ((rc = ensure_ws(h->Z, (size_t)twok * BFGS_MAX_COLS * 8)) != BFGS_OK) return rc;
-    if ((rc = ensure_ws(h->PT, (size_t)2 * h->kmax * BFGS_MAX_COLS * 8)) != BFGS_OK) return rc;
-    double* part = (double*)h->part.ptr;
-    double* Z = (double*)h->Z.ptr;
-    double* P = (double*)h->PT.ptr;
+    double *part, *Z, *P;
+    if (fixed) {
+        part = (double*)fixed->part;
+        Z = fixed->Z;
+        P = fixed->PT;
+    } else {
+        int rc;
+        if ((rc = ensure_ws(h->part, (size_t)nchunks * chunk_bytes)) != BFGS_OK) return rc;
+        if ((rc = ensure_ws(h->Z, (size_t)twok * BFGS_MAX_COLS * 8)) != BFGS_OK) return rc;
+        if ((rc = ensure_ws(h->PT, (size_t)2 * h->kmax * BFGS_MAX_COLS * 8)) != BFGS_OK) return rc;
+        part = (double*)h->part.ptr;
+        Z = (double*)h->Z.ptr;
+        P = (double*)h->PT.ptr;
+    }
     double* T = P + (size_t)k * c;
     prof_begin(h, diff ? "hdiff_gemm1" : "apply_gemm1");
     hipLaunchKernelGGL((gemm1_f64mfma<Ts, Th>), dim3(nchunks, ptiles, ctiles), dim3(256), 0, h->stream, n, h->ld, k,
@@ -438,12 +456,17 @@ int apply_small_solve(bfgsuq_ctx* h, int c, const double* Z, double* P, double* 
     return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
 }
 
-int apply_block(bfgsuq_ctx* h, const void* V, int32_t ncols, void* out, bool diff) {
-    if (mfma_apply_supported(h, ncols)) return mfma_apply(h, V, ncols, out, diff);
+int apply_block(bfgsuq_ctx* h, const void* V, int32_t ncols, void* out, bool diff, bool out64,
+                const ApplyWs* fixed) {
+    if (out64) {
+        if (h->storage != BFGS_F32) return BFGS_ERR_ARG;
+        return apply_generic<float, float, double>(h, V, ncols, out, diff, fixed);
+    }
+    if (mfma_apply_supported(h, ncols)) return mfma_apply(h, V, ncols, out, diff, fixed);
     switch (h->storage) {
-        case BFGS_F64: return apply_generic<double, double, double>(h, V, ncols, out, diff);
-        case BFGS_F32: return apply_generic<float, float, float>(h, V, ncols, out, diff);
-        case BFGS_BF16: return apply_generic<bf16_t, float, float>(h, V, ncols, out, diff);
+        case BFGS_F64: return apply_generic<double, double, double>(h, V, ncols, out, diff, fixed);
+        case BFGS_F32: return apply_generic<float, float, float>(h, V, ncols, out, diff, fixed);
+        case BFGS_BF16: return apply_generic<bf16_t, float, float>(h, V, ncols, out, diff, fixed);
     }
     return BFGS_ERR_ARG;
 }

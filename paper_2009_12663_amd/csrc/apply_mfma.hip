@@ -575,13 +575,15 @@ bool mfma_apply_supported(const bfgsuq_ctx* h, int c) {
 
 int apply_small_solve(bfgsuq_ctx* h, int c, const double* Z, double* P, double* T);
 
-int mfma_apply(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
+size_t apply_small16_bytes(int kmax) { return (size_t)2 * 256 * 2 * (mfma_groups(kmax) + 1) * 16 * 2; }
+
+int mfma_apply(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff, const ApplyWs* fixed) {
     const int64_t n = h->n;
     const int k = h->k;
     const bf16_t* V = (const bf16_t*)Vv;
     float* out = (float*)outv;
     const int NT = (c + 31) / 32;
-    const int nk = std::max(8, (h->g1_nk + 7) / 8 * 8);   // row slots, 1/8 per XCD (tunable)
+    int nk = std::max(8, (h->g1_nk + 7) / 8 * 8);         // row slots, 1/8 per XCD (tunable)
     const int64_t rows_f1 = mfma_rows_f1(n);
     const int64_t rows_per_xcd = round_up((rows_f1 + 7) / 8, g1_stage(NT));
     const int twok = 2 * k;
@@ -590,15 +592,29 @@ int mfma_apply(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
     const int Gp = (Gk + 1) / 2 * 2;
     const int cpad = NT * 32;
     int rc;
-    if ((rc = ensure_ws(h->part, (size_t)nk * twok * c * sizeof(float))) != BFGS_OK) return rc;
-    if ((rc = ensure_ws(h->Z, (size_t)2 * h->kmax * BFGS_MAX_COLS * 8)) != BFGS_OK) return rc;
-    if ((rc = ensure_ws(h->PT, (size_t)2 * h->kmax * BFGS_MAX_COLS * 8)) != BFGS_OK) return rc;
-    if ((rc = ensure_ws(h->small16, (size_t)2 * 256 * 2 * (G + 1) * 16 * 2)) != BFGS_OK) return rc;
-    float* part = (float*)h->part.ptr;
-    double* Z = (double*)h->Z.ptr;
-    double* P = (double*)h->PT.ptr;
+    float* part;
+    double *Z, *P;
+    uint16_t* shi;
+    const size_t slot_bytes = (size_t)twok * c * sizeof(float);
+    if (fixed) {
+        const int cap = (int)(fixed->part_bytes / slot_bytes) / 8 * 8;
+        if (cap < 8) return BFGS_ERR_ARG;
+        nk = std::min(nk, cap);
+        part = (float*)fixed->part;
+        Z = fixed->Z;
+        P = fixed->PT;
+        shi = fixed->small16;
+    } else {
+        if ((rc = ensure_ws(h->part, (size_t)nk * slot_bytes)) != BFGS_OK) return rc;
+        if ((rc = ensure_ws(h->Z, (size_t)2 * h->kmax * BFGS_MAX_COLS * 8)) != BFGS_OK) return rc;
+        if ((rc = ensure_ws(h->PT, (size_t)2 * h->kmax * BFGS_MAX_COLS * 8)) != BFGS_OK) return rc;
+        if ((rc = ensure_ws(h->small16, apply_small16_bytes(h->kmax))) != BFGS_OK) return rc;
+        part = (float*)h->part.ptr;
+        Z = (double*)h->Z.ptr;
+        P = (double*)h->PT.ptr;
+        shi = (uint16_t*)h->small16.ptr;
+    }
     double* T = P + (size_t)k * c;
-    uint16_t* shi = (uint16_t*)h->small16.ptr;
     uint16_t* slo = shi + (size_t)cpad * 2 * Gp * 16;
     const bool diag = !h->gamma_mode;
     {

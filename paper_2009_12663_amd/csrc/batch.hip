@@ -24,6 +24,9 @@ struct bfgsuq_batch {
     std::vector<bfgsuq_ctx*> h;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // handle_generation() of every problem when the graph was captured: the graph holds
+    // each handle's k, tunables and workspace pointers, so any later change invalidates it
+    std::vector<unsigned long long> captured_gen;
 };
 
 namespace {
@@ -51,6 +54,7 @@ void destroy_graph(bfgsuq_batch* b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
+    b->captured_gen.clear();
 }
 
 // Mean time (ms) of `reps` calls of fn on the handle's stream.
@@ -109,6 +113,7 @@ int bfgs_autotune(bfgs_t h, int32_t ncols, int32_t rank, int32_t oversample, voi
         }
         h->qr_chains = best_ch;
     }
+    ++h->gen;   // launch shapes may have changed
     return hipStreamSynchronize(h->stream) == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
 }
 
@@ -193,6 +198,42 @@ int bfgs_batch_handle(bfgs_batch_t b, int32_t i, bfgs_t* h_out) {
     return BFGS_OK;
 }
 
+int bfgs_batch_push_pairs(bfgs_batch_t b, const void* const* S, const void* const* Y, const int32_t* kcount,
+                          bfgs_dtype in_dtype) {
+    if (!b || !S || !Y || !kcount) return BFGS_ERR_ARG;
+    if (in_dtype != BFGS_F64 && in_dtype != BFGS_F32) return BFGS_ERR_ARG;
+    int kmax = 0;
+    for (int i = 0; i < b->nprob; ++i) {
+        if (kcount[i] < 0 || (kcount[i] > 0 && (!S[i] || !Y[i]))) return BFGS_ERR_ARG;
+        if (b->h[i]->k + kcount[i] > b->h[i]->kmax) return BFGS_ERR_FULL;
+        kmax = kcount[i] > kmax ? kcount[i] : kmax;
+    }
+    const size_t es = in_dtype == BFGS_F64 ? 8 : 4;
+    int first = BFGS_OK;
+    // round j: pair j of every problem is queued on the problem's stream, then each
+    // problem's check waits for its own stream only, so the pushes of the problems overlap
+    for (int j = 0; j < kmax; ++j) {
+        std::vector<int> queued(b->nprob, 0);
+        for (int i = 0; i < b->nprob; ++i) {
+            if (j >= kcount[i]) continue;
+            bfgsuq_ctx* h = b->h[i];
+            const size_t off = (size_t)j * (size_t)h->n * es;
+            const int rc = push_enqueue(h, (const char*)S[i] + off, (const char*)Y[i] + off, in_dtype);
+            if (rc != BFGS_OK) {
+                if (first == BFGS_OK) first = rc;
+            } else {
+                queued[i] = 1;
+            }
+        }
+        for (int i = 0; i < b->nprob; ++i) {
+            if (!queued[i]) continue;
+            const int rc = push_finish(b->h[i]);
+            if (rc != BFGS_OK && first == BFGS_OK) first = rc;
+        }
+    }
+    return first;
+}
+
 int bfgs_batch_apply_Hinv(bfgs_batch_t b, const void* const* V, const int32_t* ncols, void* const* out) {
     if (!b || !V || !ncols || !out) return BFGS_ERR_ARG;
     for (int i = 0; i < b->nprob; ++i)
@@ -252,12 +293,20 @@ int bfgs_batch_graph_build(bfgs_batch_t b, const void* const* V, const int32_t* 
         destroy_graph(b);
         return BFGS_ERR_HIP;
     }
+    for (bfgsuq_ctx* h : b->h) b->captured_gen.push_back(handle_generation(h));
     return BFGS_OK;
 }
 
 int bfgs_batch_graph_launch(bfgs_batch_t b) {
     if (!b) return BFGS_ERR_ARG;
     if (!b->exec) return BFGS_ERR_STATE;
+    for (int i = 0; i < b->nprob; ++i)
+        if (handle_generation(b->h[i]) != b->captured_gen[i]) {
+            // a push, a retune or a workspace reallocation since the capture: the graph
+            // would replay stale sizes or freed buffers
+            destroy_graph(b);
+            return BFGS_ERR_STATE;
+        }
     BFGS_HIP(hipEventRecord(b->cap_in, b->main));
     BFGS_HIP(hipStreamWaitEvent(b->cap, b->cap_in, 0));
     BFGS_HIP(hipGraphLaunch(b->exec, b->cap));

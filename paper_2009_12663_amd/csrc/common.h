@@ -54,6 +54,23 @@ template <> __device__ __forceinline__ float from_f64<float>(double x) { return 
 // float64 -> float32 -> bfloat16, each to nearest-even.
 template <> __device__ __forceinline__ bf16_t from_f64<bf16_t>(double x) { return float_to_bf16((float)x); }
 
+// float64 -> bfloat16 with a single rounding to nearest-even: the float64 value is
+// first rounded to float32 by round-to-odd (truncate, then set the last bit if
+// anything was cut off), which keeps every bit that decides the final rounding
+// because float32 carries 16 more significant bits than bfloat16 (round-to-odd to
+// at least p + 2 bits followed by round-to-nearest to p bits is exact).
+__device__ __forceinline__ bf16_t f64_to_bf16_rne(double x) {
+    float f = (float)x;
+    const double back = (double)f;
+    if (back != x && x == x) {
+        uint32_t u = __builtin_bit_cast(uint32_t, f);
+        if (fabs(back) > fabs(x)) u -= 1u;   // rounded away from zero: step back to the truncation
+        u |= 1u;
+        f = __builtin_bit_cast(float, u);
+    }
+    return float_to_bf16(f);
+}
+
 template <typename T> __device__ __forceinline__ T from_f32(float x);
 template <> __device__ __forceinline__ float from_f32<float>(float x) { return x; }
 template <> __device__ __forceinline__ double from_f32<double>(float x) { return (double)x; }
@@ -67,6 +84,7 @@ inline size_t dtype_size(bfgs_dtype d) { return d == BFGS_F64 ? 8 : d == BFGS_F3
 struct Workspace {
     void* ptr = nullptr;
     size_t bytes = 0;
+    unsigned gen = 0;          // bumped on every (re)allocation: captured graphs hold ptr
 };
 
 // Optional per-kernel timing with HIP events on the handle's stream.
@@ -119,8 +137,22 @@ struct bfgsuq_ctx {
     // tunables (bfgs_autotune): row ranges of the pass-1 MFMA kernel, TSQR chains (power of two)
     int g1_nk = 128;
     int qr_chains = 256;
+    // bumped whenever k or a tunable changes; with the workspaces' counters it tells a
+    // captured graph (which holds k, the tunables and the workspace pointers) that it
+    // no longer matches the handle
+    unsigned gen = 0;
+    double* host_sc = nullptr; // pinned host copy of scalars for push_pair's check
     Profiler prof;
 };
+
+// Sum of the counters a captured graph depends on.
+inline unsigned long long handle_generation(const bfgsuq_ctx* h) {
+    const Workspace* ws[] = {&h->part, &h->Z, &h->PT, &h->small16, &h->X, &h->E, &h->Q, &h->refl, &h->tau,
+                             &h->Rtree, &h->small, &h->lam, &h->diag};
+    unsigned long long g = h->gen;
+    for (const Workspace* w : ws) g += w->gen;
+    return g;
+}
 
 void prof_begin(bfgsuq_ctx* h, const char* name);
 void prof_end(bfgsuq_ctx* h);
@@ -151,11 +183,29 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // ---------------------------------------------------------------------------
 // Entry points implemented in the other translation units.
 // ---------------------------------------------------------------------------
-int apply_block(bfgsuq_ctx* h, const void* V, int32_t ncols, void* out, bool diff);
+// Scratch of one apply call: the split-K partials of pass 1, Z (2k x c float64),
+// P and T (k x c float64 each) and the bfloat16 hi/lo small operand of pass 2.
+// apply_block grows them in the handle's workspaces unless it is given a fixed
+// buffer (the allocation-free entry point); with a fixed buffer the split-K depth
+// is capped so that the partials fit in part_bytes.
+struct ApplyWs {
+    void* part = nullptr;
+    size_t part_bytes = 0;
+    double* Z = nullptr;        // >= 2 * k_max * BFGS_MAX_COLS doubles
+    double* PT = nullptr;       // >= 2 * k_max * BFGS_MAX_COLS doubles
+    uint16_t* small16 = nullptr;// >= apply_small16_bytes(k_max)
+};
+size_t apply_small16_bytes(int kmax);
+
+// out is float64 when out64 (float32 storage only: the rSVD keeps E in float64), else
+// the storage's result type.
+int apply_block(bfgsuq_ctx* h, const void* V, int32_t ncols, void* out, bool diff, bool out64 = false,
+                const ApplyWs* fixed = nullptr);
 int rsvd_run(bfgsuq_ctx* h, int32_t rank, int32_t oversample, uint64_t seed, void* U, double* Sigma);
 // Blocked Householder TSQR E = Q R (E, Q column-major n x c; *R_out: row-major c x c in
 // the handle's workspace).  tsqr.hip.
 int tsqr_run(bfgsuq_ctx* h, int c, const float* E, float* Q, double** R_out);
+int tsqr_run(bfgsuq_ctx* h, int c, const double* E, float* Q, double** R_out);
 int tsqr_run(bfgsuq_ctx* h, int c, const double* E, double* Q, double** R_out);
 // Eigenpairs of the symmetric tridiagonal (d, e), c <= 256, by divide and conquer:
 // *w_out -> the eigenvalues (in work), Z = Qh Y with Y their eigenvectors (c x c
@@ -178,5 +228,7 @@ int64_t mfma_rows_f2(int64_t n);
 int mfma_groups(int kmax);
 int mfma_scatter_pair(bfgsuq_ctx* h, int j);
 bool mfma_apply_supported(const bfgsuq_ctx* h, int c);
-int mfma_apply(bfgsuq_ctx* h, const void* V, int c, void* out, bool diff);
+int mfma_apply(bfgsuq_ctx* h, const void* V, int c, void* out, bool diff, const ApplyWs* fixed);
 int apply_small_solve(bfgsuq_ctx* h, int c, const double* Z, double* P, double* T);
+int push_enqueue(bfgsuq_ctx* h, const void* s, const void* y, bfgs_dtype in_dtype);
+int push_finish(bfgsuq_ctx* h);

@@ -939,7 +939,12 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
         return BFGS_OK;
     }
     if ((rc = ensure_ws(h->X, (size_t)n * c * sizeof(TS))) != BFGS_OK) return rc;
-    if ((rc = ensure_ws(h->E, (size_t)n * c * sizeof(TO))) != BFGS_OK) return rc;
+    // E = (B_k - B_0) X: float64 for float32 storage, whose Sigma would otherwise carry the
+    // float32 rounding of E amplified by the Omega solve (about 6e-7 relative to Sigma_0
+    // on the 1700 x 350 x 3 grid with k = 200, c = 220, against a 1e-6 budget)
+    constexpr bool e64 = std::is_same<TS, float>::value;
+    using TE = typename std::conditional<e64, double, TO>::type;
+    if ((rc = ensure_ws(h->E, (size_t)n * c * sizeof(TE))) != BFGS_OK) return rc;
     if ((rc = ensure_ws(h->Q, (size_t)n * c * sizeof(TO))) != BFGS_OK) return rc;
     // small: part(nchunks*c*c) + T, M, B, Omega, Z (5 c*c) + d, e, taus, rot, lam (5 c) + piv
     // Q^T X row chunks: about one per CU, each chunk a multiple of the staging depth
@@ -972,23 +977,22 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     double* Fm = R1c + cc;
     int* piv = (int*)(Fm + cc);
     TS* X = (TS*)h->X.ptr;
-    TO* E = (TO*)h->E.ptr;
+    TE* E = (TE*)h->E.ptr;
     TO* Q = (TO*)h->Q.ptr;
 
     {
         ProfScope ps(h, "probes");
         if ((rc = probes_launch(h, seed, c, X, h->stream)) != BFGS_OK) return rc;
     }
-    if ((rc = apply_block(h, X, c, E, true)) != BFGS_OK) return rc;
+    if ((rc = apply_block(h, X, c, E, true, e64)) != BFGS_OK) return rc;
     double* R = nullptr;
-    auto run_tsqr = [&](const TO* src, TO* dst) { return tsqr_run(h, c, src, dst, &R); };
-    if ((rc = run_tsqr(E, Q)) != BFGS_OK) return rc;
-    if (h->storage == BFGS_F64) {
+    if ((rc = tsqr_run(h, c, E, Q, &R)) != BFGS_OK) return rc;
+    if constexpr (std::is_same<TS, double>::value) {
         // E at float64 noise level is exactly rank deficient; the zero-started
         // slot then keeps part of Q.  A second pass over the (well conditioned)
         // Q restores orthonormality: E = Q2 (R2 R1).
         if (hipMemcpyAsync(R1c, R, cc * 8, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) return BFGS_ERR_HIP;
-        if ((rc = run_tsqr(Q, E)) != BFGS_OK) return rc;
+        if ((rc = tsqr_run(h, c, Q, E, &R)) != BFGS_OK) return rc;
         hipLaunchKernelGGL(tri_mul, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, h->stream, c, R, R1c, Fm);
         std::swap(E, Q);   // Q now points at the second-pass factor
         R = Fm;

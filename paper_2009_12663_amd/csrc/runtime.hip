@@ -21,6 +21,7 @@ int ensure_ws(Workspace& w, size_t bytes) {
         w.ptr = nullptr;
         w.bytes = 0;
     }
+    ++w.gen;
     if (hipMalloc(&w.ptr, bytes) != hipSuccess) {
         w.ptr = nullptr;
         return BFGS_ERR_ALLOC;
@@ -71,6 +72,18 @@ __global__ void store_pair_kernel(int64_t n, const Tin* __restrict__ s, const Ti
          r += (int64_t)gridDim.x * blockDim.x) {
         Scol[r] = from_f64<Tst>(to_f64(s[r]));
         Ycol[r] = from_f64<Tst>(to_f64(y[r]));
+    }
+}
+
+// float64 input to bfloat16 storage: one rounding to nearest-even.
+template <>
+__global__ void store_pair_kernel<double, bf16_t>(int64_t n, const double* __restrict__ s,
+                                                  const double* __restrict__ y, bf16_t* __restrict__ Scol,
+                                                  bf16_t* __restrict__ Ycol) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        Scol[r] = f64_to_bf16_rne(s[r]);
+        Ycol[r] = f64_to_bf16_rne(y[r]);
     }
 }
 
@@ -206,6 +219,67 @@ static void launch_gram(bfgsuq_ctx* h, int j) {
                        h->gram_part);
 }
 
+// push_pair in two halves, so that a batch can enqueue the pushes of many handles
+// before it waits for any: push_enqueue stores the pair as column k and queues the
+// Gram updates and the copy of (gamma, s^T y, y^T B_0 y) to pinned host memory;
+// push_finish waits for the handle's stream and accepts or drops the pair.
+int push_enqueue(bfgsuq_ctx* h, const void* s, const void* y, bfgs_dtype in_dtype) {
+    if (!h || !s || !y) return BFGS_ERR_ARG;
+    if (in_dtype != BFGS_F64 && in_dtype != BFGS_F32) return BFGS_ERR_ARG;
+    if (h->k >= h->kmax) return BFGS_ERR_FULL;
+    const int j = h->k;
+    switch (h->storage) {
+        case BFGS_F64:
+            if (in_dtype == BFGS_F64) launch_store<double, double>(h, s, y, j);
+            else launch_store<float, double>(h, s, y, j);
+            launch_gram<double, double>(h, j);
+            break;
+        case BFGS_F32:
+            if (in_dtype == BFGS_F64) launch_store<double, float>(h, s, y, j);
+            else launch_store<float, float>(h, s, y, j);
+            launch_gram<float, float>(h, j);
+            break;
+        case BFGS_BF16:
+            if (in_dtype == BFGS_F64) launch_store<double, bf16_t>(h, s, y, j);
+            else launch_store<float, bf16_t>(h, s, y, j);
+            if (mfma_scatter_pair(h, j) != BFGS_OK) return BFGS_ERR_HIP;
+            launch_gram<bf16_t, float>(h, j);
+            break;
+    }
+    BFGS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(gram_finish_kernel, dim3((j + 1 + 255) / 256), dim3(256), 0, h->stream, j, h->kmax,
+                       h->gram_blocks, h->gram_part, h->Rm, h->YHY, h->scalars, h->gamma_mode ? 1 : 0);
+    BFGS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(rinv_update_kernel, dim3(1), dim3(256), 0, h->stream, j, h->kmax, h->Rm, h->Rinv, h->RinvT);
+    BFGS_HIP(hipGetLastError());
+    BFGS_HIP(hipMemcpyAsync(h->host_sc, h->scalars, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    return BFGS_OK;
+}
+
+int push_finish(bfgsuq_ctx* h) {
+    const int j = h->k;
+    BFGS_HIP(hipStreamSynchronize(h->stream));
+    const double g = h->host_sc[0], sy = h->host_sc[1], yhy = h->host_sc[2];
+    if (!std::isfinite(sy) || !std::isfinite(yhy) || (h->gamma_mode && j == 0 && !std::isfinite(g)))
+        return BFGS_ERR_NONFINITE;
+    if (!(sy > 0.0)) return BFGS_ERR_CURVATURE;
+    if (h->gamma_mode && j == 0) {
+        if (!(g > 0.0)) return BFGS_ERR_CURVATURE;
+        if (h->storage == BFGS_F64)
+            hipLaunchKernelGGL(fill_h0_kernel<double>, dim3(grid_for(h->n)), dim3(256), 0, h->stream, h->n,
+                               (double*)h->h0, (const double*)h->scalars);
+        else
+            hipLaunchKernelGGL(fill_h0_kernel<float>, dim3(grid_for(h->n)), dim3(256), 0, h->stream, h->n,
+                               (float*)h->h0, (const double*)h->scalars);
+        BFGS_HIP(hipGetLastError());
+        h->gamma_known = true;
+    }
+    h->k = j + 1;
+    ++h->gen;
+    h->have_rsvd = false;
+    return BFGS_OK;
+}
+
 extern "C" {
 
 const char* bfgs_status_string(int code) {
@@ -234,6 +308,7 @@ int bfgs_destroy(bfgs_t h) {
                        &h->Rtree, &h->small, &h->lam, &h->diag};
     for (Workspace* w : ws) free_ws(*w);
     for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
+    if (h->host_sc) (void)hipHostFree(h->host_sc);
     delete h;
     return BFGS_OK;
 }
@@ -272,6 +347,10 @@ int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, vo
     alloc((void**)&h->gram_part, (size_t)k_max * h->gram_blocks * 2 * 8);
     alloc((void**)&h->scalars, 8 * 8);
     alloc((void**)&h->status, 64);
+    if (rc == BFGS_OK && hipHostMalloc((void**)&h->host_sc, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        h->host_sc = nullptr;
+        rc = BFGS_ERR_ALLOC;
+    }
     size_t f1_bytes = 0, f2_bytes = 0;
     if (storage == BFGS_BF16) {
         f1_bytes = (size_t)mfma_rows_f1(n) * k_max * 2;
@@ -322,55 +401,8 @@ int bfgs_num_pairs(bfgs_t h, int32_t* k_out) {
 }
 
 int bfgs_push_pair(bfgs_t h, const void* s, const void* y, bfgs_dtype in_dtype) {
-    if (!h || !s || !y) return BFGS_ERR_ARG;
-    if (in_dtype != BFGS_F64 && in_dtype != BFGS_F32) return BFGS_ERR_ARG;
-    if (h->k >= h->kmax) return BFGS_ERR_FULL;
-    const int j = h->k;
-    switch (h->storage) {
-        case BFGS_F64:
-            if (in_dtype == BFGS_F64) launch_store<double, double>(h, s, y, j);
-            else launch_store<float, double>(h, s, y, j);
-            launch_gram<double, double>(h, j);
-            break;
-        case BFGS_F32:
-            if (in_dtype == BFGS_F64) launch_store<double, float>(h, s, y, j);
-            else launch_store<float, float>(h, s, y, j);
-            launch_gram<float, float>(h, j);
-            break;
-        case BFGS_BF16:
-            if (in_dtype == BFGS_F64) launch_store<double, bf16_t>(h, s, y, j);
-            else launch_store<float, bf16_t>(h, s, y, j);
-            if (mfma_scatter_pair(h, j) != BFGS_OK) return BFGS_ERR_HIP;
-            launch_gram<bf16_t, float>(h, j);
-            break;
-    }
-    BFGS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(gram_finish_kernel, dim3((j + 1 + 255) / 256), dim3(256), 0, h->stream, j, h->kmax,
-                       h->gram_blocks, h->gram_part, h->Rm, h->YHY, h->scalars, h->gamma_mode ? 1 : 0);
-    BFGS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(rinv_update_kernel, dim3(1), dim3(256), 0, h->stream, j, h->kmax, h->Rm, h->Rinv, h->RinvT);
-    BFGS_HIP(hipGetLastError());
-    double sc[3];
-    BFGS_HIP(hipMemcpyAsync(sc, h->scalars, sizeof(sc), hipMemcpyDeviceToHost, h->stream));
-    BFGS_HIP(hipStreamSynchronize(h->stream));
-    const double sy = sc[1], yhy = sc[2];
-    if (!std::isfinite(sy) || !std::isfinite(yhy) || (h->gamma_mode && j == 0 && !std::isfinite(sc[0])))
-        return BFGS_ERR_NONFINITE;
-    if (!(sy > 0.0)) return BFGS_ERR_CURVATURE;
-    if (h->gamma_mode && j == 0) {
-        if (!(sc[0] > 0.0)) return BFGS_ERR_CURVATURE;
-        if (h->storage == BFGS_F64)
-            hipLaunchKernelGGL(fill_h0_kernel<double>, dim3(grid_for(h->n)), dim3(256), 0, h->stream, h->n,
-                               (double*)h->h0, (const double*)h->scalars);
-        else
-            hipLaunchKernelGGL(fill_h0_kernel<float>, dim3(grid_for(h->n)), dim3(256), 0, h->stream, h->n,
-                               (float*)h->h0, (const double*)h->scalars);
-        BFGS_HIP(hipGetLastError());
-        h->gamma_known = true;
-    }
-    h->k = j + 1;
-    h->have_rsvd = false;
-    return BFGS_OK;
+    const int rc = push_enqueue(h, s, y, in_dtype);
+    return rc != BFGS_OK ? rc : push_finish(h);
 }
 
 int bfgs_apply_Hinv(bfgs_t h, const void* V, int32_t ncols, void* out) {

@@ -661,8 +661,8 @@ inline int floor_pow2(int64_t x) {
 }
 
 // PF: doubles per thread that stage one stored panel in the backward passes.
-template <typename TO, typename SlotT, int BT, int PF>
-int tsqr_impl(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
+template <typename TE, typename TQ, typename SlotT, int BT, int PF>
+int tsqr_impl(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out) {
     constexpr int PS = Layout<BT>::PS;
     const int64_t n = h->n;
     const int np = (c + PW - 1) / PW;
@@ -686,7 +686,7 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     static bool attr_done = false;
     if (!attr_done) {
         const int lim = 160 * 1024;
-        if (hipFuncSetAttribute((const void*)leaf_backward<TO, SlotT, BT, PF>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
+        if (hipFuncSetAttribute((const void*)leaf_backward<TQ, SlotT, BT, PF>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
             hipFuncSetAttribute((const void*)tree_forward_q<SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess ||
             hipFuncSetAttribute((const void*)tree_backward<SlotT, BT, PF>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
             return BFGS_ERR_HIP;
@@ -694,14 +694,14 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     }
     static bool attr_q = false;
     if (!attr_q) {
-        if (hipFuncSetAttribute((const void*)leaf_forward_q<TO, SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        if (hipFuncSetAttribute((const void*)leaf_forward_q<TE, SlotT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 160 * 1024) != hipSuccess)
             return BFGS_ERR_HIP;
         attr_q = true;
     }
     const int ring = qf_ring<SlotT>(c);   // >= 2: the slot type was chosen for that
     prof_begin(h, "tsqr_leaf_fwd");
-    hipLaunchKernelGGL((leaf_forward_q<TO, SlotT>), dim3(nchains), dim3(LPC * 16 * np), qf_lds_bytes<SlotT>(c, ring),
+    hipLaunchKernelGGL((leaf_forward_q<TE, SlotT>), dim3(nchains), dim3(LPC * 16 * np), qf_lds_bytes<SlotT>(c, ring),
                        h->stream, n, c, rows_per_chain, E, refl, Rs, ring);
     prof_end(h);
     prof_begin(h, "tsqr_tree");
@@ -721,15 +721,15 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     }
     prof_end(h);
     prof_begin(h, "tsqr_leaf_bwd");
-    hipLaunchKernelGGL((leaf_backward<TO, SlotT, BT, PF>), dim3(nchains), dim3(threads), smem, h->stream, n, c,
+    hipLaunchKernelGGL((leaf_backward<TQ, SlotT, BT, PF>), dim3(nchains), dim3(threads), smem, h->stream, n, c,
                        rows_per_chain, refl, Qtop, Q);
     prof_end(h);
     *R_out = Rs;   // chain 0 holds the final R (row-major, upper triangular)
     return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
 }
 
-template <typename TO>
-int tsqr_dispatch(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
+template <typename TE, typename TQ>
+int tsqr_dispatch(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out) {
     if (c < 1 || c > 256) return BFGS_ERR_ARG;
     // 64-row tiles keep a tile's fragments, the staging registers and the panel work
     // within 128 registers per lane (1024-thread workgroups); the slot is float64
@@ -739,15 +739,24 @@ int tsqr_dispatch(bfgsuq_ctx* h, int c, const TO* E, TO* Q, double** R_out) {
     // staging doubles per thread for one stored panel (64 * ceil(c / 16) threads); more
     // than 8 (c <= 32) copies panels straight to LDS
     const int pf = ceil_div(Layout<64>::PS, 64 * ceil_div(c, PW));
-    if (pf <= 2) return dslot ? tsqr_impl<TO, double, 64, 2>(h, c, E, Q, R_out) : tsqr_impl<TO, float, 64, 2>(h, c, E, Q, R_out);
-    if (pf <= 3) return dslot ? tsqr_impl<TO, double, 64, 3>(h, c, E, Q, R_out) : tsqr_impl<TO, float, 64, 3>(h, c, E, Q, R_out);
-    if (pf <= 5) return dslot ? tsqr_impl<TO, double, 64, 5>(h, c, E, Q, R_out) : tsqr_impl<TO, float, 64, 5>(h, c, E, Q, R_out);
-    return dslot ? tsqr_impl<TO, double, 64, 8>(h, c, E, Q, R_out) : tsqr_impl<TO, float, 64, 8>(h, c, E, Q, R_out);
+    if (pf <= 2) return dslot ? tsqr_impl<TE, TQ, double, 64, 2>(h, c, E, Q, R_out) : tsqr_impl<TE, TQ, float, 64, 2>(h, c, E, Q, R_out);
+    if (pf <= 3) return dslot ? tsqr_impl<TE, TQ, double, 64, 3>(h, c, E, Q, R_out) : tsqr_impl<TE, TQ, float, 64, 3>(h, c, E, Q, R_out);
+    if (pf <= 5) return dslot ? tsqr_impl<TE, TQ, double, 64, 5>(h, c, E, Q, R_out) : tsqr_impl<TE, TQ, float, 64, 5>(h, c, E, Q, R_out);
+    return dslot ? tsqr_impl<TE, TQ, double, 64, 8>(h, c, E, Q, R_out) : tsqr_impl<TE, TQ, float, 64, 8>(h, c, E, Q, R_out);
 }
 
 }  // namespace
 
+extern "C" int bfgs_tsqr_shape(int32_t c, int32_t* slot_f64, int32_t* ring) {
+    if (c < 1 || c > BFGS_MAX_COLS) return BFGS_ERR_ARG;
+    const bool dslot = lds_bytes<64, double>(c) <= 160 * 1024 && qf_ring<double>(c) >= 2;
+    if (slot_f64) *slot_f64 = dslot ? 1 : 0;
+    if (ring) *ring = dslot ? qf_ring<double>(c) : qf_ring<float>(c);
+    return BFGS_OK;
+}
+
 int tsqr_run(bfgsuq_ctx* h, int c, const float* E, float* Q, double** R_out) { return tsqr_dispatch(h, c, E, Q, R_out); }
+int tsqr_run(bfgsuq_ctx* h, int c, const double* E, float* Q, double** R_out) { return tsqr_dispatch(h, c, E, Q, R_out); }
 int tsqr_run(bfgsuq_ctx* h, int c, const double* E, double* Q, double** R_out) {
     return tsqr_dispatch(h, c, E, Q, R_out);
 }

@@ -16,6 +16,16 @@ def rel_f(a, b) -> float:
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def col_max_rel(a, b) -> float:
+    """Element-wise error per column: max over columns of max_i |a - b| / max_i |b|
+    (rows of the (ncols, n) arrays are columns of the block)."""
+    a = np.atleast_2d(np.asarray(a, np.float64))
+    b = np.atleast_2d(np.asarray(b, np.float64))
+    num = np.abs(a - b).max(axis=1)
+    den = np.maximum(np.abs(b).max(axis=1), 1e-300)
+    return float((num / den).max())
+
+
 def gpu_input(x64: torch.Tensor, storage: str) -> torch.Tensor:
     """What the binding is handed: float64 for float64 storage, float32 otherwise."""
     return x64.to("cuda", torch.float64 if storage == "f64" else torch.float32)

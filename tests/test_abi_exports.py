@@ -32,7 +32,7 @@ def lib():
 def test_header_declares_the_path():
     d = declarations()
     for name in ["bfgs_create", "bfgs_push_pair", "bfgs_apply_Hinv", "bfgs_rsvd", "bfgs_posterior_diag",
-                 "bfgs_destroy", "bfgs_batch_create", "bfgs_batch_graph_build", "bfgs_mlp_train_step"]:
+                 "bfgs_destroy", "bfgs_batch_create", "bfgs_batch_push_pairs", "bfgs_batch_graph_build", "bfgs_mlp_train_step"]:
         assert name in d, name
 
 

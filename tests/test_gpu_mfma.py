@@ -1,14 +1,14 @@
 """Parity of the bfloat16 MFMA path of bfgs_apply_Hinv / bfgs_apply_Hdiff against the
 float64 oracle on the same stored (bfloat16-rounded) inputs: ragged and unaligned n,
 k and ncols at tile edges, diagonal and scalar B_0, and the full-size workload
-(n = 1,785,000, k = 200, 220 columns) on sampled columns."""
+(n = 1,785,000, k = 200, 220 columns) on all its columns, element-wise."""
 import numpy as np
 import pytest
 import torch
 
 from oracle import recursion
 from workloads import quadratic as wq
-from tests.helpers import rel_f, gpu_input, oracle_input, h0_storage, make_pairs, gamma_of
+from tests.helpers import rel_f, col_max_rel, gpu_input, oracle_input, h0_storage, make_pairs, gamma_of
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-3
@@ -48,13 +48,14 @@ def test_mfma_apply_parity(kind, nx, nz, k, c, precond):
     V = wq.normal_block(prob.n, c, seed=c + 1)
     out = H.apply_Hinv(gpu_input(V, "bf16")).double().cpu().numpy()
     want, h, Vq = oracle(S, Y, V, h0)
-    err = rel_f(out, want)
+    err, elem = rel_f(out, want), col_max_rel(out, want)
     corr = rel_f(out - h * Vq, want - h * Vq)
     outd = H.apply_Hdiff(gpu_input(V, "bf16")).double().cpu().numpy()
     wantd, _, _ = oracle(S, Y, V, h0, diff=True)
-    errd = rel_f(outd, wantd)
-    print(f"  rel_F={err:.3e} correction={corr:.3e} diff={errd:.3e}", flush=True)
-    assert err <= TOL and errd <= TOL
+    errd, elemd = rel_f(outd, wantd), col_max_rel(outd, wantd)
+    print(f"  rel_F={err:.3e} elem={elem:.3e} correction={corr:.3e} diff={errd:.3e} diff elem={elemd:.3e}",
+          flush=True)
+    assert err <= TOL and elem <= TOL and errd <= TOL and elemd <= TOL
     assert H.get_status() == 0
     H.close()
 
@@ -70,9 +71,9 @@ def test_mfma_matches_generic_beyond_256_pairs():
     H.close()
 
 
-def test_mfma_full_size_sampled_columns():
+def test_mfma_full_size_all_columns():
     """The benchmark workload: 1700 x 350 x 3 grid, k = 200, 220 probe columns, launched
-    exactly as bench.py does; three columns checked against the oracle."""
+    exactly as bench.py does; every column against the oracle, element-wise."""
     import paper_2009_12663_amd as P
     print("\n[mfma full size] generating pairs", flush=True)
     prob = wq.make_problem("grid3", device="cuda")
@@ -82,18 +83,19 @@ def test_mfma_full_size_sampled_columns():
         H.push_pair(s.float(), y.float())
     V = H.generate_probes(2, 220)
     out = H.apply_Hinv(V)
-    cols = [0, 111, 219]
     Sq = S.float().to(torch.bfloat16).double().cpu().numpy()
     Yq = Y.float().to(torch.bfloat16).double().cpu().numpy()
     del S, Y
     g = float(np.float32(gamma_of(Sq, Yq)))
     h = np.full(prob.n, g)
-    Vq = V[cols].double().cpu().numpy()
-    want = recursion.apply_hk(h, Sq, Yq, Vq)
-    got = out[cols].double().cpu().numpy()
-    err = rel_f(got, want)
-    corr = rel_f(got - h * Vq, want - h * Vq)
-    print(f"  sampled columns rel_F={err:.3e} correction={corr:.3e}", flush=True)
-    assert err <= TOL
+    Vq = V.double().cpu().numpy()
+    got = out.double().cpu().numpy()
     assert H.get_status() == 0
     H.close()
+    del out, V
+    print("[mfma full size] oracle over 220 columns", flush=True)
+    want = recursion.apply_hk(h, Sq, Yq, Vq)
+    err, elem = rel_f(got, want), col_max_rel(got, want)
+    corr = rel_f(got - h * Vq, want - h * Vq)
+    print(f"  rel_F={err:.3e} elem={elem:.3e} correction={corr:.3e}", flush=True)
+    assert err <= TOL and elem <= TOL

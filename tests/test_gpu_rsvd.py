@@ -124,17 +124,31 @@ def test_rsvd_parity(storage, kind, nx, nz, k, rank, p, precond):
     assert r["orth"] <= (1e-12 if storage == "f64" else 1e-5)
 
 
-@pytest.mark.parametrize("storage,c", [("f64", 184), ("f32", 185)])
-def test_rsvd_fold_configuration_edges(storage, c):
-    """The TSQR fold's configuration edges: c = 184 is the largest block with a
-    float64 slot, whose reflector ring then holds two groups (float64 E: no
-    prefetch); c = 185 takes the float32 slot and a ring of eight.  Conjugate-
-    gradient pairs, rank = the pairs' count, p = the rest of c: c >= k + 1, so the
-    sketch is exact (as in the other float32 cases)."""
+def _fold_edges():
+    """Block widths at the TSQR fold's configuration edges, from the library's own
+    shape query: the largest c with a float64 slot, the first with a float32 slot,
+    and the first float32-slot c whose reflector ring holds eight groups."""
+    from paper_2009_12663_amd import _lib
+    shapes = {c: _lib.tsqr_shape(c) for c in range(1, 257)}
+    last64 = max(c for c, (f64, _) in shapes.items() if f64)
+    ring8 = min(c for c, (f64, r) in shapes.items() if not f64 and r == 8)
+    return [("f64", last64), ("f32", last64), ("f32", last64 + 1), ("bf16", last64 + 1), ("f32", ring8)]
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_rsvd_fold_configuration_edges(case):
+    """The TSQR fold's configuration edges (widths from the library's shape query):
+    the largest block with a float64 slot, the first with a float32 slot, and a
+    float32 slot whose ring holds eight reflector groups.  Conjugate-gradient pairs,
+    rank = the pairs' count, p = the rest of c: c >= k + 1, so the sketch is exact."""
+    from paper_2009_12663_amd import _lib
+    storage, c = _fold_edges()[case]
+    f64_slot, ring = _lib.tsqr_shape(c)
     prob, S, Y, h0 = make_pairs("cg", 60, 40, c - 10, seed=c)
     rank = S.shape[0]
     p = c - rank
-    print(f"\n[rsvd fold edge] {storage} c={c} rank={rank} p={p}", flush=True)
+    print(f"\n[rsvd fold edge] {storage} c={c} slot={'f64' if f64_slot else 'f32'} ring={ring} rank={rank} p={p}",
+          flush=True)
     r = run_case(storage, S, Y, h0, rank, p, seed=5)
     print(f"  sigma {r['sig']:.2e} rec {r['rec']:.2e} diag_max {r['diag_max']:.2e} orth {r['orth']:.2e}", flush=True)
     tol = SIG_TOL[storage]
@@ -206,18 +220,19 @@ def test_rsvd_deterministic():
     H.close()
 
 
-@pytest.mark.parametrize("storage,config", [("f32", "grid2"), ("bf16", "grid3")])
+@pytest.mark.parametrize("storage,config", [("f32", "grid2"), ("f32", "grid3"), ("bf16", "grid3")])
 def test_rsvd_full_size(storage, config):
     """The full-size workloads of the two paths, gamma I, seed 5: float32 on the
     600 x 200 x 3 grid (n = 360,000, k = 100 exact-line-search pairs, rank 100 +
     oversample 20) and bfloat16 on the 1700 x 350 x 3 grid (n = 1,785,000, k = 200,
-    rank 200 + 20, the configuration the benchmark times).  Sigma, U and the posterior
+    rank 200 + 20, the configuration the benchmark times), and float32 on that grid too.  Sigma, U and the posterior
     diagonal against the oracle (Alg. 3 in float64 on the same stored S, Y and
     probes).  Sigma is compared relative to Sigma_0 (as in the cases above) and, for
-    the significant eigenvalues (|Sigma_i| >= 1e-3 |Sigma_0|), relative to itself: E
-    and Q are stored in float32 on both paths (relative rounding 6e-8), and the
-    Omega solve amplifies that by about cond(Q^T X), so the smaller significant
-    eigenvalues carry relative errors of order 1e-5 (float32) and 1e-4 (bfloat16)."""
+    the significant eigenvalues (|Sigma_i| >= 1e-3 |Sigma_0|), relative to itself: Q
+    is stored in float32 on both paths and E in float32 on the bfloat16 path
+    (relative rounding 6e-8), and the Omega solve amplifies that by about
+    cond(Q^T X), so the smaller significant eigenvalues carry relative errors of
+    order 1e-5 (float32) and 1e-4 (bfloat16)."""
     cfg = wq.CONFIGS[config]
     rank, p = cfg["rank"], cfg["oversample"]
     print(f"\n[rsvd full size] {storage} {config}: k={cfg['k']} rank={rank} p={p}", flush=True)
