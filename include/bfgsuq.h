@@ -143,6 +143,19 @@ int bfgs_rsvd(bfgs_t h, int32_t rank, int32_t oversample, uint64_t seed, void* U
  * BFGS_ERR_STATE if no rsvd has run since the last push.                      */
 int bfgs_posterior_diag(bfgs_t h, void* out);
 
+/* bfgs_apply_Hinv_noalloc — bfgs_apply_Hinv for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, result and errors as bfgs_apply_Hinv,
+ * to within the rounding of a different split-K summation; it never calls
+ * hipMalloc or hipFree.  Its scratch is a fixed device array of the library
+ * (about 90 MiB per GPU, held until the process ends) instead of the handle's
+ * workspaces: the split-K depth of the first pass is capped to fit in it, and
+ * every size the handle allows (k_max <= BFGS_MAX_PAIRS, ncols <= BFGS_MAX_COLS)
+ * fits.  Call it with the handle's device current.  All calls on one GPU share
+ * that array, so calls that may overlap on one GPU (other streams, or handles
+ * whose streams are not ordered) race; serialise them.                         */
+int bfgs_apply_Hinv_noalloc(bfgs_t h, const void* V, int32_t ncols, void* out);
+
 /* bfgs_get_pair — copies stored pair j (0 <= j < k), upcast exactly to
  * float64 (F64 storage) or float32, into s_out / y_out (device, n entries
  * each; either may be NULL).  For checking what the library stored.           */

@@ -32,7 +32,7 @@ MAX_COLS = 256
 MAX_PAIRS = 1024
 
 EXPORTS = [
-    "bfgs_create", "bfgs_destroy", "bfgs_push_pair", "bfgs_num_pairs", "bfgs_apply_Hinv",
+    "bfgs_create", "bfgs_destroy", "bfgs_push_pair", "bfgs_num_pairs", "bfgs_apply_Hinv", "bfgs_apply_Hinv_noalloc",
     "bfgs_apply_Hdiff", "bfgs_generate_probes", "bfgs_rsvd", "bfgs_posterior_diag",
     "bfgs_get_pair", "bfgs_get_h0", "bfgs_get_status", "bfgs_status_string",
     "bfgs_profile", "bfgs_profile_report", "bfgs_autotune", "bfgs_tuning", "bfgs_sync", "bfgs_tsqr_shape",
@@ -67,6 +67,7 @@ def load(path: str = LIB_PATH):
         "bfgs_push_pair": [vp, vp, vp, ctypes.c_int],
         "bfgs_num_pairs": [vp, ctypes.POINTER(i32)],
         "bfgs_apply_Hinv": [vp, vp, i32, vp],
+        "bfgs_apply_Hinv_noalloc": [vp, vp, i32, vp],
         "bfgs_apply_Hdiff": [vp, vp, i32, vp],
         "bfgs_generate_probes": [vp, u64, i32, vp],
         "bfgs_rsvd": [vp, i32, i32, u64, vp, vp],
