@@ -72,6 +72,66 @@ def rsvd(h0, S, Y, X, rank: int, E=None):
                 U=V.T.copy(), Sigma=lam[:rank].copy())
 
 
+def rsvd_precond(h0, S, Y, X, rank: int, E=None):
+    """Alg. 3 on the B_0-whitened difference A_w = B_0^-1/2 (B_k - B_0) B_0^-1/2, whose
+    eigenvalues are those of B_k B_0^-1 - I (similar matrices): the view in which the
+    retrieved operator "starts from the identity".  With V = X the probes the library
+    stores, the whitened sketch is E_w = A_w X_w for X_w = B_0^1/2 X, computed as
+    B_0^-1/2 ((B_k - B_0) X); then Q R = E_w, Omega (Q^T X_w) = Q^T E_w, and U, Sigma
+    as in rsvd().  U is the whitened basis: B_k = B_0 + B_0^1/2 U diag(Sigma) U^T B_0^1/2."""
+    h0 = np.asarray(h0, np.float64)
+    X = np.asarray(X, np.float64)
+    c, n = X.shape
+    assert rank <= c <= n
+    if E is None:
+        E = apply_hk(h0, S, Y, X, subtract_b0=True)
+    Ew = (E / np.sqrt(h0)).T
+    Xw = (X * np.sqrt(h0)).T
+    Q, R = np.linalg.qr(Ew, mode="reduced")
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    Q = Q * d
+    R = d[:, None] * R
+    T = Q.T @ Xw
+    F = Q.T @ Ew
+    lu, piv = scipy.linalg.lu_factor(T.T)
+    Omega = scipy.linalg.lu_solve((lu, piv), F.T).T
+    Omega = 0.5 * (Omega + Omega.T)
+    lam, Us = np.linalg.eigh(Omega)
+    lam, Us = order_and_sign(lam, Us)
+    V = Q @ Us[:, :rank]
+    return dict(E=E, Q=Q, T=T, Omega=Omega, lam=lam, U=V.T.copy(), Sigma=lam[:rank].copy())
+
+
+def rsvd_two_pass(h0, S, Y, X, rank: int, precond: bool = False):
+    """The two-pass variant (Halko et al.'s Q^T A Q): Q from the sketch as in rsvd()
+    (or rsvd_precond()), then a second application of the operator to Q itself and
+    Omega = Q^T (A Q), symmetrised, in place of the solve with Q^T X."""
+    h0 = np.asarray(h0, np.float64)
+    X = np.asarray(X, np.float64)
+    c, n = X.shape
+    E = apply_hk(h0, S, Y, X, subtract_b0=True)
+    w = 1.0 / np.sqrt(h0) if precond else np.ones(n)
+    Q, R = np.linalg.qr((E * w).T, mode="reduced")
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    Q = Q * d
+    AQ = (apply_hk(h0, S, Y, (Q * w[:, None]).T, subtract_b0=True) * w).T
+    Omega = Q.T @ AQ
+    Omega = 0.5 * (Omega + Omega.T)
+    lam, Us = np.linalg.eigh(Omega)
+    lam, Us = order_and_sign(lam, Us)
+    V = Q @ Us[:, :rank]
+    return dict(Q=Q, Omega=Omega, lam=lam, U=V.T.copy(), Sigma=lam[:rank].copy())
+
+
+def posterior_diag_precond(h0, U, Sigma) -> np.ndarray:
+    """diag(B_0 + B_0^1/2 U^T diag(Sigma) U B_0^1/2) with the whitened basis U (rank, n)."""
+    h0 = np.asarray(h0, np.float64)
+    U = np.asarray(U, np.float64)
+    return h0 + h0 * (np.asarray(Sigma, np.float64)[:, None] * U * U).sum(axis=0)
+
+
 def posterior_diag(h0, U, Sigma) -> np.ndarray:
     """diag(U^T diag(Sigma) U) + h0 with U of shape (rank, n)."""
     U = np.asarray(U, np.float64)

@@ -159,3 +159,49 @@ def test_box_muller_pair_members_independent():
             u, v = x[a::4], x[b::4]
             assert abs(np.corrcoef(u, v)[0, 1]) < 0.015
             assert abs(np.corrcoef(u * u, v * v)[0, 1]) < 0.015
+
+
+# --- preconditioned and two-pass variants ---------------------------------------------------
+def _small_history(n=60, k=8, seed=3):
+    rng = np.random.default_rng(seed)
+    M = rng.standard_normal((n, n))
+    A = M @ M.T / n + np.eye(n)
+    S = rng.standard_normal((k, n))
+    Y = S @ A
+    h0 = rng.uniform(0.3, 3.0, n)
+    return h0, S, Y
+
+
+def test_precond_sigma_is_spectrum_of_bk_b0inv_minus_identity():
+    """The whitened difference's eigenvalues are those of B_k B_0^-1 - I (the operator the
+    paper says starts from the identity), and when rank + p >= rank(B_k - B_0) the
+    factorisation is exact: B_0 + B_0^1/2 U Sigma U^T B_0^1/2 = B_k."""
+    h0, S, Y = _small_history()
+    n, k = h0.shape[0], S.shape[0]
+    Bk = dense.inverse_hessian(h0, S, Y)
+    ev = np.linalg.eigvals(Bk @ np.diag(1.0 / h0) - np.eye(n)).real
+    ev = ev[np.argsort(-np.abs(ev))]
+    X = probes.normal_block(n, 2 * k + 6, 5)
+    out = rsvd.rsvd_precond(h0, S, Y, X, 2 * k)
+    np.testing.assert_allclose(np.sort(out["Sigma"]), np.sort(ev[:2 * k]), rtol=0, atol=1e-10 * abs(ev[0]))
+    W = np.sqrt(h0)[:, None] * out["U"].T
+    rec = np.diag(h0) + (W * out["Sigma"]) @ W.T
+    assert np.abs(rec - Bk).max() <= 1e-10 * np.abs(Bk).max()
+    np.testing.assert_allclose(rsvd.posterior_diag_precond(h0, out["U"], out["Sigma"]), np.diag(Bk), rtol=1e-10)
+
+
+@pytest.mark.parametrize("precond", [False, True])
+def test_two_pass_is_exact_and_symmetric(precond):
+    h0, S, Y = _small_history(seed=7)
+    n, k = h0.shape[0], S.shape[0]
+    Bk = dense.inverse_hessian(h0, S, Y)
+    X = probes.normal_block(n, 2 * k + 4, 9)
+    out = rsvd.rsvd_two_pass(h0, S, Y, X, 2 * k, precond=precond)
+    if precond:
+        W = np.sqrt(h0)[:, None] * out["U"].T
+        rec = np.diag(h0) + (W * out["Sigma"]) @ W.T
+    else:
+        rec = np.diag(h0) + (out["U"].T * out["Sigma"]) @ out["U"]
+    assert np.abs(rec - Bk).max() <= 1e-10 * np.abs(Bk).max()
+    single = (rsvd.rsvd_precond if precond else rsvd.rsvd)(h0, S, Y, X, 2 * k)
+    np.testing.assert_allclose(np.sort(out["Sigma"]), np.sort(single["Sigma"]), atol=1e-10 * abs(single["Sigma"][0]))
