@@ -146,7 +146,9 @@ def oracle_rsvd_errors(S, Y, h0, storage, seed, rank, p, Sig, dg):
     dref = orsvd.posterior_diag(h0, ref["U"], ref["Sigma"])
     sig = Sig.cpu().numpy()
     d = dg.double().cpu().numpy()
-    out = {"sigma_rel_err": float(np.abs(sig - ref["Sigma"]).max() / abs(ref["Sigma"][0])),
+    # the spectra compared as sets (sorted by signed value): near-ties in |lambda| of
+    # opposite sign may be ordered either way
+    out = {"sigma_rel_err": float(np.abs(np.sort(sig) - np.sort(ref["Sigma"])).max() / abs(ref["Sigma"][0])),
            "diag_rel_F": float(np.linalg.norm(d - dref) / np.linalg.norm(dref)),
            "diag_elem_max": float(np.abs(d - dref).max() / np.abs(dref).max()),
            "oracle_rsvd_s": round(time.perf_counter() - t0, 1)}
@@ -186,7 +188,8 @@ def fp32_path(P, S, Y, n, k, V, out, rank, p, seed, Sig, dg, ncols, apply_ms_bf1
     res = {"apply_ms": round(ms, 4), "columns_per_s": round(ncols / (ms / 1e3), 2),
            "speedup_bf16_over_fp32": round(ms / apply_ms_bf16, 3),
            "bf16_apply_rel_F_vs_fp32": rel(out, of),
-           "bf16_sigma_rel_err_vs_fp32": float((Sig - Sf).abs().max() / Sf[0].abs()),
+           "bf16_sigma_rel_err_vs_fp32": float((torch.sort(Sig).values - torch.sort(Sf).values).abs().max()
+                                               / Sf[0].abs()),
            "bf16_diag_rel_F_vs_fp32": rel(dg, df), "device_status": status}
     log(f"[bench] fp32 path: {res}")
     return res
@@ -440,7 +443,7 @@ def bench_learned(args):
             hq = h0.double().cpu().numpy()
             Xp = oprobes.round_to(oprobes.normal_block(prob.n, rank + 20, 5), "f32")
             ref = orsvd.rsvd(hq, Sq_all, Yq_all, Xp, rank)
-            rsvd_err = float(np.abs(Sig.cpu().numpy() - ref["Sigma"]).max() / abs(ref["Sigma"][0]))
+            rsvd_err = float(np.abs(np.sort(Sig.cpu().numpy()) - np.sort(ref["Sigma"])).max() / abs(ref["Sigma"][0]))
             row["rsvd_sigma_rel_err_vs_oracle"] = rsvd_err
         H.close()
         evals.append(row)

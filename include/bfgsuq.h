@@ -136,6 +136,24 @@ int bfgs_generate_probes(bfgs_t h, uint64_t seed, int32_t ncols, void* X);
  * or an eigensolver failure sets BFGS_ERR_NUMERIC in the deferred status.     */
 int bfgs_rsvd(bfgs_t h, int32_t rank, int32_t oversample, uint64_t seed, void* U, double* Sigma);
 
+/* bfgs_rsvd_ex — bfgs_rsvd with variants (flags, OR-ed):
+ *   BFGS_RSVD_PRECOND   factor the whitened difference B_0^-1/2 (B_k - B_0) B_0^-1/2,
+ *                       whose eigenvalues are those of B_k B_0^-1 - I: the operator the
+ *                       paper says "starts from the identity" once B_0 preconditions
+ *                       (section "Preconditioned BFGS-based Uncertainty Quantification").
+ *                       The probes X are drawn as usual; the whitened sketch is of
+ *                       X_w = B_0^1/2 X.  U is then the whitened basis:
+ *                       B_k = B_0 + B_0^1/2 U diag(Sigma) U^T B_0^1/2, and the cached
+ *                       posterior diagonal is h0 + h0 sum_i Sigma_i U_i^2.
+ *   BFGS_RSVD_TWO_PASS  after Q, apply the operator to Q itself and take
+ *                       Omega = Q^T (A Q), symmetrised, instead of solving with Q^T X
+ *                       (Halko et al.'s two-pass form; one more apply with c columns,
+ *                       on the float64 matrix cores whatever the storage).
+ * Arguments, results and errors otherwise as bfgs_rsvd; flags = 0 is bfgs_rsvd.  */
+#define BFGS_RSVD_PRECOND 1u
+#define BFGS_RSVD_TWO_PASS 2u
+int bfgs_rsvd_ex(bfgs_t h, int32_t rank, int32_t oversample, uint64_t seed, uint32_t flags, void* U, double* Sigma);
+
 /* bfgs_posterior_diag — out_j = h0_j + sum_i Sigma_i U_ji^2, the diagonal of
  * V Lambda V^T + B_0 (eq. (10)), i.e. the posterior variance of eq. (14) with
  * prior C_m = I, from the last bfgs_rsvd on this handle.
@@ -231,6 +249,60 @@ int bfgs_batch_graph_build(bfgs_batch_t b, const void* const* V, const int32_t* 
  * nothing is launched, and bfgs_batch_graph_build must be called again.        */
 int bfgs_batch_graph_launch(bfgs_batch_t b);
 int bfgs_batch_destroy(bfgs_batch_t b);
+
+/* ---------------------------------------------------------------------------
+ * GPU-resident full-history BFGS on a quadratic (Alg. 1 with every pair kept and
+ * B_0 fixed, search direction p = -B_k g of eq. (1)), for producing histories on the
+ * device and for measuring what a B_0 buys in iterations.
+ * The misfit is 1/2 m^T A m - b^T m, with A the synthetic stand-in for the
+ * wave-equation Hessian on a field-major grid (n = nparam nz nx):
+ *   A = diag(D) + P (x) (G_z (x) G_x),  P = I + coupling (1 1^T - I),
+ * G_x, G_z the truncated Gaussian smoothers (weights exp(-t^2/(2 sigma^2)), |t| <= half,
+ * normalised to sum 1, zero outside the grid).
+ * bfgs_gridop_create — D (device, n doubles, copied); sigma > 0; 0 <= half <= 4096.
+ *   Synchronous.
+ * bfgs_gridop_apply — y = A x for ncols columns (device, n x ncols float64 each,
+ *   column-major, y must not alias x), enqueued on the operator's stream.
+ * bfgs_minimize_quadratic — runs from m = 0 on an empty handle h (float64 or float32
+ *   storage; BFGS_ERR_ARG for bfloat16, BFGS_ERR_STATE if h holds pairs), on the
+ *   stream shared by h and op (BFGS_ERR_ARG otherwise): each iteration takes
+ *   p = -B_k g (p = -g before the first pair when B_0 = gamma I), the exact line
+ *   search alpha = -g^T p / p^T A p, s = alpha p, y = A s, m += s, g += y, and pushes
+ *   (s, y) into h.  It stops after max_iter iterations, when |g| <= rel_tol |g_0|, or
+ *   when h is full.  m (device, n doubles) receives the iterate; gnorm (host, max_iter
+ *   + 1 doubles, or NULL) |g_0|, |g_1|, ...; iters (host) the iterations taken.
+ *   Dot products are fixed-order reductions: runs are deterministic.  Synchronizes
+ *   once per iteration (the pair's curvature check, the gradient norm).          */
+typedef struct bfgsuq_gridop* bfgs_gridop_t;
+int bfgs_gridop_create(int64_t nx, int64_t nz, int32_t nparam, const double* D, double sigma, int32_t half,
+                       double coupling, void* stream, bfgs_gridop_t* out);
+int bfgs_gridop_apply(bfgs_gridop_t op, const double* x, int32_t ncols, double* y);
+int bfgs_gridop_destroy(bfgs_gridop_t op);
+int bfgs_minimize_quadratic(bfgs_t h, bfgs_gridop_t op, const double* b, int32_t max_iter, double rel_tol, double* m,
+                            double* gnorm, int32_t* iters);
+
+/* ---------------------------------------------------------------------------
+ * Smoothed, damped diagonal B_0 (eq. (4)): B_0 = (H_0 + lambda I)^-1 from a
+ * per-point diagonal Hessian estimate H_0 (the role diag(J^T J) plays in the
+ * preconditioners P1-P4), smoothed and stabilised as the paper prescribes for all
+ * four ("Numerical examples", the preconditioner comparison): the estimate is
+ * smoothed like a gradient and the inverse is damped with the median of the
+ * smoothed estimate.
+ * bfgs_precond_diag — for a field-major model of nparam fields on an nz x nx grid
+ *   (n = nparam nz nx, index (p nz + iz) nx + ix):
+ *     hs = each field smoothed by a separable Gaussian, weights exp(-t^2/(2 sigma^2))
+ *          for |t| <= half, each 1-D pass divided by the weights inside the grid
+ *          (float64 sums, rounded to float32);
+ *     lambda = damping * median(hs) (mean of the two middle values for even n);
+ *     h0 = 1 / (hs + lambda) (float64, rounded to float32).
+ *   hdiag  (device) n floats, finite and > 0
+ *   sigma  > 0 (cells); half in [0, 512]; damping >= 0
+ *   h0_out (device) n floats; hs_out (device, n floats) or NULL; lambda_out (host) or NULL
+ *   stream hipStream_t (NULL = the null stream)
+ * The result can be handed to bfgs_create as H0.  Allocates and frees a small
+ * workspace; synchronous.                                                       */
+int bfgs_precond_diag(int64_t nx, int64_t nz, int32_t nparam, const float* hdiag, double sigma, int32_t half,
+                      double damping, float* h0_out, float* hs_out, double* lambda_out, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Learned diagonal B_0: a per-(grid point, parameter) network predicting log h0,

@@ -27,4 +27,7 @@ from ._lib import (  # noqa: F401
     BFGS_ERR_NONFINITE,
     BFGS_ERR_NUMERIC,
     tsqr_shape,
+    precond_diag,
+    GridOp,
+    minimize_quadratic,
 )

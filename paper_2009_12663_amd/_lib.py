@@ -33,11 +33,12 @@ MAX_PAIRS = 1024
 
 EXPORTS = [
     "bfgs_create", "bfgs_destroy", "bfgs_push_pair", "bfgs_num_pairs", "bfgs_apply_Hinv", "bfgs_apply_Hinv_noalloc",
-    "bfgs_apply_Hdiff", "bfgs_generate_probes", "bfgs_rsvd", "bfgs_posterior_diag",
+    "bfgs_apply_Hdiff", "bfgs_generate_probes", "bfgs_rsvd", "bfgs_rsvd_ex", "bfgs_posterior_diag",
     "bfgs_get_pair", "bfgs_get_h0", "bfgs_get_status", "bfgs_status_string",
     "bfgs_profile", "bfgs_profile_report", "bfgs_autotune", "bfgs_tuning", "bfgs_sync", "bfgs_tsqr_shape",
     "bfgs_batch_create", "bfgs_batch_handle", "bfgs_batch_push_pairs", "bfgs_batch_apply_Hinv", "bfgs_batch_rsvd",
     "bfgs_batch_autotune", "bfgs_batch_graph_build", "bfgs_batch_graph_launch", "bfgs_batch_destroy",
+    "bfgs_precond_diag", "bfgs_gridop_create", "bfgs_gridop_apply", "bfgs_gridop_destroy", "bfgs_minimize_quadratic",
     "bfgs_mlp_create", "bfgs_mlp_destroy", "bfgs_mlp_set_params", "bfgs_mlp_get_params", "bfgs_mlp_features",
     "bfgs_mlp_forward", "bfgs_mlp_grad", "bfgs_mlp_train_step",
 ]
@@ -71,6 +72,7 @@ def load(path: str = LIB_PATH):
         "bfgs_apply_Hdiff": [vp, vp, i32, vp],
         "bfgs_generate_probes": [vp, u64, i32, vp],
         "bfgs_rsvd": [vp, i32, i32, u64, vp, vp],
+        "bfgs_rsvd_ex": [vp, i32, i32, u64, ctypes.c_uint32, vp, vp],
         "bfgs_posterior_diag": [vp, vp],
         "bfgs_get_pair": [vp, i32, vp, vp],
         "bfgs_get_h0": [vp, vp],
@@ -91,6 +93,13 @@ def load(path: str = LIB_PATH):
         "bfgs_batch_graph_build": [vp, vp, vp, vp, vp, i32, u64, vp, vp],
         "bfgs_batch_graph_launch": [vp],
         "bfgs_batch_destroy": [vp],
+        "bfgs_precond_diag": [i64, i64, i32, vp, ctypes.c_double, i32, ctypes.c_double, vp, vp,
+                              ctypes.POINTER(ctypes.c_double), vp],
+        "bfgs_gridop_create": [i64, i64, i32, vp, ctypes.c_double, i32, ctypes.c_double, vp, ctypes.POINTER(vp)],
+        "bfgs_gridop_apply": [vp, vp, i32, vp],
+        "bfgs_gridop_destroy": [vp],
+        "bfgs_minimize_quadratic": [vp, vp, vp, i32, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(i32)],
         "bfgs_mlp_create": [vp, ctypes.POINTER(vp)],
         "bfgs_mlp_destroy": [vp],
         "bfgs_mlp_set_params": [vp, vp],
@@ -126,6 +135,23 @@ def tsqr_shape(c: int):
     a, b = ctypes.c_int32(), ctypes.c_int32()
     _check(load().bfgs_tsqr_shape(int(c), ctypes.byref(a), ctypes.byref(b)), "bfgs_tsqr_shape")
     return bool(a.value), int(b.value)
+
+
+def precond_diag(hdiag: torch.Tensor, nx: int, nz: int, nparam: int, sigma: float, half: int,
+                 damping: float = 1.0, stream: torch.cuda.Stream | None = None):
+    """B_0 of eq. (4) from a diagonal Hessian estimate (bfgs_precond_diag):
+    returns (h0, hs, lambda) with h0 and the smoothed estimate hs as float32 tensors."""
+    L = load()
+    h = hdiag.to(torch.float32).contiguous()
+    assert h.is_cuda and h.numel() == nx * nz * nparam
+    h0 = torch.empty_like(h)
+    hs = torch.empty_like(h)
+    lam = ctypes.c_double()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(L.bfgs_precond_diag(int(nx), int(nz), int(nparam), _ptr(h), float(sigma), int(half), float(damping),
+                               _ptr(h0), _ptr(hs), ctypes.byref(lam), ctypes.c_void_p(st.cuda_stream)),
+           "bfgs_precond_diag")
+    return h0, hs, lam.value
 
 
 def _ptr(t):
@@ -248,6 +274,20 @@ class Bfgs:
         self._leave()
         return U, Sigma
 
+    def rsvd_ex(self, rank: int, oversample: int, seed: int, precond: bool = False, two_pass: bool = False,
+                U: torch.Tensor | None = None, Sigma: torch.Tensor | None = None):
+        """bfgs_rsvd_ex: the preconditioned (whitened) and/or two-pass variants."""
+        if U is None:
+            U = torch.empty((rank, self.n), dtype=self.rdt, device="cuda")
+        if Sigma is None:
+            Sigma = torch.empty(rank, dtype=torch.float64, device="cuda")
+        flags = (1 if precond else 0) | (2 if two_pass else 0)
+        self._enter()
+        _check(self.L.bfgs_rsvd_ex(self.h, rank, oversample, ctypes.c_uint64(seed), flags, _ptr(U), _ptr(Sigma)),
+               "bfgs_rsvd_ex")
+        self._leave()
+        return U, Sigma
+
     def posterior_diag(self, out: torch.Tensor | None = None) -> torch.Tensor:
         if out is None:
             out = torch.empty(self.n, dtype=self.rdt, device="cuda")
@@ -322,6 +362,56 @@ def _ptr_array(tensors):
 
 def _i32_array(vals):
     return (ctypes.c_int32 * len(vals))(*[int(v) for v in vals])
+
+
+class GridOp:
+    """The synthetic grid Hessian A = diag(D) + P (x) (G_z (x) G_x) (bfgs_gridop_*)."""
+
+    def __init__(self, nx: int, nz: int, nparam: int, D: torch.Tensor, sigma: float, half: int, coupling: float,
+                 stream: torch.cuda.Stream | None = None):
+        self.L = load()
+        self.nx, self.nz, self.nparam = int(nx), int(nz), int(nparam)
+        self.n = self.nx * self.nz * self.nparam
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        D = D.to(torch.float64).contiguous()
+        assert D.is_cuda and D.numel() == self.n
+        h = ctypes.c_void_p()
+        _check(self.L.bfgs_gridop_create(self.nx, self.nz, self.nparam, _ptr(D), float(sigma), int(half),
+                                         float(coupling), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "bfgs_gridop_create")
+        self.op = h
+
+    def apply(self, x: torch.Tensor) -> torch.Tensor:
+        x = x.to(torch.float64).contiguous()
+        single = x.dim() == 1
+        xb = x.view(1, -1) if single else x
+        assert xb.is_cuda and xb.shape[1] == self.n
+        y = torch.empty_like(xb)
+        _check(self.L.bfgs_gridop_apply(self.op, _ptr(xb), xb.shape[0], _ptr(y)), "bfgs_gridop_apply")
+        return y[0] if single else y
+
+    def close(self):
+        if getattr(self, "op", None):
+            self.L.bfgs_gridop_destroy(self.op)
+            self.op = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def minimize_quadratic(H: "Bfgs", op: GridOp, b: torch.Tensor, max_iter: int, rel_tol: float):
+    """bfgs_minimize_quadratic: returns (m, gnorms) with gnorms |g_0| .. |g_iters|."""
+    L = load()
+    b = b.to(torch.float64).contiguous()
+    m = torch.empty_like(b)
+    gn = (ctypes.c_double * (max_iter + 1))()
+    it = ctypes.c_int32()
+    _check(L.bfgs_minimize_quadratic(H.h, op.op, _ptr(b), int(max_iter), float(rel_tol), _ptr(m), gn,
+                                     ctypes.byref(it)), "bfgs_minimize_quadratic")
+    return m, [gn[i] for i in range(it.value + 1)]
 
 
 class BfgsBatch:

@@ -212,10 +212,10 @@ __device__ __forceinline__ Ts w_raw(const Ts* S, const Ts* Y, int64_t ld, int k,
 
 // part[chunk][j * 2k + p] = sum over the chunk's rows of W(r, p) V(r, j).
 // Grid (nchunks, ceil(2k / 128), ceil(c / 128)).
-template <typename Ts, typename Th>
+template <typename Ts, typename Th, typename Tv>
 __global__ void __launch_bounds__(256, 2) gemm1_f64mfma(int64_t n, int64_t ld, int k, int c, const Ts* __restrict__ S,
                                                      const Ts* __restrict__ Y, const Th* __restrict__ h0,
-                                                     const Ts* __restrict__ V, double* __restrict__ part,
+                                                     const Tv* __restrict__ V, double* __restrict__ part,
                                                      int64_t rows_per_chunk) {
     __shared__ double Ws[FK][FT_LD];
     __shared__ double Vs[FK][FT_LD];
@@ -227,7 +227,8 @@ __global__ void __launch_bounds__(256, 2) gemm1_f64mfma(int64_t n, int64_t ld, i
     const int64_t re = min(n, rb + rows_per_chunk);
     // staging map: element e = tid + 256 q (q < 8): row e % 16 (= tid % 16 for every q),
     // column e / 16; values stay in the storage type until they are staged
-    Ts wreg[8], vreg[8];
+    Ts wreg[8];
+    Tv vreg[8];
     double h0r = 0.0;
 #define G1F_LOAD_STAGE(R0)                                                                   \
     {                                                                                      \
@@ -237,7 +238,7 @@ __global__ void __launch_bounds__(256, 2) gemm1_f64mfma(int64_t n, int64_t ld, i
         _Pragma("unroll") for (int q = 0; q < 8; ++q) {                                    \
             const int cc = (tid + 256 * q) / FK;                                           \
             wreg[q] = (rv && pi0 + cc < twok) ? w_raw(S, Y, ld, k, pi0 + cc, r) : Ts{};     \
-            vreg[q] = (rv && cj0 + cc < c) ? V[(int64_t)(cj0 + cc) * n + r] : Ts{};          \
+            vreg[q] = (rv && cj0 + cc < c) ? V[(int64_t)(cj0 + cc) * n + r] : Tv{};          \
         }                                                                                  \
     }
     v4d acc[4][4];
@@ -288,10 +289,10 @@ __global__ void __launch_bounds__(256, 2) gemm1_f64mfma(int64_t n, int64_t ld, i
 
 // out (column-major n x c) = W [T ; -P] (+ h0 o V unless diff); P, T column-major k x c.
 // Grid (ceil(n / 128), ceil(c / 128)).
-template <typename Ts, typename Th, typename To>
+template <typename Ts, typename Th, typename To, typename Tv>
 __global__ void __launch_bounds__(256, 2) gemm2_f64mfma(int64_t n, int64_t ld, int k, int c, const Ts* __restrict__ S,
                                                      const Ts* __restrict__ Y, const Th* __restrict__ h0,
-                                                     const Ts* __restrict__ V, const double* __restrict__ P,
+                                                     const Tv* __restrict__ V, const double* __restrict__ P,
                                                      const double* __restrict__ T, To* __restrict__ out, int diff) {
     __shared__ double stage_sh[FT * (FK + 1) + FK * FT_LD];
     double* Wsh = stage_sh;                     // [128 rows][FK + 1]
@@ -384,16 +385,16 @@ __global__ void __launch_bounds__(256, 2) gemm2_f64mfma(int64_t n, int64_t ld, i
     }
 }
 
-template <typename Ts, typename Th, typename To>
+template <typename Ts, typename Th, typename To, typename Tv = Ts>
 int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff, const ApplyWs* fixed) {
     const int64_t n = h->n;
     const int k = h->k;
     const Th* h0 = (const Th*)h->h0;
-    const Ts* V = (const Ts*)Vv;
+    const Tv* V = (const Tv*)Vv;
     To* out = (To*)outv;
     if (k == 0) {
         int64_t g = std::min<int64_t>(4096, (n * c + 255) / 256);
-        hipLaunchKernelGGL((scale_by_h0<Th, Ts, To>), dim3((int)g), dim3(256), 0, h->stream, n, c, h0, V, out,
+        hipLaunchKernelGGL((scale_by_h0<Th, Tv, To>), dim3((int)g), dim3(256), 0, h->stream, n, c, h0, V, out,
                            diff ? 1 : 0, h->status);
         return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
     }
@@ -426,7 +427,7 @@ int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff, c
     }
     double* T = P + (size_t)k * c;
     prof_begin(h, diff ? "hdiff_gemm1" : "apply_gemm1");
-    hipLaunchKernelGGL((gemm1_f64mfma<Ts, Th>), dim3(nchunks, ptiles, ctiles), dim3(256), 0, h->stream, n, h->ld, k,
+    hipLaunchKernelGGL((gemm1_f64mfma<Ts, Th, Tv>), dim3(nchunks, ptiles, ctiles), dim3(256), 0, h->stream, n, h->ld, k,
                        c, (const Ts*)h->S, (const Ts*)h->Y, h0, V, part, rows_per_chunk);
     const int64_t count = (int64_t)twok * c;
     prof_end(h);
@@ -435,7 +436,7 @@ int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff, c
     prof_end(h);
     if (int rc2 = apply_small_solve(h, c, Z, P, T)) return rc2;
     prof_begin(h, diff ? "hdiff_gemm2" : "apply_gemm2");
-    hipLaunchKernelGGL((gemm2_f64mfma<Ts, Th, To>), dim3((unsigned)ceil_div(n, (int64_t)FT), ctiles), dim3(256), 0,
+    hipLaunchKernelGGL((gemm2_f64mfma<Ts, Th, To, Tv>), dim3((unsigned)ceil_div(n, (int64_t)FT), ctiles), dim3(256), 0,
                        h->stream, n, h->ld, k, c, (const Ts*)h->S, (const Ts*)h->Y, h0, V, P, T, out,
                        diff ? 1 : 0);
     prof_end(h);
@@ -454,6 +455,23 @@ int apply_small_solve(bfgsuq_ctx* h, int c, const double* Z, double* P, double* 
         hipLaunchKernelGGL(small_solve, dim3(c), dim3(64), 3 * k * sizeof(double), h->stream, k, h->kmax, c, h->Rm,
                            h->YHY, Z, P, T, h->status);
     return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+}
+
+int apply_diff_float_block(bfgsuq_ctx* h, const void* V, bool v64, int32_t ncols, void* out, bool out64) {
+    // (B_k - B_0) V for a float32 or float64 block V (a basis, not a probe block in the
+    // storage type) on the float64 matrix cores, whatever the storage
+#define ADF(TS, TH)                                                                                      \
+    if (v64 && out64) return apply_generic<TS, TH, double, double>(h, V, ncols, out, true, nullptr);   \
+    if (v64) return apply_generic<TS, TH, float, double>(h, V, ncols, out, true, nullptr);             \
+    if (out64) return apply_generic<TS, TH, double, float>(h, V, ncols, out, true, nullptr);           \
+    return apply_generic<TS, TH, float, float>(h, V, ncols, out, true, nullptr);
+    switch (h->storage) {
+        case BFGS_F64: { ADF(double, double) }
+        case BFGS_F32: { ADF(float, float) }
+        case BFGS_BF16: { ADF(bf16_t, float) }
+    }
+#undef ADF
+    return BFGS_ERR_ARG;
 }
 
 int apply_block(bfgsuq_ctx* h, const void* V, int32_t ncols, void* out, bool diff, bool out64,

@@ -91,11 +91,14 @@ struct Workspace {
 struct ProfRec {
     const char* name;
     hipEvent_t a, b;
+    bool ended = false;
 };
 
+// Stage timers: begin/end pairs may nest (an end closes the innermost open stage).
 struct Profiler {
     bool on = false;
     std::vector<ProfRec> recs;
+    std::vector<size_t> open;   // indices into recs of the stages not yet ended
     std::vector<hipEvent_t> pool;
     size_t used = 0;
 };
@@ -131,7 +134,7 @@ struct bfgsuq_ctx {
     // apply workspaces (grow-only)
     Workspace part, Z, PT, small16;
     // rsvd workspaces
-    Workspace X, E, Q, refl, tau, Rtree, small, lam, diag;
+    Workspace X, E, Q, W, refl, tau, Rtree, small, lam, diag;
     int32_t last_rank = 0;
     bool have_rsvd = false;
     // tunables (bfgs_autotune): row ranges of the pass-1 MFMA kernel, TSQR chains (power of two)
@@ -147,7 +150,7 @@ struct bfgsuq_ctx {
 
 // Sum of the counters a captured graph depends on.
 inline unsigned long long handle_generation(const bfgsuq_ctx* h) {
-    const Workspace* ws[] = {&h->part, &h->Z, &h->PT, &h->small16, &h->X, &h->E, &h->Q, &h->refl, &h->tau,
+    const Workspace* ws[] = {&h->part, &h->Z, &h->PT, &h->small16, &h->X, &h->E, &h->Q, &h->W, &h->refl, &h->tau,
                              &h->Rtree, &h->small, &h->lam, &h->diag};
     unsigned long long g = h->gen;
     for (const Workspace* w : ws) g += w->gen;
@@ -201,12 +204,19 @@ size_t apply_small16_bytes(int kmax);
 // the storage's result type.
 int apply_block(bfgsuq_ctx* h, const void* V, int32_t ncols, void* out, bool diff, bool out64 = false,
                 const ApplyWs* fixed = nullptr);
-int rsvd_run(bfgsuq_ctx* h, int32_t rank, int32_t oversample, uint64_t seed, void* U, double* Sigma);
+// (B_k - B_0) V for a float32 or float64 block (float64 matrix cores, any storage);
+// out float64 or float32.
+int apply_diff_float_block(bfgsuq_ctx* h, const void* V, bool v64, int32_t ncols, void* out, bool out64);
+// rSVD variants (flags of bfgs_rsvd_ex)
+int rsvd_run(bfgsuq_ctx* h, int32_t rank, int32_t oversample, uint64_t seed, void* U, double* Sigma,
+             uint32_t flags = 0);
 // Blocked Householder TSQR E = Q R (E, Q column-major n x c; *R_out: row-major c x c in
 // the handle's workspace).  tsqr.hip.
 int tsqr_run(bfgsuq_ctx* h, int c, const float* E, float* Q, double** R_out);
 int tsqr_run(bfgsuq_ctx* h, int c, const double* E, float* Q, double** R_out);
 int tsqr_run(bfgsuq_ctx* h, int c, const double* E, double* Q, double** R_out);
+// Whether the TSQR of a c-column block keeps its per-chain triangle in float64.
+bool tsqr_f64_slot(int c);
 // Eigenpairs of the symmetric tridiagonal (d, e), c <= 256, by divide and conquer:
 // *w_out -> the eigenvalues (in work), Z = Qh Y with Y their eigenvectors (c x c
 // column-major device arrays); work holds tridiag_dc_workspace(c) bytes.
@@ -219,7 +229,8 @@ int qtx_bf16_launch(hipStream_t st, int64_t n, int c, const float* Q, const bf16
                     int64_t rows_per_chunk);
 size_t basis_bf16_workspace(int c, int rank);
 int basis_bf16_launch(hipStream_t st, int64_t n, int c, int rank, const float* Q, const double* Us, uint16_t* ush,
-                      const double* lam, const float* h0, float* U, float* dout);
+                      const double* lam, const float* h0, float* U, float* dout, int32_t* status,
+                      bool whitened = false);
 int tridiag_dc(hipStream_t st, int c, const double* d, const double* e, const double* Qh, double* work, double** w_out,
                double* Z, int32_t* status);
 int probes_run(bfgsuq_ctx* h, uint64_t seed, int32_t ncols, void* X);

@@ -95,13 +95,14 @@ constexpr int MT_TILE = 128;
 constexpr int MT_LD = MT_TILE + 4;
 constexpr int MT_K = 16;          // reduction depth staged per step
 
-// part[ch] = Q[rows of chunk ch, :]^T X[rows of chunk ch, :]  (c x c, column-major:
-// part[j * c + i] = sum_r Q(r, i) X(r, j)), Q and X column-major n x c.  Grid
-// (nchunk, nblk, nblk): workgroup (ch, bi, bj) owns output rows bi * 128.. and
-// columns bj * 128..
+// part[ch] = Q[rows of chunk ch, :]^T X[rows of chunk ch, :]  (cq x cx, column-major:
+// part[j * cq + i] = sum_r Q(r, i) X(r, j)), Q column-major n x cq, X n x cx (both
+// leading dimension n).  Grid (nchunk, ceil(cq / 128), ceil(cx / 128)): workgroup
+// (ch, bi, bj) owns output rows bi * 128.. and columns bj * 128..
 template <typename TQ, typename TX>
-__global__ void __launch_bounds__(256, 2) qtx_mfma(int64_t n, int c, const TQ* __restrict__ Q, const TX* __restrict__ X,
-                                                double* __restrict__ part, int64_t rows_per_chunk) {
+__global__ void __launch_bounds__(256, 2) qtx_mfma(int64_t n, int cq, int cx, const TQ* __restrict__ Q,
+                                                const TX* __restrict__ X, double* __restrict__ part,
+                                                int64_t rows_per_chunk) {
     __shared__ double Qs[MT_K][MT_LD];
     __shared__ double Xs[MT_K][MT_LD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -117,8 +118,8 @@ __global__ void __launch_bounds__(256, 2) qtx_mfma(int64_t n, int c, const TQ* _
         const int e = tid + 256 * q, rr = e % MT_K, cc = e / MT_K;                       \
         const int64_t r = (R0) + rr;                                                     \
         const bool rv = r < re;                                                          \
-        qreg[q] = (rv && ci0 + cc < c) ? Q[(int64_t)(ci0 + cc) * n + r] : TQ{};          \
-        xreg[q] = (rv && cj0 + cc < c) ? X[(int64_t)(cj0 + cc) * n + r] : TX{};          \
+        qreg[q] = (rv && ci0 + cc < cq) ? Q[(int64_t)(ci0 + cc) * n + r] : TQ{};         \
+        xreg[q] = (rv && cj0 + cc < cx) ? X[(int64_t)(cj0 + cc) * n + r] : TX{};         \
     }
     v4d acc[4][4];
 #pragma unroll
@@ -151,7 +152,7 @@ __global__ void __launch_bounds__(256, 2) qtx_mfma(int64_t n, int c, const TQ* _
         }
         __syncthreads();
     }
-    double* out = part + (int64_t)blockIdx.x * c * c;
+    double* out = part + (int64_t)blockIdx.x * cq * cx;
 #pragma unroll
     for (int ta = 0; ta < 4; ++ta)
 #pragma unroll
@@ -160,13 +161,14 @@ __global__ void __launch_bounds__(256, 2) qtx_mfma(int64_t n, int c, const TQ* _
             for (int r = 0; r < 4; ++r) {
                 const int gi = ci0 + (wi * 4 + ta) * 16 + lane / 16 + 4 * r;
                 const int gj = cj0 + (wj * 4 + tb) * 16 + lane % 16;
-                if (gi < c && gj < c) out[(int64_t)gj * c + gi] = acc[ta][tb][r];
+                if (gi < cq && gj < cx) out[(int64_t)gj * cq + gi] = acc[ta][tb][r];
             }
 }
 
 // U = Q Us[:, :rank] (n x rank, column-major, TO) from column-major Q (n x c) and
-// Us (c x c, column-major).  Grid (ceil(n / 128), ceil(rank / 128)).
-template <typename TQ, typename TO>
+// Us (column-major, leading dimension c); with SUB (float64 U) U -= Q Us instead.
+// Grid (ceil(n / 128), ceil(rank / 128)).
+template <typename TQ, typename TO, bool SUB = false>
 __global__ void __launch_bounds__(256, 2) basis_mfma(int64_t n, int c, int rank, const TQ* __restrict__ Q,
                                                   const double* __restrict__ Us, TO* __restrict__ U) {
     __shared__ double stage_sh[MT_TILE * (MT_K + 1) + MT_K * MT_LD];
@@ -254,7 +256,10 @@ __global__ void __launch_bounds__(256, 2) basis_mfma(int64_t n, int c, int rank,
                 for (int r = 0; r < 4; ++r) {
                     const int64_t row = row0 + (wi * 4 + ta) * 16 + lane / 16 + 4 * r;
                     const int j = col0 + (wj * 4 + tb) * 16 + lane % 16;
-                    if (j < rank && row < n) U[(int64_t)j * n + row] = (TO)acc[ta][tb][r];
+                    if (j < rank && row < n) {
+                        if (SUB) U[(int64_t)j * n + row] -= (TO)acc[ta][tb][r];
+                        else U[(int64_t)j * n + row] = (TO)acc[ta][tb][r];
+                    }
                 }
     }
 }
@@ -898,15 +903,22 @@ __global__ void __launch_bounds__(SMALL_THREADS) order_sign(int c, const double*
 
 template <typename TO, typename Th>
 __global__ void posterior_diag_kernel(int64_t n, int rank, const TO* __restrict__ U, const double* __restrict__ lam,
-                                      const Th* __restrict__ h0, TO* __restrict__ dout) {
+                                      const Th* __restrict__ h0, TO* __restrict__ dout, int32_t* __restrict__ status,
+                                      int whitened) {
+    // whitened basis (B_k = B_0 + B_0^1/2 U Lambda U^T B_0^1/2): d = h0 + h0 sum_i lam_i U_i^2
+    bool bad = false;
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-        double s = to_f64(h0[r]);
+        const double hr = to_f64(h0[r]);
+        double s = 0.0;
         for (int i = 0; i < rank; ++i) {
             const double u = to_f64(U[(int64_t)i * n + r]);
             s = fma(lam[i], u * u, s);
         }
-        dout[r] = (TO)s;
+        const TO d = (TO)(whitened ? fma(hr, s, hr) : hr + s);
+        bad |= !isfinite(to_f64(d));
+        dout[r] = d;
     }
+    if (bad) set_status(status, BFGS_ERR_NONFINITE);   // includes overflow of the stored type
 }
 
 template <typename TO, typename Th>
@@ -921,10 +933,149 @@ __global__ void zero_rsvd(int64_t n, int rank, TO* __restrict__ U, double* __res
 }
 
 // ---------------------------------------------------------------------------
+// Column-blocked QR of a float64 E (n x c) when c is too wide for a float64 slot:
+// E = [E1 E2] with E1 the first c1 columns; E1 = Q1 R11 (TSQR, two passes); E2 is
+// projected off Q1 twice (block Gram-Schmidt with reorthogonalisation), R12 the sum
+// of the two projections; the remainder = Q2 R22 (TSQR, two passes).  Then
+// E = [Q1 Q2] [R11 R12; 0 R22].  Every block has c1, c - c1 <= 128 columns, whose
+// slots are float64.
+// ---------------------------------------------------------------------------
+__global__ void add_into(int64_t count, const double* __restrict__ src, double* __restrict__ dst) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < count) dst[e] += src[e];
+}
+
+// R12 (column-major c1 x c2) += P (column-major c1 x c2) R22 (row-major c2 x c2, upper).
+__global__ void add_p_times_r(int c1, int c2, const double* __restrict__ P, const double* __restrict__ R22,
+                              double* __restrict__ R12) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < c1 * c2; e += gridDim.x * blockDim.x) {
+        const int i = e % c1, j = e / c1;
+        double s = 0.0;
+        for (int l = 0; l <= j; ++l) s = fma(P[(int64_t)l * c1 + i], R22[(int64_t)l * c2 + j], s);
+        R12[e] += s;
+    }
+}
+
+// R (row-major c x c) = [R11 R12; 0 R22]: R11 row-major c1 x c1, R12 column-major c1 x c2,
+// R22 row-major c2 x c2.
+__global__ void assemble_r(int c, int c1, const double* __restrict__ R11, const double* __restrict__ R12,
+                           const double* __restrict__ R22, double* __restrict__ R) {
+    const int c2 = c - c1;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < c * c; e += gridDim.x * blockDim.x) {
+        const int i = e / c, j = e % c;
+        double v = 0.0;
+        if (i < c1 && j < c1) v = R11[(int64_t)i * c1 + j];
+        else if (i < c1) v = R12[(int64_t)(j - c1) * c1 + i];
+        else if (j >= c1) v = R22[(int64_t)(i - c1) * c2 + (j - c1)];
+        R[e] = v;
+    }
+}
+
+// Two TSQR passes over one column block: src (n x cb) -> tmp -> dst; R (row-major cb x cb)
+// = R2 R1 into Rout.
+int tsqr_twice(bfgsuq_ctx* h, int cb, const double* src, double* tmp, double* dst, double* R1keep, double* Rout) {
+    double* R = nullptr;
+    int rc;
+    if ((rc = tsqr_run(h, cb, src, tmp, &R)) != BFGS_OK) return rc;
+    if (hipMemcpyAsync(R1keep, R, (size_t)cb * cb * 8, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
+        return BFGS_ERR_HIP;
+    if ((rc = tsqr_run(h, cb, tmp, dst, &R)) != BFGS_OK) return rc;
+    hipLaunchKernelGGL(tri_mul, dim3(ceil_div((int64_t)cb * cb, 256)), dim3(256), 0, h->stream, cb, R, R1keep, Rout);
+    return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+}
+
+int qr_two_blocks(bfgsuq_ctx* h, int c, double* E, double* Q, int nchunks, int64_t rows_per_chunk, double* part,
+                  double* Rb, double* Rout) {
+    const int64_t n = h->n;
+    const int c1 = (int)std::min<int64_t>(128, round_up((c + 1) / 2, 16));
+    const int c2 = c - c1;
+    if (c2 < 1 || c2 > 128) return BFGS_ERR_ARG;
+    int rc;
+    if ((rc = ensure_ws(h->W, (size_t)n * c1 * 8)) != BFGS_OK) return rc;
+    double* W = (double*)h->W.ptr;
+    const size_t cc = (size_t)c * c;
+    double* R11 = Rb;
+    double* R12 = Rb + cc;
+    double* R22 = Rb + 2 * cc;
+    double* Rk = Rb + 3 * cc;   // first-pass R of a block, then one projection
+    double* E2 = E + (int64_t)c1 * n;
+    double* Q2 = Q + (int64_t)c1 * n;
+    if ((rc = tsqr_twice(h, c1, E, W, Q, Rk, R11)) != BFGS_OK) return rc;
+    const int64_t cnt = (int64_t)c1 * c2;
+    for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL((qtx_mfma<double, double>), dim3(nchunks, ceil_div(c1, MT_TILE), ceil_div(c2, MT_TILE)),
+                           dim3(256), 0, h->stream, n, c1, c2, Q, E2, part, rows_per_chunk);
+        double* dst = pass == 0 ? R12 : Rk;
+        hipLaunchKernelGGL(sum_chunks, dim3(ceil_div(cnt, 256)), dim3(256), 0, h->stream, cnt, nchunks, part, dst);
+        hipLaunchKernelGGL((basis_mfma<double, double, true>), dim3((unsigned)ceil_div(n, (int64_t)MT_TILE),
+                           ceil_div(c2, MT_TILE)), dim3(256), 0, h->stream, n, c1, c2, Q, dst, E2);
+        if (pass == 1) hipLaunchKernelGGL(add_into, dim3(ceil_div(cnt, 256)), dim3(256), 0, h->stream, cnt, Rk, R12);
+    }
+    if ((rc = tsqr_twice(h, c2, E2, W, Q2, Rk, R22)) != BFGS_OK) return rc;
+    // Where E2 lies in span(Q1) its remainder is rounding noise, which is not orthogonal
+    // to Q1, and neither are the columns of Q2 it yields: project Q2 off Q1 once more and
+    // refactor it.  Q2 = Q1 P + Q2', Q2' = Q2'' R'', so E2 = Q1 (R12 + P R22) + Q2'' (R'' R22).
+    double* P = Rk;
+    double* Rn = Rb + 4 * cc;
+    double* Rn1 = Rb + 5 * cc;
+    hipLaunchKernelGGL((qtx_mfma<double, double>), dim3(nchunks, ceil_div(c1, MT_TILE), ceil_div(c2, MT_TILE)),
+                       dim3(256), 0, h->stream, n, c1, c2, Q, Q2, part, rows_per_chunk);
+    hipLaunchKernelGGL(sum_chunks, dim3(ceil_div(cnt, 256)), dim3(256), 0, h->stream, cnt, nchunks, part, P);
+    hipLaunchKernelGGL((basis_mfma<double, double, true>), dim3((unsigned)ceil_div(n, (int64_t)MT_TILE),
+                       ceil_div(c2, MT_TILE)), dim3(256), 0, h->stream, n, c1, c2, Q, P, Q2);
+    hipLaunchKernelGGL(add_p_times_r, dim3(ceil_div(cnt, 256)), dim3(256), 0, h->stream, c1, c2, P, R22, R12);
+    if ((rc = tsqr_twice(h, c2, Q2, W, Q2, Rn1, Rn)) != BFGS_OK) return rc;
+    hipLaunchKernelGGL(tri_mul, dim3(ceil_div((int64_t)c2 * c2, 256)), dim3(256), 0, h->stream, c2, Rn, R22, Rn1);
+    R22 = Rn1;
+    hipLaunchKernelGGL(assemble_r, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, h->stream, c, c1, R11, R12, R22,
+                       Rout);
+    return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+}
+
+// Row scaling by h0^(p/2), p = +1 or -1 (the whitening of the preconditioned variant):
+// in place, or into a copy.
+template <typename T, typename Th>
+__global__ void scale_rows_kernel(int64_t n, int c, const Th* __restrict__ h0, int p, const T* __restrict__ in,
+                                  T* __restrict__ out) {
+    const int64_t total = n * c;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const double hr = to_f64(h0[e % n]);
+        const double w = p > 0 ? sqrt(hr) : 1.0 / sqrt(hr);
+        out[e] = (T)(w * to_f64(in[e]));
+    }
+}
+
+template <typename T>
+void scale_rows_copy(bfgsuq_ctx* h, int c, const T* in, T* out, int p) {
+    const int g = (int)std::min<int64_t>(8192, (h->n * c + 255) / 256);
+    if (h->storage == BFGS_F64)
+        hipLaunchKernelGGL((scale_rows_kernel<T, double>), dim3(g), dim3(256), 0, h->stream, h->n, c,
+                           (const double*)h->h0, p, in, out);
+    else
+        hipLaunchKernelGGL((scale_rows_kernel<T, float>), dim3(g), dim3(256), 0, h->stream, h->n, c,
+                           (const float*)h->h0, p, in, out);
+}
+
+template <typename T>
+void scale_rows_launch(bfgsuq_ctx* h, int c, T* x, int p) {
+    scale_rows_copy<T>(h, c, x, x, p);
+}
+
+// Omega = (M + M^T) / 2, column-major c x c.
+__global__ void symmetrise(int c, const double* __restrict__ M, double* __restrict__ Om) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < c * c; e += gridDim.x * blockDim.x) {
+        const int i = e % c, j = e / c;
+        Om[e] = 0.5 * (M[(int64_t)j * c + i] + M[(int64_t)i * c + j]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host driver
 // ---------------------------------------------------------------------------
 template <typename TS, typename TO, typename Th>
-int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, double* Sigma) {
+int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, double* Sigma, uint32_t flags) {
+    const bool precond = (flags & BFGS_RSVD_PRECOND) != 0;
+    const bool two_pass = (flags & BFGS_RSVD_TWO_PASS) != 0;
     const int64_t n = h->n;
     const int c = rank + oversample;
     int rc;
@@ -942,17 +1093,20 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     // E = (B_k - B_0) X: float64 for float32 storage, whose Sigma would otherwise carry the
     // float32 rounding of E amplified by the Omega solve (about 6e-7 relative to Sigma_0
     // on the 1700 x 350 x 3 grid with k = 200, c = 220, against a 1e-6 budget)
+    // and so is Q: rounding Q to float32 perturbs E = Q R by the same relative amount,
+    // and with Q^T X built from the rounded Q the Omega solve amplifies it by cond(Q^T X)
     constexpr bool e64 = std::is_same<TS, float>::value;
     using TE = typename std::conditional<e64, double, TO>::type;
+    using TQ = TE;
     if ((rc = ensure_ws(h->E, (size_t)n * c * sizeof(TE))) != BFGS_OK) return rc;
-    if ((rc = ensure_ws(h->Q, (size_t)n * c * sizeof(TO))) != BFGS_OK) return rc;
+    if ((rc = ensure_ws(h->Q, (size_t)n * c * sizeof(TQ))) != BFGS_OK) return rc;
     // small: part(nchunks*c*c) + T, M, B, Omega, Z (5 c*c) + d, e, taus, rot, lam (5 c) + piv
     // Q^T X row chunks: about one per CU, each chunk a multiple of the staging depth
     int nchunks = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 63) / 64));
     const int64_t rows_per_chunk = round_up((n + nchunks - 1) / nchunks, MT_K);
     nchunks = (int)((n + rows_per_chunk - 1) / rows_per_chunk);
     const size_t cc = (size_t)c * c;
-    if ((rc = ensure_ws(h->small, ((size_t)nchunks * cc + 8 * cc + 6 * (size_t)c) * 8 + (size_t)c * 4)) != BFGS_OK)
+    if ((rc = ensure_ws(h->small, ((size_t)nchunks * cc + 14 * cc + 6 * (size_t)c) * 8 + (size_t)c * 4)) != BFGS_OK)
         return rc;
     // tridiagonal eigensolver workspace, then Z = Q_H Y (c x c)
     constexpr bool bf16_path = std::is_same<TS, bf16_t>::value;
@@ -975,41 +1129,84 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     double* lam = rot + 2 * (size_t)c;
     double* R1c = lam + c;
     double* Fm = R1c + cc;
-    int* piv = (int*)(Fm + cc);
+    double* Rb = Fm + cc;   // 6 c x c: the column-blocked QR's pieces
+    int* piv = (int*)(Rb + 6 * cc);
     TS* X = (TS*)h->X.ptr;
     TE* E = (TE*)h->E.ptr;
-    TO* Q = (TO*)h->Q.ptr;
+    TQ* Q = (TQ*)h->Q.ptr;
 
     {
         ProfScope ps(h, "probes");
         if ((rc = probes_launch(h, seed, c, X, h->stream)) != BFGS_OK) return rc;
     }
     if ((rc = apply_block(h, X, c, E, true, e64)) != BFGS_OK) return rc;
+    // whitened operator B_0^-1/2 (B_k - B_0) B_0^-1/2: its sketch of X_w = B_0^1/2 X is
+    // B_0^-1/2 E
+    if (precond) scale_rows_launch(h, c, E, -1);
     double* R = nullptr;
-    if ((rc = tsqr_run(h, c, E, Q, &R)) != BFGS_OK) return rc;
-    if constexpr (std::is_same<TS, double>::value) {
-        // E at float64 noise level is exactly rank deficient; the zero-started
-        // slot then keeps part of Q.  A second pass over the (well conditioned)
-        // Q restores orthonormality: E = Q2 (R2 R1).
-        if (hipMemcpyAsync(R1c, R, cc * 8, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) return BFGS_ERR_HIP;
-        if ((rc = tsqr_run(h, c, Q, E, &R)) != BFGS_OK) return rc;
-        hipLaunchKernelGGL(tri_mul, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, h->stream, c, R, R1c, Fm);
-        std::swap(E, Q);   // Q now points at the second-pass factor
-        R = Fm;
-    }
-    ProfScope ps(h, "proj_QtX");
-    if constexpr (bf16_path) {
-        if ((rc = qtx_bf16_launch(h->stream, n, c, Q, X, part, nchunks, rows_per_chunk)) != BFGS_OK) return rc;
+    if constexpr (std::is_same<TE, double>::value) {
+        if (tsqr_f64_slot(c)) {
+            // E kept in float64 (float64 or float32 storage) is exactly rank deficient at
+            // its noise level, and the zero-started slot then keeps part of Q.  A second
+            // pass over the (well conditioned) Q restores orthonormality: E = Q2 (R2 R1).
+            if ((rc = tsqr_run(h, c, E, Q, &R)) != BFGS_OK) return rc;
+            if (hipMemcpyAsync(R1c, R, cc * 8, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) return BFGS_ERR_HIP;
+            TQ* Q2 = reinterpret_cast<TQ*>(E);   // E is free now and as large as Q
+            if ((rc = tsqr_run(h, c, Q, Q2, &R)) != BFGS_OK) return rc;
+            hipLaunchKernelGGL(tri_mul, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, h->stream, c, R, R1c, Fm);
+            Q = Q2;
+            R = Fm;
+        } else {
+            // wider than a float64 slot fits in LDS: two column blocks, each with a float64
+            // slot (a float32 slot would round R at every fold)
+            if ((rc = qr_two_blocks(h, c, E, Q, nchunks, rows_per_chunk, part, Rb, Fm)) != BFGS_OK) return rc;
+            R = Fm;
+        }
     } else {
-        const int nblk = ceil_div(c, MT_TILE);
-        hipLaunchKernelGGL((qtx_mfma<TO, TS>), dim3(nchunks, nblk, nblk), dim3(256), 0, h->stream, n, c, Q, X, part,
-                           rows_per_chunk);
+        if ((rc = tsqr_run(h, c, E, Q, &R)) != BFGS_OK) return rc;
     }
-    hipLaunchKernelGGL(sum_chunks, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, h->stream, (int64_t)cc, nchunks, part,
-                       Tm);
-    prof_end(h);
-    prof_begin(h, "omega_lu");
-    {
+    // the E / Q buffer that Q does not occupy is free now
+    TE* Efree = (void*)Q == h->E.ptr ? (TE*)h->Q.ptr : E;
+    if (two_pass) {
+        // Halko et al.'s two-pass form: apply the operator to Q itself, Omega = Q^T (A Q)
+        ProfScope ps(h, "two_pass_AQ");
+        const TQ* V2 = Q;
+        if (precond) {
+            if ((rc = ensure_ws(h->W, (size_t)n * c * sizeof(TQ))) != BFGS_OK) return rc;
+            TQ* Qs = (TQ*)h->W.ptr;
+            scale_rows_copy(h, c, Q, Qs, -1);
+            V2 = Qs;
+        }
+        if ((rc = apply_diff_float_block(h, V2, sizeof(TQ) == 8, c, Efree, sizeof(TE) == 8)) != BFGS_OK) return rc;
+        if (precond) scale_rows_launch(h, c, Efree, -1);
+        const int nblk = ceil_div(c, MT_TILE);
+        hipLaunchKernelGGL((qtx_mfma<TQ, TE>), dim3(nchunks, nblk, nblk), dim3(256), 0, h->stream, n, c, c, Q, Efree,
+                           part, rows_per_chunk);
+        hipLaunchKernelGGL(sum_chunks, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, h->stream, (int64_t)cc, nchunks,
+                           part, Tm);
+        hipLaunchKernelGGL(symmetrise, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, h->stream, c, Tm, Om);
+    } else {
+        ProfScope ps(h, "proj_QtX");
+        const TQ* Qp = Q;
+        if (precond) {
+            // T = Q^T X_w = (B_0^1/2 Q)^T X
+            if ((rc = ensure_ws(h->W, (size_t)n * c * sizeof(TQ))) != BFGS_OK) return rc;
+            TQ* Qs = (TQ*)h->W.ptr;
+            scale_rows_copy(h, c, Q, Qs, +1);
+            Qp = Qs;
+        }
+        if constexpr (bf16_path) {
+            if ((rc = qtx_bf16_launch(h->stream, n, c, Qp, X, part, nchunks, rows_per_chunk)) != BFGS_OK) return rc;
+        } else {
+            const int nblk = ceil_div(c, MT_TILE);
+            hipLaunchKernelGGL((qtx_mfma<TQ, TS>), dim3(nchunks, nblk, nblk), dim3(256), 0, h->stream, n, c, c, Qp, X,
+                               part, rows_per_chunk);
+        }
+        hipLaunchKernelGGL(sum_chunks, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, h->stream, (int64_t)cc,
+                           nchunks, part, Tm);
+    }
+    if (!two_pass) {
+        ProfScope ps(h, "omega_lu");
         static bool attr = false;
         if (!attr) {
             if (hipFuncSetAttribute((const void*)omega_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1020,7 +1217,6 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
         hipLaunchKernelGGL(omega_solve, dim3(1), dim3(LU_THREADS), omega_smem_bytes(), h->stream, c, Tm, R, Bm, Om,
                            piv, h->status);
     }
-    prof_end(h);
     prof_begin(h, "sym_eig");
     // Bm (the LU right-hand sides) is free after omega_solve: it holds the reflectors
     {
@@ -1043,15 +1239,17 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     prof_begin(h, "basis_diag");
     if constexpr (bf16_path) {
         // the posterior diagonal is formed in the same pass
-        if ((rc = basis_bf16_launch(h->stream, n, c, rank, Q, Usm, ush, lam, (const float*)h->h0, U, dout)) != BFGS_OK)
+        if ((rc = basis_bf16_launch(h->stream, n, c, rank, Q, Usm, ush, lam, (const float*)h->h0, U, dout,
+                                    h->status, precond)) != BFGS_OK)
             return rc;
     } else {
-        hipLaunchKernelGGL((basis_mfma<TO, TO>), dim3((unsigned)ceil_div(n, (int64_t)MT_TILE), ceil_div(rank, MT_TILE)),
+        hipLaunchKernelGGL((basis_mfma<TQ, TO>), dim3((unsigned)ceil_div(n, (int64_t)MT_TILE), ceil_div(rank, MT_TILE)),
                            dim3(256), 0, h->stream, n, c, rank, Q, Usm, U);
         const int g = (int)std::min<int64_t>(4096, (n + 255) / 256);
         hipLaunchKernelGGL((posterior_diag_kernel<TO, Th>), dim3(g), dim3(256), 0, h->stream, n, rank, U, lam,
-                           (const Th*)h->h0, dout);
+                           (const Th*)h->h0, dout, h->status, precond ? 1 : 0);
     }
+    prof_end(h);
     if (hipGetLastError() != hipSuccess) return BFGS_ERR_HIP;
     h->have_rsvd = true;
     h->last_rank = rank;
@@ -1060,11 +1258,11 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
 
 }  // namespace
 
-int rsvd_run(bfgsuq_ctx* h, int32_t rank, int32_t oversample, uint64_t seed, void* U, double* Sigma) {
+int rsvd_run(bfgsuq_ctx* h, int32_t rank, int32_t oversample, uint64_t seed, void* U, double* Sigma, uint32_t flags) {
     switch (h->storage) {
-        case BFGS_F64: return rsvd_impl<double, double, double>(h, rank, oversample, seed, (double*)U, Sigma);
-        case BFGS_F32: return rsvd_impl<float, float, float>(h, rank, oversample, seed, (float*)U, Sigma);
-        case BFGS_BF16: return rsvd_impl<bf16_t, float, float>(h, rank, oversample, seed, (float*)U, Sigma);
+        case BFGS_F64: return rsvd_impl<double, double, double>(h, rank, oversample, seed, (double*)U, Sigma, flags);
+        case BFGS_F32: return rsvd_impl<float, float, float>(h, rank, oversample, seed, (float*)U, Sigma, flags);
+        case BFGS_BF16: return rsvd_impl<bf16_t, float, float>(h, rank, oversample, seed, (float*)U, Sigma, flags);
     }
     return BFGS_ERR_ARG;
 }

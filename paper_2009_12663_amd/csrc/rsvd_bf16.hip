@@ -248,7 +248,8 @@ template <bool VEC>
 __global__ void __launch_bounds__(512, 4) basis_bf16(int64_t n, int c, int rank, int nks, const float* __restrict__ Q,
                                                      const uint16_t* __restrict__ ush, const double* __restrict__ lam,
                                                      const float* __restrict__ h0, float* __restrict__ U,
-                                                     float* __restrict__ dout) {
+                                                     float* __restrict__ dout, int32_t* __restrict__ status,
+                                                     int whitened) {
     extern __shared__ uint16_t qs[];   // 2 * BS_BUF
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
     const bool mm = wave < (rank + 31) / 32;   // uniform per wave
@@ -365,13 +366,19 @@ __global__ void __launch_bounds__(512, 4) basis_bf16(int64_t n, int c, int rank,
     }
     __syncthreads();
     const int nw = (rank + 31) / 32;
+    bool bad = false;
     for (int rl = tid; rl < BS_ROWS; rl += nthr) {
         const int64_t row = r0 + rl;
         if (row >= n) continue;
-        double sd = (double)h0[row];
+        const double hr = (double)h0[row];
+        double sd = 0.0;
         for (int w = 0; w < nw; ++w) sd += dpart[w * BS_ROWS + rl];
-        dout[row] = (float)sd;
+        // whitened basis: d = h0 + h0 sum_i lam_i U_i^2
+        const float d = (float)(whitened ? fma(hr, sd, hr) : hr + sd);
+        bad |= !isfinite(d);
+        dout[row] = d;
     }
+    if (bad) set_status(status, BFGS_ERR_NONFINITE);   // includes overflow of float32
 }
 
 }  // namespace
@@ -395,7 +402,7 @@ size_t basis_bf16_workspace(int c, int rank) {
 }
 
 int basis_bf16_launch(hipStream_t st, int64_t n, int c, int rank, const float* Q, const double* Us, uint16_t* ush,
-                      const double* lam, const float* h0, float* U, float* dout) {
+                      const double* lam, const float* h0, float* U, float* dout, int32_t* status, bool whitened) {
     if (c < 1 || c > 256 || rank < 1 || rank > c) return BFGS_ERR_ARG;
     const int nks = (c + 15) / 16, ntj = (rank + 31) / 32;
     const int total = ntj * nks * 512;
@@ -406,8 +413,10 @@ int basis_bf16_launch(hipStream_t st, int64_t n, int c, int rank, const float* Q
     const dim3 grid((unsigned)((n + BS_ROWS - 1) / BS_ROWS)), block(64 * waves);
     const size_t smem = 2 * BS_BUF * sizeof(uint16_t);
     if (n % 4 == 0)
-        hipLaunchKernelGGL(basis_bf16<true>, grid, block, smem, st, n, c, rank, nks, Q, ush, lam, h0, U, dout);
+        hipLaunchKernelGGL(basis_bf16<true>, grid, block, smem, st, n, c, rank, nks, Q, ush, lam, h0, U, dout, status,
+                           whitened ? 1 : 0);
     else
-        hipLaunchKernelGGL(basis_bf16<false>, grid, block, smem, st, n, c, rank, nks, Q, ush, lam, h0, U, dout);
+        hipLaunchKernelGGL(basis_bf16<false>, grid, block, smem, st, n, c, rank, nks, Q, ush, lam, h0, U, dout, status,
+                           whitened ? 1 : 0);
     return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
 }

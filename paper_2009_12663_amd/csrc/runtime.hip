@@ -47,13 +47,23 @@ void prof_begin(bfgsuq_ctx* h, const char* name) {
     r.a = prof_event(h);
     r.b = prof_event(h);
     if (!r.a || !r.b) return;
-    (void)hipEventRecord(r.a, h->stream);
+    if (hipEventRecord(r.a, h->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    h->prof.open.push_back(h->prof.recs.size());
     h->prof.recs.push_back(r);
 }
 
 void prof_end(bfgsuq_ctx* h) {
-    if (!h->prof.on || h->prof.recs.empty()) return;
-    (void)hipEventRecord(h->prof.recs.back().b, h->stream);
+    if (!h->prof.on || h->prof.open.empty()) return;
+    ProfRec& r = h->prof.recs[h->prof.open.back()];
+    h->prof.open.pop_back();
+    if (hipEventRecord(r.b, h->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    r.ended = true;
 }
 
 static void free_ws(Workspace& w) {
@@ -304,7 +314,7 @@ int bfgs_destroy(bfgs_t h) {
                     h->S1, h->Y1, h->S2, h->Y2};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    Workspace* ws[] = {&h->part, &h->Z, &h->PT, &h->small16, &h->X, &h->E, &h->Q, &h->refl, &h->tau,
+    Workspace* ws[] = {&h->part, &h->Z, &h->PT, &h->small16, &h->X, &h->E, &h->Q, &h->W, &h->refl, &h->tau,
                        &h->Rtree, &h->small, &h->lam, &h->diag};
     for (Workspace* w : ws) free_ws(*w);
     for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
@@ -478,6 +488,15 @@ int bfgs_rsvd(bfgs_t h, int32_t rank, int32_t oversample, uint64_t seed, void* U
     return rsvd_run(h, rank, oversample, seed, U, Sigma);
 }
 
+int bfgs_rsvd_ex(bfgs_t h, int32_t rank, int32_t oversample, uint64_t seed, uint32_t flags, void* U, double* Sigma) {
+    if (!h || !U || !Sigma || rank < 1 || oversample < 0) return BFGS_ERR_ARG;
+    if (flags & ~(BFGS_RSVD_PRECOND | BFGS_RSVD_TWO_PASS)) return BFGS_ERR_ARG;
+    const int64_t c = (int64_t)rank + oversample;
+    if (c > BFGS_MAX_COLS || c > h->n) return BFGS_ERR_ARG;
+    if (h->gamma_mode && !h->gamma_known) return BFGS_ERR_STATE;
+    return rsvd_run(h, rank, oversample, seed, U, Sigma, flags);
+}
+
 int bfgs_profile(bfgs_t h, int32_t enable) {
     if (!h) return BFGS_ERR_ARG;
     h->prof.on = enable != 0;
@@ -492,7 +511,11 @@ int bfgs_profile_report(bfgs_t h, char* buf, int32_t len) {
     std::vector<int> cnt;
     for (const ProfRec& r : h->prof.recs) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+        if (!r.ended) continue;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+            (void)hipGetLastError();   // leave no error behind for the caller's next HIP call
+            continue;
+        }
         size_t i = 0;
         for (; i < names.size(); ++i)
             if (std::strcmp(names[i], r.name) == 0) break;
@@ -505,6 +528,7 @@ int bfgs_profile_report(bfgs_t h, char* buf, int32_t len) {
         cnt[i] += 1;
     }
     h->prof.recs.clear();
+    h->prof.open.clear();
     h->prof.used = 0;
     int off = std::snprintf(buf, len, "{");
     for (size_t i = 0; i < names.size() && off < len; ++i)

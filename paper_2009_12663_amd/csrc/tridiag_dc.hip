@@ -11,8 +11,10 @@
 // the last (rho > 0; a negative rho is handled by negating D).  Steps of a merge:
 //   * sort the poles; deflate components with |rho z_i| <= tol, and close poles by a
 //     Givens rotation that moves one pole's weight onto its neighbour;
-//   * each root by bisection on f, measured from the nearer pole (x = d_o + tau), so
-//     that differences x - d_i keep their relative accuracy;
+//   * each root by safeguarded Newton steps on tau f(tau) inside a bracket that every
+//     evaluation's sign narrows (falling back to the bracket's midpoint), measured from
+//     the nearer pole (x = d_o + tau), so that differences x - d_i keep their relative
+//     accuracy;
 //   * z recomputed from the roots (Loewner's formula; Gu and Eisenstat 1994), which
 //     makes the eigenvectors z_i / (d_i - x_j) numerically orthogonal;
 //   * the merged basis: the sorted, rotated columns of diag(Q_A, Q_B) times those
@@ -157,7 +159,7 @@ __global__ void __launch_bounds__(DC_THREADS) dc_merge(int c, int h, const doubl
         z2n[j] = zj * zj;
     }
     __syncthreads();
-    // secular roots: lane j finds root j by bisection from its nearer pole
+    // secular roots: lane j finds root j from its nearer pole (bracket, then Newton)
     double z2sum = 0.0;
     for (int i = 0; i < K; ++i) z2sum += z2n[i];
     for (int j = tid; j < K; j += DC_THREADS) {

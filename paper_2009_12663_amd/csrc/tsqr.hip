@@ -7,14 +7,17 @@
 // tile swaps into the slot (tau = 1) and the slot rows carry no part of Q.
 //
 // Forward (leaf_forward_q, tree_forward_q).  One quad of lanes per column holds
-// the column's 64 tile rows (16 per lane) and folds the tile with one barrier per
-// reflector: reflector j acts on (slot row j, tile rows); the quad that owns column
-// j+1 builds reflector j+1 right after it applies reflector j.  Each wave's 16
-// columns form a panel whose reflectors are stored with the panel's compact-WY
-// factor T (I - V T V^T, V the tile parts; the slot part of reflector j is the unit
-// vector e_j; T upper triangular), formed while the reflectors are still in
-// registers.  The per-chain R factors are combined by a binary tree with the same
-// fold, R_b read as tile rows (tile t is zero left of column 64 t).
+// the column's 64 tile rows (16 per lane); reflector j acts on (slot row j, tile
+// rows).  Wave k owns columns 16 k .. 16 k + 15 and builds their group of 16
+// reflectors; there is no workgroup barrier: the groups pass through a ring of LDS
+// entries with per-entry ready/done counters (q_fold).  The two waves after a
+// builder apply its reflectors one at a time as they are published (they build the
+// next groups); waves further right apply the whole group as one compact-WY block
+// (I - V T V^T, V the tile parts; the slot part of reflector j is the unit vector
+// e_j; T upper triangular) on the float64 matrix cores.  Every group is also stored
+// as a panel (V, T) for the backward pass.  The per-chain R factors are combined by
+// a binary tree with the same fold, R_b read as tile rows (tile t is zero left of
+// column 64 t).
 //
 // Backward (tree_backward, leaf_backward).  Q is formed by applying the stored
 // panels in reverse to the identity at the root and to zero tile rows at the
@@ -308,19 +311,31 @@ __device__ __forceinline__ void q_reflect_column(SlotT* slot, double (&a)[RPL], 
     for (int i = 0; i < RPL; ++i) a[i] = fma(-ws, x[i * LPC + g], a[i]);
 }
 
-// LDS of the quad fold: taus_lds[256] | counters ready[QF_RMAX], done[QF_RMAX] |
-// (tau, sc)[QF_RMAX][PW] | x ring[R][PW][QT] (R groups' unscaled reflectors) | slot.
-// The ring takes what LDS leaves beside the slot, 2 to QF_RMAX groups.
+// LDS of the quad fold: taus_lds[256] | counters ready[QF_RMAX], done[QF_RMAX], abort |
+// (tau, sc)[QF_RMAX][PW] | ring[R] of (x[PW][QT_LD], T packed) | slot.  A ring entry
+// holds one group's unscaled reflectors (tile parts, row pitch QT_LD so that the
+// block update's column-wise reads spread over the banks) and the group's compact-WY
+// factor T (its upper triangle, row-major).  The ring takes what LDS leaves beside the
+// slot, 2 to QF_RMAX groups.
 constexpr int QF_RMAX = 8;
+constexpr int QT_LD = QT + 1;
 constexpr int QF_TAUS = 0;
 constexpr int QF_CNT = QF_TAUS + 256;
-constexpr int QF_TS = QF_CNT + QF_RMAX;             // 2 QF_RMAX unsigned counters
+constexpr int QF_TS = QF_CNT + QF_RMAX + 1;         // 2 QF_RMAX + 1 unsigned counters (+ pad)
 constexpr int QF_X = QF_TS + 2 * PW * QF_RMAX;
+constexpr int QF_TPK = PW * (PW + 1) / 2;           // T packed: upper triangle, row-major
+constexpr int QF_ENTRY = PW * QT_LD + QF_TPK;       // doubles per ring entry
+// Waves k + 1 .. k + QF_SEQ apply group k one reflector at a time, as it is
+// published: they build the next groups, so they are on the chain of the fold.  The
+// waves further right apply it as one block once its T is published.
+constexpr int QF_SEQ = 2;
+
+__device__ __forceinline__ int tpk_index(int i, int j) { return i * PW - (i * (i - 1)) / 2 + (j - i); }
 constexpr size_t QF_LDS_LIMIT = 160 * 1024;
 
 template <typename SlotT>
 size_t qf_lds_bytes(int c, int ring) {
-    return (size_t)(QF_X + ring * PW * QT) * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
+    return (size_t)(QF_X + ring * QF_ENTRY) * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
 }
 
 // The deepest ring that fits beside the slot, and no deeper than a tile's groups
@@ -346,18 +361,43 @@ __device__ __forceinline__ void q_arrive(unsigned* cnt) {
     __hip_atomic_fetch_add((lds_u32*)cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ void q_wait(unsigned* cnt, unsigned value) {
-    while ((int)(__hip_atomic_load((lds_u32*)cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) - value) < 0)
+// Every wait is bounded: after QF_SPIN_CAP polls (far beyond any legitimate wait:
+// the longest is one wave waiting for another's share of a tile) the wave raises the
+// workgroup's abort flag, and every wait returns at once once the flag is up, so a
+// broken protocol ends the kernel with BFGS_ERR_NUMERIC instead of hanging.
+constexpr unsigned QF_SPIN_CAP = 1u << 22;
+
+__device__ __forceinline__ bool q_aborted(const unsigned* abort_flag) {
+    return __hip_atomic_load((lds_u32*)abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u;
+}
+
+__device__ __forceinline__ void q_wait(unsigned* cnt, unsigned value, unsigned* abort_flag) {
+    unsigned polls = 0;
+    while ((int)(__hip_atomic_load((lds_u32*)cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) - value) < 0) {
+        if (q_aborted(abort_flag)) return;
+        if (++polls == QF_SPIN_CAP) {
+            __hip_atomic_store((lds_u32*)abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return;
+        }
         __builtin_amdgcn_s_sleep(1);
+    }
 }
 
 // q_wait for a counter whose last value seen by this wave is `seen`: no load when
 // that already covers `value` (an acquire that saw a count orders everything
 // released up to it); otherwise wait and keep the new value.
-__device__ __forceinline__ void q_wait_seen(unsigned* cnt, unsigned value, unsigned& seen) {
+__device__ __forceinline__ void q_wait_seen(unsigned* cnt, unsigned value, unsigned& seen, unsigned* abort_flag) {
+    unsigned polls = 0;
     while ((int)(seen - value) < 0) {
         seen = __hip_atomic_load((lds_u32*)cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if ((int)(seen - value) < 0) __builtin_amdgcn_s_sleep(1);
+        if ((int)(seen - value) < 0) {
+            if (q_aborted(abort_flag)) return;
+            if (++polls == QF_SPIN_CAP) {
+                __hip_atomic_store((lds_u32*)abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                return;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
     }
 }
 
@@ -380,89 +420,33 @@ struct QfSeq {
     }
 };
 
-// Fold the tile held in a[] (this quad's column) into the slot with reflectors
-// j0 .. c-1 (the tile's columns below j0 are zero; j0 is a multiple of PW).
-// Reflectors come in groups of PW: group k (reflectors PW k .. PW k + PW - 1) is
-// built by wave k, which owns those columns, one reflector after the other, each
-// applied to the wave's later columns at once (a wave's LDS operations complete in
-// order, so its own writes need no synchronisation).  The groups take the `ring`
-// slots of the LDS ring in turn.  Each reflector is published in its slot's ready
-// counter (value 256 G + slot + 1 for the workgroup's G-th group) as soon as it is
-// written, and the waves to the right apply it then.  Every wave that used a group
-// (its builder and the waves to its right) arrives at the slot's done counter
-// afterwards; the wave that next fills the slot first waits for all of them, so one
-// builder at a time writes a slot and its ready counter only grows.  A wave is done
-// with a tile once it has built its own group, and goes on to the next tile: the
-// tiles' chains overlap as far as the ring allows.  No wave shares slot entries with
-// another (an entry belongs to its column's quad), so there is no barrier: each wait
-// is for an event of an earlier group, whose waves wait only for still earlier
-// ones, so every wait ends.
-template <typename SlotT>
-__device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int j0, int col, int g, double* xring,
-                                       double* tsring, double* taus_lds, unsigned* cnt, int ring, QfSeq& sq) {
-    const int wave = threadIdx.x >> 6;   // = col / PW
-    const int np = (c + PW - 1) / PW;
-    double sc_own = 0.0;                 // the scale of this quad's reflector (columns j0 .. c-1)
-    for (int k = j0 / PW; k < np; ++k) {
-        const int jb = k * PW, je = min(jb + PW, c);
-        const int r = sq.slot;
-        double* xb = xring + r * PW * QT;
-        double* tb = tsring + r * 2 * PW;
-        unsigned* ready = cnt + r;
-        unsigned* done = cnt + QF_RMAX + r;
-        const unsigned tag = sq.groups * 256u + 1u;
-        if (wave >= k) {
-            if (wave == k) {
-                q_wait(done, sq.owed_at(r));   // the slot's previous group is used up
-                // the builder carries the chain of reflectors: it goes first on its SIMD
-                __builtin_amdgcn_s_setprio(2);
-                for (int j = jb; j < je; ++j) {
-                    const int sl = j - jb;
-                    if (col == j) {
-                        sc_own = q_make_reflector(slot, a, c, j, g, xb + sl * QT, tb + 2 * sl, taus_lds);
-                        if (g == 0) q_publish(ready, tag + (unsigned)sl);
-                    }
-                    const double tau = lds_early(tb + 2 * sl), sc = lds_early(tb + 2 * sl + 1);
-                    // tau = 0 (a zero column) leaves the column and the slot as they are
-                    if (col > j && col < c) q_reflect_column(slot, a, c, j, col, g, xb + sl * QT, tau, sc, tau * sc);
-                }
-                __builtin_amdgcn_s_setprio(0);
-            } else {
-                unsigned seen = tag - 1u;   // nothing of this group seen yet
-                // the next group's builder must apply this group before it can start:
-                // it goes before the other waves that apply it
-                if (wave == k + 1) __builtin_amdgcn_s_setprio(1);
-                for (int j = jb; j < je; ++j) {
-                    const int sl = j - jb;
-                    q_wait_seen(ready, tag + (unsigned)sl, seen);
-                    const double tau = lds_early(tb + 2 * sl), sc = lds_early(tb + 2 * sl + 1);
-                    if (col < c) q_reflect_column(slot, a, c, j, col, g, xb + sl * QT, tau, sc, tau * sc);
-                }
-                if (wave == k + 1) __builtin_amdgcn_s_setprio(0);
-            }
-            if (threadIdx.x % 64 == 0) q_arrive(done);
-        }
-        sq.add_owed(r, (unsigned)(np - k));   // wave k and the waves to its right
-        ++sq.groups;
-        sq.slot = r + 1 == ring ? 0 : r + 1;
-    }
-    // x -> v (zero stays zero for a zero column, sc = 0; columns left of j0 are zero)
+// A wave's tile columns in two layouts.  Quad layout (reflector building and the
+// one-at-a-time application): lane 4 j + g holds rows 4 i + g of the wave's column j
+// in a[i].  Matrix-core layout (block application): lane 16 q + j holds rows 4 i + q
+// of column j in a[i], which is at once the B operand of v_mfma_f64_16x16x4f64 for
+// k-step i and, read as four 16-row output tiles, its accumulator layout.  Going
+// from one to the other is a lane permutation with the register index unchanged.
+__device__ __forceinline__ void quad_to_mfma(double (&a)[RPL]) {
+    const int lane = threadIdx.x & 63;
+    const int src = 4 * (lane & 15) + (lane >> 4);
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) a[i] *= sc_own;
+    for (int i = 0; i < RPL; ++i) a[i] = bpermute_f64(a[i], src);
 }
 
-// After a fold, this wave's reflectors (its 16 columns = one panel) go to dst in the
-// panel layout: the tile part (rows t = i * LPC + g), then the panel's compact-WY
-// factor T (I - V T V^T, T upper triangular) formed from the reflectors still in
-// registers.  G = V^T V on the matrix cores: V's rows 4 ks .. 4 ks + 3 sit in a[ks]
-// of the quads, one lane permutation away from the A/B operand layout.  Then T
-// column by column: lane r < 16 keeps row r, and G(b, i) (accumulator element b / 4
-// of lane 16 (b % 4) + i) is broadcast.
-__device__ __forceinline__ void q_store_panel(const double (&a)[RPL], int c, int col, int g,
-                                              const double* taus_lds, double* dst) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+__device__ __forceinline__ void mfma_to_quad(double (&a)[RPL]) {
+    const int lane = threadIdx.x & 63;
+    const int src = 16 * (lane & 3) + (lane >> 2);
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) dst[(col % PW) * QT + i * LPC + g] = a[i];
+    for (int i = 0; i < RPL; ++i) a[i] = bpermute_f64(a[i], src);
+}
+
+// The compact-WY factor of this wave's panel (its 16 columns = one group, scaled
+// v = sc x, in quad layout): G = V^T V on the matrix cores (V's rows 4 ks .. 4 ks + 3
+// sit in a[ks] of the quads, one lane permutation away from the operand layout),
+// then T (I - V T V^T, upper triangular) column by column with G's entries broadcast
+// from the accumulator lanes.  Lane r < 16 returns row r of T in trow.
+__device__ __forceinline__ void q_panel_t(const double (&a)[RPL], int c, const double* taus_lds, double (&trow)[PW]) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int src = 4 * (lane & 15) + (lane >> 4);
     v4d gacc = {0, 0, 0, 0};
 #pragma unroll
@@ -471,7 +455,6 @@ __device__ __forceinline__ void q_store_panel(const double (&a)[RPL], int c, int
         gacc = mfma64(v, v, gacc);
     }
     const int r = lane & 15;
-    double trow[PW];
 #pragma unroll
     for (int i = 0; i < PW; ++i) {
         const int ci = wave * PW + i;
@@ -481,24 +464,185 @@ __device__ __forceinline__ void q_store_panel(const double (&a)[RPL], int c, int
         for (int b = 0; b < i; ++b) sacc = fma(trow[b], read_lane(gacc[b / 4], 16 * (b % 4) + i), sacc);
         trow[i] = i < r ? 0.0 : (i == r ? tau_i : -tau_i * sacc);
     }
-    if (lane < PW) {
+}
+
+// Group (reflectors jb .. jb + ng - 1, unscaled tile parts x in xb, (tau, sc) in tb,
+// compact-WY factor T in Tb) applied at once to this wave's columns, held in the
+// matrix-core layout, and to their slot rows jb .. jb + ng - 1.  With V the
+// reflectors (slot part the unit rows, tile part X diag(sc)) the group's product
+// is I - V T V^T, and applying H_jb first, then H_jb+1, ... is its transpose:
+//   W = S_p + diag(sc) X^T A;  W' = T^T W;  S_p -= W';  A -= X diag(sc) W'.
+// Every product is a v_mfma_f64_16x16x4f64 chain: 16 + 4 + 16 per group.
+template <typename SlotT>
+__device__ __forceinline__ void q_block_apply(SlotT* slot, double (&a)[RPL], int c, int jb, int ng, const double* xb,
+                                              const double* tb, const double* Tb) {
+    const int lane = threadIdx.x & 63, jl = lane & 15, q = lane >> 4, wave = threadIdx.x >> 6;
+    const int colw = wave * PW + jl;
+    const bool colok = colw < c;
+    v4d wt = {0, 0, 0, 0};
 #pragma unroll
-        for (int i = 0; i < PW; ++i) dst[PW * QT + lane * PW + i] = trow[i];
+    for (int ks = 0; ks < RPL; ++ks) {
+        const double xa = jl < ng ? xb[jl * QT_LD + 4 * ks + q] : 0.0;   // X(4 ks + q, jl)
+        wt = mfma64(xa, a[ks], wt);
+    }
+    v4d w;
+    double scr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = q + 4 * r;
+        scr[r] = i < ng ? tb[2 * i + 1] : 0.0;
+        const double sp = (colok && i < ng) ? (double)slot[tri_index(jb + i, colw, c)] : 0.0;
+        w[r] = fma(scr[r], wt[r], sp);
+    }
+    // phases stay in order: the loads of a later phase are not hoisted over the
+    // earlier MFMA chains (they would hold 32 more registers across them)
+    __builtin_amdgcn_sched_barrier(0);
+    v4d wp = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        const int ti = 4 * ks + q;   // T(ti, jl), zero below the diagonal
+        wp = mfma64(jl >= ti ? Tb[tpk_index(ti, jl)] : 0.0, w[ks], wp);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = q + 4 * r;
+        if (colok && i < ng) {
+            const int idx = tri_index(jb + i, colw, c);
+            slot[idx] = (SlotT)((double)slot[idx] - wp[r]);
+        }
+        wp[r] *= scr[r];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+        v4d acc = {a[4 * blk], a[4 * blk + 1], a[4 * blk + 2], a[4 * blk + 3]};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int i = 4 * m + q;
+            const double xa = i < ng ? -xb[i * QT_LD + 16 * blk + jl] : 0.0;   // -X(16 blk + jl, 4 m + q)
+            acc = mfma64(xa, wp[m], acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[4 * blk + r] = acc[r];
+    }
+}
+
+// Fold the tile held in a[] (this quad's column, quad layout) into the slot with
+// reflectors j0 .. c-1 (the tile's columns below j0 are zero; j0 is a multiple of PW).
+// Reflectors come in groups of PW: group k (reflectors PW k .. PW k + PW - 1) is
+// built by wave k, which owns those columns, one reflector after the other, each
+// applied to the wave's later columns at once (a wave's LDS operations complete in
+// order, so its own writes need no synchronisation).  The groups take the `ring`
+// entries of the LDS ring in turn.  Each reflector is published in its entry's
+// ready counter (value 256 G + slot + 1 for the workgroup's G-th group) as soon as it
+// is written; once the group is complete its builder forms the group's compact-WY
+// factor T, writes it beside the reflectors, publishes one count more and stores its
+// panel (V, T) to `panels`.  Waves k + 1 .. k + QF_SEQ, the next groups' builders,
+// apply each reflector as it is published (they are on the chain of the fold); the
+// waves further right wait for the final count and apply the whole group as one
+// block on the matrix cores (q_block_apply), holding their columns in the
+// matrix-core layout until they reach the first group they apply one at a time.
+// Every wave that used a group (its builder included) arrives at the entry's done
+// counter afterwards; the wave that next fills the entry first waits for all of
+// them, so one builder at a time writes an entry and its ready counter only grows.  A wave is done with a tile once it has built its
+// own group, and goes on to the next tile: the tiles' chains overlap as far as the
+// ring allows.  No wave shares slot entries with another (an entry belongs to its
+// column's wave), so there is no barrier: each wait is for an event of an earlier
+// group, whose waves wait only for still earlier ones, so every wait ends.
+template <typename SlotT>
+__device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int j0, int col, int g, double* xring,
+                                       double* tsring, double* taus_lds, unsigned* cnt, int ring, QfSeq& sq,
+                                       double* panels) {
+    const int wave = threadIdx.x >> 6;   // = col / PW
+    const int np = (c + PW - 1) / PW;
+    const int k0 = j0 / PW;
+    unsigned* abort_flag = cnt + 2 * QF_RMAX;
+    double sc_own = 0.0;                 // the scale of this quad's reflector (columns j0 .. c-1)
+    const bool block_first = wave >= k0 + QF_SEQ + 1;
+    if (block_first) quad_to_mfma(a);
+    for (int k = k0; k < np; ++k) {
+        const int jb = k * PW, je = min(jb + PW, c), ng = je - jb;
+        const int r = sq.slot;
+        double* xb = xring + r * QF_ENTRY;
+        double* Tb = xb + PW * QT_LD;
+        double* tb = tsring + r * 2 * PW;
+        unsigned* ready = cnt + r;
+        unsigned* done = cnt + QF_RMAX + r;
+        const unsigned tag = sq.groups * 256u + 1u;
+        if (wave >= k) {
+            if (wave == k) {
+                q_wait(done, sq.owed_at(r), abort_flag);   // the entry's previous group is used up
+                // the builder carries the chain of reflectors: it goes first on its SIMD
+                __builtin_amdgcn_s_setprio(2);
+                for (int j = jb; j < je; ++j) {
+                    const int sl = j - jb;
+                    if (col == j) {
+                        sc_own = q_make_reflector(slot, a, c, j, g, xb + sl * QT_LD, tb + 2 * sl, taus_lds);
+                        if (g == 0) q_publish(ready, tag + (unsigned)sl);
+                    }
+                    const double tau = lds_early(tb + 2 * sl), sc = lds_early(tb + 2 * sl + 1);
+                    // tau = 0 (a zero column) leaves the column and the slot as they are
+                    if (col > j && col < c) q_reflect_column(slot, a, c, j, col, g, xb + sl * QT_LD, tau, sc, tau * sc);
+                }
+                __builtin_amdgcn_s_setprio(0);
+                // x -> v (zero stays zero for a zero column, sc = 0); the group's T beside
+                // its reflectors, then the count the block consumers wait for
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) a[i] *= sc_own;
+                double trow[PW];
+                q_panel_t(a, c, taus_lds, trow);
+                const int lane = threadIdx.x & 63;
+                if (lane < PW) {
+#pragma unroll
+                    for (int i = 0; i < PW; ++i)
+                        if (i >= lane) Tb[tpk_index(lane, i)] = trow[i];
+                }
+                if (lane == 0) q_publish(ready, tag + (unsigned)ng);
+                if (panels) {
+                    double* dst = panels + (int64_t)wave * Layout<QT>::PS;
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) dst[(col % PW) * QT + i * LPC + g] = a[i];
+                    if (lane < PW) {
+#pragma unroll
+                        for (int i = 0; i < PW; ++i) dst[PW * QT + lane * PW + i] = trow[i];
+                    }
+                }
+            } else if (wave <= k + QF_SEQ) {
+                // the next groups' builders apply this group as it is published
+                if (block_first && wave == k + QF_SEQ) mfma_to_quad(a);
+                unsigned seen = tag - 1u;   // nothing of this group seen yet
+                if (wave == k + 1) __builtin_amdgcn_s_setprio(1);
+                for (int j = jb; j < je; ++j) {
+                    const int sl = j - jb;
+                    q_wait_seen(ready, tag + (unsigned)sl, seen, abort_flag);
+                    const double tau = lds_early(tb + 2 * sl), sc = lds_early(tb + 2 * sl + 1);
+                    if (col < c) q_reflect_column(slot, a, c, j, col, g, xb + sl * QT_LD, tau, sc, tau * sc);
+                }
+                __builtin_amdgcn_s_setprio(0);
+            } else {
+                q_wait(ready, tag + (unsigned)ng, abort_flag);
+                q_block_apply(slot, a, c, jb, ng, xb, tb, Tb);
+            }
+            if (threadIdx.x % 64 == 0) q_arrive(done);
+        }
+        sq.add_owed(r, (unsigned)(np - k));   // wave k and the waves to its right
+        ++sq.groups;
+        sq.slot = r + 1 == ring ? 0 : r + 1;
     }
 }
 
 template <typename TE, typename SlotT>
 __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t rows_per_chain,
                                                        const TE* __restrict__ E, double* __restrict__ refl,
-                                                       double* __restrict__ Rs, int ring) {
+                                                       double* __restrict__ Rs, int ring, int32_t* __restrict__ status) {
     extern __shared__ double lds[];
     double* xring = lds + QF_X;
     double* tsring = lds + QF_TS;
     double* taus_lds = lds + QF_TAUS;
     unsigned* cnt = (unsigned*)(lds + QF_CNT);
-    SlotT* slot = (SlotT*)(lds + QF_X + ring * PW * QT);
+    SlotT* slot = (SlotT*)(lds + QF_X + ring * QF_ENTRY);
     QfSeq sq;
-    if (threadIdx.x < 2 * QF_RMAX) cnt[threadIdx.x] = 0;   // the slot set-up's barrier follows
+    if (threadIdx.x <= 2 * QF_RMAX) cnt[threadIdx.x] = 0;   // counters and the abort flag; the slot set-up's barrier follows
     constexpr int PS = Layout<QT>::PS;
     const int ch = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
     const int np = (c + PW - 1) / PW;
@@ -533,11 +677,12 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
 #pragma unroll
             for (int i = 0; i < RPL; ++i) nx[i] = E[(int64_t)colc * n + min(r0 + QT + i * LPC + g, r_end - 1)];
         }
-        q_fold(slot, a, c, 0, col, g, xring, tsring, taus_lds, cnt, ring, sq);
         const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
-        q_store_panel(a, c, col, g, taus_lds, refl + (gtile * np + (threadIdx.x >> 6)) * PS);
+        q_fold(slot, a, c, 0, col, g, xring, tsring, taus_lds, cnt, ring, sq, refl + gtile * np * PS);
+        if (q_aborted(cnt + 2 * QF_RMAX)) break;
     }
     __syncthreads();   // the folds have no barrier; slot_store reads every column's entries
+    if (threadIdx.x == 0 && q_aborted(cnt + 2 * QF_RMAX)) set_status(status, BFGS_ERR_NUMERIC);
     slot_store(slot, Rs + (int64_t)ch * c * c, c);
 }
 
@@ -547,15 +692,15 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
 // tree + ((comb_off + i) * ntt + t) * np * PS + p * PS, as the backward pass reads them.
 template <typename SlotT>
 __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_t comb_off, double* __restrict__ Rs,
-                                                       double* __restrict__ tree, int ring) {
+                                                       double* __restrict__ tree, int ring, int32_t* __restrict__ status) {
     extern __shared__ double lds[];
     double* xring = lds + QF_X;
     double* tsring = lds + QF_TS;
     double* taus_lds = lds + QF_TAUS;
     unsigned* cnt = (unsigned*)(lds + QF_CNT);
-    SlotT* slot = (SlotT*)(lds + QF_X + ring * PW * QT);
+    SlotT* slot = (SlotT*)(lds + QF_X + ring * QF_ENTRY);
     QfSeq sq;
-    if (threadIdx.x < 2 * QF_RMAX) cnt[threadIdx.x] = 0;   // the slot set-up's barrier follows
+    if (threadIdx.x <= 2 * QF_RMAX) cnt[threadIdx.x] = 0;   // counters and the abort flag; the slot set-up's barrier follows
     constexpr int PS = Layout<QT>::PS;
     const int i = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC, wave = threadIdx.x >> 6;
     const int np = (c + PW - 1) / PW, ntt = (c + QT - 1) / QT;
@@ -571,10 +716,12 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
             const double v = Rb[(int64_t)min(row, c - 1) * c + colc];   // clamped, masked below
             a[q] = (col < c && row < c && col >= row) ? v : 0.0;
         }
-        q_fold(slot, a, c, t * QT, col, g, xring, tsring, taus_lds, cnt, ring, sq);
-        if (wave >= (t * QT) / PW) q_store_panel(a, c, col, g, taus_lds, tree + (((comb_off + i) * ntt + t) * np + wave) * PS);
+        q_fold(slot, a, c, t * QT, col, g, xring, tsring, taus_lds, cnt, ring, sq,
+               tree + ((comb_off + i) * ntt + t) * np * PS);
+        if (q_aborted(cnt + 2 * QF_RMAX)) break;
     }
     __syncthreads();   // the folds have no barrier; slot_store reads every column's entries
+    if (threadIdx.x == 0 && q_aborted(cnt + 2 * QF_RMAX)) set_status(status, BFGS_ERR_NUMERIC);
     slot_store(slot, Rs + (int64_t)a_idx * c * c, c);
 }
 
@@ -702,14 +849,14 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out) {
     const int ring = qf_ring<SlotT>(c);   // >= 2: the slot type was chosen for that
     prof_begin(h, "tsqr_leaf_fwd");
     hipLaunchKernelGGL((leaf_forward_q<TE, SlotT>), dim3(nchains), dim3(LPC * 16 * np), qf_lds_bytes<SlotT>(c, ring),
-                       h->stream, n, c, rows_per_chain, E, refl, Rs, ring);
+                       h->stream, n, c, rows_per_chain, E, refl, Rs, ring, h->status);
     prof_end(h);
     prof_begin(h, "tsqr_tree");
     int64_t off = 0;
     for (int stride = 1; stride < nchains; stride *= 2) {
         const int ncomb = nchains / (2 * stride);
         hipLaunchKernelGGL((tree_forward_q<SlotT>), dim3(ncomb), dim3(threads), qf_lds_bytes<SlotT>(c, ring),
-                           h->stream, c, stride, off, Rs, tree, ring);
+                           h->stream, c, stride, off, Rs, tree, ring, h->status);
         off += ncomb;
     }
     hipLaunchKernelGGL(set_identity_kernel, dim3(64), dim3(256), 0, h->stream, Qtop, c);
@@ -747,9 +894,11 @@ int tsqr_dispatch(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out) {
 
 }  // namespace
 
+bool tsqr_f64_slot(int c) { return c >= 1 && c <= 256 && lds_bytes<64, double>(c) <= 160 * 1024 && qf_ring<double>(c) >= 2; }
+
 extern "C" int bfgs_tsqr_shape(int32_t c, int32_t* slot_f64, int32_t* ring) {
     if (c < 1 || c > BFGS_MAX_COLS) return BFGS_ERR_ARG;
-    const bool dslot = lds_bytes<64, double>(c) <= 160 * 1024 && qf_ring<double>(c) >= 2;
+    const bool dslot = tsqr_f64_slot(c);
     if (slot_f64) *slot_f64 = dslot ? 1 : 0;
     if (ring) *ring = dslot ? qf_ring<double>(c) : qf_ring<float>(c);
     return BFGS_OK;

@@ -26,6 +26,22 @@ def col_max_rel(a, b) -> float:
     return float((num / den).max())
 
 
+def sigma_err(got, ref) -> float:
+    """max_i |got_i - ref_i| / |ref_0| after sorting both by signed value.  The ordering
+    by |lambda| is not unique where two eigenvalues of opposite sign have nearly equal
+    magnitude (rounding decides which comes first), so the spectra are compared as
+    sets; sigma_order_ok checks the ordering itself."""
+    got = np.sort(np.asarray(got, np.float64))
+    ref = np.asarray(ref, np.float64)
+    return float(np.abs(got - np.sort(ref)).max() / abs(ref[0]))
+
+
+def sigma_order_ok(got, tol) -> bool:
+    """|Sigma| is non-increasing, up to tol |Sigma_0| for near ties."""
+    a = np.abs(np.asarray(got, np.float64))
+    return bool((np.diff(a) <= tol * a[0]).all())
+
+
 def gpu_input(x64: torch.Tensor, storage: str) -> torch.Tensor:
     """What the binding is handed: float64 for float64 storage, float32 otherwise."""
     return x64.to("cuda", torch.float64 if storage == "f64" else torch.float32)

@@ -5,9 +5,12 @@ ready and a done counter.  Group k of 16 reflectors is built by wave k: it waits
 until its slot's done counter has every arrival owed by the slot's earlier
 groups, then writes and publishes each reflector (the slot's ready counter takes
 256 G + slot + 1 for the workgroup's G-th group) and finally arrives at done.
-The waves to its right wait for each reflector, apply it, and arrive at done
-after the group.  A wave that has built its group goes on to the next tile, so
-the tiles' chains overlap as far as the ring allows.
+The next two waves (k + 1 and k + 2, the next groups' builders) wait for each
+reflector and apply it as it comes; the waves further right wait once, for the
+group's last count (256 G + slot + n + 1, published after the builder has written the group's
+compact-WY factor T), and apply the whole group as one block.  Every wave that
+used the group arrives at done afterwards.  A wave that has built its group goes
+on to the next tile, so the tiles' chains overlap as far as the ring allows.
 
 Here each wave is a generator that follows exactly that control flow, and a
 seeded random scheduler interleaves them.  The model fails on a deadlock, on a
@@ -19,9 +22,10 @@ import random
 import pytest
 
 PW = 16
+SEQ = 2   # waves k + 1 .. k + SEQ apply group k one reflector at a time
 
 
-def wave_program(w, c, tiles, st, R):
+def wave_program(w, c, tiles, st, R, block=True):
     """Wave w's accesses over `tiles` tiles of leaf folds (starts) or tree folds."""
     np_ = (c + PW - 1) // PW
     groups = 0
@@ -42,24 +46,35 @@ def wave_program(w, c, tiles, st, R):
                         st["owner"][half] = groups
                         st["ready"][half] = groups * 256 + (j - jb + 1)
                         yield "step"
-                else:
+                    # the group's T, then the count the block consumers wait for
+                    st["ready"][half] = groups * 256 + (je - jb + 1)
+                    yield "step"
+                elif w <= k + SEQ or not block:
                     st["users"][groups] = st["users"].get(groups, 0) + 1
                     for j in range(jb, je):
                         while st["ready"][half] - (groups * 256 + (j - jb + 1)) < 0:
                             yield "wait"
                         assert st["owner"][half] == groups, ("stale reflector", w, k)
                         yield "step"
+                else:
+                    st["users"][groups] = st["users"].get(groups, 0) + 1
+                    while st["ready"][half] - (groups * 256 + (je - jb + 1)) < 0:
+                        yield "wait"
+                    assert st["owner"][half] == groups, ("stale group", w, k)
+                    yield "step"
+                    assert st["owner"][half] == groups, ("group refilled during the block update", w, k)
+                    yield "step"
                 st["users"][groups] -= 1
                 st["done"][half] += 1
             owed[half] += np_ - k
             groups += 1
 
 
-def run(c, tiles, seed, R=2):
+def run(c, tiles, seed, R=2, block=True):
     rnd = random.Random(seed)
     np_ = (c + PW - 1) // PW
     st = {"ready": [0] * R, "done": [0] * R, "owner": [None] * R, "users": {}}
-    progs = {w: wave_program(w, c, tiles, st, R) for w in range(np_)}
+    progs = {w: wave_program(w, c, tiles, st, R, block) for w in range(np_)}
     alive = set(progs)
     idle = 0
     while alive:
@@ -76,13 +91,14 @@ def run(c, tiles, seed, R=2):
 
 
 @pytest.mark.parametrize("c", [1, 15, 16, 17, 26, 32, 40, 64, 100, 184, 220, 256])
-@pytest.mark.parametrize("R", [1, 2, 3, 7, 8])
-def test_fold_protocol_leaf_and_tree(c, R):
+@pytest.mark.parametrize("R", [1, 2, 3, 5, 7, 8])
+@pytest.mark.parametrize("block", [False, True])
+def test_fold_protocol_leaf_and_tree(c, R, block):
     leaf = [0, 0, 0, 0]                               # four leaf tiles
     tree = [64 * t for t in range((c + 63) // 64)]    # one tree combine: tile t starts at 64 t
     for seed in range(12):
-        assert run(c, leaf, seed, R), ("deadlock", c, R, "leaf", seed)
-        assert run(c, tree + tree, seed, R), ("deadlock", c, R, "tree", seed)
+        assert run(c, leaf, seed, R, block), ("deadlock", c, R, "leaf", seed)
+        assert run(c, tree + tree, seed, R, block), ("deadlock", c, R, "tree", seed)
 
 
 def test_fold_protocol_detects_a_shared_counter():

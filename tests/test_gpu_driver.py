@@ -1,0 +1,83 @@
+"""The GPU-resident BFGS driver (bfgs_minimize_quadratic) and its grid operator
+(bfgs_gridop_apply) against the float64 oracle: the operator against the problem's
+own definition, the iterates and gradient norms against the oracle's full-history
+BFGS with exact line search (Alg. 1, eq. 1) on the same quadratic."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bfgs as obfgs
+from workloads import quadratic as wq
+
+pytestmark = pytest.mark.gpu
+
+
+def gridop(prob):
+    import paper_2009_12663_amd as P
+    return P.GridOp(prob.nx, prob.nz, prob.nparam, prob.D.cuda(), prob.sigma, wq.SMOOTH_HALF, prob.coupling)
+
+
+@pytest.mark.parametrize("nx,nz", [(20, 15), (7, 3), (45, 50), (1, 9)])
+def test_gridop_matches_problem(nx, nz):
+    prob = wq.make_grid(nx, nz, seed=nx + nz)
+    op = gridop(prob)
+    X = wq.normal_block(prob.n, 3, seed=1)
+    got = op.apply(X.cuda()).cpu().numpy()
+    want = prob.matvec(X).numpy()
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"\n[gridop] {nx}x{nz}x3: max rel err {err:.2e}", flush=True)
+    assert err <= 1e-14
+    op.close()
+
+
+@pytest.mark.parametrize("precond", [False, True])
+def test_minimize_matches_oracle_bfgs(precond):
+    import paper_2009_12663_amd as P
+    prob = wq.make_grid(20, 15, seed=4)
+    n = prob.n
+    A = prob.matvec(torch.eye(n, dtype=torch.float64)).numpy()          # dense, for the oracle
+    b = prob.b.numpy()
+    h0 = (1.0 / prob.diag()).numpy() if precond else None
+    k = 25
+    op = gridop(prob)
+    H = P.Bfgs(n, k, None if h0 is None else torch.from_numpy(h0).cuda(), "f64")
+    m, gn = P.minimize_quadratic(H, op, prob.b.cuda(), k, 0.0)
+    assert len(gn) == k + 1 and H.k == k
+    S_o, Y_o, _, m_o, gn_o = obfgs.bfgs_quadratic(A, b, k, h0=h0)
+    rel = np.abs(np.array(gn) - np.array(gn_o)) / np.array(gn_o)
+    m_err = np.abs(m.cpu().numpy() - m_o).max() / np.abs(m_o).max()
+    S_g, Y_g = (t.cpu().numpy() for t in H.get_pairs())
+    s_err = np.abs(S_g - S_o).max() / np.abs(S_o).max()
+    print(f"\n[driver] precond={precond}: |g| rel err max {rel.max():.2e} (|g_k|/|g_0| = {gn[-1] / gn[0]:.2e}), "
+          f"m {m_err:.2e}, pairs {s_err:.2e}", flush=True)
+    assert rel[:15].max() <= 1e-9 and rel.max() <= 1e-6
+    assert m_err <= 1e-9 and s_err <= 1e-8
+    H.close()
+    op.close()
+
+
+def test_minimize_converges_and_stops():
+    """float32 storage reaches a relative gradient of 1e-6 on the 600 x 200 x 3 grid in
+    about as many iterations as the float64 oracle's conjugate-gradient equivalent, and
+    stops there; argument and state errors are refused."""
+    import paper_2009_12663_amd as P
+    prob = wq.make_problem("grid2", device="cuda")
+    op = gridop(prob)
+    H = P.Bfgs(prob.n, 200, None, "f32")
+    m, gn = P.minimize_quadratic(H, op, prob.b, 200, 1e-6)
+    _, _, gn_cg = wq.cg_pairs(prob, 200, rel_tol=1e-6)
+    it, it_cg = len(gn) - 1, len(gn_cg) - 1
+    print(f"\n[driver] grid2 f32: {it} iterations to 1e-6 (float64 CG: {it_cg})", flush=True)
+    assert gn[-1] <= 1e-6 * gn[0] and abs(it - it_cg) <= 2 and H.k == it
+    r = prob.matvec(m) - prob.b
+    assert float(torch.linalg.vector_norm(r)) <= 2e-6 * gn[0]
+    with pytest.raises(P.BfgsError) as e:
+        P.minimize_quadratic(H, op, prob.b, 5, 0.0)          # history not empty
+    assert e.value.code == P.BFGS_ERR_STATE
+    Hb = P.Bfgs(prob.n, 4, None, "bf16")
+    with pytest.raises(P.BfgsError) as e:
+        P.minimize_quadratic(Hb, op, prob.b, 5, 0.0)
+    assert e.value.code == P.BFGS_ERR_ARG
+    Hb.close()
+    H.close()
+    op.close()
