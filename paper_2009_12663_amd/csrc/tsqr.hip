@@ -71,6 +71,16 @@ __device__ __forceinline__ double read_lane(double x, int l) {
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// The lane index as a value the compiler cannot see through: masks computed from it
+// are formed where they are used, instead of being hoisted out of the fold's loops
+// into scalar registers (the fold has none to spare, and spilled masks cost more to
+// restore than to recompute).
+__device__ __forceinline__ int fresh_lane() {
+    int l = (int)(threadIdx.x & 63);
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
 // x of lane src (any lane, chosen per lane)
 __device__ __forceinline__ double bpermute_f64(double x, int src) {
     const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
@@ -261,7 +271,7 @@ __device__ __forceinline__ double quad_sum(double x) {
 // takes no further reflector).
 template <typename SlotT>
 __device__ __forceinline__ double q_make_reflector(SlotT* slot, const double (&a)[RPL], int c, int j, int g,
-                                                   double* vbuf, double* ts, double* taus_lds) {
+                                                   double* vbuf, double* ts, double* taus_lds, double& tau_out) {
     const int dj = tri_index(j, j, c);
     const double rjj = lds_early(slot + dj);
 #pragma unroll
@@ -289,6 +299,7 @@ __device__ __forceinline__ double q_make_reflector(SlotT* slot, const double (&a
         ts[1] = sc;
         taus_lds[j] = tau;
     }
+    tau_out = tau;
     return sc;
 }
 
@@ -357,6 +368,15 @@ __device__ __forceinline__ void q_publish(unsigned* cnt, unsigned value) {
     __hip_atomic_store((lds_u32*)cnt, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// A count published without a hardware wait: the LDS executes a wave's operations in
+// the order they are issued, so a waiter that sees the count (by an acquire load) also
+// sees every LDS write the publishing wave issued before it.  Only the compiler must
+// be kept from moving those writes past the count.
+__device__ __forceinline__ void q_publish_inorder(unsigned* cnt, unsigned value) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __hip_atomic_store((lds_u32*)cnt, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ void q_arrive(unsigned* cnt) {
     __hip_atomic_fetch_add((lds_u32*)cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -374,6 +394,19 @@ __device__ __forceinline__ bool q_aborted(const unsigned* abort_flag) {
 __device__ __forceinline__ void q_wait(unsigned* cnt, unsigned value, unsigned* abort_flag) {
     unsigned polls = 0;
     while ((int)(__hip_atomic_load((lds_u32*)cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) - value) < 0) {
+        if (q_aborted(abort_flag)) return;
+        if (++polls == QF_SPIN_CAP) {
+            __hip_atomic_store((lds_u32*)abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Wait until the counter, read as a signed value, is no longer negative.
+__device__ __forceinline__ void q_wait_nonneg(unsigned* cnt, unsigned* abort_flag) {
+    unsigned polls = 0;
+    while ((int)__hip_atomic_load((lds_u32*)cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < 0) {
         if (q_aborted(abort_flag)) return;
         if (++polls == QF_SPIN_CAP) {
             __hip_atomic_store((lds_u32*)abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -401,23 +434,11 @@ __device__ __forceinline__ void q_wait_seen(unsigned* cnt, unsigned value, unsig
     }
 }
 
-// Progress of a workgroup's folds, the same in every thread: groups started, the
-// ring slot of the next one, and per ring slot the arrivals owed by its groups so
-// far (registers: every index below is a constant after unrolling).
+// Progress of a workgroup's folds, the same in every thread: groups started and the
+// ring slot of the next one.
 struct QfSeq {
     unsigned groups = 0;
     int slot = 0;
-    unsigned owed[QF_RMAX] = {0, 0, 0, 0, 0, 0, 0, 0};
-    __device__ unsigned owed_at(int r) const {
-        unsigned v = 0;
-#pragma unroll
-        for (int i = 0; i < QF_RMAX; ++i) v = i == r ? owed[i] : v;
-        return v;
-    }
-    __device__ void add_owed(int r, unsigned n) {
-#pragma unroll
-        for (int i = 0; i < QF_RMAX; ++i) owed[i] += i == r ? n : 0u;
-    }
 };
 
 // A wave's tile columns in two layouts.  Quad layout (reflector building and the
@@ -427,26 +448,30 @@ struct QfSeq {
 // k-step i and, read as four 16-row output tiles, its accumulator layout.  Going
 // from one to the other is a lane permutation with the register index unchanged.
 __device__ __forceinline__ void quad_to_mfma(double (&a)[RPL]) {
-    const int lane = threadIdx.x & 63;
+    const int lane = fresh_lane();
     const int src = 4 * (lane & 15) + (lane >> 4);
 #pragma unroll
     for (int i = 0; i < RPL; ++i) a[i] = bpermute_f64(a[i], src);
 }
 
 __device__ __forceinline__ void mfma_to_quad(double (&a)[RPL]) {
-    const int lane = threadIdx.x & 63;
+    const int lane = fresh_lane();
     const int src = 16 * (lane & 3) + (lane >> 2);
 #pragma unroll
     for (int i = 0; i < RPL; ++i) a[i] = bpermute_f64(a[i], src);
 }
 
 // The compact-WY factor of this wave's panel (its 16 columns = one group, scaled
-// v = sc x, in quad layout): G = V^T V on the matrix cores (V's rows 4 ks .. 4 ks + 3
-// sit in a[ks] of the quads, one lane permutation away from the operand layout),
-// then T (I - V T V^T, upper triangular) column by column with G's entries broadcast
-// from the accumulator lanes.  Lane r < 16 returns row r of T in trow.
-__device__ __forceinline__ void q_panel_t(const double (&a)[RPL], int c, const double* taus_lds, double (&trow)[PW]) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+// v = sc x, in quad layout), written to Tb (upper triangle, packed) and returned in
+// trow (lane r < 16: row r).  G = V^T V is formed on the matrix cores (V's rows
+// 4 ks .. 4 ks + 3 sit in a[ks] of the quads, one lane permutation away from the
+// operand layout) and its upper triangle stored to Tb; every lane then reads the G
+// entries it needs from there (the same address in every lane), lane r forms row r
+// of T (I - V T V^T, upper triangular) and T replaces G in Tb.  A wave's LDS
+// operations complete in order, so the reads of G precede the writes of T.
+__device__ __forceinline__ void q_panel_t(const double (&a)[RPL], int c, const double* taus_lds, double* Tb,
+                                          double (&trow)[PW]) {
+    const int wave = threadIdx.x >> 6, lane = fresh_lane();
     const int src = 4 * (lane & 15) + (lane >> 4);
     v4d gacc = {0, 0, 0, 0};
 #pragma unroll
@@ -454,55 +479,71 @@ __device__ __forceinline__ void q_panel_t(const double (&a)[RPL], int c, const d
         const double v = bpermute_f64(a[ks], src);
         gacc = mfma64(v, v, gacc);
     }
+    // lane 16 m + i holds G(4 reg + m, i) in gacc[reg]
+    const int gi = lane & 15, gm = lane >> 4;
+#pragma unroll
+    for (int reg = 0; reg < 4; ++reg)
+        if (4 * reg + gm <= gi) Tb[tpk_index(4 * reg + gm, gi)] = gacc[reg];
     const int r = lane & 15;
 #pragma unroll
     for (int i = 0; i < PW; ++i) {
-        const int ci = wave * PW + i;
-        const double tau_i = ci < c ? taus_lds[ci] : 0.0;
+        const int ci = wave * PW + i;             // < 256: taus_lds[ci] exists
+        const double tau_r = lds_early(taus_lds + ci);
+        const double tau_i = ci < c ? tau_r : 0.0;
         double sacc = 0.0;
+        // volatile reads, in order: merged and hoisted, the 120 reads of G would take
+        // 240 registers
 #pragma unroll
-        for (int b = 0; b < i; ++b) sacc = fma(trow[b], read_lane(gacc[b / 4], 16 * (b % 4) + i), sacc);
-        trow[i] = i < r ? 0.0 : (i == r ? tau_i : -tau_i * sacc);
+        for (int b = 0; b < i; ++b) sacc = fma(trow[b], lds_early(Tb + tpk_index(b, i)), sacc);
+        // rows above r come out zero: every term of their sums is
+        trow[i] = i == r ? tau_i : -tau_i * sacc;
+    }
+    if (lane < PW) {
+#pragma unroll
+        for (int i = 0; i < PW; ++i)
+            if (i >= lane) Tb[tpk_index(lane, i)] = trow[i];
     }
 }
 
-// Group (reflectors jb .. jb + ng - 1, unscaled tile parts x in xb, (tau, sc) in tb,
-// compact-WY factor T in Tb) applied at once to this wave's columns, held in the
-// matrix-core layout, and to their slot rows jb .. jb + ng - 1.  With V the
-// reflectors (slot part the unit rows, tile part X diag(sc)) the group's product
-// is I - V T V^T, and applying H_jb first, then H_jb+1, ... is its transpose:
-//   W = S_p + diag(sc) X^T A;  W' = T^T W;  S_p -= W';  A -= X diag(sc) W'.
+// Group (reflectors jb .. jb + 15) applied at once to this wave's columns, held in
+// the matrix-core layout, and to their slot rows jb .. jb + 15, read from the group's
+// stored panel: V (16 columns of 64 tile rows, v = sc x, column-major) and the full
+// 16 x 16 T (row-major), both zero past the group's ng reflectors.  With the slot
+// part of reflector i the unit row, the group's product is I - V T V^T, and applying
+// H_jb first, then H_jb+1, ... is its transpose:
+//   W = S_p + V^T A;  W' = T^T W;  S_p -= W';  A -= V W'.
 // Every product is a v_mfma_f64_16x16x4f64 chain: 16 + 4 + 16 per group.
 template <typename SlotT>
-__device__ __forceinline__ void q_block_apply(SlotT* slot, double (&a)[RPL], int c, int jb, int ng, const double* xb,
-                                              const double* tb, const double* Tb) {
-    const int lane = threadIdx.x & 63, jl = lane & 15, q = lane >> 4, wave = threadIdx.x >> 6;
+__device__ __forceinline__ void q_block_apply(SlotT* slot, double (&a)[RPL], int c, int jb, int ng,
+                                              const double* __restrict__ panel) {
+    const int lane = fresh_lane(), jl = lane & 15, q = lane >> 4, wave = threadIdx.x >> 6;
     const int colw = wave * PW + jl;
     const bool colok = colw < c;
+    const double* V = panel;
+    const double* T = panel + PW * QT;
+    double xa[RPL];
+#pragma unroll
+    for (int ks = 0; ks < RPL; ++ks) xa[ks] = V[jl * QT + 4 * ks + q];   // V(4 ks + q, jl)
     v4d wt = {0, 0, 0, 0};
 #pragma unroll
-    for (int ks = 0; ks < RPL; ++ks) {
-        const double xa = jl < ng ? xb[jl * QT_LD + 4 * ks + q] : 0.0;   // X(4 ks + q, jl)
-        wt = mfma64(xa, a[ks], wt);
-    }
+    for (int ks = 0; ks < RPL; ++ks) wt = mfma64(xa[ks], a[ks], wt);
+    double tv[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) tv[ks] = T[(4 * ks + q) * PW + jl];   // T(4 ks + q, jl)
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) xa[4 * blk + m] = V[(4 * m + q) * QT + 16 * blk + jl];   // V(16 blk + jl, 4 m + q)
     v4d w;
-    double scr[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = q + 4 * r;
-        scr[r] = i < ng ? tb[2 * i + 1] : 0.0;
         const double sp = (colok && i < ng) ? (double)slot[tri_index(jb + i, colw, c)] : 0.0;
-        w[r] = fma(scr[r], wt[r], sp);
+        w[r] = wt[r] + sp;
     }
-    // phases stay in order: the loads of a later phase are not hoisted over the
-    // earlier MFMA chains (they would hold 32 more registers across them)
-    __builtin_amdgcn_sched_barrier(0);
     v4d wp = {0, 0, 0, 0};
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-        const int ti = 4 * ks + q;   // T(ti, jl), zero below the diagonal
-        wp = mfma64(jl >= ti ? Tb[tpk_index(ti, jl)] : 0.0, w[ks], wp);
-    }
+    for (int ks = 0; ks < 4; ++ks) wp = mfma64(tv[ks], w[ks], wp);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = q + 4 * r;
@@ -510,18 +551,12 @@ __device__ __forceinline__ void q_block_apply(SlotT* slot, double (&a)[RPL], int
             const int idx = tri_index(jb + i, colw, c);
             slot[idx] = (SlotT)((double)slot[idx] - wp[r]);
         }
-        wp[r] *= scr[r];
     }
-    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int blk = 0; blk < 4; ++blk) {
         v4d acc = {a[4 * blk], a[4 * blk + 1], a[4 * blk + 2], a[4 * blk + 3]};
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int i = 4 * m + q;
-            const double xa = i < ng ? -xb[i * QT_LD + 16 * blk + jl] : 0.0;   // -X(16 blk + jl, 4 m + q)
-            acc = mfma64(xa, wp[m], acc);
-        }
+        for (int m = 0; m < 4; ++m) acc = mfma64(-xa[4 * blk + m], wp[m], acc);
 #pragma unroll
         for (int r = 0; r < 4; ++r) a[4 * blk + r] = acc[r];
     }
@@ -550,7 +585,7 @@ __device__ __forceinline__ void q_block_apply(SlotT* slot, double (&a)[RPL], int
 // column's wave), so there is no barrier: each wait is for an event of an earlier
 // group, whose waves wait only for still earlier ones, so every wait ends.
 template <typename SlotT>
-__device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int j0, int col, int g, double* xring,
+__device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int j0, double* xring,
                                        double* tsring, double* taus_lds, unsigned* cnt, int ring, QfSeq& sq,
                                        double* panels) {
     const int wave = threadIdx.x >> 6;   // = col / PW
@@ -561,6 +596,8 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
     const bool block_first = wave >= k0 + QF_SEQ + 1;
     if (block_first) quad_to_mfma(a);
     for (int k = k0; k < np; ++k) {
+        const int lane_k = fresh_lane();
+        const int col = wave * PW + (lane_k >> 2), g = lane_k & 3;   // as the caller's, re-formed
         const int jb = k * PW, je = min(jb + PW, c), ng = je - jb;
         const int r = sq.slot;
         double* xb = xring + r * QF_ENTRY;
@@ -571,16 +608,34 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
         const unsigned tag = sq.groups * 256u + 1u;
         if (wave >= k) {
             if (wave == k) {
-                q_wait(done, sq.owed_at(r), abort_flag);   // the entry's previous group is used up
+                if (sq.groups >= (unsigned)ring) {
+                    // the entry's previous group: once its builder has published (and so
+                    // has set done to minus its users), done back at zero means every
+                    // user has arrived
+                    q_wait(ready, (sq.groups - (unsigned)ring) * 256u + 1u, abort_flag);
+                    q_wait_nonneg(done, abort_flag);
+                }
+                // this group's slot users: the builder and the waves that apply it one
+                // reflector at a time (ordered before the first publication by its
+                // release)
+                if ((threadIdx.x & 63) == 0)
+                    __hip_atomic_store((lds_u32*)done, (unsigned)(-(1 + min(QF_SEQ, np - 1 - k))), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
                 // the builder carries the chain of reflectors: it goes first on its SIMD
                 __builtin_amdgcn_s_setprio(2);
                 for (int j = jb; j < je; ++j) {
-                    const int sl = j - jb;
+                    const int sl = j - jb;   // quad sl of this wave holds column j
+                    double tau_q = 0.0, sc_q = 0.0;
                     if (col == j) {
-                        sc_own = q_make_reflector(slot, a, c, j, g, xb + sl * QT_LD, tb + 2 * sl, taus_lds);
-                        if (g == 0) q_publish(ready, tag + (unsigned)sl);
+                        sc_q = q_make_reflector(slot, a, c, j, g, xb + sl * QT_LD, tb + 2 * sl, taus_lds, tau_q);
+                        sc_own = sc_q;
                     }
-                    const double tau = lds_early(tb + 2 * sl), sc = lds_early(tb + 2 * sl + 1);
+                    // publish the reflector for the waves that apply the group one
+                    // reflector at a time (no wait, see q_publish_inorder)
+                    if (fresh_lane() == 0) q_publish_inorder(ready, tag + (unsigned)sl);
+                    // the scalars straight from quad sl's registers, x from the ring (the
+                    // 16 quads read the same 4 addresses per instruction, a broadcast)
+                    const double tau = read_lane(tau_q, 4 * sl), sc = read_lane(sc_q, 4 * sl);
                     // tau = 0 (a zero column) leaves the column and the slot as they are
                     if (col > j && col < c) q_reflect_column(slot, a, c, j, col, g, xb + sl * QT_LD, tau, sc, tau * sc);
                 }
@@ -590,23 +645,19 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) a[i] *= sc_own;
                 double trow[PW];
-                q_panel_t(a, c, taus_lds, trow);
-                const int lane = threadIdx.x & 63;
+                q_panel_t(a, c, taus_lds, Tb, trow);
+                const int lane = fresh_lane();
+                // the panel (V, T) for the block appliers and the backward pass; the
+                // count that releases the block appliers follows once it is written
+                double* dst = panels + (int64_t)k * Layout<QT>::PS;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) dst[(col % PW) * QT + i * LPC + g] = a[i];
                 if (lane < PW) {
 #pragma unroll
-                    for (int i = 0; i < PW; ++i)
-                        if (i >= lane) Tb[tpk_index(lane, i)] = trow[i];
+                    for (int i = 0; i < PW; ++i) dst[PW * QT + lane * PW + i] = trow[i];
                 }
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
                 if (lane == 0) q_publish(ready, tag + (unsigned)ng);
-                if (panels) {
-                    double* dst = panels + (int64_t)wave * Layout<QT>::PS;
-#pragma unroll
-                    for (int i = 0; i < RPL; ++i) dst[(col % PW) * QT + i * LPC + g] = a[i];
-                    if (lane < PW) {
-#pragma unroll
-                        for (int i = 0; i < PW; ++i) dst[PW * QT + lane * PW + i] = trow[i];
-                    }
-                }
             } else if (wave <= k + QF_SEQ) {
                 // the next groups' builders apply this group as it is published
                 if (block_first && wave == k + QF_SEQ) mfma_to_quad(a);
@@ -620,12 +671,13 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
                 }
                 __builtin_amdgcn_s_setprio(0);
             } else {
+                // counts only grow: a later group's count in this slot also means
+                // this group's panel is stored
                 q_wait(ready, tag + (unsigned)ng, abort_flag);
-                q_block_apply(slot, a, c, jb, ng, xb, tb, Tb);
+                q_block_apply(slot, a, c, jb, ng, panels + (int64_t)k * Layout<QT>::PS);
             }
-            if (threadIdx.x % 64 == 0) q_arrive(done);
+            if (wave <= k + QF_SEQ && threadIdx.x % 64 == 0) q_arrive(done);
         }
-        sq.add_owed(r, (unsigned)(np - k));   // wave k and the waves to its right
         ++sq.groups;
         sq.slot = r + 1 == ring ? 0 : r + 1;
     }
@@ -651,34 +703,23 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
     const int tiles_per_chain = (int)(rows_per_chain / QT);
     slot_zero(slot, c);
     // Every load of E is issued (clamped to an element of E) and masked after it: a
-    // conditional load would be waited for on its own.  A float32 E has the next
-    // tile's loads in flight during the current fold (16 registers; a float64 E would
-    // not fit in 128 and is loaded at the tile's start).
+    // conditional load would be waited for on its own.  The tile is loaded when the
+    // wave starts it (the other waves' work covers the latency; a prefetch of the
+    // next tile would hold 16 more registers through the fold, which has none left).
     const int colc = min(col, c - 1);
-    constexpr bool prefetch = sizeof(TE) == 4;
-    TE nx[RPL];
-    if (prefetch && r_begin < r_end) {
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) nx[i] = E[(int64_t)colc * n + min(r_begin + i * LPC + g, r_end - 1)];
-    }
     for (int tile = 0; r_begin + (int64_t)tile * QT < r_end; ++tile) {
         const int64_t r0 = r_begin + (int64_t)tile * QT;
-        if (!prefetch) {
+        TE nx[RPL];
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) nx[i] = E[(int64_t)colc * n + min(r0 + i * LPC + g, r_end - 1)];
-        }
+        for (int i = 0; i < RPL; ++i) nx[i] = E[(int64_t)colc * n + min(r0 + i * LPC + g, r_end - 1)];
         double a[RPL];
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
             const int64_t r = r0 + i * LPC + g;
             a[i] = (col < c && r < r_end) ? to_f64(nx[i]) : 0.0;
         }
-        if (prefetch && r0 + QT < r_end) {
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) nx[i] = E[(int64_t)colc * n + min(r0 + QT + i * LPC + g, r_end - 1)];
-        }
         const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
-        q_fold(slot, a, c, 0, col, g, xring, tsring, taus_lds, cnt, ring, sq, refl + gtile * np * PS);
+        q_fold(slot, a, c, 0, xring, tsring, taus_lds, cnt, ring, sq, refl + gtile * np * PS);
         if (q_aborted(cnt + 2 * QF_RMAX)) break;
     }
     __syncthreads();   // the folds have no barrier; slot_store reads every column's entries
@@ -716,7 +757,7 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
             const double v = Rb[(int64_t)min(row, c - 1) * c + colc];   // clamped, masked below
             a[q] = (col < c && row < c && col >= row) ? v : 0.0;
         }
-        q_fold(slot, a, c, t * QT, col, g, xring, tsring, taus_lds, cnt, ring, sq,
+        q_fold(slot, a, c, t * QT, xring, tsring, taus_lds, cnt, ring, sq,
                tree + ((comb_off + i) * ntt + t) * np * PS);
         if (q_aborted(cnt + 2 * QF_RMAX)) break;
     }

@@ -1,21 +1,28 @@
 """CPU model of the synchronisation inside the TSQR quad fold (tsqr.hip, q_fold).
 
 The fold's waves share a ring of R group slots of reflectors in LDS, each with a
-ready and a done counter.  Group k of 16 reflectors is built by wave k: it waits
-until its slot's done counter has every arrival owed by the slot's earlier
-groups, then writes and publishes each reflector (the slot's ready counter takes
-256 G + slot + 1 for the workgroup's G-th group) and finally arrives at done.
-The next two waves (k + 1 and k + 2, the next groups' builders) wait for each
-reflector and apply it as it comes; the waves further right wait once, for the
-group's last count (256 G + slot + n + 1, published after the builder has written the group's
-compact-WY factor T), and apply the whole group as one block.  Every wave that
-used the group arrives at done afterwards.  A wave that has built its group goes
-on to the next tile, so the tiles' chains overlap as far as the ring allows.
+ready and a done counter.  Group k of 16 reflectors is built by wave k.  If an
+earlier group G' = G - R used the slot, the builder first waits until G' has
+published its first reflector (ready >= 256 G' + 1) and then until done, which
+G''s builder set to minus the number of G''s slot users, is back at zero (every
+user has arrived).  It sets done to minus its own group's slot users (itself and
+the sequential appliers), writes and publishes each reflector (the slot's ready
+counter takes 256 G + slot + 1 for the workgroup's G-th group), stores the
+group's panel (V, T) to global memory, waits for those stores and publishes one
+count more; then it arrives at done.
+The next SEQ waves (k + 1 .. k + SEQ, the next groups' builders) wait for each
+reflector, apply it from the slot as it comes and arrive at done.  The waves
+further right wait once, for the group's last count (or any later group's count
+in the slot, since counts only grow) and apply the whole group as one block read
+from the stored panel: they never touch the slot, so the slot is free for the
+next group as soon as the builder and the sequential appliers are done.  A wave
+that has built its group goes on to the next tile, so the tiles' chains overlap.
 
 Here each wave is a generator that follows exactly that control flow, and a
 seeded random scheduler interleaves them.  The model fails on a deadlock, on a
-reflector read from a slot that has since been refilled by another group, and
-on a slot refilled while some wave still reads the previous group in it.
+reflector read from a slot that has since been refilled by another group, on a
+slot refilled while some wave still reads the previous group in it, and on a
+block applied before its panel was stored.
 """
 import random
 
@@ -25,19 +32,26 @@ PW = 16
 SEQ = 2   # waves k + 1 .. k + SEQ apply group k one reflector at a time
 
 
-def wave_program(w, c, tiles, st, R, block=True):
+def wave_program(w, c, tiles, st, R, block=True, naive=False):
     """Wave w's accesses over `tiles` tiles of leaf folds (starts) or tree folds."""
     np_ = (c + PW - 1) // PW
     groups = 0
-    owed = [0] * R
     for j0 in tiles:
         for k in range(j0 // PW, np_):
             jb, je = PW * k, min(PW * k + PW, c)
             half = groups % R
+            slot_users = 1 + (min(SEQ, np_ - 1 - k) if block else np_ - 1 - k)
             if w >= k:
                 if w == k:
-                    while st["done"][half] - owed[half] < 0:
-                        yield "wait"
+                    if groups >= R:
+                        # the slot's previous group: its builder has reset done, then
+                        # every one of its slot users has arrived
+                        while not naive and st["ready"][half] - ((groups - R) * 256 + 1) < 0:
+                            yield "wait"
+                        while st["done"][half] < 0:
+                            yield "wait"
+                    st["done"][half] = -slot_users
+                    yield "step"
                     st["users"][groups] = st["users"].get(groups, 0) + 1
                     for j in range(jb, je):
                         prev = st["owner"][half]
@@ -46,9 +60,14 @@ def wave_program(w, c, tiles, st, R, block=True):
                         st["owner"][half] = groups
                         st["ready"][half] = groups * 256 + (j - jb + 1)
                         yield "step"
-                    # the group's T, then the count the block consumers wait for
+                    # the group's panel (V, T) to global memory, waited for, then the
+                    # count the block appliers wait for
+                    st["panel"][groups] = True
+                    yield "step"
                     st["ready"][half] = groups * 256 + (je - jb + 1)
                     yield "step"
+                    st["users"][groups] -= 1
+                    st["done"][half] += 1
                 elif w <= k + SEQ or not block:
                     st["users"][groups] = st["users"].get(groups, 0) + 1
                     for j in range(jb, je):
@@ -56,25 +75,21 @@ def wave_program(w, c, tiles, st, R, block=True):
                             yield "wait"
                         assert st["owner"][half] == groups, ("stale reflector", w, k)
                         yield "step"
+                    st["users"][groups] -= 1
+                    st["done"][half] += 1
                 else:
-                    st["users"][groups] = st["users"].get(groups, 0) + 1
                     while st["ready"][half] - (groups * 256 + (je - jb + 1)) < 0:
                         yield "wait"
-                    assert st["owner"][half] == groups, ("stale group", w, k)
+                    assert st["panel"].get(groups), ("block applied before its panel was stored", w, k)
                     yield "step"
-                    assert st["owner"][half] == groups, ("group refilled during the block update", w, k)
-                    yield "step"
-                st["users"][groups] -= 1
-                st["done"][half] += 1
-            owed[half] += np_ - k
             groups += 1
 
 
-def run(c, tiles, seed, R=2, block=True):
+def run(c, tiles, seed, R=2, block=True, naive=False):
     rnd = random.Random(seed)
     np_ = (c + PW - 1) // PW
-    st = {"ready": [0] * R, "done": [0] * R, "owner": [None] * R, "users": {}}
-    progs = {w: wave_program(w, c, tiles, st, R, block) for w in range(np_)}
+    st = {"ready": [0] * R, "done": [0] * R, "owner": [None] * R, "users": {}, "panel": {}}
+    progs = {w: wave_program(w, c, tiles, st, R, block, naive) for w in range(np_)}
     alive = set(progs)
     idle = 0
     while alive:
@@ -99,6 +114,20 @@ def test_fold_protocol_leaf_and_tree(c, R, block):
     for seed in range(12):
         assert run(c, leaf, seed, R, block), ("deadlock", c, R, "leaf", seed)
         assert run(c, tree + tree, seed, R, block), ("deadlock", c, R, "tree", seed)
+
+
+def test_fold_protocol_needs_the_previous_group_published():
+    """Without the wait for the slot's previous group to have started, a builder can
+    see done = 0 left from the group before it (whose users have all arrived) while
+    the previous group has not been built yet, and refill the slot under it."""
+    bad = 0
+    for seed in range(40):
+        try:
+            ok = run(220, [0, 0, 0, 0], seed, 3, True, naive=True)
+        except AssertionError:
+            ok = False
+        bad += not ok
+    assert bad > 0
 
 
 def test_fold_protocol_detects_a_shared_counter():
