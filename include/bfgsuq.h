@@ -80,6 +80,30 @@ enum {
 int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, void* stream,
                 bfgs_t* out);
 
+/* bfgs_create_streamed — a handle whose pairs stay in host memory, for histories
+ * larger than device memory (the paper keeps its pairs in memory-mapped files
+ * on disk and reads them back for every product, section on the 2D elastic
+ * Marmousi benchmark).
+ *   n, k_max, H0, stream, out   as for bfgs_create
+ *   storage      BFGS_F64 or BFGS_F32 (BFGS_ERR_ARG for BFGS_BF16, whose
+ *                matrix-core layouts are built in device memory)
+ *   slice_rows   rows of S and Y staged to the device at a time, >= 1
+ *                (values above n are taken as n)
+ * S and Y (2 * n * k_max * sizeof(storage) bytes) live in pinned host memory.
+ * The device holds two staging slices of S and Y (4 * slice_rows * k_max *
+ * sizeof(storage) bytes), the pair being pushed (2 n) and the same workspaces
+ * as a device-resident handle.  Every pass over the pairs (the Gram update of
+ * bfgs_push_pair, both passes of bfgs_apply_Hinv / bfgs_apply_Hdiff, the range
+ * sample of bfgs_rsvd) copies the slices host -> device on a second stream,
+ * the copy of slice i + 1 overlapping the kernels on slice i, so one apply moves
+ * 2 * 2 * n * k * sizeof(storage) bytes over the host link.  Results equal
+ * those of a device-resident handle up to the order of the float64 partial sums
+ * of the first pass (one partial per slice part).  bfgs_apply_Hinv_noalloc
+ * returns BFGS_ERR_STATE for such a handle.  Every other call is as for
+ * bfgs_create's handles.  Synchronous.                                         */
+int bfgs_create_streamed(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, int64_t slice_rows,
+                         void* stream, bfgs_t* out);
+
 /* bfgs_destroy — frees the handle and all its device memory.  Synchronizes
  * the handle's stream first.  NULL is accepted and ignored.                  */
 int bfgs_destroy(bfgs_t h);

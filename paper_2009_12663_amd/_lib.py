@@ -32,7 +32,8 @@ MAX_COLS = 256
 MAX_PAIRS = 1024
 
 EXPORTS = [
-    "bfgs_create", "bfgs_destroy", "bfgs_push_pair", "bfgs_num_pairs", "bfgs_apply_Hinv", "bfgs_apply_Hinv_noalloc",
+    "bfgs_create", "bfgs_create_streamed", "bfgs_destroy", "bfgs_push_pair", "bfgs_num_pairs", "bfgs_apply_Hinv",
+    "bfgs_apply_Hinv_noalloc",
     "bfgs_apply_Hdiff", "bfgs_generate_probes", "bfgs_rsvd", "bfgs_rsvd_ex", "bfgs_posterior_diag",
     "bfgs_get_pair", "bfgs_get_h0", "bfgs_get_status", "bfgs_status_string",
     "bfgs_profile", "bfgs_profile_report", "bfgs_autotune", "bfgs_tuning", "bfgs_sync", "bfgs_tsqr_shape",
@@ -64,6 +65,7 @@ def load(path: str = LIB_PATH):
     vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
     sig = {
         "bfgs_create": [i64, i32, vp, ctypes.c_int, vp, ctypes.POINTER(vp)],
+        "bfgs_create_streamed": [i64, i32, vp, ctypes.c_int, i64, vp, ctypes.POINTER(vp)],
         "bfgs_destroy": [vp],
         "bfgs_push_pair": [vp, vp, vp, ctypes.c_int],
         "bfgs_num_pairs": [vp, ctypes.POINTER(i32)],
@@ -165,7 +167,9 @@ class Bfgs:
     vectors of length n has shape (ncols, n) (column-major n x ncols)."""
 
     def __init__(self, n: int, k_max: int, h0: torch.Tensor | None = None, storage: str = "f32",
-                 stream: torch.cuda.Stream | None = None, _handle=None):
+                 stream: torch.cuda.Stream | None = None, _handle=None, slice_rows: int | None = None):
+        """slice_rows: keep the pairs in host memory and stream them to the device in
+        row slices of this many rows (bfgs_create_streamed)."""
         self.L = load()
         self.n, self.k_max, self.storage = int(n), int(k_max), storage
         self.sdt = STORAGE_TORCH[storage]
@@ -182,9 +186,15 @@ class Bfgs:
             assert h0.is_cuda and h0.numel() == self.n
             self._h0 = h0.to(self.hdt).contiguous()
         handle = ctypes.c_void_p()
-        _check(self.L.bfgs_create(self.n, self.k_max, _ptr(self._h0), STORAGE_CODES[storage],
-                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)),
-               "bfgs_create")
+        if slice_rows is None:
+            _check(self.L.bfgs_create(self.n, self.k_max, _ptr(self._h0), STORAGE_CODES[storage],
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)),
+                   "bfgs_create")
+        else:
+            _check(self.L.bfgs_create_streamed(self.n, self.k_max, _ptr(self._h0), STORAGE_CODES[storage],
+                                               int(slice_rows), ctypes.c_void_p(self.stream.cuda_stream),
+                                               ctypes.byref(handle)),
+                   "bfgs_create_streamed")
         self.h = handle
 
     # -- life cycle -------------------------------------------------------------------

@@ -210,12 +210,13 @@ __device__ __forceinline__ Ts w_raw(const Ts* S, const Ts* Y, int64_t ld, int k,
     return p < k ? S[(int64_t)p * ld + r] : Y[(int64_t)(p - k) * ld + r];
 }
 
-// part[chunk][j * 2k + p] = sum over the chunk's rows of W(r, p) V(r, j).
-// Grid (nchunks, ceil(2k / 128), ceil(c / 128)).
+// part[chunk][j * 2k + p] = sum over the chunk's rows of W(r, p) V(r, j); V's
+// columns are ldv apart (n for a whole block; the block's row count when the rows
+// come in slices).  Grid (nchunks, ceil(2k / 128), ceil(c / 128)).
 template <typename Ts, typename Th, typename Tv>
 __global__ void __launch_bounds__(256, 2) gemm1_f64mfma(int64_t n, int64_t ld, int k, int c, const Ts* __restrict__ S,
                                                      const Ts* __restrict__ Y, const Th* __restrict__ h0,
-                                                     const Tv* __restrict__ V, double* __restrict__ part,
+                                                     const Tv* __restrict__ V, int64_t ldv, double* __restrict__ part,
                                                      int64_t rows_per_chunk) {
     __shared__ double Ws[FK][FT_LD];
     __shared__ double Vs[FK][FT_LD];
@@ -238,7 +239,7 @@ __global__ void __launch_bounds__(256, 2) gemm1_f64mfma(int64_t n, int64_t ld, i
         _Pragma("unroll") for (int q = 0; q < 8; ++q) {                                    \
             const int cc = (tid + 256 * q) / FK;                                           \
             wreg[q] = (rv && pi0 + cc < twok) ? w_raw(S, Y, ld, k, pi0 + cc, r) : Ts{};     \
-            vreg[q] = (rv && cj0 + cc < c) ? V[(int64_t)(cj0 + cc) * n + r] : Tv{};          \
+            vreg[q] = (rv && cj0 + cc < c) ? V[(int64_t)(cj0 + cc) * ldv + r] : Tv{};        \
         }                                                                                  \
     }
     v4d acc[4][4];
@@ -287,12 +288,12 @@ __global__ void __launch_bounds__(256, 2) gemm1_f64mfma(int64_t n, int64_t ld, i
             }
 }
 
-// out (column-major n x c) = W [T ; -P] (+ h0 o V unless diff); P, T column-major k x c.
-// Grid (ceil(n / 128), ceil(c / 128)).
+// out (column-major n x c, columns ldv apart, as V's) = W [T ; -P] (+ h0 o V unless
+// diff); P, T column-major k x c.  Grid (ceil(n / 128), ceil(c / 128)).
 template <typename Ts, typename Th, typename To, typename Tv>
 __global__ void __launch_bounds__(256, 2) gemm2_f64mfma(int64_t n, int64_t ld, int k, int c, const Ts* __restrict__ S,
                                                      const Ts* __restrict__ Y, const Th* __restrict__ h0,
-                                                     const Tv* __restrict__ V, const double* __restrict__ P,
+                                                     const Tv* __restrict__ V, int64_t ldv, const double* __restrict__ P,
                                                      const double* __restrict__ T, To* __restrict__ out, int diff) {
     __shared__ double stage_sh[FT * (FK + 1) + FK * FT_LD];
     double* Wsh = stage_sh;                     // [128 rows][FK + 1]
@@ -377,8 +378,8 @@ __global__ void __launch_bounds__(256, 2) gemm2_f64mfma(int64_t n, int64_t ld, i
             const int j = col0 + g0 + jj;
             if (r < n && j < c) {
                 double o = Os[jj * (FT + 1) + rr];
-                if (!diff) o += to_f64(h0[r]) * to_f64(V[(int64_t)j * n + r]);
-                out[(int64_t)j * n + r] = (To)o;
+                if (!diff) o += to_f64(h0[r]) * to_f64(V[(int64_t)j * ldv + r]);
+                out[(int64_t)j * ldv + r] = (To)o;
             }
         }
         __syncthreads();
@@ -428,7 +429,7 @@ int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff, c
     double* T = P + (size_t)k * c;
     prof_begin(h, diff ? "hdiff_gemm1" : "apply_gemm1");
     hipLaunchKernelGGL((gemm1_f64mfma<Ts, Th, Tv>), dim3(nchunks, ptiles, ctiles), dim3(256), 0, h->stream, n, h->ld, k,
-                       c, (const Ts*)h->S, (const Ts*)h->Y, h0, V, part, rows_per_chunk);
+                       c, (const Ts*)h->S, (const Ts*)h->Y, h0, V, n, part, rows_per_chunk);
     const int64_t count = (int64_t)twok * c;
     prof_end(h);
     prof_begin(h, "apply_reduce");
@@ -437,10 +438,64 @@ int apply_generic(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff, c
     if (int rc2 = apply_small_solve(h, c, Z, P, T)) return rc2;
     prof_begin(h, diff ? "hdiff_gemm2" : "apply_gemm2");
     hipLaunchKernelGGL((gemm2_f64mfma<Ts, Th, To, Tv>), dim3((unsigned)ceil_div(n, (int64_t)FT), ctiles), dim3(256), 0,
-                       h->stream, n, h->ld, k, c, (const Ts*)h->S, (const Ts*)h->Y, h0, V, P, T, out,
+                       h->stream, n, h->ld, k, c, (const Ts*)h->S, (const Ts*)h->Y, h0, V, n, P, T, out,
                        diff ? 1 : 0);
     prof_end(h);
     return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+}
+
+// The same two passes for a history kept in host memory (bfgs_create_streamed): each
+// pass streams S and Y through the device in row slices and runs its kernel on one
+// slice while the next is copied; the pass-1 partials of all slices are summed in one
+// fixed order, so the result does not depend on the copy timing.
+template <typename Ts, typename Th, typename To, typename Tv = Ts>
+int apply_streamed(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) {
+    const int64_t n = h->n;
+    const int k = h->k;
+    if (k == 0) return apply_generic<Ts, Th, To, Tv>(h, Vv, c, outv, diff, nullptr);   // reads no pair
+    const Th* h0 = (const Th*)h->h0;
+    const Tv* V = (const Tv*)Vv;
+    To* out = (To*)outv;
+    const int twok = 2 * k;
+    const int ptiles = ceil_div(twok, FT), ctiles = ceil_div(c, FT);
+    const int64_t sr = h->slice_rows;
+    const int ns = (int)((n + sr - 1) / sr);
+    int nsub = (int)std::min<int64_t>((sr + FK - 1) / FK, std::max(1, 2048 / (ptiles * ctiles)));
+    const int64_t rows_per_sub = round_up((sr + nsub - 1) / nsub, FK);
+    nsub = (int)((sr + rows_per_sub - 1) / rows_per_sub);
+    const int64_t last_rows = n - (int64_t)(ns - 1) * sr;
+    const int used = (ns - 1) * nsub + (int)((last_rows + rows_per_sub - 1) / rows_per_sub);
+    const size_t chunk_bytes = (size_t)twok * c * 8;
+    int rc;
+    if ((rc = ensure_ws(h->part, (size_t)ns * nsub * chunk_bytes)) != BFGS_OK) return rc;
+    if ((rc = ensure_ws(h->Z, (size_t)twok * BFGS_MAX_COLS * 8)) != BFGS_OK) return rc;
+    if ((rc = ensure_ws(h->PT, (size_t)2 * h->kmax * BFGS_MAX_COLS * 8)) != BFGS_OK) return rc;
+    double* part = (double*)h->part.ptr;
+    double* Z = (double*)h->Z.ptr;
+    double* P = (double*)h->PT.ptr;
+    double* T = P + (size_t)k * c;
+    {
+        ProfScope ps(h, diff ? "hdiff_stream_pass1" : "apply_stream_pass1");
+        rc = stream_slices(h, k, [&](int i, int64_t r0, int64_t rows, const void* Sst, const void* Yst) {
+            const int nsi = (int)((rows + rows_per_sub - 1) / rows_per_sub);
+            hipLaunchKernelGGL((gemm1_f64mfma<Ts, Th, Tv>), dim3(nsi, ptiles, ctiles), dim3(256), 0, h->stream, rows,
+                               h->slice_ld, k, c, (const Ts*)Sst, (const Ts*)Yst, h0 + r0, V + r0, n,
+                               part + (size_t)i * nsub * twok * c, rows_per_sub);
+            return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+        });
+        if (rc != BFGS_OK) return rc;
+    }
+    const int64_t count = (int64_t)twok * c;
+    hipLaunchKernelGGL(reduce_partials, dim3(ceil_div(count, 256)), dim3(256), 0, h->stream, count, used, part, Z);
+    if ((rc = apply_small_solve(h, c, Z, P, T)) != BFGS_OK) return rc;
+    ProfScope ps(h, diff ? "hdiff_stream_pass2" : "apply_stream_pass2");
+    rc = stream_slices(h, k, [&](int, int64_t r0, int64_t rows, const void* Sst, const void* Yst) {
+        hipLaunchKernelGGL((gemm2_f64mfma<Ts, Th, To, Tv>), dim3((unsigned)ceil_div(rows, (int64_t)FT), ctiles),
+                           dim3(256), 0, h->stream, rows, h->slice_ld, k, c, (const Ts*)Sst, (const Ts*)Yst, h0 + r0,
+                           V + r0, n, P, T, out + r0, diff ? 1 : 0);
+        return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+    });
+    return rc;
 }
 
 }  // namespace
@@ -460,6 +515,17 @@ int apply_small_solve(bfgsuq_ctx* h, int c, const double* Z, double* P, double* 
 int apply_diff_float_block(bfgsuq_ctx* h, const void* V, bool v64, int32_t ncols, void* out, bool out64) {
     // (B_k - B_0) V for a float32 or float64 block V (a basis, not a probe block in the
     // storage type) on the float64 matrix cores, whatever the storage
+    if (h->streamed) {
+#define ADS(TS, TH)                                                                                      \
+    if (v64 && out64) return apply_streamed<TS, TH, double, double>(h, V, ncols, out, true);           \
+    if (v64) return apply_streamed<TS, TH, float, double>(h, V, ncols, out, true);                     \
+    if (out64) return apply_streamed<TS, TH, double, float>(h, V, ncols, out, true);                   \
+    return apply_streamed<TS, TH, float, float>(h, V, ncols, out, true);
+        if (h->storage == BFGS_F64) { ADS(double, double) }
+        if (h->storage == BFGS_F32) { ADS(float, float) }
+#undef ADS
+        return BFGS_ERR_ARG;
+    }
 #define ADF(TS, TH)                                                                                      \
     if (v64 && out64) return apply_generic<TS, TH, double, double>(h, V, ncols, out, true, nullptr);   \
     if (v64) return apply_generic<TS, TH, float, double>(h, V, ncols, out, true, nullptr);             \
@@ -476,6 +542,15 @@ int apply_diff_float_block(bfgsuq_ctx* h, const void* V, bool v64, int32_t ncols
 
 int apply_block(bfgsuq_ctx* h, const void* V, int32_t ncols, void* out, bool diff, bool out64,
                 const ApplyWs* fixed) {
+    if (h->streamed) {
+        // staged slices need the handle's own buffers: no fixed workspace
+        if (fixed) return BFGS_ERR_STATE;
+        if (h->storage == BFGS_F64 && !out64) return apply_streamed<double, double, double>(h, V, ncols, out, diff);
+        if (h->storage == BFGS_F32)
+            return out64 ? apply_streamed<float, float, double>(h, V, ncols, out, diff)
+                         : apply_streamed<float, float, float>(h, V, ncols, out, diff);
+        return BFGS_ERR_ARG;
+    }
     if (out64) {
         if (h->storage != BFGS_F32) return BFGS_ERR_ARG;
         return apply_generic<float, float, double>(h, V, ncols, out, diff, fixed);

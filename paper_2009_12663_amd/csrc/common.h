@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <vector>
 
 #include "../../include/bfgsuq.h"
@@ -146,7 +147,25 @@ struct bfgsuq_ctx {
     unsigned gen = 0;
     double* host_sc = nullptr; // pinned host copy of scalars for push_pair's check
     Profiler prof;
+
+    // Out-of-core history (bfgs_create_streamed): S and Y in pinned host memory (same
+    // layout), staged to the device in row slices of slice_rows through two buffers
+    // (leading dimension slice_ld) by a copy stream, so that the copy of one slice
+    // overlaps the kernels of the previous one.
+    bool streamed = false;
+    int64_t slice_rows = 0, slice_ld = 0;
+    void* stage[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [buffer][S, Y]
+    void* push_tmp = nullptr;  // the pair being pushed, rounded to storage (2 x n)
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr}, ev_start = nullptr;
 };
+
+// Streams the first ncols columns of S and Y through the staging buffers, one row
+// slice at a time, and calls body(slice, r0, rows, S_slice, Y_slice) for each once its
+// copy has landed (body enqueues on the handle's stream; the slices' columns are
+// slice_ld apart).
+int stream_slices(bfgsuq_ctx* h, int ncols,
+                  const std::function<int(int, int64_t, int64_t, const void*, const void*)>& body);
 
 // Sum of the counters a captured graph depends on.
 inline unsigned long long handle_generation(const bfgsuq_ctx* h) {

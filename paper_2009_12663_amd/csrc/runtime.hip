@@ -123,11 +123,12 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // Partial sums over row chunk b of s_i^T y_j and y_i^T (h0 o y_j) (or y_i^T y_j
-// when B_0 = gamma I), for i = blockIdx.y.
+// when B_0 = gamma I), for i = blockIdx.y, stored as partial b0 + b of nbt per i (a
+// history streamed in row slices fills its partials one slice at a time).
 template <typename Tst, typename Th>
 __global__ void __launch_bounds__(256) gram_partial_kernel(int64_t n, int64_t ld, int j, const Tst* __restrict__ S,
                                                            const Tst* __restrict__ Y, const Th* __restrict__ h0,
-                                                           int gamma_mode, double* __restrict__ part) {
+                                                           int gamma_mode, double* __restrict__ part, int b0, int nbt) {
     __shared__ double sh[8];
     const int i = blockIdx.y, b = blockIdx.x, nb = gridDim.x;
     const int64_t chunk = (n + nb - 1) / nb;
@@ -145,8 +146,8 @@ __global__ void __launch_bounds__(256) gram_partial_kernel(int64_t n, int64_t ld
     sy = block_sum<256>(sy, sh);
     yhy = block_sum<256>(yhy, sh);
     if (threadIdx.x == 0) {
-        part[((int64_t)i * nb + b) * 2 + 0] = sy;
-        part[((int64_t)i * nb + b) * 2 + 1] = yhy;
+        part[((int64_t)i * nbt + b0 + b) * 2 + 0] = sy;
+        part[((int64_t)i * nbt + b0 + b) * 2 + 1] = yhy;
     }
 }
 
@@ -226,7 +227,64 @@ template <typename Tst, typename Th>
 static void launch_gram(bfgsuq_ctx* h, int j) {
     hipLaunchKernelGGL((gram_partial_kernel<Tst, Th>), dim3(h->gram_blocks, j + 1), dim3(256), 0, h->stream, h->n,
                        h->ld, j, (const Tst*)h->S, (const Tst*)h->Y, (const Th*)h->h0, h->gamma_mode ? 1 : 0,
-                       h->gram_part);
+                       h->gram_part, 0, h->gram_blocks);
+}
+
+int stream_slices(bfgsuq_ctx* h, int ncols,
+                  const std::function<int(int, int64_t, int64_t, const void*, const void*)>& body) {
+    const size_t es = dtype_size(h->storage);
+    const int64_t n = h->n, sr = h->slice_rows;
+    const int ns = (int)((n + sr - 1) / sr);
+    // the copies start after everything already queued on the handle's stream: a push's
+    // host write of its column, and the kernels that still read a buffer
+    BFGS_HIP(hipEventRecord(h->ev_start, h->stream));
+    BFGS_HIP(hipStreamWaitEvent(h->copy_stream, h->ev_start, 0));
+    for (int i = 0; i < ns; ++i) {
+        const int b = i & 1;
+        const int64_t r0 = (int64_t)i * sr, rows = std::min(sr, n - r0);
+        if (i >= 2) BFGS_HIP(hipStreamWaitEvent(h->copy_stream, h->ev_free[b], 0));
+        for (int w = 0; w < 2; ++w) {
+            const char* src = (const char*)(w ? h->Y : h->S) + r0 * es;
+            BFGS_HIP(hipMemcpy2DAsync(h->stage[b][w], (size_t)h->slice_ld * es, src, (size_t)h->ld * es, (size_t)rows * es,
+                                      (size_t)ncols, hipMemcpyHostToDevice, h->copy_stream));
+        }
+        BFGS_HIP(hipEventRecord(h->ev_ready[b], h->copy_stream));
+        BFGS_HIP(hipStreamWaitEvent(h->stream, h->ev_ready[b], 0));
+        const int rc = body(i, r0, rows, h->stage[b][0], h->stage[b][1]);
+        if (rc != BFGS_OK) return rc;
+        BFGS_HIP(hipEventRecord(h->ev_free[b], h->stream));
+    }
+    return BFGS_OK;
+}
+
+// A streamed history's push: the pair is rounded into device memory, written to its
+// host column, and the Gram updates read columns 0 .. j back slice by slice (the same
+// O(n j) pass as for a device-resident history, over the host link).
+template <typename Tin, typename Tst>
+static int store_streamed(bfgsuq_ctx* h, const void* s, const void* y, int j) {
+    const size_t es = sizeof(Tst);
+    Tst* ts = (Tst*)h->push_tmp;
+    Tst* ty = ts + h->n;
+    hipLaunchKernelGGL((store_pair_kernel<Tin, Tst>), dim3(grid_for(h->n)), dim3(256), 0, h->stream, h->n,
+                       (const Tin*)s, (const Tin*)y, ts, ty);
+    BFGS_HIP(hipGetLastError());
+    BFGS_HIP(hipMemcpyAsync((char*)h->S + (size_t)j * h->ld * es, ts, (size_t)h->n * es, hipMemcpyDeviceToHost,
+                            h->stream));
+    BFGS_HIP(hipMemcpyAsync((char*)h->Y + (size_t)j * h->ld * es, ty, (size_t)h->n * es, hipMemcpyDeviceToHost,
+                            h->stream));
+    return BFGS_OK;
+}
+
+template <typename Tst, typename Th>
+static int gram_streamed(bfgsuq_ctx* h, int j) {
+    const int ns = (int)((h->n + h->slice_rows - 1) / h->slice_rows);
+    const int gb = h->gram_blocks / ns;
+    return stream_slices(h, j + 1, [&](int i, int64_t r0, int64_t rows, const void* Sst, const void* Yst) {
+        hipLaunchKernelGGL((gram_partial_kernel<Tst, Th>), dim3(gb, j + 1), dim3(256), 0, h->stream, rows, h->slice_ld,
+                           j, (const Tst*)Sst, (const Tst*)Yst, (const Th*)h->h0 + r0, h->gamma_mode ? 1 : 0,
+                           h->gram_part, i * gb, h->gram_blocks);
+        return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+    });
 }
 
 // push_pair in two halves, so that a batch can enqueue the pushes of many handles
@@ -238,6 +296,17 @@ int push_enqueue(bfgsuq_ctx* h, const void* s, const void* y, bfgs_dtype in_dtyp
     if (in_dtype != BFGS_F64 && in_dtype != BFGS_F32) return BFGS_ERR_ARG;
     if (h->k >= h->kmax) return BFGS_ERR_FULL;
     const int j = h->k;
+    if (h->streamed) {
+        int rc;
+        if (h->storage == BFGS_F64) {
+            rc = in_dtype == BFGS_F64 ? store_streamed<double, double>(h, s, y, j) : store_streamed<float, double>(h, s, y, j);
+            if (rc == BFGS_OK) rc = gram_streamed<double, double>(h, j);
+        } else {
+            rc = in_dtype == BFGS_F64 ? store_streamed<double, float>(h, s, y, j) : store_streamed<float, float>(h, s, y, j);
+            if (rc == BFGS_OK) rc = gram_streamed<float, float>(h, j);
+        }
+        if (rc != BFGS_OK) return rc;
+    } else
     switch (h->storage) {
         case BFGS_F64:
             if (in_dtype == BFGS_F64) launch_store<double, double>(h, s, y, j);
@@ -310,6 +379,19 @@ const char* bfgs_status_string(int code) {
 int bfgs_destroy(bfgs_t h) {
     if (!h) return BFGS_OK;
     (void)hipStreamSynchronize(h->stream);
+    if (h->copy_stream) (void)hipStreamSynchronize(h->copy_stream);
+    if (h->streamed) {
+        if (h->S) (void)hipHostFree(h->S);
+        if (h->Y) (void)hipHostFree(h->Y);
+        h->S = h->Y = nullptr;
+        void* st[] = {h->stage[0][0], h->stage[0][1], h->stage[1][0], h->stage[1][1], h->push_tmp};
+        for (void* p : st)
+            if (p) (void)hipFree(p);
+        hipEvent_t evs[] = {h->ev_ready[0], h->ev_ready[1], h->ev_free[0], h->ev_free[1], h->ev_start};
+        for (hipEvent_t e : evs)
+            if (e) (void)hipEventDestroy(e);
+        if (h->copy_stream) (void)hipStreamDestroy(h->copy_stream);
+    }
     void* ptrs[] = {h->S, h->Y, h->h0, h->Rm, h->YHY, h->Rinv, h->RinvT, h->gram_part, h->scalars, h->status,
                     h->S1, h->Y1, h->S2, h->Y2};
     for (void* p : ptrs)
@@ -323,11 +405,16 @@ int bfgs_destroy(bfgs_t h) {
     return BFGS_OK;
 }
 
-int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, void* stream, bfgs_t* out) {
+}  // extern "C"
+
+// slice_rows = 0: S and Y in device memory; > 0: in pinned host memory, streamed.
+static int create_impl(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, void* stream,
+                       int64_t slice_rows, bfgs_t* out) {
     if (!out) return BFGS_ERR_ARG;
     *out = nullptr;
-    if (n < 1 || k_max < 1 || k_max > BFGS_MAX_PAIRS) return BFGS_ERR_ARG;
+    if (n < 1 || k_max < 1 || k_max > BFGS_MAX_PAIRS || slice_rows < 0) return BFGS_ERR_ARG;
     if (storage != BFGS_F64 && storage != BFGS_F32 && storage != BFGS_BF16) return BFGS_ERR_ARG;
+    if (slice_rows > 0 && storage == BFGS_BF16) return BFGS_ERR_ARG;
     bfgsuq_ctx* h = new (std::nothrow) bfgsuq_ctx();
     if (!h) return BFGS_ERR_ALLOC;
     h->n = n;
@@ -339,6 +426,19 @@ int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, vo
     const size_t es = dtype_size(storage);
     const size_t hs = storage == BFGS_F64 ? 8 : 4;
     h->gram_blocks = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 4095) / 4096));
+    if (slice_rows > 0) {
+        h->streamed = true;
+        h->slice_rows = std::min(slice_rows, n);
+        h->slice_ld = round_up(h->slice_rows, 128);
+        // per slice the Gram partials of a push: gram_blocks = slices x per-slice blocks
+        const int64_t ns = (n + h->slice_rows - 1) / h->slice_rows;
+        const int64_t gb = std::min<int64_t>(64, std::max<int64_t>(1, (h->slice_rows + 4095) / 4096));
+        if (ns * gb > (1 << 20)) {
+            delete h;
+            return BFGS_ERR_ARG;
+        }
+        h->gram_blocks = (int)(ns * gb);
+    }
     int rc = BFGS_OK;
     auto alloc = [&](void** p, size_t bytes) {
         if (rc != BFGS_OK) return;
@@ -347,8 +447,36 @@ int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, vo
             rc = BFGS_ERR_ALLOC;
         }
     };
-    alloc(&h->S, (size_t)h->ld * k_max * es);
-    alloc(&h->Y, (size_t)h->ld * k_max * es);
+    const size_t hist_bytes = (size_t)h->ld * k_max * es;
+    if (h->streamed) {
+        auto halloc = [&](void** p) {
+            if (rc != BFGS_OK) return;
+            if (hipHostMalloc(p, hist_bytes, hipHostMallocDefault) != hipSuccess) {
+                *p = nullptr;
+                rc = BFGS_ERR_ALLOC;
+                return;
+            }
+            std::memset(*p, 0, hist_bytes);
+        };
+        halloc(&h->S);
+        halloc(&h->Y);
+        for (int b = 0; b < 2; ++b)
+            for (int w = 0; w < 2; ++w) alloc(&h->stage[b][w], (size_t)h->slice_ld * k_max * es);
+        alloc(&h->push_tmp, 2 * (size_t)n * es);
+        if (rc == BFGS_OK && hipStreamCreateWithFlags(&h->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+            h->copy_stream = nullptr;
+            rc = BFGS_ERR_HIP;
+        }
+        hipEvent_t* evs[] = {&h->ev_ready[0], &h->ev_ready[1], &h->ev_free[0], &h->ev_free[1], &h->ev_start};
+        for (hipEvent_t* e : evs)
+            if (rc == BFGS_OK && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+                *e = nullptr;
+                rc = BFGS_ERR_HIP;
+            }
+    } else {
+        alloc(&h->S, hist_bytes);
+        alloc(&h->Y, hist_bytes);
+    }
     alloc(&h->h0, (size_t)h->ld * hs);
     alloc((void**)&h->Rm, (size_t)k_max * k_max * 8);
     alloc((void**)&h->YHY, (size_t)k_max * k_max * 8);
@@ -374,8 +502,8 @@ int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, vo
         bfgs_destroy(h);
         return rc;
     }
-    if (hipMemsetAsync(h->S, 0, (size_t)h->ld * k_max * es, h->stream) != hipSuccess ||
-        hipMemsetAsync(h->Y, 0, (size_t)h->ld * k_max * es, h->stream) != hipSuccess ||
+    if ((!h->streamed && (hipMemsetAsync(h->S, 0, hist_bytes, h->stream) != hipSuccess ||
+                          hipMemsetAsync(h->Y, 0, hist_bytes, h->stream) != hipSuccess)) ||
         hipMemsetAsync(h->h0, 0, (size_t)h->ld * hs, h->stream) != hipSuccess ||
         hipMemsetAsync(h->Rm, 0, (size_t)k_max * k_max * 8, h->stream) != hipSuccess ||
         hipMemsetAsync(h->YHY, 0, (size_t)k_max * k_max * 8, h->stream) != hipSuccess ||
@@ -402,6 +530,18 @@ int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, vo
     }
     *out = h;
     return BFGS_OK;
+}
+
+extern "C" {
+
+int bfgs_create(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, void* stream, bfgs_t* out) {
+    return create_impl(n, k_max, H0, storage, stream, 0, out);
+}
+
+int bfgs_create_streamed(int64_t n, int32_t k_max, const void* H0, bfgs_dtype storage, int64_t slice_rows,
+                         void* stream, bfgs_t* out) {
+    if (slice_rows < 1) return BFGS_ERR_ARG;
+    return create_impl(n, k_max, H0, storage, stream, slice_rows, out);
 }
 
 int bfgs_num_pairs(bfgs_t h, int32_t* k_out) {
