@@ -196,8 +196,10 @@ def fp32_path(P, S, Y, n, k, V, out, rank, p, seed, Sig, dg, ncols, apply_ms_bf1
 
 
 def bench_batch(args):
-    """64-problem batch: plain float32 per-problem launches on one stream vs the
-    bfloat16 batch (forked streams, autotuned, replayed from one captured hipGraph)."""
+    """64-problem batch: plain float32 per-problem launches on one stream; the float32
+    batch (persistent work-queue passes, the same arithmetic as the per-problem
+    launches); the bfloat16 batch (forked streams, autotuned, replayed from one
+    captured hipGraph)."""
     import torch
     import paper_2009_12663_amd as P
     from workloads import quadratic as wq
@@ -253,6 +255,18 @@ def bench_batch(args):
         H.close()
     del plain, Vp, outp, Up, Sp
 
+    # float32 batch: the persistent passes take (problem, tile) items from a work queue
+    B32 = P.BfgsBatch(ns, ks, None, "f32")
+    B32.push_pairs([S for S, _ in pairs], [Y for _, Y in pairs])
+    V32 = [B32.problems[i].generate_probes(2 + i, c) for i, c in enumerate(cs)]
+    out32 = [torch.empty(v.shape, dtype=torch.float32, device="cuda") for v in V32]
+    t_p32 = timed(lambda: B32.apply_Hinv(V32, out32), args.steps)
+    B32.autotune(V32)
+    t_p32_tuned = timed(lambda: B32.apply_Hinv(V32, out32), args.steps)
+    log(f"[bench-batch] f32 persistent batch: apply {t_p32:.2f} ms, after tuning the grid {t_p32_tuned:.2f} ms")
+    B32.close()
+    del V32, out32
+
     B = P.BfgsBatch(ns, ks, None, "bf16")
     for (S, Y), H in zip(pairs, B.problems):
         for s, y in zip(S, Y):
@@ -278,9 +292,70 @@ def bench_batch(args):
         "batch_apply_ms": round(t_batch_apply, 4), "batch_rsvd_ms": round(t_batch_rsvd, 4),
         "graph_apply_plus_rsvd_ms": round(t_graph, 4),
         "plain_f32_apply_ms": round(t_plain_apply, 4), "plain_f32_rsvd_ms": round(t_plain_rsvd, 4),
+        "f32_persistent_apply_ms": round(min(t_p32, t_p32_tuned), 4),
+        "speedup_f32_persistent_over_plain_f32": round(t_plain_apply / min(t_p32, t_p32_tuned), 3),
         "speedup_apply": round(t_plain_apply / t_batch_apply, 3),
         "speedup_apply_plus_rsvd": round((t_plain_apply + t_plain_rsvd) / t_graph, 3),
     }
+    print(json.dumps(res), flush=True)
+
+
+def bench_streamed(args):
+    """Out-of-core history: the 1700 x 350 x 3 grid with k = 50 float32 pairs kept in
+    pinned host memory (bfgs_create_streamed, row slices of --slice-rows), against the
+    same pairs in device memory.  Reports the apply time of 220 columns, the bytes the
+    two passes stage over the host link and the rate they reach."""
+    import torch
+    import paper_2009_12663_amd as P
+    from workloads import quadratic as wq
+
+    k, c = 50, args.ncols
+    prob = wq.make_problem("grid3", device="cuda")
+    S, Y, _ = wq.cg_pairs(prob, k)
+    n = prob.n
+    k = S.shape[0]
+    del prob
+
+    def build(slice_rows):
+        H = P.Bfgs(n, k, None, "f32", slice_rows=slice_rows)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s_, y_ in zip(S, Y):
+            H.push_pair(s_.float(), y_.float())
+        torch.cuda.synchronize()
+        return H, (time.perf_counter() - t0) * 1e3
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    Hs, push_ms = build(args.slice_rows)
+    Hd, push_dev_ms = build(None)
+    V = Hd.generate_probes(seed=2, ncols=c)
+    out_s = torch.empty((c, n), dtype=torch.float32, device="cuda")
+    out_d = torch.empty_like(out_s)
+    t_s = timed(lambda: Hs.apply_Hinv(V, out_s), max(1, args.steps // 4))
+    t_d = timed(lambda: Hd.apply_Hinv(V, out_d), args.steps)
+    diff = float(((out_s - out_d).abs().amax(dim=1) / out_d.abs().amax(dim=1)).max())
+    staged = 2 * 2 * n * k * 4
+    res = {"metric": "streamed B_k V: host-link rate of the staged pair slices", "value": round(staged / t_s / 1e6, 2),
+           "unit": "GB/s", "n_gpus": 1, "steps": max(1, args.steps // 4), "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"grid3: n={n}, k={k} float32 pairs in pinned host memory, {c} columns",
+                      "slice_rows": args.slice_rows},
+           "streamed_apply_ms": round(t_s, 3), "device_resident_apply_ms": round(t_d, 3),
+           "staged_bytes_per_apply": staged, "push_all_ms": round(push_ms, 1),
+           "push_all_device_resident_ms": round(push_dev_ms, 1), "max_col_rel_diff_vs_device": diff,
+           "status": [Hs.get_status(), Hd.get_status()]}
+    Hs.close()
+    Hd.close()
     print(json.dumps(res), flush=True)
 
 
@@ -629,6 +704,7 @@ def main():
     ap.add_argument("--ncols", type=int, default=220)
     ap.add_argument("--config", default="grid3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--slice-rows", type=int, default=1 << 18, help="row slice of --config streamed")
     ap.add_argument("--no-fp32-path", action="store_true",
                     help="skip the float32-storage comparison run after the timed region")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -665,6 +741,9 @@ def main():
         return
     if args.config == "sweep":
         bench_sweep(args)
+        return
+    if args.config == "streamed":
+        bench_streamed(args)
         return
 
     import torch

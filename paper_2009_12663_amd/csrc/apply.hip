@@ -17,6 +17,9 @@
 // apply) and the inner solve shared by all forms.
 #include <cmath>
 
+#include <algorithm>
+#include <vector>
+
 #include "common.h"
 
 namespace {
@@ -100,16 +103,15 @@ __global__ void __launch_bounds__(64) small_solve(int k, int kmax, int c, const 
 //   P = R^-1 Z_s;  W = (D + YHY) P - Z_y;  T = R^-T W
 constexpr int SB_COLS = 4;
 
-__global__ void __launch_bounds__(256) small_solve_blocks(int k, int kmax, int c, const double* __restrict__ Rm,
-                                                          const double* __restrict__ Rinv,
-                                                          const double* __restrict__ RinvT,
-                                                          const double* __restrict__ YHY, const double* __restrict__ Z,
-                                                          double* __restrict__ P, double* __restrict__ T,
-                                                          int32_t* __restrict__ status) {
+__device__ __forceinline__ void small_solve_block(int k, int kmax, int c, const double* __restrict__ Rm,
+                                                  const double* __restrict__ Rinv, const double* __restrict__ RinvT,
+                                                  const double* __restrict__ YHY, const double* __restrict__ Z,
+                                                  double* __restrict__ P, double* __restrict__ T,
+                                                  int32_t* __restrict__ status, int blk) {
     __shared__ double a_sh[256][SB_COLS + 1];
     __shared__ double b_sh[256][SB_COLS + 1];
     const int i = threadIdx.x;
-    const int j0 = blockIdx.x * SB_COLS;
+    const int j0 = blk * SB_COLS;
     const int nj = min(SB_COLS, c - j0);
     for (int e = threadIdx.x; e < k * SB_COLS; e += blockDim.x) {
         const int l = e % k, jj = e / k;
@@ -166,6 +168,16 @@ __global__ void __launch_bounds__(256) small_solve_blocks(int k, int kmax, int c
         }
     }
     if (bad) set_status(status, BFGS_ERR_NONFINITE);
+    __syncthreads();   // a_sh and b_sh are free for the next block of columns
+}
+
+__global__ void __launch_bounds__(256) small_solve_blocks(int k, int kmax, int c, const double* __restrict__ Rm,
+                                                          const double* __restrict__ Rinv,
+                                                          const double* __restrict__ RinvT,
+                                                          const double* __restrict__ YHY, const double* __restrict__ Z,
+                                                          double* __restrict__ P, double* __restrict__ T,
+                                                          int32_t* __restrict__ status) {
+    small_solve_block(k, kmax, c, Rm, Rinv, RinvT, YHY, Z, P, T, status, blockIdx.x);
 }
 
 // k = 0: B_0 V (or zero for B_k - B_0); a non-finite input sets the deferred status.
@@ -214,17 +226,17 @@ __device__ __forceinline__ Ts w_raw(const Ts* S, const Ts* Y, int64_t ld, int k,
 // columns are ldv apart (n for a whole block; the block's row count when the rows
 // come in slices).  Grid (nchunks, ceil(2k / 128), ceil(c / 128)).
 template <typename Ts, typename Th, typename Tv>
-__global__ void __launch_bounds__(256, 2) gemm1_f64mfma(int64_t n, int64_t ld, int k, int c, const Ts* __restrict__ S,
-                                                     const Ts* __restrict__ Y, const Th* __restrict__ h0,
-                                                     const Tv* __restrict__ V, int64_t ldv, double* __restrict__ part,
-                                                     int64_t rows_per_chunk) {
+__device__ __forceinline__ void gemm1_tile(int64_t n, int64_t ld, int k, int c, const Ts* __restrict__ S,
+                                           const Ts* __restrict__ Y, const Th* __restrict__ h0,
+                                           const Tv* __restrict__ V, int64_t ldv, double* __restrict__ part,
+                                           int64_t rows_per_chunk, int bx, int by, int bz) {
     __shared__ double Ws[FK][FT_LD];
     __shared__ double Vs[FK][FT_LD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wi = wave >> 1, wj = wave & 1;
     const int twok = 2 * k;
-    const int pi0 = blockIdx.y * FT, cj0 = blockIdx.z * FT;
-    const int64_t rb = (int64_t)blockIdx.x * rows_per_chunk;
+    const int pi0 = by * FT, cj0 = bz * FT;
+    const int64_t rb = (int64_t)bx * rows_per_chunk;
     const int64_t re = min(n, rb + rows_per_chunk);
     // staging map: element e = tid + 256 q (q < 8): row e % 16 (= tid % 16 for every q),
     // column e / 16; values stay in the storage type until they are staged
@@ -275,7 +287,7 @@ __global__ void __launch_bounds__(256, 2) gemm1_f64mfma(int64_t n, int64_t ld, i
         __syncthreads();
     }
 #undef G1F_LOAD_STAGE
-    double* dst = part + (int64_t)blockIdx.x * twok * c;
+    double* dst = part + (int64_t)bx * twok * c;
 #pragma unroll
     for (int ta = 0; ta < 4; ++ta)
 #pragma unroll
@@ -288,21 +300,30 @@ __global__ void __launch_bounds__(256, 2) gemm1_f64mfma(int64_t n, int64_t ld, i
             }
 }
 
+template <typename Ts, typename Th, typename Tv>
+__global__ void __launch_bounds__(256, 2) gemm1_f64mfma(int64_t n, int64_t ld, int k, int c, const Ts* __restrict__ S,
+                                                     const Ts* __restrict__ Y, const Th* __restrict__ h0,
+                                                     const Tv* __restrict__ V, int64_t ldv, double* __restrict__ part,
+                                                     int64_t rows_per_chunk) {
+    gemm1_tile<Ts, Th, Tv>(n, ld, k, c, S, Y, h0, V, ldv, part, rows_per_chunk, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // out (column-major n x c, columns ldv apart, as V's) = W [T ; -P] (+ h0 o V unless
 // diff); P, T column-major k x c.  Grid (ceil(n / 128), ceil(c / 128)).
 template <typename Ts, typename Th, typename To, typename Tv>
-__global__ void __launch_bounds__(256, 2) gemm2_f64mfma(int64_t n, int64_t ld, int k, int c, const Ts* __restrict__ S,
-                                                     const Ts* __restrict__ Y, const Th* __restrict__ h0,
-                                                     const Tv* __restrict__ V, int64_t ldv, const double* __restrict__ P,
-                                                     const double* __restrict__ T, To* __restrict__ out, int diff) {
+__device__ __forceinline__ void gemm2_tile(int64_t n, int64_t ld, int k, int c, const Ts* __restrict__ S,
+                                           const Ts* __restrict__ Y, const Th* __restrict__ h0,
+                                           const Tv* __restrict__ V, int64_t ldv, const double* __restrict__ P,
+                                           const double* __restrict__ T, To* __restrict__ out, int diff, int bx,
+                                           int by) {
     __shared__ double stage_sh[FT * (FK + 1) + FK * FT_LD];
     double* Wsh = stage_sh;                     // [128 rows][FK + 1]
     double* Ms = stage_sh + FT * (FK + 1);      // [FK][FT_LD]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wi = wave >> 1, wj = wave & 1;
     const int twok = 2 * k;
-    const int64_t row0 = (int64_t)blockIdx.x * FT;
-    const int col0 = blockIdx.y * FT;
+    const int64_t row0 = (int64_t)bx * FT;
+    const int col0 = by * FT;
     // W stage element e = tid + 256 q: row e % 128 (= tid % 128 for every q), pair
     // e / 128; M stage: pair e % 16, column e / 16
     Ts wreg[8];
@@ -384,6 +405,14 @@ __global__ void __launch_bounds__(256, 2) gemm2_f64mfma(int64_t n, int64_t ld, i
         }
         __syncthreads();
     }
+}
+
+template <typename Ts, typename Th, typename To, typename Tv>
+__global__ void __launch_bounds__(256, 2) gemm2_f64mfma(int64_t n, int64_t ld, int k, int c, const Ts* __restrict__ S,
+                                                     const Ts* __restrict__ Y, const Th* __restrict__ h0,
+                                                     const Tv* __restrict__ V, int64_t ldv, const double* __restrict__ P,
+                                                     const double* __restrict__ T, To* __restrict__ out, int diff) {
+    gemm2_tile<Ts, Th, To, Tv>(n, ld, k, c, S, Y, h0, V, ldv, P, T, out, diff, blockIdx.x, blockIdx.y);
 }
 
 template <typename Ts, typename Th, typename To, typename Tv = Ts>
@@ -498,7 +527,191 @@ int apply_streamed(bfgsuq_ctx* h, const void* Vv, int c, void* outv, bool diff) 
     return rc;
 }
 
+// ---------------------------------------------------------------------------
+// Persistent batched apply (float32 and float64 storage): the first pass of every
+// problem, the float64 small steps of every problem and the second pass of every
+// problem are one launch each.  A pass's workgroups take (problem, tile) items from
+// a work queue (an atomic counter) until it runs dry; the problems are laid out
+// longest first (work n k c), so the last items to be taken are small ones.  Each
+// item is exactly one workgroup of the per-problem kernels (same tiles, same
+// chunking, same fixed-order sums), so the results equal the per-problem path's.
+// ---------------------------------------------------------------------------
+template <typename Ts, typename Th, typename Tv>
+__global__ void __launch_bounds__(256, 2) batch_pass1(const PersistProblem* __restrict__ pr, int nprob, int total,
+                                                    unsigned* __restrict__ head) {
+    __shared__ int item_sh;
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = (int)atomicAdd(head, 1u);
+        __syncthreads();
+        const int item = item_sh;
+        __syncthreads();
+        if (item >= total) break;
+        int lo = 0, hi = nprob - 1;   // last problem whose first item is <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pr[mid].first1 <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const PersistProblem& q = pr[lo];
+        const int local = item - q.first1, per = q.ptiles * q.ctiles;
+        const int bx = local / per, rest = local % per;
+        gemm1_tile<Ts, Th, Tv>(q.n, q.ld, q.k, q.c, (const Ts*)q.S, (const Ts*)q.Y, (const Th*)q.h0, (const Tv*)q.V,
+                               q.n, q.part, q.rows_per_chunk, bx, rest % q.ptiles, rest / q.ptiles);
+    }
+}
+
+// One workgroup per (problem, block of SB_COLS columns): the fixed-order sum of that
+// block's pass-1 partials into Z, then the small solve of the block.
+__global__ void __launch_bounds__(256) batch_solve(const PersistProblem* __restrict__ pr, int nprob) {
+    int blk = blockIdx.x, p = 0;
+    while (p < nprob && blk >= (pr[p].c + SB_COLS - 1) / SB_COLS) {
+        blk -= (pr[p].c + SB_COLS - 1) / SB_COLS;
+        ++p;
+    }
+    if (p >= nprob) return;   // whole workgroup
+    const PersistProblem& q = pr[p];
+    const int twok = 2 * q.k, j0 = blk * SB_COLS, nj = min(SB_COLS, q.c - j0);
+    const int64_t count = (int64_t)twok * q.c;
+    for (int e = threadIdx.x; e < twok * nj; e += blockDim.x) {
+        const int64_t idx = (int64_t)j0 * twok + e;
+        double sacc = 0.0;
+        for (int ch = 0; ch < q.nchunks; ++ch) sacc += q.part[(int64_t)ch * count + idx];
+        q.Z[idx] = sacc;
+    }
+    __threadfence_block();
+    __syncthreads();
+    small_solve_block(q.k, q.kmax, q.c, q.Rm, q.Rinv, q.RinvT, q.YHY, q.Z, q.P, q.P + (size_t)q.k * q.c, q.status,
+                      blk);
+}
+
+template <typename Ts, typename Th, typename To, typename Tv>
+__global__ void __launch_bounds__(256, 2) batch_pass2(const PersistProblem* __restrict__ pr, int nprob, int total,
+                                                    unsigned* __restrict__ head) {
+    __shared__ int item_sh;
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = (int)atomicAdd(head, 1u);
+        __syncthreads();
+        const int item = item_sh;
+        __syncthreads();
+        if (item >= total) break;
+        int lo = 0, hi = nprob - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pr[mid].first2 <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const PersistProblem& q = pr[lo];
+        const int local = item - q.first2;
+        gemm2_tile<Ts, Th, To, Tv>(q.n, q.ld, q.k, q.c, (const Ts*)q.S, (const Ts*)q.Y, (const Th*)q.h0,
+                                   (const Tv*)q.V, q.n, q.P, q.P + (size_t)q.k * q.c, (To*)q.out, 0,
+                                   local / q.ctiles, local % q.ctiles);
+    }
+}
+
+// The work-queue heads start at zero for every launch (a kernel, so that a captured
+// graph resets them on every replay).
+__global__ void batch_reset(unsigned* __restrict__ head) {
+    if (threadIdx.x < 2) head[threadIdx.x] = 0u;
+}
+
+template <typename Ts, typename Th>
+int batch_persistent_impl(bfgsuq_ctx* const* hs, int nprob, const void* const* V, const int32_t* ncols,
+                          void* const* out, hipStream_t st, PersistSlot* slot, bool upload, int wg_per_cu) {
+    if (upload) {
+        std::vector<int> order(nprob);
+        for (int i = 0; i < nprob; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return (double)hs[a]->n * hs[a]->k * ncols[a] > (double)hs[b]->n * hs[b]->k * ncols[b];
+        });
+        std::vector<PersistProblem> host(nprob);
+        int t1 = 0, t2 = 0, tsolve = 0;
+        for (int r = 0; r < nprob; ++r) {
+            const int i = order[r];
+            bfgsuq_ctx* h = hs[i];
+            const int k = h->k, c = ncols[i], twok = 2 * k;
+            if (k < 1 || k > 256) return BFGS_ERR_ARG;
+            PersistProblem& q = host[r];
+            q.n = h->n;
+            q.ld = h->ld;
+            q.k = k;
+            q.kmax = h->kmax;
+            q.c = c;
+            q.S = h->S;
+            q.Y = h->Y;
+            q.h0 = h->h0;
+            q.V = V[i];
+            q.out = out[i];
+            q.ptiles = ceil_div(twok, FT);
+            q.ctiles = ceil_div(c, FT);
+            // the per-problem path's chunking, so that the partial sums match it
+            const int64_t max_chunks = std::max<int64_t>(1, (q.n + FK - 1) / FK);
+            int nch = (int)std::min<int64_t>(max_chunks, std::max(1, 2048 / (q.ptiles * q.ctiles)));
+            q.rows_per_chunk = round_up((q.n + nch - 1) / nch, FK);
+            q.nchunks = (int)((q.n + q.rows_per_chunk - 1) / q.rows_per_chunk);
+            int rc;
+            if ((rc = ensure_ws(h->part, (size_t)q.nchunks * twok * c * 8)) != BFGS_OK) return rc;
+            if ((rc = ensure_ws(h->Z, (size_t)twok * BFGS_MAX_COLS * 8)) != BFGS_OK) return rc;
+            if ((rc = ensure_ws(h->PT, (size_t)2 * h->kmax * BFGS_MAX_COLS * 8)) != BFGS_OK) return rc;
+            q.part = (double*)h->part.ptr;
+            q.Z = (double*)h->Z.ptr;
+            q.P = (double*)h->PT.ptr;
+            q.Rm = h->Rm;
+            q.Rinv = h->Rinv;
+            q.RinvT = h->RinvT;
+            q.YHY = h->YHY;
+            q.status = h->status;
+            q.first1 = t1;
+            q.first2 = t2;
+            t1 += q.nchunks * q.ptiles * q.ctiles;
+            t2 += ceil_div(q.n, (int64_t)FT) * q.ctiles;
+            tsolve += ceil_div(c, SB_COLS);
+        }
+        if (slot->cap < (size_t)nprob) {
+            if (slot->prob) (void)hipFree(slot->prob);
+            slot->prob = nullptr;
+            slot->cap = 0;
+            if (hipMalloc((void**)&slot->prob, (size_t)nprob * sizeof(PersistProblem)) != hipSuccess)
+                return BFGS_ERR_ALLOC;
+            slot->cap = (size_t)nprob;
+        }
+        if (!slot->head && hipMalloc((void**)&slot->head, 64) != hipSuccess) {
+            slot->head = nullptr;
+            return BFGS_ERR_ALLOC;
+        }
+        // pageable source: the call returns once the data is staged
+        BFGS_HIP(hipMemcpyAsync(slot->prob, host.data(), (size_t)nprob * sizeof(PersistProblem),
+                                hipMemcpyHostToDevice, st));
+        slot->nprob = nprob;
+        slot->items1 = t1;
+        slot->items2 = t2;
+        slot->solve_blocks = tsolve;
+    }
+    if (slot->nprob != nprob || !slot->prob) return BFGS_ERR_STATE;
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int g1 = std::max(1, std::min(slot->items1, ncu * wg_per_cu));
+    const int g2 = std::max(1, std::min(slot->items2, ncu * wg_per_cu));
+    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, st, slot->head);
+    hipLaunchKernelGGL((batch_pass1<Ts, Th, Ts>), dim3(g1), dim3(256), 0, st, slot->prob, nprob, slot->items1,
+                       slot->head);
+    hipLaunchKernelGGL(batch_solve, dim3(slot->solve_blocks), dim3(256), 0, st, slot->prob, nprob);
+    hipLaunchKernelGGL((batch_pass2<Ts, Th, Th, Ts>), dim3(g2), dim3(256), 0, st, slot->prob, nprob, slot->items2,
+                       slot->head + 1);
+    return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
+}
+
 }  // namespace
+
+int batch_apply_persistent(bfgsuq_ctx* const* hs, int nprob, const void* const* V, const int32_t* ncols,
+                           void* const* out, hipStream_t st, PersistSlot* slot, bool upload, int wg_per_cu) {
+    if (nprob < 1) return BFGS_ERR_ARG;
+    const bfgs_dtype s0 = hs[0]->storage;
+    for (int i = 0; i < nprob; ++i)
+        if (hs[i]->storage != s0 || hs[i]->streamed || hs[i]->k < 1 || hs[i]->k > 256) return BFGS_ERR_ARG;
+    if (s0 == BFGS_F64) return batch_persistent_impl<double, double>(hs, nprob, V, ncols, out, st, slot, upload, wg_per_cu);
+    if (s0 == BFGS_F32) return batch_persistent_impl<float, float>(hs, nprob, V, ncols, out, st, slot, upload, wg_per_cu);
+    return BFGS_ERR_ARG;
+}
 
 int apply_small_solve(bfgsuq_ctx* h, int c, const double* Z, double* P, double* T) {
     ProfScope ps(h, "apply_solve");

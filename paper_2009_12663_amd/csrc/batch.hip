@@ -1,12 +1,15 @@
 // Batched form: many independent inversions (uneven n and k) driven together.
 //
-// A batch owns one handle per problem.  Problems are spread over a small set
-// of side streams forked from the caller's stream with events and joined back,
-// so their kernels overlap on the device; the same fork/join sequence can be
-// captured once into a hipGraph (apply + rSVD of every problem) and replayed
-// with a single launch.  The autotuner times the tunable launch shapes of each
-// problem (rows per pass-1 workgroup, TSQR chain count) with HIP events and
-// keeps the fastest in the problem's handle.
+// A batch owns one handle per problem.  With float32 or float64 storage (and
+// 1 <= k <= 256 everywhere) the apply of all problems is four launches in all:
+// persistent pass kernels take (problem, tile) items from a work queue, longest
+// problems first (batch_apply_persistent).  Otherwise, and for the rSVD, problems
+// are spread over a small set of side streams forked from the caller's stream with
+// events and joined back, so their kernels overlap on the device.  Apply + rSVD of
+// every problem can be captured once into a hipGraph and replayed with a single
+// launch.  The autotuner times the tunable launch shapes of each problem (rows per
+// pass-1 workgroup, TSQR chain count) and the persistent grid (workgroups per
+// compute unit) with HIP events and keeps the fastest.
 #include <cstring>
 #include <new>
 #include <vector>
@@ -27,6 +30,9 @@ struct bfgsuq_batch {
     // handle_generation() of every problem when the graph was captured: the graph holds
     // each handle's k, tunables and workspace pointers, so any later change invalidates it
     std::vector<unsigned long long> captured_gen;
+    // persistent apply: descriptors for eager calls [0] and for the captured graph [1]
+    PersistSlot pslot[2];
+    int wg_per_cu = 2;
 };
 
 namespace {
@@ -47,6 +53,43 @@ int forked(bfgsuq_batch* b, hipStream_t root, F&& fn) {
         BFGS_HIP(hipStreamWaitEvent(root, b->join[s], 0));
     }
     return first;
+}
+
+// Every side stream's work so far ordered before fn's work on root, and fn's work
+// before anything queued on the side streams afterwards.
+template <typename F>
+int joined(bfgsuq_batch* b, hipStream_t root, F&& fn) {
+    for (size_t s = 0; s < b->side.size(); ++s) {
+        BFGS_HIP(hipEventRecord(b->join[s], b->side[s]));
+        BFGS_HIP(hipStreamWaitEvent(root, b->join[s], 0));
+    }
+    const int rc = fn();
+    BFGS_HIP(hipEventRecord(b->fork, root));
+    for (hipStream_t s : b->side) BFGS_HIP(hipStreamWaitEvent(s, b->fork, 0));
+    return rc;
+}
+
+bool persistent_ok(const bfgsuq_batch* b) {
+    const bfgs_dtype s0 = b->h[0]->storage;
+    if (s0 != BFGS_F32 && s0 != BFGS_F64) return false;
+    for (const bfgsuq_ctx* h : b->h)
+        if (h->storage != s0 || h->streamed || h->k < 1 || h->k > 256) return false;
+    return true;
+}
+
+// capture: root is capturing and the apply opens the captured work, so it needs no
+// join (events recorded outside a capture cannot be waited for inside it); the rSVD
+// forked after it orders the side streams behind it.
+int batch_apply(bfgsuq_batch* b, hipStream_t root, const void* const* V, const int32_t* ncols, void* const* out,
+                int slot, bool upload, bool capture = false) {
+    if (persistent_ok(b)) {
+        auto launch = [&] {
+            return batch_apply_persistent(b->h.data(), b->nprob, V, ncols, out, root, &b->pslot[slot], upload,
+                                          b->wg_per_cu);
+        };
+        return capture ? launch() : joined(b, root, launch);
+    }
+    return forked(b, root, [&](int i) { return apply_block(b->h[i], V[i], ncols[i], out[i], false); });
 }
 
 void destroy_graph(bfgsuq_batch* b) {
@@ -134,6 +177,10 @@ int bfgs_batch_destroy(bfgs_batch_t b) {
     (void)hipStreamSynchronize(b->main);
     destroy_graph(b);
     for (bfgsuq_ctx* h : b->h) bfgs_destroy(h);
+    for (PersistSlot& ps : b->pslot) {
+        if (ps.prob) (void)hipFree(ps.prob);
+        if (ps.head) (void)hipFree(ps.head);
+    }
     for (hipStream_t s : b->side) {
         (void)hipStreamSynchronize(s);
         (void)hipStreamDestroy(s);
@@ -240,7 +287,7 @@ int bfgs_batch_apply_Hinv(bfgs_batch_t b, const void* const* V, const int32_t* n
         if (!V[i] || !out[i] || ncols[i] < 1 || ncols[i] > BFGS_MAX_COLS || V[i] == out[i] ||
             (b->h[i]->gamma_mode && !b->h[i]->gamma_known))
             return BFGS_ERR_ARG;
-    return forked(b, b->main, [&](int i) { return apply_block(b->h[i], V[i], ncols[i], out[i], false); });
+    return batch_apply(b, b->main, V, ncols, out, 0, true);
 }
 
 int bfgs_batch_rsvd(bfgs_batch_t b, const int32_t* rank, int32_t oversample, uint64_t seed, void* const* U,
@@ -263,6 +310,39 @@ int bfgs_batch_autotune(bfgs_batch_t b, const void* const* V, const int32_t* nco
                                      U ? U[i] : nullptr, Sigma ? Sigma[i] : nullptr);
         if (rc != BFGS_OK) return rc;
     }
+    if (persistent_ok(b)) {
+        // the persistent grid: workgroups per compute unit
+        const int cand[] = {1, 2, 4};
+        float best = 1e30f;
+        int best_w = b->wg_per_cu;
+        hipEvent_t e0, e1;
+        BFGS_HIP(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return BFGS_ERR_HIP;
+        }
+        int rc = BFGS_OK;
+        for (int w : cand) {
+            b->wg_per_cu = w;
+            rc = batch_apply(b, b->main, V, ncols, out, 0, true);   // warm, uploads the descriptors
+            if (rc != BFGS_OK) break;
+            (void)hipEventRecord(e0, b->main);
+            for (int r = 0; r < 3 && rc == BFGS_OK; ++r) rc = batch_apply(b, b->main, V, ncols, out, 0, false);
+            (void)hipEventRecord(e1, b->main);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rc == BFGS_OK && ms < best) {
+                best = ms;
+                best_w = w;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        b->wg_per_cu = best_w;
+        for (bfgsuq_ctx* h : b->h) ++h->gen;   // the persistent grid is part of a captured graph
+        if (rc != BFGS_OK) return rc;
+    }
     return BFGS_OK;
 }
 
@@ -270,14 +350,16 @@ int bfgs_batch_graph_build(bfgs_batch_t b, const void* const* V, const int32_t* 
                            const int32_t* rank, int32_t oversample, uint64_t seed, void* const* U,
                            double* const* Sigma) {
     if (!b) return BFGS_ERR_ARG;
-    // One eager pass sizes every workspace, so nothing is allocated while capturing.
+    // One eager pass sizes every workspace (and fills the graph's persistent
+    // descriptors), so nothing is allocated or copied while capturing.
     int rc = bfgs_batch_apply_Hinv(b, V, ncols, out);
+    if (rc == BFGS_OK && persistent_ok(b)) rc = batch_apply(b, b->main, V, ncols, out, 1, true);
     if (rc == BFGS_OK) rc = bfgs_batch_rsvd(b, rank, oversample, seed, U, Sigma);
     if (rc != BFGS_OK) return rc;
     BFGS_HIP(hipStreamSynchronize(b->main));
     destroy_graph(b);
     BFGS_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
-    rc = forked(b, b->cap, [&](int i) { return apply_block(b->h[i], V[i], ncols[i], out[i], false); });
+    rc = batch_apply(b, b->cap, V, ncols, out, 1, false, true);
     if (rc == BFGS_OK)
         rc = forked(b, b->cap, [&](int i) {
             return rsvd_run(b->h[i], rank[i], oversample, seed + (uint64_t)i, U[i], Sigma[i]);

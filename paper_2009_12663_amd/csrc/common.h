@@ -260,5 +260,33 @@ int mfma_scatter_pair(bfgsuq_ctx* h, int j);
 bool mfma_apply_supported(const bfgsuq_ctx* h, int c);
 int mfma_apply(bfgsuq_ctx* h, const void* V, int c, void* out, bool diff, const ApplyWs* fixed);
 int apply_small_solve(bfgsuq_ctx* h, int c, const double* Z, double* P, double* T);
+
+// One problem of a persistent batched apply (device copy read by the pass kernels).
+struct PersistProblem {
+    int64_t n, ld, rows_per_chunk;
+    int k, kmax, c, ptiles, ctiles, nchunks, first1, first2;
+    const void *S, *Y, *h0, *V;
+    void* out;
+    double *part, *Z, *P;
+    const double *Rm, *Rinv, *RinvT, *YHY;
+    int32_t* status;
+};
+
+// Device descriptors and work-queue heads of one persistent batched apply (a batch
+// keeps one for eager calls and one for its captured graph).
+struct PersistSlot {
+    PersistProblem* prob = nullptr;
+    size_t cap = 0;
+    unsigned* head = nullptr;
+    int nprob = 0, items1 = 0, items2 = 0, solve_blocks = 0;
+};
+
+// Apply B_k of every problem to its block (float32 or float64 storage, all of one
+// type, 1 <= k <= 256): four launches on st in all (queue reset, pass 1 of every
+// problem, the small solves, pass 2).  upload = false reuses the slot's descriptors
+// (a graph capture after an eager call with the same arguments).  wg_per_cu sets the
+// persistent grid (workgroups per compute unit).
+int batch_apply_persistent(bfgsuq_ctx* const* hs, int nprob, const void* const* V, const int32_t* ncols,
+                           void* const* out, hipStream_t st, PersistSlot* slot, bool upload, int wg_per_cu);
 int push_enqueue(bfgsuq_ctx* h, const void* s, const void* y, bfgs_dtype in_dtype);
 int push_finish(bfgsuq_ctx* h);

@@ -1,7 +1,8 @@
-"""Batched form: independent problems of uneven n and k driven together (fork/join over
-side streams, pairs pushed by bfgs_batch_push_pairs, captured hipGraph), every problem
-checked against the float64 oracle; the captured graph refuses to replay once a
-handle has changed."""
+"""Batched form: independent problems of uneven n and k driven together (persistent
+work-queue passes for float32/float64 storage, fork/join over side streams otherwise,
+pairs pushed by bfgs_batch_push_pairs, captured hipGraph), every problem checked
+against the float64 oracle; the persistent apply equals the per-problem apply bit for
+bit; the captured graph refuses to replay once a handle has changed."""
 import numpy as np
 import pytest
 import torch
@@ -11,8 +12,8 @@ from workloads import quadratic as wq
 from tests.helpers import sigma_err, sigma_order_ok, rel_f, col_max_rel, gpu_input, oracle_input, h0_storage, make_pairs, gamma_of
 
 pytestmark = pytest.mark.gpu
-TOL = {"f32": 1e-6, "bf16": 1e-3}
-SIG_TOL = {"f32": 1e-6, "bf16": 1e-3}
+TOL = {"f64": 1e-12, "f32": 1e-6, "bf16": 1e-3}
+SIG_TOL = {"f64": 1e-11, "f32": 1e-6, "bf16": 1e-3}
 
 SMALL = [  # kind, nx, nz, k, diagonal B0
     ("cg", 20, 9, 12, True),
@@ -27,11 +28,44 @@ SMALL = [  # kind, nx, nz, k, diagonal B0
 def oracle_h(storage, S, Y, h0):
     if h0 is None:
         g = gamma_of(oracle_input(S, storage), oracle_input(Y, storage))
-        return np.full(S.shape[1], float(np.float32(g)))
+        return np.full(S.shape[1], g if storage == "f64" else float(np.float32(g)))
     return h0_storage(h0, storage)
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_persistent_apply_equals_per_problem_apply(storage):
+    """The persistent passes run the per-problem kernels' tiles with the same chunking
+    and fixed-order sums: the batch result is the per-problem result, bit for bit, and
+    both match the oracle.  Uneven problems, including k and c past one 128 tile."""
+    import paper_2009_12663_amd as P
+    shapes = SMALL + [("secant", 61, 29, 150, False), ("cg", 9, 7, 3, True)]
+    print(f"\n[persistent apply {storage}] {len(shapes)} problems", flush=True)
+    probs = [make_pairs(kind, nx, nz, k, seed=i + 11, precond=pre) for i, (kind, nx, nz, k, pre) in enumerate(shapes)]
+    ns = [p[0].n for p in probs]
+    ks = [p[1].shape[0] for p in probs]
+    h0s = [None if p[3] is None else gpu_input(p[3], storage) for p in probs]
+    B = P.BfgsBatch(ns, ks, h0s, storage)
+    assert B.push_pairs([gpu_input(p[1], storage) for p in probs], [gpu_input(p[2], storage) for p in probs]) == 0
+    cs = [min(ns[i], k + 10 + 3 * i) for i, k in enumerate(ks)]
+    V = [gpu_input(wq.normal_block(n, c, seed=40 + i), storage) for i, (n, c) in enumerate(zip(ns, cs))]
+    out = B.apply_Hinv(V)
+    torch.cuda.synchronize()
+    for i, (prob, S, Y, h0) in enumerate(probs):
+        single = B.problems[i].apply_Hinv(V[i])
+        torch.cuda.synchronize()
+        assert torch.equal(out[i], single), i
+        h = oracle_h(storage, S, Y, h0)
+        want = recursion.apply_hk(h, oracle_input(S, storage), oracle_input(Y, storage),
+                                  oracle_input(V[i].double().cpu(), storage))
+        got = out[i].double().cpu().numpy()
+        err, elem = rel_f(got, want), col_max_rel(got, want)
+        print(f"  problem {i}: n={ns[i]} k={ks[i]} c={cs[i]} rel_F {err:.2e} elem {elem:.2e}", flush=True)
+        assert err <= TOL[storage] and elem <= TOL[storage]
+    assert all(H.get_status() == 0 for H in B.problems)
+    B.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
 def test_batch_parity_and_graph(storage):
     import paper_2009_12663_amd as P
     print(f"\n[batch small {storage}]", flush=True)
