@@ -269,13 +269,13 @@ __device__ __forceinline__ double quad_sum(double x) {
 // scale sc (v = sc x) and tau follow in ts[0..1], tau also in taus_lds[j].  Returns
 // sc: a[] keeps x, and the fold scales it to v once the tile is done (the column
 // takes no further reflector).
-template <typename SlotT>
+template <typename SlotT, typename RingT>
 __device__ __forceinline__ double q_make_reflector(SlotT* slot, const double (&a)[RPL], int c, int j, int g,
-                                                   double* vbuf, double* ts, double* taus_lds, double& tau_out) {
+                                                   RingT* vbuf, double* ts, double* taus_lds, double& tau_out) {
     const int dj = tri_index(j, j, c);
     const double rjj = lds_early(slot + dj);
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) vbuf[i * LPC + g] = a[i];
+    for (int i = 0; i < RPL; ++i) vbuf[i * LPC + g] = (RingT)a[i];
     double p4[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < RPL; ++i) p4[i & 3] = fma(a[i], a[i], p4[i & 3]);
@@ -306,9 +306,9 @@ __device__ __forceinline__ double q_make_reflector(SlotT* slot, const double (&a
 // Reflector j (v = sc x, x the unscaled tile part in LDS) applied to column col:
 // w = tau (r + v^T a), r -= w, a -= w v; tsc = tau sc, formed while the dot product
 // runs.
-template <typename SlotT>
+template <typename SlotT, typename RingT>
 __device__ __forceinline__ void q_reflect_column(SlotT* slot, double (&a)[RPL], int c, int j, int col, int g,
-                                                 const double* x, double tau, double sc, double tsc) {
+                                                 const RingT* x, double tau, double sc, double tsc) {
     const int idx = tri_index(j, col, c);
     const double r = lds_early(slot + idx);
     double p4[4] = {0, 0, 0, 0};
@@ -324,18 +324,28 @@ __device__ __forceinline__ void q_reflect_column(SlotT* slot, double (&a)[RPL], 
 
 // LDS of the quad fold: taus_lds[256] | counters ready[QF_RMAX], done[QF_RMAX], abort |
 // (tau, sc)[QF_RMAX][PW] | ring[R] of (x[PW][QT_LD], T packed) | slot.  A ring entry
-// holds one group's unscaled reflectors (tile parts, row pitch QT_LD so that the
-// block update's column-wise reads spread over the banks) and the group's compact-WY
-// factor T (its upper triangle, row-major).  The ring takes what LDS leaves beside the
-// slot, 2 to QF_RMAX groups.
-constexpr int QF_RMAX = 8;
+// holds one group's unscaled reflectors (tile parts, row pitch QT_LD), for the waves
+// that apply the group one reflector at a time, and the staging of the group's G and
+// then T (upper triangle, row-major).  The ring takes what LDS leaves beside the slot,
+// 2 to QF_RMAX groups; its depth bounds how many tiles' chains overlap (the first
+// group of a tile waits for the entry that the group R earlier used).  The reflectors
+// stay in float64 (RingT): the returned Q has orthonormal columns only as far as the
+// fold's R agrees with the stored reflectors, and for a rank-deficient E that
+// disagreement is divided by R's tiny diagonal entries, so reflectors rounded to
+// float32 where they are applied cost orthonormality (3e-2 measured on a sketch with
+// half its columns at noise level).
+constexpr int QF_RMAX = 12;
 constexpr int QT_LD = QT + 1;
 constexpr int QF_TAUS = 0;
 constexpr int QF_CNT = QF_TAUS + 256;
 constexpr int QF_TS = QF_CNT + QF_RMAX + 1;         // 2 QF_RMAX + 1 unsigned counters (+ pad)
 constexpr int QF_X = QF_TS + 2 * PW * QF_RMAX;
 constexpr int QF_TPK = PW * (PW + 1) / 2;           // T packed: upper triangle, row-major
-constexpr int QF_ENTRY = PW * QT_LD + QF_TPK;       // doubles per ring entry
+// doubles per ring entry: the reflectors in the ring's type, then the T staging
+template <typename RingT>
+constexpr int qf_xdoubles() { return (PW * QT_LD * (int)sizeof(RingT) + 7) / 8; }
+template <typename RingT>
+constexpr int qf_entry() { return qf_xdoubles<RingT>() + QF_TPK; }
 // Waves k + 1 .. k + QF_SEQ apply group k one reflector at a time, as it is
 // published: they build the next groups, so they are on the chain of the fold.  The
 // waves further right apply it as one block once its T is published.
@@ -344,18 +354,18 @@ constexpr int QF_SEQ = 2;
 __device__ __forceinline__ int tpk_index(int i, int j) { return i * PW - (i * (i - 1)) / 2 + (j - i); }
 constexpr size_t QF_LDS_LIMIT = 160 * 1024;
 
-template <typename SlotT>
+template <typename SlotT, typename RingT>
 size_t qf_lds_bytes(int c, int ring) {
-    return (size_t)(QF_X + ring * QF_ENTRY) * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
+    return (size_t)(QF_X + ring * qf_entry<RingT>()) * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
 }
 
 // The deepest ring that fits beside the slot, and no deeper than a tile's groups
 // plus one (LDS left free lets small problems share a CU); 0 if not even 2 fit.
-template <typename SlotT>
+template <typename SlotT, typename RingT>
 int qf_ring(int c) {
     const int want = std::min(QF_RMAX, std::max(2, (c + PW - 1) / PW + 1));
     for (int r = want; r >= 2; --r)
-        if (qf_lds_bytes<SlotT>(c, r) <= QF_LDS_LIMIT) return r;
+        if (qf_lds_bytes<SlotT, RingT>(c, r) <= QF_LDS_LIMIT) return r;
     return 0;
 }
 
@@ -584,7 +594,7 @@ __device__ __forceinline__ void q_block_apply(SlotT* slot, double (&a)[RPL], int
 // ring allows.  No wave shares slot entries with another (an entry belongs to its
 // column's wave), so there is no barrier: each wait is for an event of an earlier
 // group, whose waves wait only for still earlier ones, so every wait ends.
-template <typename SlotT>
+template <typename SlotT, typename RingT>
 __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int j0, double* xring,
                                        double* tsring, double* taus_lds, unsigned* cnt, int ring, QfSeq& sq,
                                        double* panels) {
@@ -600,8 +610,8 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
         const int col = wave * PW + (lane_k >> 2), g = lane_k & 3;   // as the caller's, re-formed
         const int jb = k * PW, je = min(jb + PW, c), ng = je - jb;
         const int r = sq.slot;
-        double* xb = xring + r * QF_ENTRY;
-        double* Tb = xb + PW * QT_LD;
+        RingT* xb = (RingT*)(xring + r * qf_entry<RingT>());
+        double* Tb = xring + r * qf_entry<RingT>() + qf_xdoubles<RingT>();
         double* tb = tsring + r * 2 * PW;
         unsigned* ready = cnt + r;
         unsigned* done = cnt + QF_RMAX + r;
@@ -692,7 +702,7 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
     double* tsring = lds + QF_TS;
     double* taus_lds = lds + QF_TAUS;
     unsigned* cnt = (unsigned*)(lds + QF_CNT);
-    SlotT* slot = (SlotT*)(lds + QF_X + ring * QF_ENTRY);
+    SlotT* slot = (SlotT*)(lds + QF_X + ring * qf_entry<double>());
     QfSeq sq;
     if (threadIdx.x <= 2 * QF_RMAX) cnt[threadIdx.x] = 0;   // counters and the abort flag; the slot set-up's barrier follows
     constexpr int PS = Layout<QT>::PS;
@@ -719,7 +729,7 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
             a[i] = (col < c && r < r_end) ? to_f64(nx[i]) : 0.0;
         }
         const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
-        q_fold(slot, a, c, 0, xring, tsring, taus_lds, cnt, ring, sq, refl + gtile * np * PS);
+        q_fold<SlotT, double>(slot, a, c, 0, xring, tsring, taus_lds, cnt, ring, sq, refl + gtile * np * PS);
         if (q_aborted(cnt + 2 * QF_RMAX)) break;
     }
     __syncthreads();   // the folds have no barrier; slot_store reads every column's entries
@@ -739,7 +749,7 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
     double* tsring = lds + QF_TS;
     double* taus_lds = lds + QF_TAUS;
     unsigned* cnt = (unsigned*)(lds + QF_CNT);
-    SlotT* slot = (SlotT*)(lds + QF_X + ring * QF_ENTRY);
+    SlotT* slot = (SlotT*)(lds + QF_X + ring * qf_entry<double>());
     QfSeq sq;
     if (threadIdx.x <= 2 * QF_RMAX) cnt[threadIdx.x] = 0;   // counters and the abort flag; the slot set-up's barrier follows
     constexpr int PS = Layout<QT>::PS;
@@ -757,7 +767,7 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
             const double v = Rb[(int64_t)min(row, c - 1) * c + colc];   // clamped, masked below
             a[q] = (col < c && row < c && col >= row) ? v : 0.0;
         }
-        q_fold(slot, a, c, t * QT, xring, tsring, taus_lds, cnt, ring, sq,
+        q_fold<SlotT, double>(slot, a, c, t * QT, xring, tsring, taus_lds, cnt, ring, sq,
                tree + ((comb_off + i) * ntt + t) * np * PS);
         if (q_aborted(cnt + 2 * QF_RMAX)) break;
     }
@@ -887,17 +897,21 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out) {
             return BFGS_ERR_HIP;
         attr_q = true;
     }
-    const int ring = qf_ring<SlotT>(c);   // >= 2: the slot type was chosen for that
+    // float64 rings in both folds (>= 2 entries: the slot type was chosen for that)
+    const int ring = qf_ring<SlotT, double>(c);
+    const int tring = ring;
+    if (ring < 2) return BFGS_ERR_ARG;
+    const size_t leaf_lds = qf_lds_bytes<SlotT, double>(c, ring), tree_lds = leaf_lds;
     prof_begin(h, "tsqr_leaf_fwd");
-    hipLaunchKernelGGL((leaf_forward_q<TE, SlotT>), dim3(nchains), dim3(LPC * 16 * np), qf_lds_bytes<SlotT>(c, ring),
+    hipLaunchKernelGGL((leaf_forward_q<TE, SlotT>), dim3(nchains), dim3(LPC * 16 * np), leaf_lds,
                        h->stream, n, c, rows_per_chain, E, refl, Rs, ring, h->status);
     prof_end(h);
     prof_begin(h, "tsqr_tree");
     int64_t off = 0;
     for (int stride = 1; stride < nchains; stride *= 2) {
         const int ncomb = nchains / (2 * stride);
-        hipLaunchKernelGGL((tree_forward_q<SlotT>), dim3(ncomb), dim3(threads), qf_lds_bytes<SlotT>(c, ring),
-                           h->stream, c, stride, off, Rs, tree, ring, h->status);
+        hipLaunchKernelGGL((tree_forward_q<SlotT>), dim3(ncomb), dim3(threads), tree_lds,
+                           h->stream, c, stride, off, Rs, tree, tring, h->status);
         off += ncomb;
     }
     hipLaunchKernelGGL(set_identity_kernel, dim3(64), dim3(256), 0, h->stream, Qtop, c);
@@ -923,7 +937,7 @@ int tsqr_dispatch(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out) {
     // within 128 registers per lane (1024-thread workgroups); the slot is float64
     // whenever it fits in LDS (c <= 184) and float32 above that
     const size_t lim = 160 * 1024;
-    const bool dslot = lds_bytes<64, double>(c) <= lim && qf_ring<double>(c) >= 2;
+    const bool dslot = lds_bytes<64, double>(c) <= lim && qf_ring<double, double>(c) >= 2;
     // staging doubles per thread for one stored panel (64 * ceil(c / 16) threads); more
     // than 8 (c <= 32) copies panels straight to LDS
     const int pf = ceil_div(Layout<64>::PS, 64 * ceil_div(c, PW));
@@ -935,13 +949,15 @@ int tsqr_dispatch(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out) {
 
 }  // namespace
 
-bool tsqr_f64_slot(int c) { return c >= 1 && c <= 256 && lds_bytes<64, double>(c) <= 160 * 1024 && qf_ring<double>(c) >= 2; }
+bool tsqr_f64_slot(int c) {
+    return c >= 1 && c <= 256 && lds_bytes<64, double>(c) <= 160 * 1024 && qf_ring<double, double>(c) >= 2;
+}
 
 extern "C" int bfgs_tsqr_shape(int32_t c, int32_t* slot_f64, int32_t* ring) {
     if (c < 1 || c > BFGS_MAX_COLS) return BFGS_ERR_ARG;
     const bool dslot = tsqr_f64_slot(c);
     if (slot_f64) *slot_f64 = dslot ? 1 : 0;
-    if (ring) *ring = dslot ? qf_ring<double>(c) : qf_ring<float>(c);
+    if (ring) *ring = dslot ? qf_ring<double, double>(c) : qf_ring<float, double>(c);
     return BFGS_OK;
 }
 

@@ -106,7 +106,7 @@ def run(c, tiles, seed, R=2, block=True, naive=False):
 
 
 @pytest.mark.parametrize("c", [1, 15, 16, 17, 26, 32, 40, 64, 100, 184, 220, 256])
-@pytest.mark.parametrize("R", [1, 2, 3, 5, 7, 8])
+@pytest.mark.parametrize("R", [1, 2, 3, 5, 7, 8, 10, 12])
 @pytest.mark.parametrize("block", [False, True])
 def test_fold_protocol_leaf_and_tree(c, R, block):
     leaf = [0, 0, 0, 0]                               # four leaf tiles
