@@ -264,3 +264,28 @@ def test_f64_input_to_bf16_storage_rounds_once():
     via_f32 = torch.from_numpy(s).float().to(torch.bfloat16).double().numpy()
     assert (via_f32 != want_s).sum() == n // 2
     H.close()
+
+
+def test_apply_with_ill_conditioned_r():
+    """Pairs whose scales span six orders of magnitude (s_i scaled by 10^u, u uniform in
+    [-3, 3], y_i = A s_i), so R = triu(S^T Y) has curvatures from about 1e-6 to 1e6 of
+    each other and a condition number near 1e12.  The inner solve goes through the
+    R^-1 kept at push time; the oracle (the eq. (3) recursion) never forms R.  Float64
+    storage, every column element-wise."""
+    prob = wq.make_problem("tiny")
+    n = prob.n
+    rng = np.random.default_rng(17)
+    k = 24
+    S = torch.from_numpy(rng.standard_normal((k, n)) * 10.0 ** rng.uniform(-3, 3, (k, 1)))
+    Y = prob.matvec(S).contiguous()
+    H = build_handle("f64", S, Y)
+    V = wq.normal_block(n, 31, seed=4)
+    out = H.apply_Hinv(gpu_input(V, "f64")).double().cpu().numpy()
+    want, _ = oracle_apply("f64", S, Y, V)
+    R = np.triu(S.numpy() @ Y.numpy().T)
+    err, elem = rel_f(out, want), col_max_rel(out, want)
+    print(f"\n[ill-conditioned R] cond(R) {np.linalg.cond(R):.2e}: rel_F {err:.2e} elem {elem:.2e}", flush=True)
+    assert np.linalg.cond(R) > 1e10
+    assert elem <= TOL["f64"]          # measured 2e-15 at cond(R) = 9e11
+    assert H.get_status() == 0
+    H.close()
