@@ -624,7 +624,7 @@ def summarize_profiles(d, out_dir, digest, cmd_prefix):
     lines = ["# Kernel times: 1700 x 350 x 3 grid, n = 1,785,000, k = 200, bfloat16, 220 columns, rSVD 200 + 20", "",
              "Command (from the repository root, on one MI355X):", "",
              f"    {cmd_prefix} --kernel-trace --stats -d <dir> -o kt --output-format csv -- "
-             "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline", "",
+             "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-fp32-path", "",
              "| kernel | group | calls | total ms | avg ms |", "|---|---|---|---|---|"]
     groups = {}
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:40]:
@@ -671,9 +671,9 @@ def summarize_profiles(d, out_dir, digest, cmd_prefix):
     lines = ["# HBM traffic per dispatch: 1700 x 350 x 3 grid, n = 1,785,000, k = 200, bfloat16", "",
              "Commands (from the repository root, one counter per run):", "",
              f"    {cmd_prefix} --pmc FETCH_SIZE -d <dir> -o fetch --output-format csv -- "
-             "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline",
+             "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-fp32-path",
              f"    {cmd_prefix} --pmc WRITE_SIZE -d <dir> -o write --output-format csv -- "
-             "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline",
+             "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-fp32-path",
              f"    {cmd_prefix} --pmc FETCH_SIZE -d <dir> -o cfetch --output-format csv -- "
              "python3 bench.py --calibrate-copy 1024",
              f"    {cmd_prefix} --pmc WRITE_SIZE -d <dir> -o cwrite --output-format csv -- "
@@ -719,7 +719,9 @@ def summarize_profiles(d, out_dir, digest, cmd_prefix):
                  "SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE -d <dir> -o mfma --output-format csv -- "
                  "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-fp32-path", "",
                  "flops = MOPS x 512; TFLOP/s uses the kernel-trace average duration of the same kernel; "
-                 "busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x 1024 SIMDs). Peaks: bfloat16 dense "
+                 "busy = SQ_VALU_MFMA_BUSY_CYCLES / (that duration x 2.4 GHz x 1024 SIMDs), the share of "
+                 "the matrix cores' cycles they were busy (GRBM_GUI_ACTIVE, collected in the same pass, "
+                 "includes the profiler's dispatch window and is not used). Peaks: bfloat16 dense "
                  "2.5 PFLOP/s, float64 matrix 78.6 TFLOP/s.", "",
                  "| kernel | group | bf16 GFLOP | f64 GFLOP | avg ms | bf16 TFLOP/s (% of 2500) | "
                  "f64 TFLOP/s (% of 78.6) | MFMA busy % |", "|---|---|---|---|---|---|---|---|"]
@@ -731,8 +733,8 @@ def summarize_profiles(d, out_dir, digest, cmd_prefix):
             if fb + fd == 0:
                 continue
             ms = avg_ns.get(k, 0.0) / 1e6
-            gui = mops["GRBM_GUI_ACTIVE"].get(k, 0.0)
-            busy = 100 * mops["SQ_VALU_MFMA_BUSY_CYCLES"].get(k, 0.0) / (gui * simds) if gui else 0.0
+            cyc = avg_ns.get(k, 0.0) * 2.4
+            busy = 100 * mops["SQ_VALU_MFMA_BUSY_CYCLES"].get(k, 0.0) / (cyc * simds) if cyc else 0.0
             tb = fb / ms / 1e9 if ms else 0.0
             td = fd / ms / 1e9 if ms else 0.0
             lines.append(f"| {short_name(k)[:60]} | {group_of(k) or '-'} | {fb / 1e9:.2f} | {fd / 1e9:.2f} | {ms:.4f} | "
