@@ -83,15 +83,17 @@ __global__ void scatter_pair_layouts(int64_t n, int64_t rows_f1, int64_t rows_f2
 // Pass 1
 // ---------------------------------------------------------------------------
 // Rows per stage: 128 (8 MFMA k-steps of 16) while the register budget allows it,
-// 64 for eight column tiles; one stage is in flight while the previous one is used.
+// 64 from six column tiles.  Two stages are in flight while a third is used: each
+// register set is refilled as soon as its stage is consumed (V once staged in LDS, the
+// pair fragments once multiplied).
 template <int NT>
 struct G1Shape {
-    static constexpr int STAGE = NT >= 8 ? 64 : 128;
+    static constexpr int STAGE = NT >= 6 ? 64 : 128;
     static constexpr int KS = STAGE / 16;
     static constexpr int CPC = STAGE / 8;   // 16-byte chunks per staged V column
     static constexpr int LD = STAGE + 8;    // LDS pitch (elements) of a staged V column
 };
-int g1_stage(int NT) { return NT >= 8 ? G1Shape<8>::STAGE : G1Shape<1>::STAGE; }
+int g1_stage(int NT) { return NT >= 6 ? G1Shape<8>::STAGE : G1Shape<1>::STAGE; }
 
 // blockDim = 64 * MT (one 32-pair tile per wave); grid = 16 * ceil(nk / 8)
 template <int NT, bool DIAG>
@@ -133,10 +135,10 @@ __global__ void __launch_bounds__(512) gemm1_mfma(int64_t n, int k, int kmax, in
 
     constexpr int VCH = NT * 32 * G1_CPC;                // 16-byte chunks per staged V block
     constexpr int VQ = (VCH + 511) / 512;                // per thread (512 threads)
-    uint4 vreg[VQ];
-    uint4 areg[G1_KS];
+    uint4 vreg0[VQ], vreg1[VQ];
+    uint4 areg0[G1_KS], areg1[G1_KS];
 
-    auto load_v = [&](int64_t r0) {
+    auto load_v = [&](uint4 (&vreg)[VQ], int64_t r0) {
 #pragma unroll
         for (int q = 0; q < VQ; ++q) {
             const int idx = tid + q * 512;
@@ -158,7 +160,7 @@ __global__ void __launch_bounds__(512) gemm1_mfma(int64_t n, int k, int kmax, in
             vreg[q] = val;
         }
     };
-    auto store_v = [&](int64_t r0) {
+    auto store_v = [&](const uint4 (&vreg)[VQ], int64_t r0) {
 #pragma unroll
         for (int q = 0; q < VQ; ++q) {
             const int idx = tid + q * 512;
@@ -183,7 +185,7 @@ __global__ void __launch_bounds__(512) gemm1_mfma(int64_t n, int k, int kmax, in
             }
         }
     };
-    auto load_a = [&](int64_t r0) {
+    auto load_a = [&](uint4 (&areg)[G1_KS], int64_t r0) {
 #pragma unroll
         for (int s = 0; s < G1_KS; ++s) {
             const int64_t rr = r0 + 16 * s;
@@ -195,35 +197,39 @@ __global__ void __launch_bounds__(512) gemm1_mfma(int64_t n, int k, int kmax, in
     };
 
     if (r_begin < r_end) {
-        load_v(r_begin);
-        load_a(r_begin);
+        load_v(vreg0, r_begin);
+        load_a(areg0, r_begin);
     }
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += r_step) {
+    if (r_begin + r_step < r_end) {
+        load_v(vreg1, r_begin + r_step);
+        load_a(areg1, r_begin + r_step);
+    }
+    auto stage = [&](uint4 (&vreg)[VQ], uint4 (&areg)[G1_KS], int64_t r0) {
         __syncthreads();
-        store_v(r0);
+        store_v(vreg, r0);
         __syncthreads();
-        uint4 acur[G1_KS];
-#pragma unroll
-        for (int s = 0; s < G1_KS; ++s) acur[s] = areg[s];
-        if (r0 + r_step < r_end) {
-            load_v(r0 + r_step);
-            load_a(r0 + r_step);
-        }
+        if (r0 + 2 * r_step < r_end) load_v(vreg, r0 + 2 * r_step);
         if (active) {
 #pragma unroll
-        for (int s = 0; s < G1_KS; ++s) {
-            const bf16x8 a = as_bf16x8(acur[s]);
+            for (int s = 0; s < G1_KS; ++s) {
+                const bf16x8 a = as_bf16x8(areg[s]);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const uint16_t* bp = Vs + (t * 32 + (lane & 31)) * VS_LD + s * 16 + half * 8;
-                acc[t] = mfma32(a, as_bf16x8(*(const uint4*)bp), acc[t]);
-                if (scaled) {
-                    const uint16_t* bl = Vl + (t * 32 + (lane & 31)) * VS_LD + s * 16 + half * 8;
-                    acc[t] = mfma32(a, as_bf16x8(*(const uint4*)bl), acc[t]);
+                for (int t = 0; t < NT; ++t) {
+                    const uint16_t* bp = Vs + (t * 32 + (lane & 31)) * VS_LD + s * 16 + half * 8;
+                    acc[t] = mfma32(a, as_bf16x8(*(const uint4*)bp), acc[t]);
+                    if (scaled) {
+                        const uint16_t* bl = Vl + (t * 32 + (lane & 31)) * VS_LD + s * 16 + half * 8;
+                        acc[t] = mfma32(a, as_bf16x8(*(const uint4*)bl), acc[t]);
+                    }
                 }
             }
         }
-        }
+        if (r0 + 2 * r_step < r_end) load_a(areg, r0 + 2 * r_step);
+    };
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += 2 * r_step) {
+        stage(vreg0, areg0, r0);
+        if (r0 + r_step >= r_end) break;
+        stage(vreg1, areg1, r0 + r_step);
     }
     if (!active) return;
     // partial Z for this row range: part[kr][col][2k], float32

@@ -327,8 +327,9 @@ __device__ __forceinline__ void q_reflect_column(SlotT* slot, double (&a)[RPL], 
 // holds one group's unscaled reflectors (tile parts, row pitch QT_LD), for the waves
 // that apply the group one reflector at a time, and the staging of the group's G and
 // then T (upper triangle, row-major).  The ring takes what LDS leaves beside the slot,
-// 2 to QF_RMAX groups; its depth bounds how many tiles' chains overlap (the first
-// group of a tile waits for the entry that the group R earlier used).  The reflectors
+// 2 to QF_RMAX entries, in sets of two: tile t of a fold uses set t mod m (m = ring / 2),
+// its group k the entry k mod 2 of the set (qf_set), so m tiles' chains are in
+// flight at once, each alternating between its two entries.  The reflectors
 // stay in float64 (RingT): the returned Q has orthonormal columns only as far as the
 // fold's R agrees with the stored reflectors, and for a rank-deficient E that
 // disagreement is divided by R's tiny diagonal entries, so reflectors rounded to
@@ -359,12 +360,13 @@ size_t qf_lds_bytes(int c, int ring) {
     return (size_t)(QF_X + ring * qf_entry<RingT>()) * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
 }
 
-// The deepest ring that fits beside the slot, and no deeper than a tile's groups
-// plus one (LDS left free lets small problems share a CU); 0 if not even 2 fit.
+// The deepest ring of whole sets that fits beside the slot, up to three sets (three
+// tiles in flight, and fewer when a tile has few groups: LDS left free lets small
+// problems share a CU); 0 if not even one set fits.
 template <typename SlotT, typename RingT>
 int qf_ring(int c) {
-    const int want = std::min(QF_RMAX, std::max(2, (c + PW - 1) / PW + 1));
-    for (int r = want; r >= 2; --r)
+    const int want = std::min(QF_RMAX, std::max(2, 2 * std::min(3, ((c + PW - 1) / PW + 1) / 2)));
+    for (int r = want; r >= 2; r -= 2)
         if (qf_lds_bytes<SlotT, RingT>(c, r) <= QF_LDS_LIMIT) return r;
     return 0;
 }
@@ -444,12 +446,25 @@ __device__ __forceinline__ void q_wait_seen(unsigned* cnt, unsigned value, unsig
     }
 }
 
-// Progress of a workgroup's folds, the same in every thread: groups started and the
-// ring slot of the next one.
-struct QfSeq {
-    unsigned groups = 0;
-    int slot = 0;
-};
+// Ring entries come in m = ring / 2 sets of two: tile t of a fold takes set t mod m
+// and its group k the entry k mod 2 of the set, so m tiles' chains are in flight at
+// once, each alternating between its two entries.  Group (t, k) counts
+// 256 (t np + k) + 1 + (reflectors published) in its entry's ready counter, so the
+// counts of an entry only grow from one group to the next.  The entry's previous
+// group is (t, k - 2) if the tile has it, else the last group of tile t - m with the
+// parity of k (a fold's tiles start at group k0 = 0 for the leaves and 4 t for a tree
+// combine, never later than the tile before, so tile t - m has that group), else
+// none.  qf_prev_first returns that group's first count, or 0 for none (a first count
+// is never 0).
+__device__ __forceinline__ int qf_set(int t, int ring) { return (t % (ring >= 2 ? ring / 2 : 1)) * 2; }
+
+__device__ __forceinline__ unsigned qf_prev_first(unsigned tag, int k, int k0, int np, int ring) {
+    if (k - 2 >= k0) return tag - 512u;
+    // the tags of m tiles: group (t, k) has a tile t - m iff its tag exceeds them
+    const unsigned back = (unsigned)((ring >= 2 ? ring / 2 : 1) * np) * 256u;
+    if (tag <= back) return 0u;
+    return tag - back + (unsigned)((np - 1 - k) >> 1) * 512u;
+}
 
 // A wave's tile columns in two layouts.  Quad layout (reflector building and the
 // one-at-a-time application): lane 4 j + g holds rows 4 i + g of the wave's column j
@@ -577,26 +592,27 @@ __device__ __forceinline__ void q_block_apply(SlotT* slot, double (&a)[RPL], int
 // Reflectors come in groups of PW: group k (reflectors PW k .. PW k + PW - 1) is
 // built by wave k, which owns those columns, one reflector after the other, each
 // applied to the wave's later columns at once (a wave's LDS operations complete in
-// order, so its own writes need no synchronisation).  The groups take the `ring`
-// entries of the LDS ring in turn.  Each reflector is published in its entry's
-// ready counter (value 256 G + slot + 1 for the workgroup's G-th group) as soon as it
-// is written; once the group is complete its builder forms the group's compact-WY
-// factor T, writes it beside the reflectors, publishes one count more and stores its
-// panel (V, T) to `panels`.  Waves k + 1 .. k + QF_SEQ, the next groups' builders,
+// order, so its own writes need no synchronisation).  Group k of the fold's tile t
+// takes entry k mod 2 of the ring's set t mod (ring / 2).  Each reflector is
+// published in its entry's ready counter (value 256 (t np + k) + slot + 1) as soon as
+// it is written; once the group is complete its builder forms the group's compact-WY
+// factor T, stores the panel (V, T) to `panels` and, once those stores are complete,
+// publishes one count more.  Waves k + 1 .. k + QF_SEQ, the next groups' builders,
 // apply each reflector as it is published (they are on the chain of the fold); the
 // waves further right wait for the final count and apply the whole group as one
 // block on the matrix cores (q_block_apply), holding their columns in the
 // matrix-core layout until they reach the first group they apply one at a time.
 // Every wave that used a group (its builder included) arrives at the entry's done
 // counter afterwards; the wave that next fills the entry first waits for all of
-// them, so one builder at a time writes an entry and its ready counter only grows.  A wave is done with a tile once it has built its
-// own group, and goes on to the next tile: the tiles' chains overlap as far as the
-// ring allows.  No wave shares slot entries with another (an entry belongs to its
+// them, so one builder at a time writes an entry and its ready counter only grows.
+// A wave is done with a tile once it has built its own group, and goes on to the
+// next tile: the chains of ring / 2 tiles overlap, each in its own set of entries.
+// No wave shares slot entries with another (an entry belongs to its
 // column's wave), so there is no barrier: each wait is for an event of an earlier
 // group, whose waves wait only for still earlier ones, so every wait ends.
 template <typename SlotT, typename RingT>
 __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int j0, double* xring,
-                                       double* tsring, double* taus_lds, unsigned* cnt, int ring, QfSeq& sq,
+                                       double* tsring, double* taus_lds, unsigned* cnt, int ring, int t,
                                        double* panels) {
     const int wave = threadIdx.x >> 6;   // = col / PW
     const int np = (c + PW - 1) / PW;
@@ -605,24 +621,26 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
     double sc_own = 0.0;                 // the scale of this quad's reflector (columns j0 .. c-1)
     const bool block_first = wave >= k0 + QF_SEQ + 1;
     if (block_first) quad_to_mfma(a);
-    for (int k = k0; k < np; ++k) {
+    const int set = qf_set(t, ring);
+    unsigned tag = (unsigned)(t * np + k0) * 256u + 1u;   // group k's first count
+    for (int k = k0; k < np; ++k, tag += 256u) {
         const int lane_k = fresh_lane();
         const int col = wave * PW + (lane_k >> 2), g = lane_k & 3;   // as the caller's, re-formed
         const int jb = k * PW, je = min(jb + PW, c), ng = je - jb;
-        const int r = sq.slot;
+        const int r = set + (k & 1);
         RingT* xb = (RingT*)(xring + r * qf_entry<RingT>());
         double* Tb = xring + r * qf_entry<RingT>() + qf_xdoubles<RingT>();
         double* tb = tsring + r * 2 * PW;
         unsigned* ready = cnt + r;
         unsigned* done = cnt + QF_RMAX + r;
-        const unsigned tag = sq.groups * 256u + 1u;
         if (wave >= k) {
             if (wave == k) {
-                if (sq.groups >= (unsigned)ring) {
+                const unsigned prev = qf_prev_first(tag, k, k0, np, ring);
+                if (prev != 0u) {
                     // the entry's previous group: once its builder has published (and so
                     // has set done to minus its users), done back at zero means every
                     // user has arrived
-                    q_wait(ready, (sq.groups - (unsigned)ring) * 256u + 1u, abort_flag);
+                    q_wait(ready, prev, abort_flag);
                     q_wait_nonneg(done, abort_flag);
                 }
                 // this group's slot users: the builder and the waves that apply it one
@@ -688,8 +706,6 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
             }
             if (wave <= k + QF_SEQ && threadIdx.x % 64 == 0) q_arrive(done);
         }
-        ++sq.groups;
-        sq.slot = r + 1 == ring ? 0 : r + 1;
     }
 }
 
@@ -703,7 +719,6 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
     double* taus_lds = lds + QF_TAUS;
     unsigned* cnt = (unsigned*)(lds + QF_CNT);
     SlotT* slot = (SlotT*)(lds + QF_X + ring * qf_entry<double>());
-    QfSeq sq;
     if (threadIdx.x <= 2 * QF_RMAX) cnt[threadIdx.x] = 0;   // counters and the abort flag; the slot set-up's barrier follows
     constexpr int PS = Layout<QT>::PS;
     const int ch = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
@@ -729,7 +744,7 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
             a[i] = (col < c && r < r_end) ? to_f64(nx[i]) : 0.0;
         }
         const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
-        q_fold<SlotT, double>(slot, a, c, 0, xring, tsring, taus_lds, cnt, ring, sq, refl + gtile * np * PS);
+        q_fold<SlotT, double>(slot, a, c, 0, xring, tsring, taus_lds, cnt, ring, tile, refl + gtile * np * PS);
         if (q_aborted(cnt + 2 * QF_RMAX)) break;
     }
     __syncthreads();   // the folds have no barrier; slot_store reads every column's entries
@@ -750,7 +765,6 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
     double* taus_lds = lds + QF_TAUS;
     unsigned* cnt = (unsigned*)(lds + QF_CNT);
     SlotT* slot = (SlotT*)(lds + QF_X + ring * qf_entry<double>());
-    QfSeq sq;
     if (threadIdx.x <= 2 * QF_RMAX) cnt[threadIdx.x] = 0;   // counters and the abort flag; the slot set-up's barrier follows
     constexpr int PS = Layout<QT>::PS;
     const int i = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC, wave = threadIdx.x >> 6;
@@ -767,7 +781,7 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
             const double v = Rb[(int64_t)min(row, c - 1) * c + colc];   // clamped, masked below
             a[q] = (col < c && row < c && col >= row) ? v : 0.0;
         }
-        q_fold<SlotT, double>(slot, a, c, t * QT, xring, tsring, taus_lds, cnt, ring, sq,
+        q_fold<SlotT, double>(slot, a, c, t * QT, xring, tsring, taus_lds, cnt, ring, t,
                tree + ((comb_off + i) * ntt + t) * np * PS);
         if (q_aborted(cnt + 2 * QF_RMAX)) break;
     }

@@ -127,20 +127,21 @@ def test_rsvd_parity(storage, kind, nx, nz, k, rank, p, precond):
 def _fold_edges():
     """Block widths at the TSQR fold's configuration edges, from the library's own
     shape query: the largest c with a float64 slot, the first with a float32 slot,
-    and the first float32-slot c whose reflector ring holds eight groups."""
+    and the first float32-slot c whose reflector ring holds only two sets (two tiles
+    in flight) of entries."""
     from paper_2009_12663_amd import _lib
     shapes = {c: _lib.tsqr_shape(c) for c in range(1, 257)}
     last64 = max(c for c, (f64, _) in shapes.items() if f64)
-    ring8 = min(c for c, (f64, r) in shapes.items() if not f64 and r == 8)
-    return [("f64", last64), ("f32", last64), ("f32", last64 + 1), ("bf16", last64 + 1), ("f32", ring8),
+    ring4 = min(c for c, (f64, r) in shapes.items() if not f64 and r == 4)
+    return [("f64", last64), ("f32", last64), ("f32", last64 + 1), ("bf16", last64 + 1), ("f32", ring4),
             ("f64", 200)]
 
 
 @pytest.mark.parametrize("case", range(6))
 def test_rsvd_fold_configuration_edges(case):
     """The TSQR fold's configuration edges (widths from the library's shape query):
-    the largest block with a float64 slot, the first with a float32 slot, and a
-    float32 slot whose ring holds eight reflector groups.  Float32 and float64
+    the largest block with a float64 slot, the first with a float32 slot, and the
+    first float32 slot whose ring holds two sets of entries.  Float32 and float64
     storage keep E in float64 and split blocks wider than a float64 slot into two
     column blocks (c = 200 in float64 runs that path).  Conjugate-gradient pairs,
     rank = the pairs' count, p = the rest of c: c >= k + 1, so the sketch is exact."""
