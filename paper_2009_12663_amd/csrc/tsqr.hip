@@ -8,7 +8,9 @@
 //
 // Forward (leaf_forward_q, tree_forward_q).  One quad of lanes per column holds
 // the column's 64 tile rows (16 per lane); reflector j acts on (slot row j, tile
-// rows).  Wave k owns columns 16 k .. 16 k + 15 and builds their group of 16
+// rows).  Wave k (in the fold's numbering: hardware waves take the groups in the
+// order qf_perm gives, which spreads the groups that apply many blocks over the
+// SIMDs) owns columns 16 k .. 16 k + 15 and builds their group of 16
 // reflectors; there is no workgroup barrier: the groups pass through a ring of LDS
 // entries with per-entry ready/done counters (q_fold).  The two waves after a
 // builder apply its reflectors one at a time as they are published (they build the
@@ -22,8 +24,8 @@
 // Backward (tree_backward, leaf_backward).  Q is formed by applying the stored
 // panels in reverse to the identity at the root and to zero tile rows at the
 // leaves, on the float64 matrix cores from register-resident accumulator tiles
-// (wave w owns column tile w; lane l holds rows 16 rt + l/16 + 4 r of column
-// 16 w + l%16):  W = S_p + V^T A,  W' = T W,  S_p -= W',  A -= V W', with S_p the
+// (the wave of group w, as in the forward folds, owns column tile w; lane l holds
+// rows 16 rt + l/16 + 4 r of column 16 w + l%16):  W = S_p + V^T A,  W' = T W,  S_p -= W',  A -= V W', with S_p the
 // panel's 16 slot rows.  Every slot met on the way stays upper triangular.
 #include <algorithm>
 #include <cmath>
@@ -80,6 +82,11 @@ __device__ __forceinline__ int fresh_lane() {
     asm volatile("" : "+v"(l));
     return l;
 }
+
+// The column group this wave owns: hardware wave w (on SIMD w mod 4) takes group
+// (perm >> 4 w) & 15, so that the heavy groups (those with many groups before them)
+// are spread over the SIMDs.
+__device__ __forceinline__ int qf_group(uint64_t perm) { return (int)((perm >> (4 * (threadIdx.x >> 6))) & 15u); }
 
 // x of lane src (any lane, chosen per lane)
 __device__ __forceinline__ double bpermute_f64(double x, int src) {
@@ -148,18 +155,43 @@ __device__ void slot_zero(SlotT* slot, int c) {
     __syncthreads();
 }
 
+// A c x c upper-triangular matrix (row-major in M) into and out of the packed slot.
+// Thread t takes column t (and t + blockDim.x, ...), rows in groups of SL_ROWS whose
+// loads are all in flight before the first is stored: one row at a time would wait a
+// full memory round trip per row.  Loads past the diagonal are clamped to it (issued,
+// unused), so that none is conditional.
+constexpr int SL_ROWS = 16;
+
 template <typename SlotT>
 __device__ void slot_load(SlotT* slot, const double* M, int c) {
-    for (int j = 0; j < c; ++j)
-        for (int col = j + threadIdx.x; col < c; col += blockDim.x) slot[tri_index(j, col, c)] = (SlotT)M[(int64_t)j * c + col];
+    for (int col = threadIdx.x; col < c; col += blockDim.x) {
+        for (int j0 = 0; j0 <= col; j0 += SL_ROWS) {
+            double v[SL_ROWS];
+#pragma unroll
+            for (int u = 0; u < SL_ROWS; ++u) v[u] = M[(int64_t)min(j0 + u, col) * c + col];
+#pragma unroll
+            for (int u = 0; u < SL_ROWS; ++u)
+                if (j0 + u <= col) slot[tri_index(j0 + u, col, c)] = (SlotT)v[u];
+        }
+    }
     __syncthreads();
 }
 
 template <typename SlotT>
 __device__ void slot_store(const SlotT* slot, double* M, int c) {
-    for (int j = 0; j < c; ++j)
-        for (int col = threadIdx.x; col < c; col += blockDim.x)
-            M[(int64_t)j * c + col] = col >= j ? (double)slot[tri_index(j, col, c)] : 0.0;
+    for (int col = threadIdx.x; col < c; col += blockDim.x) {
+        for (int j0 = 0; j0 < c; j0 += SL_ROWS) {
+            double v[SL_ROWS];
+#pragma unroll
+            for (int u = 0; u < SL_ROWS; ++u) {
+                const int j = j0 + u;
+                v[u] = j <= col ? (double)slot[tri_index(j, col, c)] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < SL_ROWS; ++u)
+                if (j0 + u < c) M[(int64_t)(j0 + u) * c + col] = v[u];
+        }
+    }
     __syncthreads();
 }
 
@@ -169,9 +201,10 @@ __device__ void slot_store(const SlotT* slot, double* M, int c) {
 // per thread cannot hold a panel (few columns, so few threads), a panel is copied
 // straight to LDS instead.
 template <int BT, typename SlotT, int PF>
-__device__ void unfold_tile(SlotT* slot, v4d (&A)[Layout<BT>::RT], int c, int p0, double* lds, const double* store) {
+__device__ void unfold_tile(SlotT* slot, v4d (&A)[Layout<BT>::RT], int c, int p0, double* lds, const double* store,
+                            uint64_t perm) {
     constexpr int VLD = Layout<BT>::VLD, VP = Layout<BT>::VP, TSZ = Layout<BT>::TSZ, PS = Layout<BT>::PS;
-    const int wave = threadIdx.x >> 6;
+    const int wave = qf_group(perm);   // the column tile this wave owns
     const int np = (c + PW - 1) / PW;
     double* Vbuf = lds;
     double* Tbuf = lds + 2 * VP;
@@ -360,6 +393,27 @@ size_t qf_lds_bytes(int c, int ring) {
     return (size_t)(QF_X + ring * qf_entry<RingT>()) * sizeof(double) + (size_t)c * (c + 1) / 2 * sizeof(SlotT);
 }
 
+// Groups to waves: group k applies about k - 2 earlier groups as blocks, so the groups
+// go, heaviest first, to the SIMD (waves w with w mod 4 = s) with the least work so
+// far that still has a wave free.  Packed 4 bits per wave.
+uint64_t qf_perm(int np) {
+    int load[4] = {0, 0, 0, 0}, used[4] = {0, 0, 0, 0};
+    uint64_t perm = 0;
+    for (int g = np - 1; g >= 0; --g) {
+        int best = -1;
+        for (int s = 0; s < 4; ++s) {
+            const int w = s + 4 * used[s];
+            if (w >= np) continue;
+            if (best < 0 || load[s] < load[best]) best = s;
+        }
+        const int w = best + 4 * used[best];
+        perm |= (uint64_t)g << (4 * w);
+        load[best] += 3 + std::max(0, g - 2);
+        ++used[best];
+    }
+    return perm;
+}
+
 // The deepest ring of whole sets that fits beside the slot, up to three sets (three
 // tiles in flight, and fewer when a tile has few groups: LDS left free lets small
 // problems share a CU); 0 if not even one set fits.
@@ -495,8 +549,8 @@ __device__ __forceinline__ void mfma_to_quad(double (&a)[RPL]) {
 // of T (I - V T V^T, upper triangular) and T replaces G in Tb.  A wave's LDS
 // operations complete in order, so the reads of G precede the writes of T.
 __device__ __forceinline__ void q_panel_t(const double (&a)[RPL], int c, const double* taus_lds, double* Tb,
-                                          double (&trow)[PW]) {
-    const int wave = threadIdx.x >> 6, lane = fresh_lane();
+                                          double (&trow)[PW], uint64_t perm) {
+    const int wave = qf_group(perm), lane = fresh_lane();
     const int src = 4 * (lane & 15) + (lane >> 4);
     v4d gacc = {0, 0, 0, 0};
 #pragma unroll
@@ -540,8 +594,8 @@ __device__ __forceinline__ void q_panel_t(const double (&a)[RPL], int c, const d
 // Every product is a v_mfma_f64_16x16x4f64 chain: 16 + 4 + 16 per group.
 template <typename SlotT>
 __device__ __forceinline__ void q_block_apply(SlotT* slot, double (&a)[RPL], int c, int jb, int ng,
-                                              const double* __restrict__ panel) {
-    const int lane = fresh_lane(), jl = lane & 15, q = lane >> 4, wave = threadIdx.x >> 6;
+                                              const double* __restrict__ panel, uint64_t perm) {
+    const int lane = fresh_lane(), jl = lane & 15, q = lane >> 4, wave = qf_group(perm);
     const int colw = wave * PW + jl;
     const bool colok = colw < c;
     const double* V = panel;
@@ -613,8 +667,8 @@ __device__ __forceinline__ void q_block_apply(SlotT* slot, double (&a)[RPL], int
 template <typename SlotT, typename RingT>
 __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int j0, double* xring,
                                        double* tsring, double* taus_lds, unsigned* cnt, int ring, int t,
-                                       double* panels) {
-    const int wave = threadIdx.x >> 6;   // = col / PW
+                                       double* panels, uint64_t perm) {
+    const int wave = qf_group(perm);   // = col / PW
     const int np = (c + PW - 1) / PW;
     const int k0 = j0 / PW;
     unsigned* abort_flag = cnt + 2 * QF_RMAX;
@@ -673,7 +727,7 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
 #pragma unroll
                 for (int i = 0; i < RPL; ++i) a[i] *= sc_own;
                 double trow[PW];
-                q_panel_t(a, c, taus_lds, Tb, trow);
+                q_panel_t(a, c, taus_lds, Tb, trow, perm);
                 const int lane = fresh_lane();
                 // the panel (V, T) for the block appliers and the backward pass; the
                 // count that releases the block appliers follows once it is written
@@ -702,7 +756,7 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
                 // counts only grow: a later group's count in this slot also means
                 // this group's panel is stored
                 q_wait(ready, tag + (unsigned)ng, abort_flag);
-                q_block_apply(slot, a, c, jb, ng, panels + (int64_t)k * Layout<QT>::PS);
+                q_block_apply(slot, a, c, jb, ng, panels + (int64_t)k * Layout<QT>::PS, perm);
             }
             if (wave <= k + QF_SEQ && threadIdx.x % 64 == 0) q_arrive(done);
         }
@@ -712,7 +766,8 @@ __device__ __forceinline__ void q_fold(SlotT* slot, double (&a)[RPL], int c, int
 template <typename TE, typename SlotT>
 __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t rows_per_chain,
                                                        const TE* __restrict__ E, double* __restrict__ refl,
-                                                       double* __restrict__ Rs, int ring, int32_t* __restrict__ status) {
+                                                       double* __restrict__ Rs, int ring, int32_t* __restrict__ status,
+                                                       uint64_t perm) {
     extern __shared__ double lds[];
     double* xring = lds + QF_X;
     double* tsring = lds + QF_TS;
@@ -721,7 +776,7 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
     SlotT* slot = (SlotT*)(lds + QF_X + ring * qf_entry<double>());
     if (threadIdx.x <= 2 * QF_RMAX) cnt[threadIdx.x] = 0;   // counters and the abort flag; the slot set-up's barrier follows
     constexpr int PS = Layout<QT>::PS;
-    const int ch = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC;
+    const int ch = blockIdx.x, col = qf_group(perm) * PW + (threadIdx.x & 63) / LPC, g = threadIdx.x % LPC;
     const int np = (c + PW - 1) / PW;
     const int64_t r_begin = ch * rows_per_chain;
     const int64_t r_end = min(n, r_begin + rows_per_chain);
@@ -744,7 +799,7 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
             a[i] = (col < c && r < r_end) ? to_f64(nx[i]) : 0.0;
         }
         const int64_t gtile = (int64_t)ch * tiles_per_chain + tile;
-        q_fold<SlotT, double>(slot, a, c, 0, xring, tsring, taus_lds, cnt, ring, tile, refl + gtile * np * PS);
+        q_fold<SlotT, double>(slot, a, c, 0, xring, tsring, taus_lds, cnt, ring, tile, refl + gtile * np * PS, perm);
         if (q_aborted(cnt + 2 * QF_RMAX)) break;
     }
     __syncthreads();   // the folds have no barrier; slot_store reads every column's entries
@@ -758,7 +813,8 @@ __global__ void __launch_bounds__(1024) leaf_forward_q(int64_t n, int c, int64_t
 // tree + ((comb_off + i) * ntt + t) * np * PS + p * PS, as the backward pass reads them.
 template <typename SlotT>
 __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_t comb_off, double* __restrict__ Rs,
-                                                       double* __restrict__ tree, int ring, int32_t* __restrict__ status) {
+                                                       double* __restrict__ tree, int ring, int32_t* __restrict__ status,
+                                                       uint64_t perm) {
     extern __shared__ double lds[];
     double* xring = lds + QF_X;
     double* tsring = lds + QF_TS;
@@ -767,7 +823,7 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
     SlotT* slot = (SlotT*)(lds + QF_X + ring * qf_entry<double>());
     if (threadIdx.x <= 2 * QF_RMAX) cnt[threadIdx.x] = 0;   // counters and the abort flag; the slot set-up's barrier follows
     constexpr int PS = Layout<QT>::PS;
-    const int i = blockIdx.x, col = threadIdx.x / LPC, g = threadIdx.x % LPC, wave = threadIdx.x >> 6;
+    const int i = blockIdx.x, col = qf_group(perm) * PW + (threadIdx.x & 63) / LPC, g = threadIdx.x % LPC;
     const int np = (c + PW - 1) / PW, ntt = (c + QT - 1) / QT;
     const int a_idx = i * 2 * stride, b_idx = a_idx + stride;
     const double* Rb = Rs + (int64_t)b_idx * c * c;
@@ -782,7 +838,7 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
             a[q] = (col < c && row < c && col >= row) ? v : 0.0;
         }
         q_fold<SlotT, double>(slot, a, c, t * QT, xring, tsring, taus_lds, cnt, ring, t,
-               tree + ((comb_off + i) * ntt + t) * np * PS);
+               tree + ((comb_off + i) * ntt + t) * np * PS, perm);
         if (q_aborted(cnt + 2 * QF_RMAX)) break;
     }
     __syncthreads();   // the folds have no barrier; slot_store reads every column's entries
@@ -797,13 +853,13 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
 template <typename TQ, typename SlotT, int BT, int PF>
 __global__ void __launch_bounds__(1024) leaf_backward(int64_t n, int c, int64_t rows_per_chain,
                                                       const double* __restrict__ refl, const double* __restrict__ Qtop,
-                                                      TQ* __restrict__ Q) {
+                                                      TQ* __restrict__ Q, uint64_t perm) {
     extern __shared__ double lds[];
     constexpr int RT = Layout<BT>::RT, PS = Layout<BT>::PS;
     SlotT* slot = (SlotT*)(lds + Layout<BT>::HEAD);
-    const int ch = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6, jl = lane & 15, q = lane >> 4;
+    const int ch = blockIdx.x, lane = threadIdx.x & 63, jl = lane & 15, q = lane >> 4;
     const int np = (c + PW - 1) / PW;
-    const int col = wave * PW + jl;
+    const int col = qf_group(perm) * PW + jl;
     const int64_t r_begin = ch * rows_per_chain;
     if (r_begin >= n) return;   // uniform: whole workgroup leaves
     const int64_t r_end = min(n, r_begin + rows_per_chain);
@@ -816,7 +872,7 @@ __global__ void __launch_bounds__(1024) leaf_backward(int64_t n, int c, int64_t 
         v4d A[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) A[rt] = v4d{0, 0, 0, 0};
-        unfold_tile<BT, SlotT, PF>(slot, A, c, 0, lds, refl + gtile * np * PS);
+        unfold_tile<BT, SlotT, PF>(slot, A, c, 0, lds, refl + gtile * np * PS, perm);
         if (col < c) {
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
@@ -833,13 +889,13 @@ __global__ void __launch_bounds__(1024) leaf_backward(int64_t n, int c, int64_t 
 // applies the panels tree_forward_q stored for its tiles t (rows t * BT .. of R_b).
 template <typename SlotT, int BT, int PF>
 __global__ void __launch_bounds__(1024) tree_backward(int c, int stride, int64_t comb_off, double* __restrict__ Qtop,
-                                                      const double* __restrict__ tree) {
+                                                      const double* __restrict__ tree, uint64_t perm) {
     extern __shared__ double lds[];
     constexpr int RT = Layout<BT>::RT, PS = Layout<BT>::PS;
     SlotT* slot = (SlotT*)(lds + Layout<BT>::HEAD);
-    const int i = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6, jl = lane & 15, q = lane >> 4;
+    const int i = blockIdx.x, lane = threadIdx.x & 63, jl = lane & 15, q = lane >> 4;
     const int np = (c + PW - 1) / PW, ntt = (c + BT - 1) / BT;
-    const int col = wave * PW + jl;
+    const int col = qf_group(perm) * PW + jl;
     const int a_idx = i * 2 * stride, b_idx = a_idx + stride;
     double* Qb = Qtop + (int64_t)b_idx * c * c;
     slot_load(slot, Qtop + (int64_t)a_idx * c * c, c);
@@ -847,7 +903,7 @@ __global__ void __launch_bounds__(1024) tree_backward(int c, int stride, int64_t
         v4d A[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) A[rt] = v4d{0, 0, 0, 0};
-        unfold_tile<BT, SlotT, PF>(slot, A, c, (t * BT) / PW, lds, tree + ((comb_off + i) * ntt + t) * np * PS);
+        unfold_tile<BT, SlotT, PF>(slot, A, c, (t * BT) / PW, lds, tree + ((comb_off + i) * ntt + t) * np * PS, perm);
         if (col < c) {
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
@@ -914,18 +970,19 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out) {
     // float64 rings in both folds (>= 2 entries: the slot type was chosen for that)
     const int ring = qf_ring<SlotT, double>(c);
     const int tring = ring;
+    const uint64_t perm = qf_perm(np);
     if (ring < 2) return BFGS_ERR_ARG;
     const size_t leaf_lds = qf_lds_bytes<SlotT, double>(c, ring), tree_lds = leaf_lds;
     prof_begin(h, "tsqr_leaf_fwd");
     hipLaunchKernelGGL((leaf_forward_q<TE, SlotT>), dim3(nchains), dim3(LPC * 16 * np), leaf_lds,
-                       h->stream, n, c, rows_per_chain, E, refl, Rs, ring, h->status);
+                       h->stream, n, c, rows_per_chain, E, refl, Rs, ring, h->status, perm);
     prof_end(h);
     prof_begin(h, "tsqr_tree");
     int64_t off = 0;
     for (int stride = 1; stride < nchains; stride *= 2) {
         const int ncomb = nchains / (2 * stride);
         hipLaunchKernelGGL((tree_forward_q<SlotT>), dim3(ncomb), dim3(threads), tree_lds,
-                           h->stream, c, stride, off, Rs, tree, tring, h->status);
+                           h->stream, c, stride, off, Rs, tree, tring, h->status, perm);
         off += ncomb;
     }
     hipLaunchKernelGGL(set_identity_kernel, dim3(64), dim3(256), 0, h->stream, Qtop, c);
@@ -933,12 +990,12 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out) {
         const int ncomb = nchains / (2 * stride);
         off -= ncomb;
         hipLaunchKernelGGL((tree_backward<SlotT, BT, PF>), dim3(ncomb), dim3(threads), smem, h->stream, c, stride, off,
-                           Qtop, tree);
+                           Qtop, tree, perm);
     }
     prof_end(h);
     prof_begin(h, "tsqr_leaf_bwd");
     hipLaunchKernelGGL((leaf_backward<TQ, SlotT, BT, PF>), dim3(nchains), dim3(threads), smem, h->stream, n, c,
-                       rows_per_chain, refl, Qtop, Q);
+                       rows_per_chain, refl, Qtop, Q, perm);
     prof_end(h);
     *R_out = Rs;   // chain 0 holds the final R (row-major, upper triangular)
     return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
