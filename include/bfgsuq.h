@@ -374,7 +374,9 @@ int bfgs_profile_report(bfgs_t h, char* buf, int32_t len);
 /* bfgs_tsqr_shape — the configuration the tall-skinny QR of a c-column block
  *   takes (host outputs, either may be NULL): slot_f64 = 1 when the per-chain
  *   c x c triangle is kept in float64 in LDS (0: float32), ring = the number of
- *   16-reflector groups in flight per chain.  BFGS_ERR_ARG unless 1 <= c <= 256. */
+ *   LDS entries for 16-reflector groups per chain (even: ring / 2 row tiles of a
+ *   chain are folded at once, each in two entries of its own).  BFGS_ERR_ARG
+ *   unless 1 <= c <= 256.                                                     */
 int bfgs_tsqr_shape(int32_t c, int32_t* slot_f64, int32_t* ring);
 
 /* bfgs_sync — waits until all work enqueued on the handle's stream is done. */
