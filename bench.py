@@ -566,14 +566,20 @@ def bench_learned(args):
         op = P.GridOp(prob.nx, prob.nz, prob.nparam, prob.D, prob.sigma, wq.SMOOTH_HALF, prob.coupling)
         h0_sm, _, lam = P.precond_diag(prob.diag(), prob.nx, prob.nz, prob.nparam, 5.0, 20, 1.0)
 
-        def lib_iters(h0v):
-            Hm = P.Bfgs(prob.n, 200, h0v, "f32")
-            _, gn = P.minimize_quadratic(Hm, op, prob.b, 200, 1e-6)
+        def lib_iters(h0v, memory=0, damping=1.0, max_iter=200):
+            Hm = P.Bfgs(prob.n, memory if memory else max_iter, h0v, "f32")
+            _, gn = P.minimize_quadratic(Hm, op, prob.b, max_iter, 1e-6, memory=memory, damping=damping)
             Hm.close()
             return len(gn) - 1 if gn[-1] <= 1e-6 * gn[0] else None
 
         row.update({"lib_iters_gamma_I": lib_iters(None), "lib_iters_learned": lib_iters(h0.float()),
                     "lib_iters_smoothed_jacobi": lib_iters(h0_sm), "smoothed_jacobi_lambda": lam})
+        # the paper's L-BFGS (m = 5) against full-memory BFGS, with the learned B_0: with
+        # exact line searches on a quadratic the two coincide in exact arithmetic, so the
+        # comparison also runs with every step halved (an inexact line search)
+        row.update({"lib_iters_lbfgs5_learned": lib_iters(h0.float(), memory=5),
+                    "lib_iters_bfgs_learned_half_steps": lib_iters(h0.float(), damping=0.5, max_iter=400),
+                    "lib_iters_lbfgs5_learned_half_steps": lib_iters(h0.float(), memory=5, damping=0.5, max_iter=400)})
         op.close()
         if seed == 100 and not args.no_cpu_baseline:
             # rSVD of the learned-H0 history against the float64 oracle (same stored values)
@@ -603,7 +609,10 @@ def bench_learned(args):
         "mean_iters_gamma_I": round(float(np.mean(it_g)), 2),
         "library_driver_mean_iters": {key: round(float(np.mean([e[key] for e in evals if e[key] is not None])), 2)
                                       for key in ("lib_iters_gamma_I", "lib_iters_learned",
-                                                  "lib_iters_smoothed_jacobi")},
+                                                  "lib_iters_smoothed_jacobi", "lib_iters_lbfgs5_learned",
+                                                  "lib_iters_bfgs_learned_half_steps",
+                                                  "lib_iters_lbfgs5_learned_half_steps")
+                                      if any(e[key] is not None for e in evals)},
         "iteration_ratio_gamma_over_learned": round(float(np.mean(it_g)) / float(np.mean(it_l)), 3),
         "training_seconds": round(t_train, 2), "data_seconds": round(t_data, 2),
         "loss_first_last": [losses[0][1], losses[-1][1]], "evaluations": evals,

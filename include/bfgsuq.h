@@ -120,6 +120,16 @@ int bfgs_destroy(bfgs_t h);
  * s and y may be reused once the call has returned.                           */
 int bfgs_push_pair(bfgs_t h, const void* s, const void* y, bfgs_dtype in_dtype);
 
+/* bfgs_pop_oldest — forgets the oldest stored pair (s_0, y_0), the step of the
+ * limited-memory form (L-BFGS) that the paper compares with full-memory BFGS (the
+ * 2-D Marmousi section): the remaining pairs keep their order and B_0 stays as it is
+ * (gamma, if it came from the first pair, stays frozen).  The compact form's k x k
+ * matrices lose their first row and column; R's inverse is the trailing block of the
+ * old one.  Enqueued on the handle's stream; any rSVD result is invalidated.
+ * BFGS_ERR_STATE with no pair or for a streamed handle; BFGS_ERR_ARG for bfloat16
+ * storage (its matrix-core copies group the pairs by 16).                        */
+int bfgs_pop_oldest(bfgs_t h);
+
 /* bfgs_num_pairs — number of accepted pairs k (host). */
 int bfgs_num_pairs(bfgs_t h, int32_t* k_out);
 
@@ -296,7 +306,16 @@ int bfgs_batch_destroy(bfgs_batch_t b);
  *   when h is full.  m (device, n doubles) receives the iterate; gnorm (host, max_iter
  *   + 1 doubles, or NULL) |g_0|, |g_1|, ...; iters (host) the iterations taken.
  *   Dot products are fixed-order reductions: runs are deterministic.  Synchronizes
- *   once per iteration (the pair's curvature check, the gradient norm).          */
+ *   once per iteration (the pair's curvature check, the gradient norm).
+ * bfgs_minimize_quadratic_ex — the same with two options of the paper's comparison of
+ *   L-BFGS with full-memory BFGS (the 2-D Marmousi section): memory > 0 keeps only the
+ *   last `memory` pairs (1 <= memory <= k_max; the oldest is dropped by
+ *   bfgs_pop_oldest before each push once the window is full, B_0 stays as fixed), 0
+ *   keeps them all (bfgs_minimize_quadratic); each step is `damping` times the exact
+ *   line minimiser (0 < damping <= 1; 1 = the exact line search).  With exact line
+ *   searches on a quadratic both forms take the same steps in exact arithmetic.
+ *   BFGS_ERR_ARG for a memory or damping out of range, BFGS_ERR_STATE for a
+ *   streamed handle with memory > 0.                                             */
 typedef struct bfgsuq_gridop* bfgs_gridop_t;
 int bfgs_gridop_create(int64_t nx, int64_t nz, int32_t nparam, const double* D, double sigma, int32_t half,
                        double coupling, void* stream, bfgs_gridop_t* out);
@@ -304,6 +323,8 @@ int bfgs_gridop_apply(bfgs_gridop_t op, const double* x, int32_t ncols, double* 
 int bfgs_gridop_destroy(bfgs_gridop_t op);
 int bfgs_minimize_quadratic(bfgs_t h, bfgs_gridop_t op, const double* b, int32_t max_iter, double rel_tol, double* m,
                             double* gnorm, int32_t* iters);
+int bfgs_minimize_quadratic_ex(bfgs_t h, bfgs_gridop_t op, const double* b, int32_t max_iter, double rel_tol,
+                               int32_t memory, double damping, double* m, double* gnorm, int32_t* iters);
 
 /* ---------------------------------------------------------------------------
  * Smoothed, damped diagonal B_0 (eq. (4)): B_0 = (H_0 + lambda I)^-1 from a

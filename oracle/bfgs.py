@@ -11,6 +11,10 @@ The step length minimises the quadratic exactly along p (times `damping`, which
 keeps the Wolfe conditions for damping in (0, 1] and leaves S^T Y far from
 diagonal).  s = alpha p, y = A s, g <- g + y.
 
+`memory` > 0 is the limited-memory form the paper compares with full-memory BFGS
+(L-BFGS, the 2-D Marmousi section): the recursion runs over the last `memory`
+pairs only, with the same fixed B_0.
+
 Used only to pin the input generator (its conjugate-gradient pairs are BFGS
 pairs) and the oracle itself (quadratic termination, hereditary secant
 conditions).  Never feeds the GPU library.
@@ -22,7 +26,7 @@ import numpy as np
 from .recursion import apply_hk
 
 
-def bfgs_quadratic(A, b, k: int, h0=None, damping: float = 1.0):
+def bfgs_quadratic(A, b, k: int, h0=None, damping: float = 1.0, memory: int = 0):
     A = np.asarray(A, np.float64)
     b = np.asarray(b, np.float64)
     n = b.shape[0]
@@ -35,7 +39,8 @@ def bfgs_quadratic(A, b, k: int, h0=None, damping: float = 1.0):
         if not S and h is None:
             p = -g
         else:
-            p = -apply_hk(h, np.array(S), np.array(Y), g)
+            keep = slice(-memory, None) if memory > 0 else slice(None)
+            p = -apply_hk(h, np.array(S[keep]), np.array(Y[keep]), g)
         Ap = A @ p
         alpha = damping * (-(g @ p) / (p @ Ap))
         s = alpha * p

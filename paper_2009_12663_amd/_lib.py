@@ -32,7 +32,8 @@ MAX_COLS = 256
 MAX_PAIRS = 1024
 
 EXPORTS = [
-    "bfgs_create", "bfgs_create_streamed", "bfgs_destroy", "bfgs_push_pair", "bfgs_num_pairs", "bfgs_apply_Hinv",
+    "bfgs_create", "bfgs_create_streamed", "bfgs_destroy", "bfgs_push_pair", "bfgs_pop_oldest", "bfgs_num_pairs",
+    "bfgs_apply_Hinv",
     "bfgs_apply_Hinv_noalloc",
     "bfgs_apply_Hdiff", "bfgs_generate_probes", "bfgs_rsvd", "bfgs_rsvd_ex", "bfgs_posterior_diag",
     "bfgs_get_pair", "bfgs_get_h0", "bfgs_get_status", "bfgs_status_string",
@@ -40,6 +41,7 @@ EXPORTS = [
     "bfgs_batch_create", "bfgs_batch_handle", "bfgs_batch_push_pairs", "bfgs_batch_apply_Hinv", "bfgs_batch_rsvd",
     "bfgs_batch_autotune", "bfgs_batch_graph_build", "bfgs_batch_graph_launch", "bfgs_batch_destroy",
     "bfgs_precond_diag", "bfgs_gridop_create", "bfgs_gridop_apply", "bfgs_gridop_destroy", "bfgs_minimize_quadratic",
+    "bfgs_minimize_quadratic_ex",
     "bfgs_mlp_create", "bfgs_mlp_destroy", "bfgs_mlp_set_params", "bfgs_mlp_get_params", "bfgs_mlp_features",
     "bfgs_mlp_forward", "bfgs_mlp_grad", "bfgs_mlp_train_step",
 ]
@@ -102,6 +104,9 @@ def load(path: str = LIB_PATH):
         "bfgs_gridop_destroy": [vp],
         "bfgs_minimize_quadratic": [vp, vp, vp, i32, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(i32)],
+        "bfgs_minimize_quadratic_ex": [vp, vp, vp, i32, ctypes.c_double, i32, ctypes.c_double, vp,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)],
+        "bfgs_pop_oldest": [vp],
         "bfgs_mlp_create": [vp, ctypes.POINTER(vp)],
         "bfgs_mlp_destroy": [vp],
         "bfgs_mlp_set_params": [vp, vp],
@@ -234,6 +239,12 @@ class Bfgs:
         self._enter()
         _check(self.L.bfgs_push_pair(self.h, _ptr(s), _ptr(y), F64 if dt == torch.float64 else F32),
                "bfgs_push_pair")
+        self._leave()
+
+    def pop_oldest(self) -> None:
+        """bfgs_pop_oldest: forget the oldest stored pair (the limited-memory form)."""
+        self._enter()
+        _check(self.L.bfgs_pop_oldest(self.h), "bfgs_pop_oldest")
         self._leave()
 
     @property
@@ -412,15 +423,22 @@ class GridOp:
             pass
 
 
-def minimize_quadratic(H: "Bfgs", op: GridOp, b: torch.Tensor, max_iter: int, rel_tol: float):
-    """bfgs_minimize_quadratic: returns (m, gnorms) with gnorms |g_0| .. |g_iters|."""
+def minimize_quadratic(H: "Bfgs", op: GridOp, b: torch.Tensor, max_iter: int, rel_tol: float, memory: int = 0,
+                       damping: float = 1.0):
+    """bfgs_minimize_quadratic (memory 0, damping 1) or bfgs_minimize_quadratic_ex:
+    returns (m, gnorms) with gnorms |g_0| .. |g_iters|."""
     L = load()
     b = b.to(torch.float64).contiguous()
     m = torch.empty_like(b)
     gn = (ctypes.c_double * (max_iter + 1))()
     it = ctypes.c_int32()
-    _check(L.bfgs_minimize_quadratic(H.h, op.op, _ptr(b), int(max_iter), float(rel_tol), _ptr(m), gn,
-                                     ctypes.byref(it)), "bfgs_minimize_quadratic")
+    if memory == 0 and damping == 1.0:
+        _check(L.bfgs_minimize_quadratic(H.h, op.op, _ptr(b), int(max_iter), float(rel_tol), _ptr(m), gn,
+                                         ctypes.byref(it)), "bfgs_minimize_quadratic")
+    else:
+        _check(L.bfgs_minimize_quadratic_ex(H.h, op.op, _ptr(b), int(max_iter), float(rel_tol), int(memory),
+                                            float(damping), _ptr(m), gn, ctypes.byref(it)),
+               "bfgs_minimize_quadratic_ex")
     return m, [gn[i] for i in range(it.value + 1)]
 
 

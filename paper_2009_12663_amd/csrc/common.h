@@ -290,3 +290,5 @@ int batch_apply_persistent(bfgsuq_ctx* const* hs, int nprob, const void* const* 
                            void* const* out, hipStream_t st, PersistSlot* slot, bool upload, int wg_per_cu);
 int push_enqueue(bfgsuq_ctx* h, const void* s, const void* y, bfgs_dtype in_dtype);
 int push_finish(bfgsuq_ctx* h);
+// Forget the oldest pair (float32/float64 storage, device-resident history).
+int pop_oldest(bfgsuq_ctx* h);

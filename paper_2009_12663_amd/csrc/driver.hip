@@ -110,8 +110,8 @@ __global__ void dot_final(int nb, const double* __restrict__ part, double* __res
 // m += s, g += y.
 __global__ void line_step(int64_t n, const double* __restrict__ sc, const double* __restrict__ p,
                           const double* __restrict__ Ap, double* __restrict__ s, double* __restrict__ y,
-                          double* __restrict__ m, double* __restrict__ g) {
-    const double alpha = -sc[0] / sc[1];
+                          double* __restrict__ m, double* __restrict__ g, double damping) {
+    const double alpha = damping * (-sc[0] / sc[1]);
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const double se = alpha * p[e], ye = alpha * Ap[e];
         s[e] = se;
@@ -209,7 +209,14 @@ int bfgs_gridop_apply(bfgs_gridop_t op, const double* x, int32_t ncols, double* 
 
 int bfgs_minimize_quadratic(bfgs_t h, bfgs_gridop_t op, const double* b, int32_t max_iter, double rel_tol, double* m,
                             double* gnorm, int32_t* iters) {
+    return bfgs_minimize_quadratic_ex(h, op, b, max_iter, rel_tol, 0, 1.0, m, gnorm, iters);
+}
+
+int bfgs_minimize_quadratic_ex(bfgs_t h, bfgs_gridop_t op, const double* b, int32_t max_iter, double rel_tol,
+                               int32_t memory, double damping, double* m, double* gnorm, int32_t* iters) {
     if (!h || !op || !b || !m || !iters || max_iter < 0 || !(rel_tol >= 0.0) || op->n != h->n) return BFGS_ERR_ARG;
+    if (memory < 0 || memory > h->kmax || !(damping > 0.0 && damping <= 1.0)) return BFGS_ERR_ARG;
+    if (memory > 0 && h->streamed) return BFGS_ERR_STATE;   // the window moves in device memory
     if (h->storage == BFGS_BF16) return BFGS_ERR_ARG;   // a bfloat16 gradient cannot reach small tolerances
     if (h->k != 0) return BFGS_ERR_STATE;                // the run starts from m = 0 with an empty history
     if (op->stream != h->stream) return BFGS_ERR_ARG;
@@ -245,7 +252,7 @@ int bfgs_minimize_quadratic(bfgs_t h, bfgs_gridop_t op, const double* b, int32_t
     if (rc == BFGS_OK) rc = gg(&gn0);
     if (rc == BFGS_OK && gnorm) gnorm[0] = gn0;
     int it = 0;
-    while (rc == BFGS_OK && it < max_iter && h->k < h->kmax) {
+    while (rc == BFGS_OK && it < max_iter && (memory > 0 || h->k < h->kmax)) {
         if (h->k == 0 && h->gamma_mode) {
             hipLaunchKernelGGL(negate_to, dim3(blocks_for(n)), dim3(256), 0, st, n, g, p);   // gamma unknown: p = -g
         } else if (f32) {
@@ -259,11 +266,13 @@ int bfgs_minimize_quadratic(bfgs_t h, bfgs_gridop_t op, const double* b, int32_t
         if ((rc = gridop_apply_impl(op, p, Ap, st)) != BFGS_OK) break;
         launch_dot(n, g, p, part, sc + 0, st);
         launch_dot(n, p, Ap, part, sc + 1, st);
-        hipLaunchKernelGGL(line_step, dim3(blocks_for(n)), dim3(256), 0, st, n, sc, p, Ap, s, y, m, g);
+        hipLaunchKernelGGL(line_step, dim3(blocks_for(n)), dim3(256), 0, st, n, sc, p, Ap, s, y, m, g, damping);
         if (hipGetLastError() != hipSuccess) {
             rc = BFGS_ERR_HIP;
             break;
         }
+        // the limited-memory form keeps the last `memory` pairs
+        if (memory > 0 && h->k == memory && (rc = pop_oldest(h)) != BFGS_OK) break;
         if ((rc = bfgs_push_pair(h, s, y, BFGS_F64)) != BFGS_OK) break;
         ++it;
         double gn = 0.0;

@@ -359,7 +359,65 @@ int push_finish(bfgsuq_ctx* h) {
     return BFGS_OK;
 }
 
+// Forgetting the oldest pair (the limited-memory form): column j of S and Y moves to
+// column j - 1 for j = 1 .. k-1.  A thread moves one row of both, in increasing j, so
+// every value is read before its slot is overwritten.
+template <typename T>
+__global__ void shift_pairs_kernel(int64_t n, int64_t ld, int k, T* __restrict__ S, T* __restrict__ Y) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        for (int j = 1; j < k; ++j) {
+            S[(int64_t)(j - 1) * ld + r] = S[(int64_t)j * ld + r];
+            Y[(int64_t)(j - 1) * ld + r] = Y[(int64_t)j * ld + r];
+        }
+    }
+}
+
+// The small matrices lose their first row and column: entry (i + 1, j + 1) moves to
+// (i, j).  One thread per diagonal d = j - i walks it in increasing i, so every entry
+// is read before it is overwritten.  The inverse of R's trailing block is the trailing
+// block of R^-1 (R is upper triangular), so R^-1 and its transpose shift like R.
+__global__ void shift_small_kernel(int k, int kmax, double* __restrict__ Rm, double* __restrict__ YHY,
+                                   double* __restrict__ Rinv, double* __restrict__ RinvT) {
+    const int d = (int)(blockIdx.x * blockDim.x + threadIdx.x) - (k - 2);   // -(k-2) .. k-2
+    if (d > k - 2) return;
+    for (int i = d < 0 ? -d : 0; i < k - 1 && i + d < k - 1; ++i) {
+        const int64_t to = (int64_t)(i + d) * kmax + i, from = (int64_t)(i + d + 1) * kmax + (i + 1);
+        Rm[to] = Rm[from];
+        YHY[to] = YHY[from];
+        Rinv[to] = Rinv[from];
+        RinvT[to] = RinvT[from];
+    }
+}
+
+int pop_oldest(bfgsuq_ctx* h) {
+    if (h->storage == BFGS_BF16) return BFGS_ERR_ARG;   // its matrix-core layouts group the pairs by 16
+    if (h->streamed) return BFGS_ERR_STATE;
+    if (h->k < 1) return BFGS_ERR_STATE;
+    const int k = h->k;
+    if (k > 1) {
+        if (h->storage == BFGS_F64)
+            hipLaunchKernelGGL(shift_pairs_kernel<double>, dim3(grid_for(h->n)), dim3(256), 0, h->stream, h->n, h->ld,
+                               k, (double*)h->S, (double*)h->Y);
+        else
+            hipLaunchKernelGGL(shift_pairs_kernel<float>, dim3(grid_for(h->n)), dim3(256), 0, h->stream, h->n, h->ld,
+                               k, (float*)h->S, (float*)h->Y);
+        BFGS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(shift_small_kernel, dim3((2 * k - 3 + 63) / 64), dim3(64), 0, h->stream, k, h->kmax, h->Rm,
+                           h->YHY, h->Rinv, h->RinvT);
+        BFGS_HIP(hipGetLastError());
+    }
+    h->k = k - 1;
+    ++h->gen;
+    h->have_rsvd = false;
+    return BFGS_OK;
+}
+
 extern "C" {
+
+int bfgs_pop_oldest(bfgs_t h) {
+    if (!h) return BFGS_ERR_ARG;
+    return pop_oldest(h);
+}
 
 const char* bfgs_status_string(int code) {
     switch (code) {

@@ -168,3 +168,55 @@ def test_zero_pairs_is_b0():
     h0 = np.array([1.0, 2.0, 3.0])
     V = np.arange(6.0).reshape(2, 3)
     np.testing.assert_array_equal(recursion.apply_hk(h0, np.zeros((0, 3)), np.zeros((0, 3)), V), V * h0)
+
+
+# --- the limited-memory form (L-BFGS with a fixed B_0) ----------------------------------
+def test_limited_memory_one_pair_is_a_single_update():
+    """memory = 1: every direction is -B g with B the single eq. (3) update of B_0 by
+    the last pair, written out here as a dense matrix, (I - r s y^T) B_0 (I - r y s^T)
+    + r s s^T.  Damped steps keep the iterates away from full BFGS."""
+    n, k = 9, 6
+    A = spd(n, 30.0, 5)
+    b = np.random.default_rng(6).standard_normal(n)
+    h0 = np.linspace(0.5, 2.0, n)
+    S, Y, _, _, _ = bfgs.bfgs_quadratic(A, b, k, h0=h0, damping=0.6, memory=1)
+    g = -b.copy()
+    for i in range(k):
+        if i == 0:
+            B = np.diag(h0)
+        else:
+            s, y = S[i - 1], Y[i - 1]
+            r = 1.0 / (y @ s)
+            I = np.eye(n)
+            B = (I - r * np.outer(s, y)) @ np.diag(h0) @ (I - r * np.outer(y, s)) + r * np.outer(s, s)
+        p = -B @ g
+        alpha = 0.6 * (-(g @ p) / (p @ A @ p))
+        np.testing.assert_allclose(S[i], alpha * p, rtol=1e-12, atol=1e-14)
+        g = g + A @ S[i]
+    S_full, _, _, _, _ = bfgs.bfgs_quadratic(A, b, k, h0=h0, damping=0.6)
+    assert np.abs(S_full[2:] - S[2:]).max() > 1e-3 * np.abs(S).max()   # the memory matters here
+
+
+@pytest.mark.parametrize("memory", [1, 3])
+def test_limited_memory_exact_line_search_is_full_bfgs(memory):
+    """With exact line searches on a quadratic and a fixed B_0, limited-memory BFGS
+    takes the steps of full-memory BFGS (both are conjugate gradients preconditioned by
+    B_0: the directions depend only on the last pair once the earlier ones are
+    conjugate), so the two agree to rounding over a few iterations."""
+    n, k = 12, 6
+    A = spd(n, 15.0, 8)
+    b = np.random.default_rng(9).standard_normal(n)
+    h0 = np.linspace(0.7, 1.3, n)
+    S_l, _, _, m_l, _ = bfgs.bfgs_quadratic(A, b, k, h0=h0, memory=memory)
+    S_f, _, _, m_f, _ = bfgs.bfgs_quadratic(A, b, k, h0=h0)
+    assert np.abs(S_l - S_f).max() <= 1e-10 * np.abs(S_f).max()
+    assert np.abs(m_l - m_f).max() <= 1e-10 * np.abs(m_f).max()
+
+
+def test_limited_memory_covering_all_pairs_is_full_bfgs():
+    n, k = 8, 5
+    A = spd(n, 10.0, 2)
+    b = np.random.default_rng(3).standard_normal(n)
+    S_l, _, _, _, _ = bfgs.bfgs_quadratic(A, b, k, damping=0.5, memory=k)
+    S_f, _, _, _, _ = bfgs.bfgs_quadratic(A, b, k, damping=0.5)
+    assert np.array_equal(S_l, S_f)
