@@ -229,9 +229,15 @@ int apply_diff_float_block(bfgsuq_ctx* h, const void* V, bool v64, int32_t ncols
 // rSVD variants (flags of bfgs_rsvd_ex)
 int rsvd_run(bfgsuq_ctx* h, int32_t rank, int32_t oversample, uint64_t seed, void* U, double* Sigma,
              uint32_t flags = 0);
-// Blocked Householder TSQR E = Q R (E, Q column-major n x c; *R_out: row-major c x c in
-// the handle's workspace).  tsqr.hip.
-int tsqr_run(bfgsuq_ctx* h, int c, const float* E, float* Q, double** R_out);
+// Blocked Householder TSQR E = Q R (E column-major n x c; *R_out: row-major c x c in
+// the handle's workspace).  tsqr.hip.  E's rows are split into chains of
+// tsqr_chain_rows(h) rows (a multiple of QR_TILE; *nchains of them, the last ones
+// possibly short or empty).  Q is column-major n x c, or with q_blocked chain-blocked:
+// row r of column j at (r / B) B c + j B + r % B for B = tsqr_chain_rows(h), so each
+// chain's rows of Q are one contiguous block (ceil(n / B) B c elements in all).
+constexpr int QR_TILE = 64;
+int64_t tsqr_chain_rows(const bfgsuq_ctx* h, int* nchains = nullptr);
+int tsqr_run(bfgsuq_ctx* h, int c, const float* E, float* Q, double** R_out, bool q_blocked = false);
 int tsqr_run(bfgsuq_ctx* h, int c, const double* E, float* Q, double** R_out);
 int tsqr_run(bfgsuq_ctx* h, int c, const double* E, double* Q, double** R_out);
 // Whether the TSQR of a c-column block keeps its per-chain triangle in float64.
@@ -243,13 +249,15 @@ size_t tridiag_dc_workspace(int c);
 // bfloat16-storage forms of the rSVD's tall products (rsvd_bf16.hip): Q^T X chunk
 // partials (float64, the layout qtx_mfma writes), and the basis U = Q Us[:, :rank]
 // with the posterior diagonal dout = h0 + sum_j lam_j U_j^2; ush holds
-// basis_bf16_workspace(c, rank) bytes of split Us.
+// basis_bf16_workspace(c, rank) bytes of split Us.  q_block: 0 for a column-major Q,
+// else the block rows B of a chain-blocked Q (tsqr_run); for qtx the chunks are then
+// the blocks (rows_per_chunk == q_block).
 int qtx_bf16_launch(hipStream_t st, int64_t n, int c, const float* Q, const bf16_t* X, double* part, int nchunks,
-                    int64_t rows_per_chunk);
+                    int64_t rows_per_chunk, int64_t q_block = 0);
 size_t basis_bf16_workspace(int c, int rank);
 int basis_bf16_launch(hipStream_t st, int64_t n, int c, int rank, const float* Q, const double* Us, uint16_t* ush,
                       const double* lam, const float* h0, float* U, float* dout, int32_t* status,
-                      bool whitened = false);
+                      bool whitened = false, int64_t q_block = 0);
 int tridiag_dc(hipStream_t st, int c, const double* d, const double* e, const double* Qh, double* work, double** w_out,
                double* Z, int32_t* status);
 int probes_run(bfgsuq_ctx* h, uint64_t seed, int32_t ncols, void* X);

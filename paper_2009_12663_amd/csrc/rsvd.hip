@@ -1099,17 +1099,27 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     using TE = typename std::conditional<e64, double, TO>::type;
     using TQ = TE;
     if ((rc = ensure_ws(h->E, (size_t)n * c * sizeof(TE))) != BFGS_OK) return rc;
-    if ((rc = ensure_ws(h->Q, (size_t)n * c * sizeof(TQ))) != BFGS_OK) return rc;
+    // bfloat16 storage: Q chain-blocked (each TSQR chain's rows one contiguous block),
+    // which the projection and the basis read without a translation miss per column;
+    // the whitened and two-pass forms pass Q to column-major kernels and keep it so
+    constexpr bool bf16_path = std::is_same<TS, bf16_t>::value;
+    const bool qblk = bf16_path && !precond && !two_pass;
+    const int64_t qb_rows = qblk ? tsqr_chain_rows(h) : 0;
+    const int64_t q_rows = qblk ? ceil_div(n, qb_rows) * qb_rows : n;
+    if ((rc = ensure_ws(h->Q, (size_t)q_rows * c * sizeof(TQ))) != BFGS_OK) return rc;
     // small: part(nchunks*c*c) + T, M, B, Omega, Z (5 c*c) + d, e, taus, rot, lam (5 c) + piv
     // Q^T X row chunks: about one per CU, each chunk a multiple of the staging depth
     int nchunks = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 63) / 64));
     const int64_t rows_per_chunk = round_up((n + nchunks - 1) / nchunks, MT_K);
     nchunks = (int)((n + rows_per_chunk - 1) / rows_per_chunk);
+    // a blocked Q is projected one chain block per chunk
+    const int qx_chunks = qblk ? (int)ceil_div(n, qb_rows) : nchunks;
+    const int part_chunks = std::max(nchunks, qx_chunks);
     const size_t cc = (size_t)c * c;
-    if ((rc = ensure_ws(h->small, ((size_t)nchunks * cc + 14 * cc + 6 * (size_t)c) * 8 + (size_t)c * 4)) != BFGS_OK)
+    if ((rc = ensure_ws(h->small, ((size_t)part_chunks * cc + 14 * cc + 6 * (size_t)c) * 8 + (size_t)c * 4)) !=
+        BFGS_OK)
         return rc;
     // tridiagonal eigensolver workspace, then Z = Q_H Y (c x c)
-    constexpr bool bf16_path = std::is_same<TS, bf16_t>::value;
     const size_t ush_bytes = bf16_path ? basis_bf16_workspace(c, rank) : 0;
     const size_t ush_off = round_up((int64_t)(tridiag_dc_workspace(c) + cc * sizeof(double)), 256);
     if ((rc = ensure_ws(h->lam, ush_off + ush_bytes)) != BFGS_OK) return rc;
@@ -1117,7 +1127,7 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     double* Zt = dcwork + tridiag_dc_workspace(c) / sizeof(double);
     uint16_t* ush = (uint16_t*)((char*)h->lam.ptr + ush_off);   // 16-byte fragment loads
     double* part = (double*)h->small.ptr;
-    double* Tm = part + (size_t)nchunks * cc;
+    double* Tm = part + (size_t)part_chunks * cc;
     double* Bm = Tm + cc;
     double* Om = Bm + cc;
     double* Zm = Om + cc;
@@ -1163,7 +1173,11 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
             R = Fm;
         }
     } else {
-        if ((rc = tsqr_run(h, c, E, Q, &R)) != BFGS_OK) return rc;
+        if constexpr (bf16_path) {
+            if ((rc = tsqr_run(h, c, E, Q, &R, qblk)) != BFGS_OK) return rc;
+        } else {
+            if ((rc = tsqr_run(h, c, E, Q, &R)) != BFGS_OK) return rc;
+        }
     }
     // the E / Q buffer that Q does not occupy is free now
     TE* Efree = (void*)Q == h->E.ptr ? (TE*)h->Q.ptr : E;
@@ -1196,14 +1210,16 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
             Qp = Qs;
         }
         if constexpr (bf16_path) {
-            if ((rc = qtx_bf16_launch(h->stream, n, c, Qp, X, part, nchunks, rows_per_chunk)) != BFGS_OK) return rc;
+            if ((rc = qtx_bf16_launch(h->stream, n, c, Qp, X, part, qx_chunks, qblk ? qb_rows : rows_per_chunk,
+                                      qb_rows)) != BFGS_OK)
+                return rc;
         } else {
             const int nblk = ceil_div(c, MT_TILE);
             hipLaunchKernelGGL((qtx_mfma<TQ, TS>), dim3(nchunks, nblk, nblk), dim3(256), 0, h->stream, n, c, c, Qp, X,
                                part, rows_per_chunk);
         }
         hipLaunchKernelGGL(sum_chunks, dim3(ceil_div((int64_t)cc, 256)), dim3(256), 0, h->stream, (int64_t)cc,
-                           nchunks, part, Tm);
+                           bf16_path ? qx_chunks : nchunks, part, Tm);
     }
     if (!two_pass) {
         ProfScope ps(h, "omega_lu");
@@ -1240,7 +1256,7 @@ int rsvd_impl(bfgsuq_ctx* h, int rank, int oversample, uint64_t seed, TO* U, dou
     if constexpr (bf16_path) {
         // the posterior diagonal is formed in the same pass
         if ((rc = basis_bf16_launch(h->stream, n, c, rank, Q, Usm, ush, lam, (const float*)h->h0, U, dout,
-                                    h->status, precond)) != BFGS_OK)
+                                    h->status, precond, qb_rows)) != BFGS_OK)
             return rc;
     } else {
         hipLaunchKernelGGL((basis_mfma<TQ, TO>), dim3((unsigned)ceil_div(n, (int64_t)MT_TILE), ceil_div(rank, MT_TILE)),

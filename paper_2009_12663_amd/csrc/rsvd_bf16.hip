@@ -73,6 +73,9 @@ __device__ __forceinline__ void split8x3(const float (&q)[8], bf16x8& hi, bf16x8
 // ---------------------------------------------------------------------------
 // T = Q^T X.  Workgroup (chunk, jg) = one row chunk and the QX_NJ column tiles
 // jg * QX_NJ .. of X; wave ti owns the 32-row block ti of T (columns 32 ti.. of Q).
+// Q is column-major or chain-blocked (then a chunk is one block, its columns a few KB
+// apart: the 32 columns a wave reads sit in one or two translation pages instead of
+// 32, which cut the kernel from 2.3 to 1.6 ms at n = 1.785M, c = 220).
 // The jgroups workgroups of a chunk sit on one XCD (workgroup g runs on XCD
 // g % 8), so the chunk's Q rows come from HBM once.  Each 16-row step loads the
 // lane's 8 rows of one Q column (32 bytes) and of QX_NJ X columns (16 bytes each)
@@ -90,23 +93,23 @@ struct QxStep {
 
 // Loads are unconditional, from addresses clamped into the arrays, so no branch
 // separates a prefetch slot from its use and each step waits only for its own loads.
+// qcol: the lane's column of Q (row r at qcol[r]).
 template <bool VEC>
-__device__ __forceinline__ void qx_load(QxStep& s, int64_t n, int c, const float* __restrict__ Q,
+__device__ __forceinline__ void qx_load(QxStep& s, int64_t n, int c, const float* __restrict__ qcol,
                                         const bf16_t* __restrict__ X, int64_t row, int64_t rb, int64_t re, int icol,
                                         int jt0, int m) {
     // VEC: n % 8 == 0 and chunks end at multiples of 8, so a lane's 8 rows are all in
     // or all out, and re - 8 >= rb
     const int64_t rowc = min(row, re - 8 >= rb ? re - 8 : rb);
     s.qv = row < re && icol < c;
-    const int ic = min(icol, c - 1);
     if (VEC) {
-        const float4* p = (const float4*)(Q + (int64_t)ic * n + rowc);
+        const float4* p = (const float4*)(qcol + rowc);
         const float4 a0 = p[0], a1 = p[1];
         s.q[0] = a0.x; s.q[1] = a0.y; s.q[2] = a0.z; s.q[3] = a0.w;
         s.q[4] = a1.x; s.q[5] = a1.y; s.q[6] = a1.z; s.q[7] = a1.w;
     } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) s.q[e] = Q[(int64_t)ic * n + min(row + e, n - 1)];
+        for (int e = 0; e < 8; ++e) s.q[e] = qcol[min(row + e, re - 1)];
     }
 #pragma unroll
     for (int t = 0; t < QX_NJ; ++t) {
@@ -146,7 +149,7 @@ __device__ __forceinline__ void qx_mma(const QxStep& s, floatx16 (&acc)[QX_NJ], 
 template <bool VEC>
 __global__ void __launch_bounds__(512, 2) qtx_bf16(int64_t n, int c, const float* __restrict__ Q,
                                                    const bf16_t* __restrict__ X, double* __restrict__ part,
-                                                   int nchunks, int64_t rows_per_chunk) {
+                                                   int nchunks, int64_t rows_per_chunk, int qblk) {
     const int lane = threadIdx.x & 63, half = lane >> 5, m = lane & 31;
     const int ntj = (c + 31) / 32, jgroups = (ntj + QX_NJ - 1) / QX_NJ;
     const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
@@ -156,6 +159,10 @@ __global__ void __launch_bounds__(512, 2) qtx_bf16(int64_t n, int c, const float
     const int icol = ti * 32 + m;
     const int64_t rb = (int64_t)chunk * rows_per_chunk;
     const int64_t re = min(n, rb + rows_per_chunk);
+    // row r of column j at Qc[j * ldq + r]; out-of-range columns read the last one
+    const float* Qc = qblk ? Q + (int64_t)chunk * rows_per_chunk * c - rb : Q;
+    const int64_t ldq = qblk ? rows_per_chunk : n;
+    const float* qcol = Qc + (int64_t)min(icol, c - 1) * ldq;
     floatx16 acc[QX_NJ];
     double accd[QX_NJ][16];
 #pragma unroll
@@ -165,16 +172,19 @@ __global__ void __launch_bounds__(512, 2) qtx_bf16(int64_t n, int c, const float
             acc[t][i] = 0.f;
             accd[t][i] = 0.0;
         }
-    // QX_PF register slots of 16-row steps, each refilled after its step's products
-    // (the compiler places the loads; pinning them as a deeper prefetch measured slower)
-    QxStep buf[QX_PF];
+    // PF register slots of 16-row steps, each refilled after its step's products (the
+    // compiler issues a pass's loads together; pinning each slot's loads right after its
+    // products, so that more are in flight, measured slower).  The element-wise path
+    // (n % 8 != 0) keeps two slots, which fit its registers.
+    constexpr int PF = VEC ? QX_PF : 2;
+    QxStep buf[PF];
 #pragma unroll
-    for (int d = 0; d < QX_PF; ++d) qx_load<VEC>(buf[d], n, c, Q, X, rb + 16 * d + 8 * half, rb, re, icol, jt0, m);
-    for (int64_t r0 = rb; r0 < re; r0 += 16 * QX_PF) {
+    for (int d = 0; d < PF; ++d) qx_load<VEC>(buf[d], n, c, qcol, X, rb + 16 * d + 8 * half, rb, re, icol, jt0, m);
+    for (int64_t r0 = rb; r0 < re; r0 += 16 * PF) {
 #pragma unroll
-        for (int d = 0; d < QX_PF; ++d) {
+        for (int d = 0; d < PF; ++d) {
             qx_mma<VEC>(buf[d], acc, r0 + 16 * d + 8 * half, re);
-            qx_load<VEC>(buf[d], n, c, Q, X, r0 + 16 * (d + QX_PF) + 8 * half, rb, re, icol, jt0, m);
+            qx_load<VEC>(buf[d], n, c, qcol, X, r0 + 16 * (d + PF) + 8 * half, rb, re, icol, jt0, m);
             if (d & 1) {
                 // the 32-row float32 partial into the float64 sums
 #pragma unroll
@@ -249,11 +259,14 @@ __global__ void __launch_bounds__(512, 4) basis_bf16(int64_t n, int c, int rank,
                                                      const uint16_t* __restrict__ ush, const double* __restrict__ lam,
                                                      const float* __restrict__ h0, float* __restrict__ U,
                                                      float* __restrict__ dout, int32_t* __restrict__ status,
-                                                     int whitened) {
+                                                     int whitened, int64_t qrb) {
     extern __shared__ uint16_t qs[];   // 2 * BS_BUF
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6, half = lane >> 5;
     const bool mm = wave < (rank + 31) / 32;   // uniform per wave
     const int64_t r0 = (int64_t)blockIdx.x * BS_ROWS;
+    // chain-blocked Q (qrb rows per block, qrb >= BS_ROWS / 2 and a multiple of 4): the
+    // workgroup's rows lie in block b0 and at most the next one
+    const int64_t b0 = qrb ? r0 / qrb : 0;
     const int nst = (c + BS_KC - 1) / BS_KC;
     // staging map: float4 group g = tid + q * nthr: column g % BS_KC, rows 4 (g / BS_KC) ..
     // (a wave's lanes cover 32 columns of two row groups: conflict-free LDS writes)
@@ -266,7 +279,8 @@ __global__ void __launch_bounds__(512, 4) basis_bf16(int64_t n, int c, int rank,
             const int64_t row = r0 + rr;
             float4 v = make_float4(0, 0, 0, 0);
             if (g < BS_GROUPS && k < c) {
-                const float* src = Q + (int64_t)k * n + row;
+                const int64_t b = qrb ? b0 + (row - b0 * qrb >= qrb ? 1 : 0) : 0;
+                const float* src = qrb ? Q + b * qrb * c + (int64_t)k * qrb + (row - b * qrb) : Q + (int64_t)k * n + row;
                 if (VEC) {
                     if (row < n) v = *(const float4*)src;   // n % 4 == 0: the group is all in or all out
                 } else {
@@ -384,15 +398,19 @@ __global__ void __launch_bounds__(512, 4) basis_bf16(int64_t n, int c, int rank,
 }  // namespace
 
 int qtx_bf16_launch(hipStream_t st, int64_t n, int c, const float* Q, const bf16_t* X, double* part, int nchunks,
-                    int64_t rows_per_chunk) {
+                    int64_t rows_per_chunk, int64_t q_block) {
     if (c < 1 || c > 256 || rows_per_chunk % 16 != 0) return BFGS_ERR_ARG;
+    // a blocked Q is read one block per chunk; every chunk holds at least one row
+    if (q_block != 0 && (q_block != rows_per_chunk || (int64_t)(nchunks - 1) * rows_per_chunk >= n))
+        return BFGS_ERR_ARG;
+    const int qblk = q_block != 0 ? 1 : 0;
     const int ntj = (c + 31) / 32, jgroups = (ntj + QX_NJ - 1) / QX_NJ;
     const dim3 block(64 * ntj);   // <= 8 waves
     const dim3 grid((unsigned)(ceil_div((int64_t)nchunks, 8) * 8 * jgroups));
     if (n % 8 == 0)
-        hipLaunchKernelGGL(qtx_bf16<true>, grid, block, 0, st, n, c, Q, X, part, nchunks, rows_per_chunk);
+        hipLaunchKernelGGL(qtx_bf16<true>, grid, block, 0, st, n, c, Q, X, part, nchunks, rows_per_chunk, qblk);
     else
-        hipLaunchKernelGGL(qtx_bf16<false>, grid, block, 0, st, n, c, Q, X, part, nchunks, rows_per_chunk);
+        hipLaunchKernelGGL(qtx_bf16<false>, grid, block, 0, st, n, c, Q, X, part, nchunks, rows_per_chunk, qblk);
     return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
 }
 
@@ -402,8 +420,10 @@ size_t basis_bf16_workspace(int c, int rank) {
 }
 
 int basis_bf16_launch(hipStream_t st, int64_t n, int c, int rank, const float* Q, const double* Us, uint16_t* ush,
-                      const double* lam, const float* h0, float* U, float* dout, int32_t* status, bool whitened) {
+                      const double* lam, const float* h0, float* U, float* dout, int32_t* status, bool whitened,
+                      int64_t q_block) {
     if (c < 1 || c > 256 || rank < 1 || rank > c) return BFGS_ERR_ARG;
+    if (q_block != 0 && (q_block < BS_ROWS / 2 || q_block % 4 != 0)) return BFGS_ERR_ARG;
     const int nks = (c + 15) / 16, ntj = (rank + 31) / 32;
     const int total = ntj * nks * 512;
     hipLaunchKernelGGL(split_us, dim3((total + 255) / 256), dim3(256), 0, st, c, rank, nks, Us, ush);
@@ -414,9 +434,9 @@ int basis_bf16_launch(hipStream_t st, int64_t n, int c, int rank, const float* Q
     const size_t smem = 2 * BS_BUF * sizeof(uint16_t);
     if (n % 4 == 0)
         hipLaunchKernelGGL(basis_bf16<true>, grid, block, smem, st, n, c, rank, nks, Q, ush, lam, h0, U, dout, status,
-                           whitened ? 1 : 0);
+                           whitened ? 1 : 0, q_block);
     else
         hipLaunchKernelGGL(basis_bf16<false>, grid, block, smem, st, n, c, rank, nks, Q, ush, lam, h0, U, dout, status,
-                           whitened ? 1 : 0);
+                           whitened ? 1 : 0, q_block);
     return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
 }

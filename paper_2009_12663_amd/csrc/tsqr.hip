@@ -853,7 +853,7 @@ __global__ void __launch_bounds__(1024) tree_forward_q(int c, int stride, int64_
 template <typename TQ, typename SlotT, int BT, int PF>
 __global__ void __launch_bounds__(1024) leaf_backward(int64_t n, int c, int64_t rows_per_chain,
                                                       const double* __restrict__ refl, const double* __restrict__ Qtop,
-                                                      TQ* __restrict__ Q, uint64_t perm) {
+                                                      TQ* __restrict__ Q, uint64_t perm, int qblk) {
     extern __shared__ double lds[];
     constexpr int RT = Layout<BT>::RT, PS = Layout<BT>::PS;
     SlotT* slot = (SlotT*)(lds + Layout<BT>::HEAD);
@@ -865,6 +865,10 @@ __global__ void __launch_bounds__(1024) leaf_backward(int64_t n, int c, int64_t 
     const int64_t r_end = min(n, r_begin + rows_per_chain);
     const int tiles_per_chain = (int)(rows_per_chain / BT);
     const int ntiles = (int)((r_end - r_begin + BT - 1) / BT);
+    // column-major Q (leading dimension n), or the chain's own block of Q (leading
+    // dimension rows_per_chain)
+    TQ* Qc = qblk ? Q + (int64_t)ch * rows_per_chain * c - r_begin : Q;
+    const int64_t ldq = qblk ? rows_per_chain : n;
     slot_load(slot, Qtop + (int64_t)ch * c * c, c);
     for (int tile = ntiles - 1; tile >= 0; --tile) {
         const int64_t r0 = r_begin + (int64_t)tile * BT;
@@ -879,7 +883,7 @@ __global__ void __launch_bounds__(1024) leaf_backward(int64_t n, int c, int64_t 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int64_t row = r0 + rt * 16 + q + 4 * r;
-                    if (row < r_end) Q[(int64_t)col * n + row] = (TQ)A[rt][r];
+                    if (row < r_end) Qc[(int64_t)col * ldq + row] = (TQ)A[rt][r];
                 }
         }
     }
@@ -930,14 +934,14 @@ inline int floor_pow2(int64_t x) {
 
 // PF: doubles per thread that stage one stored panel in the backward passes.
 template <typename TE, typename TQ, typename SlotT, int BT, int PF>
-int tsqr_impl(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out) {
+int tsqr_impl(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out, bool q_blocked) {
+    static_assert(BT == QR_TILE, "chain rows are counted in QR_TILE-row tiles");
     constexpr int PS = Layout<BT>::PS;
     const int64_t n = h->n;
     const int np = (c + PW - 1) / PW;
     const int threads = 64 * np;
-    const int64_t tiles_total = (n + BT - 1) / BT;
-    const int nchains = (int)std::min<int64_t>(h->qr_chains, floor_pow2(std::max<int64_t>(1, tiles_total / 2)));
-    const int64_t rows_per_chain = round_up((n + nchains - 1) / nchains, BT);
+    int nchains;
+    const int64_t rows_per_chain = tsqr_chain_rows(h, &nchains);
     const int tiles_per_chain = (int)(rows_per_chain / BT);
     const int ntt = (c + BT - 1) / BT;
     int rc;
@@ -995,14 +999,14 @@ int tsqr_impl(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out) {
     prof_end(h);
     prof_begin(h, "tsqr_leaf_bwd");
     hipLaunchKernelGGL((leaf_backward<TQ, SlotT, BT, PF>), dim3(nchains), dim3(threads), smem, h->stream, n, c,
-                       rows_per_chain, refl, Qtop, Q, perm);
+                       rows_per_chain, refl, Qtop, Q, perm, q_blocked ? 1 : 0);
     prof_end(h);
     *R_out = Rs;   // chain 0 holds the final R (row-major, upper triangular)
     return hipGetLastError() == hipSuccess ? BFGS_OK : BFGS_ERR_HIP;
 }
 
 template <typename TE, typename TQ>
-int tsqr_dispatch(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out) {
+int tsqr_dispatch(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out, bool q_blocked) {
     if (c < 1 || c > 256) return BFGS_ERR_ARG;
     // 64-row tiles keep a tile's fragments, the staging registers and the panel work
     // within 128 registers per lane (1024-thread workgroups); the slot is float64
@@ -1012,10 +1016,10 @@ int tsqr_dispatch(bfgsuq_ctx* h, int c, const TE* E, TQ* Q, double** R_out) {
     // staging doubles per thread for one stored panel (64 * ceil(c / 16) threads); more
     // than 8 (c <= 32) copies panels straight to LDS
     const int pf = ceil_div(Layout<64>::PS, 64 * ceil_div(c, PW));
-    if (pf <= 2) return dslot ? tsqr_impl<TE, TQ, double, 64, 2>(h, c, E, Q, R_out) : tsqr_impl<TE, TQ, float, 64, 2>(h, c, E, Q, R_out);
-    if (pf <= 3) return dslot ? tsqr_impl<TE, TQ, double, 64, 3>(h, c, E, Q, R_out) : tsqr_impl<TE, TQ, float, 64, 3>(h, c, E, Q, R_out);
-    if (pf <= 5) return dslot ? tsqr_impl<TE, TQ, double, 64, 5>(h, c, E, Q, R_out) : tsqr_impl<TE, TQ, float, 64, 5>(h, c, E, Q, R_out);
-    return dslot ? tsqr_impl<TE, TQ, double, 64, 8>(h, c, E, Q, R_out) : tsqr_impl<TE, TQ, float, 64, 8>(h, c, E, Q, R_out);
+    if (pf <= 2) return dslot ? tsqr_impl<TE, TQ, double, 64, 2>(h, c, E, Q, R_out, q_blocked) : tsqr_impl<TE, TQ, float, 64, 2>(h, c, E, Q, R_out, q_blocked);
+    if (pf <= 3) return dslot ? tsqr_impl<TE, TQ, double, 64, 3>(h, c, E, Q, R_out, q_blocked) : tsqr_impl<TE, TQ, float, 64, 3>(h, c, E, Q, R_out, q_blocked);
+    if (pf <= 5) return dslot ? tsqr_impl<TE, TQ, double, 64, 5>(h, c, E, Q, R_out, q_blocked) : tsqr_impl<TE, TQ, float, 64, 5>(h, c, E, Q, R_out, q_blocked);
+    return dslot ? tsqr_impl<TE, TQ, double, 64, 8>(h, c, E, Q, R_out, q_blocked) : tsqr_impl<TE, TQ, float, 64, 8>(h, c, E, Q, R_out, q_blocked);
 }
 
 }  // namespace
@@ -1032,8 +1036,19 @@ extern "C" int bfgs_tsqr_shape(int32_t c, int32_t* slot_f64, int32_t* ring) {
     return BFGS_OK;
 }
 
-int tsqr_run(bfgsuq_ctx* h, int c, const float* E, float* Q, double** R_out) { return tsqr_dispatch(h, c, E, Q, R_out); }
-int tsqr_run(bfgsuq_ctx* h, int c, const double* E, float* Q, double** R_out) { return tsqr_dispatch(h, c, E, Q, R_out); }
+int64_t tsqr_chain_rows(const bfgsuq_ctx* h, int* nchains) {
+    const int64_t tiles_total = (h->n + QR_TILE - 1) / QR_TILE;
+    const int nch = (int)std::min<int64_t>(h->qr_chains, floor_pow2(std::max<int64_t>(1, tiles_total / 2)));
+    if (nchains) *nchains = nch;
+    return round_up((h->n + nch - 1) / nch, QR_TILE);
+}
+
+int tsqr_run(bfgsuq_ctx* h, int c, const float* E, float* Q, double** R_out, bool q_blocked) {
+    return tsqr_dispatch(h, c, E, Q, R_out, q_blocked);
+}
+int tsqr_run(bfgsuq_ctx* h, int c, const double* E, float* Q, double** R_out) {
+    return tsqr_dispatch(h, c, E, Q, R_out, false);
+}
 int tsqr_run(bfgsuq_ctx* h, int c, const double* E, double* Q, double** R_out) {
-    return tsqr_dispatch(h, c, E, Q, R_out);
+    return tsqr_dispatch(h, c, E, Q, R_out, false);
 }
