@@ -17,6 +17,18 @@ struct u64x4 {
     uint64_t v[4];
 };
 
+// Full 128-bit product of a 64-bit word and the constant M = (mh, ml), from the four
+// 32 x 32 -> 64 partial products, each with the carry-in folded into its addend (so
+// each is one multiply-add on the vector unit, and the low word reuses them).
+__device__ __forceinline__ void mul_128(uint64_t x, uint32_t mh, uint32_t ml, uint64_t& hi, uint64_t& lo) {
+    const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
+    const uint64_t p00 = (uint64_t)xl * ml;
+    const uint64_t t = (uint64_t)xl * mh + (p00 >> 32);          // < 2^64
+    const uint64_t u = (uint64_t)xh * ml + (uint32_t)t;          // < 2^64
+    lo = (u << 32) | (uint32_t)p00;
+    hi = (uint64_t)xh * mh + ((t >> 32) + (u >> 32));            // the high word of x M
+}
+
 __device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
                                                uint64_t k1) {
     const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
@@ -27,8 +39,9 @@ __device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
             k0 += W0;
             k1 += W1;
         }
-        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t hi0, lo0, hi1, lo1;
+        mul_128(c0, (uint32_t)(M0 >> 32), (uint32_t)M0, hi0, lo0);
+        mul_128(c2, (uint32_t)(M1 >> 32), (uint32_t)M1, hi1, lo1);
         const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
