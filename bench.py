@@ -49,7 +49,9 @@ def kernel_models(n, k, c, rank, wb, vb, ob):
     """Algorithmic bytes and flops per launch of each kernel group: GEMM1 reads S, Y
     (2 n k words), the block and h0; GEMM2 reads S, Y, the block (B_k V only: the h0 V
     term) and h0, and writes the output; the rSVD groups are listed with their inputs
-    and outputs read and written once."""
+    and outputs read and written once.  The TSQR passes count the usual Householder
+    flops for n >> c: 2 n c^2 to factor and 4 n c^2 to form the thin Q explicitly
+    (4/3 c^2 (3n - c) in full)."""
     pass_bytes = 2 * n * k * wb
     return {
         "apply_gemm1": dict(bound="hbm", bytes=pass_bytes + n * c * vb + 4 * n, flops=2 * n * 2 * k * c),
@@ -58,7 +60,7 @@ def kernel_models(n, k, c, rank, wb, vb, ob):
         "hdiff_gemm1": dict(bound="hbm", bytes=pass_bytes + n * c * vb + 4 * n, flops=2 * n * 2 * k * c),
         "hdiff_gemm2": dict(bound="hbm", bytes=pass_bytes + n * c * ob + 4 * n, flops=2 * n * 2 * k * c),
         "tsqr_leaf_fwd": dict(bound="alu", bytes=n * c * ob + n * c * 8, flops=2 * n * c * c),
-        "tsqr_leaf_bwd": dict(bound="alu", bytes=n * c * 8 + n * c * ob, flops=2 * n * c * c),
+        "tsqr_leaf_bwd": dict(bound="alu", bytes=n * c * 8 + n * c * ob, flops=4 * n * c * c),
         "proj_QtX": dict(bound="hbm", bytes=n * c * (ob + vb), flops=2 * n * c * c),
         "basis_diag": dict(bound="hbm", bytes=n * c * ob + 2 * n * rank * ob + 8 * n, flops=2 * n * c * rank),
         "probes": dict(bound="hbm", bytes=n * c * vb, flops=0),
