@@ -803,6 +803,29 @@ def summarize_profiles(d, out_dir, digest, cmd_prefix):
             lines.append(f"| {short_name(k)[:60]} | {group_of(k) or '-'} | {fb / 1e9:.2f} | {fd / 1e9:.2f} | {ms:.4f} | "
                          f"{tb:.1f} ({100 * tb / 2500:.1f} %) | {td:.2f} ({100 * td / 78.6:.1f} %) | {busy:.1f} |")
         open(os.path.join(out_dir, "mfma_grid3_bf16.md"), "w").write("\n".join(lines) + "\n")
+    # address translation: the per-CU translation cache's requests, hits and misses
+    tl = {c: counter_means("utcl1_*counter_collection.csv", c)
+          for c in ("TCP_UTCL1_REQUEST_sum", "TCP_UTCL1_TRANSLATION_HIT_sum", "TCP_UTCL1_TRANSLATION_MISS_sum",
+                    "TCP_UTCL1_THRASHING_STALL_sum")}
+    if tl["TCP_UTCL1_REQUEST_sum"]:
+        lines = ["# Address translation per dispatch: 1700 x 350 x 3 grid, n = 1,785,000, k = 200, bfloat16", "",
+                 "Command (from the repository root; one pass, 4 TCP counters):", "",
+                 f"    {cmd_prefix} --pmc TCP_UTCL1_TRANSLATION_MISS_sum TCP_UTCL1_TRANSLATION_HIT_sum "
+                 "TCP_UTCL1_REQUEST_sum TCP_UTCL1_THRASHING_STALL_sum -d <dir> -o utcl1 --output-format csv -- "
+                 "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-fp32-path", "",
+                 "miss % = misses / (hits + misses) of the per-CU translation cache (UTCL1), summed over "
+                 "the CUs; library kernels with at least 10^6 requests.", "",
+                 "| kernel | group | requests | miss % | thrashing stalls |", "|---|---|---|---|---|"]
+        req = tl["TCP_UTCL1_REQUEST_sum"]
+        for k in sorted(req, key=lambda k: -req[k]):
+            if group_of(k) is None or req[k] < 1e6:
+                continue
+            hit = tl["TCP_UTCL1_TRANSLATION_HIT_sum"].get(k, 0.0)
+            miss = tl["TCP_UTCL1_TRANSLATION_MISS_sum"].get(k, 0.0)
+            lines.append(f"| {short_name(k)[:60]} | {group_of(k)} | {req[k]:.3e} | "
+                         f"{100 * miss / max(hit + miss, 1.0):.2f} | "
+                         f"{tl['TCP_UTCL1_THRASHING_STALL_sum'].get(k, 0.0):.3e} |")
+        open(os.path.join(out_dir, "translation_grid3_bf16.md"), "w").write("\n".join(lines) + "\n")
     log(f"[bench] wrote profile summaries for {len(per_group)} kernel groups to {out_dir}")
 
 
