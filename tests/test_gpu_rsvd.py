@@ -124,6 +124,41 @@ def test_rsvd_parity(storage, kind, nx, nz, k, rank, p, precond):
     assert r["orth"] <= (1e-12 if storage == "f64" else 1e-5)
 
 
+def _chains(n, max_chains=256, tile=64):
+    """TSQR chain count and rows per chain for n rows (the library's split: whole
+    64-row tiles, a power-of-two count of chains with at least two tiles each)."""
+    tiles = -(-n // tile)
+    nch = 1
+    while nch * 2 <= min(max_chains, max(1, tiles // 2)):
+        nch *= 2
+    rpc = -(-(-(-n // nch)) // tile) * tile
+    return nch, rpc
+
+
+# Edges of the chain-blocked Q of the bfloat16 rSVD (each chain's rows one block of B
+# = rows per chain): one chain with B = 64 (the basis pass's 128-row workgroup
+# reaches past the only block) and with B = 192; 256 chains of B = 128 with a short
+# last chain, n % 8 == 0 (the vector loads); B = 192 with empty trailing chains.
+CHAIN_EDGES = [(5, 4, (1, 64)), (43, 1, (1, 192)), (273, 40, (256, 128)), (331, 33, (256, 192))]
+
+
+@pytest.mark.parametrize("nx,nz,shape", CHAIN_EDGES)
+def test_bf16_rsvd_chain_block_edges(nx, nz, shape):
+    n = 3 * nx * nz
+    nch, rpc = _chains(n)
+    assert (nch, rpc) == shape
+    if n == 32769:
+        assert (nch - 1) * rpc >= n   # some chains are empty
+    print(f"\n[rsvd chain blocks] bf16 n={n} chains={nch} rows/chain={rpc}", flush=True)
+    prob, S, Y, h0 = make_pairs("cg", nx, nz, 12, seed=5)
+    r = run_case("bf16", S, Y, h0, 16, 4, seed=3)
+    print(f"  sigma {r['sig']:.2e} rec {r['rec']:.2e} diag_max {r['diag_max']:.2e} orth {r['orth']:.2e}",
+          flush=True)
+    # measured: Sigma 1.6e-6-6.4e-6, reconstruction up to 3.0e-5, diagonal up to 6.4e-6
+    assert r["sig"] <= 1e-4 and r["rec"] <= 2e-4
+    assert r["diag_max"] <= 1e-4 and r["orth"] <= 1e-5
+
+
 def _fold_edges():
     """Block widths at the TSQR fold's configuration edges, from the library's own
     shape query: the largest c with a float64 slot, the first with a float32 slot,
