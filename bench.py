@@ -975,6 +975,12 @@ def main():
         if name in prof:
             cnt, tot_ms = prof[name]
             roof_apply.append(roofline_entry(name, models[name], tot_ms / cnt / 1e3, load_traffic(name, digest)))
+    # the other modelled groups of the rSVD step, each against its own bound
+    roof_rsvd = []
+    for name in ("tsqr_leaf_bwd", "proj_QtX", "basis_diag", "hdiff_gemm1", "hdiff_gemm2"):
+        if name in prof and name in models_rsvd and not (dom and dom[1] == name):
+            cnt, tot_ms = prof[name]
+            roof_rsvd.append(roofline_entry(name, models_rsvd[name], tot_ms / cnt / 1e3, load_traffic(name, digest)))
 
     result = {
         "metric": "H_k V columns/s + rSVD wall time at n=1.785M, k=200; rel err vs FP64 oracle",
@@ -999,6 +1005,7 @@ def main():
         "device_status": status,
         "roofline": roof,
         "roofline_apply": roof_apply,
+        "roofline_rsvd": roof_rsvd,
         "kernels_ms_per_step": {name: round(v[1] / args.steps, 4) for name, v in prof.items()},
         "source_digest": digest,
     }
