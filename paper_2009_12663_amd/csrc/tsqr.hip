@@ -1,5 +1,6 @@
 // Householder TSQR of E (n x c, column-major, c <= 256) for Alg. 3's "E = Q R":
-// Q explicit (n x c, column-major), R upper triangular (c x c, row-major).
+// Q explicit (n x c, column-major, or chain-blocked: each chain's rows one
+// contiguous column-major block), R upper triangular (c x c, row-major).
 //
 // Layout.  E is split into `nchains` contiguous row ranges, one workgroup each.
 // A workgroup keeps an upper-triangular c x c slot (packed, LDS) and folds its
