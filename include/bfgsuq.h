@@ -225,18 +225,24 @@ int bfgs_get_status(bfgs_t h);
 /* ---------------------------------------------------------------------------
  * Launch-shape tuning.
  * bfgs_autotune — times the tunable launch shapes for this handle and ncols
- *   probe columns (rows per pass-1 workgroup of the bfloat16 MFMA apply; number
- *   of TSQR chains when rank/U/Sigma are given) with HIP events on the handle's
+ *   probe columns (row slots of the bfloat16 MFMA apply's pass 1, its split-K
+ *   depth; number of TSQR chains when rank/U/Sigma are given) with HIP events on the handle's
  *   stream and keeps the fastest in the handle.  V (device, n x ncols, storage
  *   type) and out (device, n x ncols) are scratch inputs/outputs it may
  *   overwrite; U (n x rank) and Sigma (rank) likewise, or NULL to tune the
  *   apply only.  Synchronous; results are unchanged by tuning except for the
  *   summation order of the split-K reduction and of the TSQR tree.
  * bfgs_tuning — reads the current choices (host pointers, either may be NULL).
+ * bfgs_set_tuning — sets them: g1_rows in 8 .. 1024 row slots, qr_chains a power
+ *   of two in 1 .. 256 (the TSQR uses at most that many chains, fewer when E has
+ *   fewer than two 64-row tiles per chain); a value <= 0 keeps the current
+ *   choice.  BFGS_ERR_ARG for anything else.  Like bfgs_autotune it changes the
+ *   handle's generation, so a captured batch graph refuses to replay.
  * ------------------------------------------------------------------------- */
 int bfgs_autotune(bfgs_t h, int32_t ncols, int32_t rank, int32_t oversample, void* V, void* out, void* U,
                   double* Sigma);
 int bfgs_tuning(bfgs_t h, int32_t* g1_rows, int32_t* qr_chains);
+int bfgs_set_tuning(bfgs_t h, int32_t g1_rows, int32_t qr_chains);
 
 /* ---------------------------------------------------------------------------
  * Batched form: nprob independent inversions of uneven n and k driven as one

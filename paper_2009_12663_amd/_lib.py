@@ -37,7 +37,7 @@ EXPORTS = [
     "bfgs_apply_Hinv_noalloc",
     "bfgs_apply_Hdiff", "bfgs_generate_probes", "bfgs_rsvd", "bfgs_rsvd_ex", "bfgs_posterior_diag",
     "bfgs_get_pair", "bfgs_get_h0", "bfgs_get_status", "bfgs_status_string",
-    "bfgs_profile", "bfgs_profile_report", "bfgs_autotune", "bfgs_tuning", "bfgs_sync", "bfgs_tsqr_shape",
+    "bfgs_profile", "bfgs_profile_report", "bfgs_autotune", "bfgs_tuning", "bfgs_set_tuning", "bfgs_sync", "bfgs_tsqr_shape",
     "bfgs_batch_create", "bfgs_batch_handle", "bfgs_batch_push_pairs", "bfgs_batch_apply_Hinv", "bfgs_batch_rsvd",
     "bfgs_batch_autotune", "bfgs_batch_graph_build", "bfgs_batch_graph_launch", "bfgs_batch_destroy",
     "bfgs_precond_diag", "bfgs_gridop_create", "bfgs_gridop_apply", "bfgs_gridop_destroy", "bfgs_minimize_quadratic",
@@ -86,6 +86,7 @@ def load(path: str = LIB_PATH):
         "bfgs_profile_report": [vp, ctypes.c_char_p, i32],
         "bfgs_autotune": [vp, i32, i32, i32, vp, vp, vp, vp],
         "bfgs_tuning": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "bfgs_set_tuning": [vp, i32, i32],
         "bfgs_sync": [vp],
         "bfgs_tsqr_shape": [i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "bfgs_batch_create": [i32, vp, vp, vp, ctypes.c_int, vp, ctypes.POINTER(vp)],
@@ -363,6 +364,10 @@ class Bfgs:
         a, b = ctypes.c_int32(), ctypes.c_int32()
         _check(self.L.bfgs_tuning(self.h, ctypes.byref(a), ctypes.byref(b)), "bfgs_tuning")
         return {"g1_rows": a.value, "qr_chains": b.value}
+
+    def set_tuning(self, g1_rows: int = 0, qr_chains: int = 0):
+        """bfgs_set_tuning: pin the launch shapes (0 keeps a choice)."""
+        _check(self.L.bfgs_set_tuning(self.h, int(g1_rows), int(qr_chains)), "bfgs_set_tuning")
 
     def profile(self, enable: bool):
         _check(self.L.bfgs_profile(self.h, 1 if enable else 0), "bfgs_profile")

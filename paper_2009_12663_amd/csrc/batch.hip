@@ -172,6 +172,18 @@ int bfgs_tuning(bfgs_t h, int32_t* g1_rows, int32_t* qr_chains) {
     return BFGS_OK;
 }
 
+int bfgs_set_tuning(bfgs_t h, int32_t g1_rows, int32_t qr_chains) {
+    if (!h) return BFGS_ERR_ARG;
+    // the TSQR tree pairs chains: a power of two, at most the partials' 256
+    const bool g1_ok = g1_rows <= 0 || (g1_rows >= 8 && g1_rows <= 1024);
+    const bool qr_ok = qr_chains <= 0 || (qr_chains <= 256 && (qr_chains & (qr_chains - 1)) == 0);
+    if (!g1_ok || !qr_ok) return BFGS_ERR_ARG;
+    if (g1_rows > 0) h->g1_nk = g1_rows;
+    if (qr_chains > 0) h->qr_chains = qr_chains;
+    ++h->gen;   // launch shapes may have changed
+    return BFGS_OK;
+}
+
 int bfgs_batch_destroy(bfgs_batch_t b) {
     if (!b) return BFGS_OK;
     (void)hipStreamSynchronize(b->main);

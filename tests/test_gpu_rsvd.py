@@ -39,9 +39,12 @@ def oracle_h0(storage, S, Y, h0):
     return h0_storage(h0, storage)
 
 
-def run_case(storage, S, Y, h0, rank, p, seed):
+def run_case(storage, S, Y, h0, rank, p, seed, qr_chains=0):
     n = S.shape[1]
     H = build_handle(storage, S, Y, h0)
+    if qr_chains:
+        H.set_tuning(qr_chains=qr_chains)
+        assert H.tuning()["qr_chains"] == qr_chains
     U, Sig = H.rsvd(rank, p, seed)
     d = H.posterior_diag()
     assert H.get_status() == 0
@@ -157,6 +160,38 @@ def test_bf16_rsvd_chain_block_edges(nx, nz, shape):
     # measured: Sigma 1.6e-6-6.4e-6, reconstruction up to 3.0e-5, diagonal up to 6.4e-6
     assert r["sig"] <= 1e-4 and r["rec"] <= 2e-4
     assert r["diag_max"] <= 1e-4 and r["orth"] <= 1e-5
+
+
+@pytest.mark.parametrize("chains", [1, 64, 128])
+def test_bf16_rsvd_chain_counts(chains):
+    """Fewer TSQR chains (bfgs_set_tuning) give longer chain blocks of Q: n = 32760
+    in one block of 32768 rows, 64 of 512 and 128 of 256 (256 chains of 128 rows by
+    default)."""
+    nx, nz = 273, 40
+    n = 3 * nx * nz
+    nch, rpc = _chains(n, max_chains=chains)
+    assert nch == chains and rpc == -(-n // (chains * 64)) * 64
+    print(f"\n[rsvd chain count] bf16 n={n} chains={nch} rows/chain={rpc}", flush=True)
+    prob, S, Y, h0 = make_pairs("cg", nx, nz, 12, seed=5)
+    r = run_case("bf16", S, Y, h0, 16, 4, seed=3, qr_chains=chains)
+    print(f"  sigma {r['sig']:.2e} rec {r['rec']:.2e} diag_max {r['diag_max']:.2e} orth {r['orth']:.2e}",
+          flush=True)
+    assert r["sig"] <= 1e-4 and r["rec"] <= 2e-4
+    assert r["diag_max"] <= 1e-4 and r["orth"] <= 1e-5
+
+
+def test_set_tuning_rejects_bad_shapes():
+    P = lib()
+    H = P.Bfgs(1000, 4, None, "bf16")
+    for g1, qr in ((4, 0), (2048, 0), (0, 3), (0, 512), (0, 96)):
+        with pytest.raises(P.BfgsError) as e:
+            H.set_tuning(g1_rows=g1, qr_chains=qr)
+        assert e.value.code == P.BFGS_ERR_ARG
+    H.set_tuning(g1_rows=64, qr_chains=32)
+    assert H.tuning() == {"g1_rows": 64, "qr_chains": 32}
+    H.set_tuning()                     # zeros keep both
+    assert H.tuning() == {"g1_rows": 64, "qr_chains": 32}
+    H.close()
 
 
 def _fold_edges():
