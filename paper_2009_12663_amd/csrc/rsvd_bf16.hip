@@ -371,8 +371,9 @@ __global__ void __launch_bounds__(512, 4) basis_bf16(int64_t n, int c, int rank,
                 const int j = wave * 32 + 8 * (i / 4) + 4 * half + i % 4;
                 const double u = (double)acc[t][i];
                 sd = fma(lv[i], u * u, sd);
-                // U is not read again here: streaming stores keep it out of the caches
-                if (j < rank && row < n) __builtin_nontemporal_store(acc[t][i], U + (int64_t)j * n + row);
+                // plain stores: streaming (non-temporal) ones made this pass 7 % slower and the
+                // next apply 2 % slower
+                if (j < rank && row < n) U[(int64_t)j * n + row] = acc[t][i];
             }
             sd += __shfl_xor(sd, 32, 64);   // the other half's columns of the same row
             if (half == 0) dpart[wave * BS_ROWS + t * 32 + lane] = sd;
